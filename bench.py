@@ -1,0 +1,221 @@
+"""Benchmark of the PIV hot path on one MI355X.
+
+A step is one pass of the whole path (predict -> validate predictor ->
+correct -> validate -> vorticity) over one batch of synthetic 1 MP u8 pairs
+resident in HBM (1024 x 1024, 0.04 ppp, Lamb-Oseen vortex with 20 px peak
+displacement and 10% particle dropout; 16 x 16 windows at step 8 -> 128 x 128
+vectors; +-4 px correction search; 3-level predictor with radii 6/2).
+
+Prints ONE JSON line with pairs/s (value), Mvectors/s, p50/p99 latency of
+the batched step and of a single pair, the HBM-roofline fraction of the
+whole step, the roofline of the dominant kernel (the correlation stage)
+measured with HIP events on its stream, and the FP64 CPU oracle timed on
+a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP32_PEAK_TFLOPS = 157.3       # MI355X FP32 vector (dense)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--batch", type=int, default=64)
+    ap.add_argument("--distinct", type=int, default=8, help="distinct rendered pairs in the batch")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-latency", action="store_true")
+    ap.add_argument("--quiet", action="store_true")
+    return ap.parse_args()
+
+
+def log(args, *a):
+    if not args.quiet:
+        print(*a, file=sys.stderr, flush=True)
+
+
+def algorithmic(W, H, nx, ny, r):
+    """Per-pair algorithmic bytes and FP32 flops of the correlation stage and
+    of the whole path (what the method must touch/compute, not what a kernel
+    happens to do)."""
+    S = (2 * r + 1) ** 2
+    xcorr_flop = 2.0 * S * W * H            # one FMA per pixel-shift product (shared by windows)
+    combine_flop = 25.0 * S * nx * ny       # window sums -> coefficient, argmax
+    warp_flop = 20.0 * W * H                # bilinear deformation of B
+    corr_flop = xcorr_flop + combine_flop + warp_flop
+    corr_bytes = 2.0 * W * H + nx * ny * (2 * 4 + 2 * 4 + 4 + 1)   # A, B, pred in, disp, peak, flags
+    path_bytes = 2.0 * W * H + nx * ny * 17.0  # A, B in; disp 8, flags 1, omega 4, peak 4 out
+    return dict(corr_flop=corr_flop, corr_bytes=corr_bytes, path_bytes=path_bytes)
+
+
+def cpu_baseline(A, B, plan_kw, log_fn):
+    """The FP64 oracle (as it stands) on a bounded sample of one pair: the
+    full predictor, then the correction on a 512-row strip (8192 of the
+    16384 windows), validation and vorticity on the full grid; seconds per
+    pair are scaled from the strip."""
+    import oracle
+    W = A.shape[1]
+    t0 = time.perf_counter()
+    pred = oracle.predict(A, B, 8, 16, 3, 6, 2).astype(np.float64)
+    pred, _ = oracle.validate(pred, None)
+    t_pred = time.perf_counter() - t0
+    rows = 64
+    strip = slice(256, 768)
+    # a strip of the image with its predictor rows; windows of the strip see
+    # their true neighbours except at the strip's top and bottom rows
+    As, Bs = A[strip], B[strip]
+    ps = np.ascontiguousarray(pred[:, 32:32 + rows])
+    t0 = time.perf_counter()
+    disp, peak, flags = oracle.correct(As, Bs, 16, 8, 4, ps)
+    t_corr = (time.perf_counter() - t0) * (A.shape[0] // 8) / rows
+    t0 = time.perf_counter()
+    full = np.zeros((2, A.shape[0] // 8, W // 8))
+    fl = np.zeros(full.shape[1:], np.uint8)
+    oracle.validate(full, fl)
+    oracle.vorticity(full, 8)
+    t_post = time.perf_counter() - t0
+    sec = t_pred + t_corr + t_post
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    log_fn(f"cpu oracle: predict {t_pred:.2f}s, correct (scaled) {t_corr:.2f}s, post {t_post:.3f}s")
+    return {"value": round(1.0 / sec, 5), "unit": "pairs/s", "cores": cores, "kind": "oracle",
+            "sample": "one 1024x1024 pair: full predictor + validation + vorticity; correction on a "
+                      "512-row strip (8192 of 16384 windows) scaled x2"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: this build runs on a single MI355X (asked for {args.gpus}); "
+              "pairs are independent, so N GPUs would each run this benchmark on their own stream of pairs.",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2504_17987_amd import api, synth
+
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    dev = torch.device("cuda:0")
+    W = H = 1024
+    kw = dict(win=16, step=8, radius=4, levels=3, radius_coarse=6, radius_fine=2)
+    nb, nd = args.batch, min(args.distinct, args.batch)
+    log(args, f"rendering {nd} distinct 1 MP pairs ...")
+    pairs = [synth.cfg2_pair(2000 + i) for i in range(nd)]
+    A = torch.empty((nb, H, W), dtype=torch.uint8, device=dev)
+    B = torch.empty((nb, H, W), dtype=torch.uint8, device=dev)
+    for i in range(nb):
+        A[i].copy_(torch.from_numpy(pairs[i % nd][0]))
+        B[i].copy_(torch.from_numpy(pairs[i % nd][1]))
+    plan = api.Plan(W, H, max_batch=nb, **kw)
+    nx, ny = plan.nx, plan.ny
+    out = dict(pred=torch.empty((nb, 2, ny, nx), device=dev), disp=torch.empty((nb, 2, ny, nx), device=dev),
+               peak=torch.empty((nb, ny, nx), device=dev), flags=torch.empty((nb, ny, nx), dtype=torch.uint8, device=dev),
+               omega=torch.empty((nb, ny, nx), device=dev))
+    stream = torch.cuda.current_stream(dev)
+
+    for _ in range(args.warmup):
+        plan.run(A, B, out)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    t0 = time.perf_counter()
+    ev[0].record(stream)
+    for k in range(args.steps):
+        plan.run(A, B, out)
+        ev[k + 1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    step_ms = np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(args.steps)])
+    total_ms = ev[0].elapsed_time(ev[-1])
+    ms_per_step = total_ms / args.steps
+    pairs_s = nb * args.steps / (total_ms / 1e3)
+    log(args, f"step {ms_per_step:.3f} ms ({wall / args.steps * 1e3:.3f} ms wall), {pairs_s:.0f} pairs/s")
+
+    # dominant kernel: the correlation stage, timed alone with events on its stream
+    pred = out["pred"].clone()
+    disp, peakb, flags = out["disp"], out["peak"], out["flags"]
+    for _ in range(3):
+        plan.correct(A, B, pred, disp, peakb, flags)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        plan.correct(A, B, pred, disp, peakb, flags)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    corr_ms = e0.elapsed_time(e1) / args.steps
+    alg = algorithmic(W, H, nx, ny, kw["radius"])
+    corr_tflops = alg["corr_flop"] * nb / (corr_ms / 1e3) / 1e12
+    log(args, f"correct kernel {corr_ms:.3f} ms/launch, {corr_tflops:.2f} TFLOP/s algorithmic")
+
+    lat = {}
+    if not args.no_latency:
+        # single pair, plain per-pair form
+        p1 = api.Plan(W, H, max_batch=1, **kw)
+        o1 = {k: v[:1].clone() for k, v in out.items()}
+        a1, b1 = A[:1].clone(), B[:1].clone()
+        for _ in range(5):
+            p1.run(a1, b1, o1)
+        torch.cuda.synchronize()
+        xs = []
+        for _ in range(100):
+            s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            s0.record(stream)
+            p1.run(a1, b1, o1)
+            s1.record(stream)
+            s1.synchronize()
+            xs.append(s0.elapsed_time(s1))
+        xs = np.array(xs)
+        lat = {"pair_p50_ms": round(float(np.percentile(xs, 50)), 4),
+               "pair_p99_ms": round(float(np.percentile(xs, 99)), 4)}
+    lat.update({"batch_p50_ms": round(float(np.percentile(step_ms, 50)), 4),
+                "batch_p99_ms": round(float(np.percentile(step_ms, 99)), 4)})
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(pairs[0][0], pairs[0][1], kw, lambda *a: log(args, *a))
+
+    path_gbs = alg["path_bytes"] * nb / (ms_per_step / 1e3) / 1e9
+    line = {
+        "metric": "1MP image-pair fields/sec + Mvectors/s; p50/p99 latency; % HBM roofline",
+        "value": round(pairs_s, 1),
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "1024x1024 u8 particle-image pairs (0.04 ppp, Lamb-Oseen 20 px peak, "
+                               "10% dropout), 16x16 windows step 8 (128x128 vectors), +-4 px search, "
+                               "3-level SAD predictor (radii 6/2), full path per step",
+                   "global_batch": nb, "distinct_pairs": nd, "parallelism": "single GPU"},
+        "mvec_per_s": round(pairs_s * nx * ny / 1e6, 2),
+        "latency": lat,
+        "hbm_roofline": {"achieved_gbs": round(path_gbs, 1), "peak_gbs": HBM_PEAK_GBS,
+                         "frac": round(path_gbs / HBM_PEAK_GBS, 5),
+                         "bytes_per_pair": alg["path_bytes"]},
+        "roofline": {"kernel": "k_correct_tiled (deformation + correlation + fit)", "bound": "alu",
+                     "achieved": round(corr_tflops, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(corr_tflops / FP32_PEAK_TFLOPS, 5), "traffic": None,
+                     "ms_per_launch": round(corr_ms, 4), "flop_per_pair": alg["corr_flop"]},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,206 @@
+/*
+ * piv.h -- C ABI of the MI355X (gfx950) PIV hot path.
+ *
+ * The library turns particle-image pairs into dense, validated displacement
+ * fields with vorticity, following the processing pipeline of "RapidPIV:
+ * Full Flow-Field kHz PIV for Real-Time Display and Control" (Bollt,
+ * Foxman, Gharib), Sec. 2: a coarse predictor of the displacement field,
+ * deformation of the pair by that predictor, correlation with a Gaussian
+ * sub-pixel fit about the best shift, universal outlier detection with
+ * median replacement (Sec. 3: threshold 2, regulariser 0.1 px), and the
+ * vorticity that the paper displays and compares (Sec. 4).  The paper's
+ * predictor is a fixed-function optical-flow engine; here it is a
+ * coarse-to-fine integer block-matching search written for the GPU's
+ * compute units.
+ *
+ * Conventions shared by every entry point:
+ *  - Every image/field pointer is a DEVICE pointer owned by the caller.
+ *    Pointers marked "host" are host memory.
+ *  - Images are [n][height][pitch_bytes] with separate A (first exposure)
+ *    and B (second exposure) pointers; pitch_bytes is a multiple of 4 and
+ *    both base pointers are 4-byte aligned.  Intensity outside the image is 0.
+ *  - Pixel (row i, col j) has its centre at x = j, y = i.  The vector grid
+ *    has nx = width/step by ny = height/step nodes; node (a, b) sits at
+ *    (b*step + (step-1)/2, a*step + (step-1)/2) and its win x win window
+ *    starts at b*step - (win-step)/2.
+ *  - Fields are float32 [n][2][ny][nx] (u plane, then v plane), in pixels
+ *    per frame pair, displacement from A to B.  Per-vector flags are
+ *    uint8 [n][ny][nx]; scalar per-vector outputs float32 [n][ny][nx].
+ *  - Every call only enqueues kernels on `stream` and returns: it never
+ *    allocates, never synchronises, never reads device memory on the host,
+ *    so it may be captured into a HIP graph.  Argument errors are detected
+ *    on the host before any launch (no partial work).  Faults inside a
+ *    kernel surface at the caller's next synchronisation.
+ *  - A plan is immutable after workspace binding; use one plan (and one
+ *    workspace) per concurrently used stream.
+ */
+#ifndef PIV_H
+#define PIV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct piv_plan_s* piv_plan_t;
+
+typedef enum {
+  PIV_OK = 0,
+  PIV_EINVAL = 1,          /* bad argument, shape or parameter              */
+  PIV_EUNSUPPORTED = 2,    /* valid for the method, not built in this library */
+  PIV_ENOWORKSPACE = 3,    /* workspace missing or too small for n            */
+  PIV_EDEVICE = 4          /* a HIP launch or query failed                    */
+} piv_status;
+
+typedef enum { PIV_U8 = 1, PIV_U16 = 2, PIV_F32 = 3 } piv_dtype;
+
+/* Deformation of the pair by the predictor (Sec. 2).  PIV_WARP_B deforms
+ * frame B only: B'(p) = B(p + u(p)).  PIV_WARP_CENTRAL deforms both frames
+ * symmetrically: A'(p) = A(p - u(p)/2), B'(p) = B(p + u(p)/2). */
+typedef enum { PIV_WARP_B = 0, PIV_WARP_CENTRAL = 1 } piv_warp;
+
+/* Peak selection (Sec. 2, Sec. 4.3).  PIV_PEAK_ARGMAX searches every shift
+ * in [-radius, radius]^2; PIV_PEAK_FIXED_CENTER uses the paper's a-priori
+ * 5-point stencil centred at zero shift. */
+typedef enum { PIV_PEAK_ARGMAX = 0, PIV_PEAK_FIXED_CENTER = 1 } piv_peak;
+
+typedef struct {
+  int32_t width, height;   /* image size in pixels                                   */
+  int32_t max_batch;       /* largest n any call will pass                           */
+  piv_dtype dtype;         /* element type of A and B                                */
+  int32_t bit_depth;       /* meaningful bits of U16 data (12 or 16); ignored else   */
+  int32_t win;             /* correlation window (px); 2*step for 50% overlap        */
+  int32_t step;            /* node spacing (px)                                      */
+  int32_t radius;          /* correction search radius r: shifts in [-r, r]^2        */
+  int32_t levels;          /* predictor pyramid levels (1 = no pyramid)              */
+  int32_t block;           /* predictor block size (0 = win)                         */
+  int32_t radius_coarse;   /* predictor search radius on the coarsest level          */
+  int32_t radius_fine;     /* predictor search radius on every finer level           */
+  int32_t median;          /* 3x3 median of the predictor after every level (0/1)    */
+  piv_warp warp;
+  piv_peak peak;
+  float uod_threshold;     /* normalised-median threshold (Sec. 3: 2)                */
+  float uod_epsilon;       /* normalised-median regulariser in px (Sec. 3: 0.1)      */
+} piv_params;
+
+/* Per-vector flag bits. */
+enum {
+  PIV_F_FLAT = 1,        /* correlation denominator zero at every shift (blank window) */
+  PIV_F_BORDER = 2,      /* best shift on the edge of the search: no sub-pixel fit     */
+  PIV_F_NOCURV = 4,      /* log-coefficients not concave on an axis: no fit on it      */
+  PIV_F_OUTLIER = 8,     /* rejected by validation                                     */
+  PIV_F_REPLACED = 16,   /* replaced by the median of non-outlier neighbours           */
+  PIV_F_UNRESOLVED = 32  /* outlier without a non-outlier neighbour: value kept        */
+};
+
+/* Fill *p (host) with the paper's processing parameters for 1 MP u8 pairs:
+ * 16 x 16 windows at 50% step-over, UOD threshold 2 and regulariser 0.1 px
+ * (Sec. 3.1), +-4 px correction search, a 3-level predictor with radii 6/2. */
+void piv_params_default(piv_params* p);
+
+/* Validate *p (host) and create a plan.  Host-only: no device work.
+ * Errors: PIV_EINVAL for shapes/parameters the method cannot take
+ * (width/height not multiples of step, win < step, (win-step) odd,
+ * win > 64, radius outside [1, 16], levels outside [1, 6], bad dtype ...),
+ * PIV_EUNSUPPORTED for combinations the kernels are not built for.
+ * On error *out is NULL and piv_last_error() tells why. */
+piv_status piv_plan(const piv_params* p, piv_plan_t* out);
+
+/* Vector grid size of the plan (host outputs). */
+piv_status piv_plan_grid(piv_plan_t plan, int32_t* nx, int32_t* ny);
+
+/* Bytes of device workspace needed for `batch` pairs: predictor pyramids,
+ * per-level integer fields and the validation mask.  Exact, so that callers
+ * can admit work against an HBM budget. */
+size_t piv_plan_workspace_bytes(piv_plan_t plan, int32_t batch);
+
+/* Bind caller-owned device workspace (e.g. a torch tensor) to the plan.
+ * The plan remembers how many pairs it can hold; later calls with a larger
+ * n fail with PIV_ENOWORKSPACE.  The memory must outlive its use. */
+piv_status piv_plan_bind_workspace(piv_plan_t plan, void* d_ws, size_t bytes);
+
+/* Optional device slot mask uint8 [max_batch]: when bound, every kernel of
+ * every call skips pair i whose mask byte is 0 (its outputs are left
+ * untouched).  Lets a graph captured for max_batch pairs run a partial
+ * batch.  NULL unbinds. */
+piv_status piv_plan_bind_slot_mask(piv_plan_t plan, const uint8_t* d_mask);
+
+void piv_plan_destroy(piv_plan_t plan);
+
+/* Predictor: coarse-to-fine integer SAD block matching.  For each level l
+ * (coarsest first) and node, the block of `block` x `block` level-l pixels
+ * at the node is compared with frame B moved by every integer d in
+ * cand + [-R, R]^2 (R = radius_coarse on the coarsest level around 0,
+ * radius_fine below, around twice the parent node's result); the d with the
+ * least (SAD, |dx|+|dy|, dy, dx) wins.  Pyramid levels are 2x2 box means
+ * floor((sum+2)/4).  pred: [n][2][ny][nx] float32 holding integers.
+ * Needs a bound workspace. */
+piv_status piv_predict(piv_plan_t plan, const void* A, const void* B, int64_t pitch_bytes,
+                       int32_t n, float* pred, hipStream_t stream);
+
+/* Correction (Sec. 2): deform the pair by the bilinearly interpolated
+ * predictor (NULL = zero), compute the Pearson correlation coefficient of
+ * each window with the deformed B window moved by every shift s in
+ * [-r, r]^2 (or the 5-point stencil), take the best shift (largest
+ * coefficient; ties to smaller |sx|+|sy|, then smaller sy, then smaller sx)
+ * and a 3-point Gaussian fit per axis on coefficients floored at 1e-3.
+ * disp = pred(node) + s* + fit.  peak (nullable) = coefficient at s*.
+ * flags: FLAT / BORDER / NOCURV.  Needs no workspace. */
+piv_status piv_correct(piv_plan_t plan, const void* A, const void* B, int64_t pitch_bytes,
+                       int32_t n, const float* pred, float* disp, float* peak, uint8_t* flags,
+                       hipStream_t stream);
+
+/* Universal outlier detection (Sec. 2, Sec. 3) in place on field [n][2][ny][nx].
+ * Vectors whose input flags hold FLAT or BORDER are outliers and never
+ * neighbours.  Per component r0 = |u0 - med(u_j)| / (med|u_j - med(u_j)| + eps)
+ * over the valid 3x3 neighbours; outlier if the larger r0 exceeds the
+ * threshold.  Outliers take the component medians of their non-outlier
+ * neighbours from the detection-pass field (UNRESOLVED if none).  flags
+ * (nullable) in/out gain OUTLIER / REPLACED / UNRESOLVED.  Needs a bound
+ * workspace. */
+piv_status piv_validate(piv_plan_t plan, float* field, uint8_t* flags, int32_t n, hipStream_t stream);
+
+/* Vorticity omega = dv/dx - du/dy (1/frame) on the node grid, spacing step:
+ * central differences inside, second-order one-sided on the edges.
+ * disp [n][2][ny][nx] -> omega [n][ny][nx]. */
+piv_status piv_vorticity(piv_plan_t plan, const float* disp, float* omega, int32_t n,
+                         hipStream_t stream);
+
+/* The whole plain path in one call: predict, validate the predictor,
+ * correct, validate, vorticity.  pred (scratch for the predictor, also an
+ * output), disp, flags and omega are required; peak is nullable. */
+piv_status piv_run(piv_plan_t plan, const void* A, const void* B, int64_t pitch_bytes, int32_t n,
+                   float* pred, float* disp, float* peak, uint8_t* flags, float* omega,
+                   hipStream_t stream);
+
+/* Windowed SSD of the deformation (an addition, not in the paper): for
+ * float32 frames A, B [n][height][width] (pitch = width) and a node field
+ * U [n][2][ny][nx], loss[n][ny][nx] = sum over each window of
+ * (B(p + u(p)) - A(p))^2 with u the clamped bilinear interpolation of U.
+ * The plan's dtype must be PIV_F32. */
+piv_status piv_ssd_forward(piv_plan_t plan, const float* A, const float* B, const float* U,
+                           int32_t n, float* loss, hipStream_t stream);
+
+/* Adjoint of piv_ssd_forward: g_U = d(sum g_loss * loss)/dU (derivative of
+ * the bilinear sample taken on its floor cell), and the Gauss-Newton
+ * diagonal gn_diag = sum_p 2 m(p) (dB'/du)^2 w_n(p)^2 with m(p) the sum of
+ * g_loss over the windows holding p (nullable).  Deterministic: every node
+ * gathers its own terms, no atomics. */
+piv_status piv_ssd_backward(piv_plan_t plan, const float* A, const float* B, const float* U,
+                            const float* g_loss, int32_t n, float* g_U, float* gn_diag,
+                            hipStream_t stream);
+
+const char* piv_status_string(piv_status s);
+
+/* Detail of the last failure on the calling thread (never NULL). */
+const char* piv_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PIV_H */

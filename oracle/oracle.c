@@ -305,13 +305,14 @@ void o_corr_plane(const double* A, const double* B, int W, int H, int win, int s
  *   shift sits on the search edge);
  * peak_mode 1: the paper's a-priori stencil -- centre fixed at zero shift,
  *   Gaussian fit on the 5 points, offset clamped to [-1, 1].
- * Result = pred(node) + best shift + fitted offset; *pk receives the
+ * Result = (mean over the window of the interpolated predictor) + best shift
+ * + fitted offset: the correlation measures the displacement left after the
+ * deformation actually applied to the window's pixels.  *pk receives the
  * coefficient at the chosen shift, *fl the per-vector flags. */
 void o_correct_node(const double* A, const double* B, int W, int H, int win, int step, int r,
                     int warp_mode, int peak_mode, const double* pred, int a, int b, double* du,
                     double* dv, double* pk, uint8_t* flo) {
   int nx = W / step, ny = H / step;
-  size_t np = (size_t)nx * ny;
   int R = peak_mode == 1 ? 1 : r, S = 2 * R + 1;
   double* rho = (double*)malloc(sizeof(double) * S * S);
   int nflat = 0, nev = 0;
@@ -351,8 +352,21 @@ void o_correct_node(const double* A, const double* B, int W, int H, int win, int
     dxs = dxs < -1 ? -1 : dxs > 1 ? 1 : dxs;
     dys = dys < -1 ? -1 : dys > 1 ? 1 : dys;
   }
-  size_t i = (size_t)a * nx + b;
-  double pu = pred ? pred[i] : 0.0, pv = pred ? pred[np + i] : 0.0;
+  /* the correction is relative to the deformation applied to the window:
+   * add it to the window mean of the interpolated predictor */
+  double pu = 0.0, pv = 0.0;
+  if (pred) {
+    int h = (win - step) / 2;
+    for (int i = 0; i < win; ++i)
+      for (int j = 0; j < win; ++j) {
+        double u, v;
+        o_interp(pred, nx, ny, step, b * step - h + j, a * step - h + i, &u, &v);
+        pu += u;
+        pv += v;
+      }
+    pu /= (double)win * win;
+    pv /= (double)win * win;
+  }
   *du = pu + bx + dxs;
   *dv = pv + by + dys;
   *pk = c0;

@@ -1,0 +1,683 @@
+// Correction kernels (Sec. 2 of the paper): deform the pair by the
+// interpolated predictor, correlate every window with the deformed frame B
+// over the search shifts (Pearson coefficient), pick the best shift and fit
+// a 3-point Gaussian per axis.
+//
+// Two implementations of the same definition:
+//  * k_correct_generic -- one workgroup per window; any window/step/radius.
+//  * k_correct_tiled   -- the fast path for 50%-overlap windows (win = 2 step):
+//    a workgroup owns a TW x TH tile of windows; the deformed B' tile and the
+//    A tile live in LDS; each thread correlates one step x step cell with a
+//    band of SYG shift rows, so every pixel-shift product is formed once and
+//    shared by the four windows that contain the cell; window sums are then
+//    assembled from cell sums.
+//
+// Numerics (FP32): all sums are taken about a per-tile integer offset K
+// (the rounded mean intensity of the tile), which leaves the coefficient
+// unchanged and keeps E[x^2] - E[x]^2 well conditioned.  A window counts as
+// flat when its variance is below 1e-6 of its second moment about K (an
+// exact zero cannot be certified in FP32); a flat window has coefficient 0.
+#include "dev_common.h"
+#include "piv_internal.h"
+
+namespace piv {
+namespace {
+
+constexpr float kFlatRel = 1e-6f;
+
+struct CorrArgs {
+  const uint8_t* A;
+  const uint8_t* B;
+  int64_t pitch, stride;   // bytes per row / per pair
+  int W, H, nx, ny;
+  int win, step, R;        // R: searched radius (1 in fixed-centre mode)
+  int central;             // deform both frames by -u/2, +u/2
+  int fixed;               // fixed-centre 5-point stencil
+  const float* pred;       // [n][2][ny][nx] or null
+  float* disp;
+  float* peak;             // nullable
+  uint8_t* flags;
+  const uint8_t* mask;
+};
+
+// tie key: smaller is preferred among equal coefficients (|sx|+|sy|, sy, sx)
+__device__ __forceinline__ int tie_key(int sy, int sx) {
+  return ((abs(sx) + abs(sy)) << 12) | ((sy + 32) << 6) | (sx + 32);
+}
+
+__device__ __forceinline__ bool better(float r1, int k1, float r2, int k2) {
+  return r1 > r2 || (r1 == r2 && k1 < k2);
+}
+
+// 3-point Gaussian offset on coefficients floored at 1e-3; nocurv when the
+// log-parabola does not open downward.
+__device__ __forceinline__ float gauss3(float cm, float c0, float cp, bool& nocurv) {
+  float lm = logf(fmaxf(cm, 1e-3f)), l0 = logf(fmaxf(c0, 1e-3f)), lp = logf(fmaxf(cp, 1e-3f));
+  float den = 2.0f * (lm - 2.0f * l0 + lp);
+  nocurv = !(den < 0.0f);
+  return nocurv ? 0.0f : (lm - lp) / den;
+}
+
+// displacement at pixel (x, y) from a node field read through `node(c, a, b)`
+// (clamped to the hull of node centres), bilinear.
+template <typename NodeFn>
+__device__ __forceinline__ void interp_u(float x, float y, int nx, int ny, int step, NodeFn node,
+                                         float& u, float& v) {
+  const float c = 0.5f * (float)(step - 1);
+  float tx = (x - c) / (float)step, ty = (y - c) / (float)step;
+  tx = fminf(fmaxf(tx, 0.0f), (float)(nx - 1));
+  ty = fminf(fmaxf(ty, 0.0f), (float)(ny - 1));
+  int bx = min((int)tx, max(nx - 2, 0)), by = min((int)ty, max(ny - 2, 0));
+  float fx = tx - (float)bx, fy = ty - (float)by;
+  int bx1 = nx > 1 ? bx + 1 : bx, by1 = ny > 1 ? by + 1 : by;
+  u = (1.0f - fy) * ((1.0f - fx) * node(0, by, bx) + fx * node(0, by, bx1)) +
+      fy * ((1.0f - fx) * node(0, by1, bx) + fx * node(0, by1, bx1));
+  v = (1.0f - fy) * ((1.0f - fx) * node(1, by, bx) + fx * node(1, by, bx1)) +
+      fy * ((1.0f - fx) * node(1, by1, bx) + fx * node(1, by1, bx1));
+}
+
+// The correction is relative to the deformation applied to the window, so
+// it is added to the window mean of the interpolated predictor.  Bilinear
+// interpolation with clamping is separable, so the mean is a product of
+// per-axis node weights: for 50%-overlap windows (win = 2 step, step even)
+// these are (1/4, 1/2, 1/4) inside, (3/4, 1/4) on the first node and
+// (1/4, 3/4) on the last.
+__device__ __forceinline__ void half_overlap_weights(int b, int n, float& wm, float& w0, float& wp) {
+  if (n == 1) { wm = 0.0f; w0 = 1.0f; wp = 0.0f; }
+  else if (b == 0) { wm = 0.0f; w0 = 0.75f; wp = 0.25f; }
+  else if (b == n - 1) { wm = 0.25f; w0 = 0.75f; wp = 0.0f; }
+  else { wm = 0.25f; w0 = 0.5f; wp = 0.25f; }
+}
+
+template <typename NodeFn>
+__device__ __forceinline__ void window_mean_half_overlap(int a, int b, int nx, int ny, NodeFn node,
+                                                         float& pu, float& pv) {
+  float wy[3], wx[3];
+  half_overlap_weights(a, ny, wy[0], wy[1], wy[2]);
+  half_overlap_weights(b, nx, wx[0], wx[1], wx[2]);
+  pu = pv = 0.0f;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      float w = wy[i] * wx[j];
+      if (w != 0.0f) {
+        pu += w * node(0, a + i - 1, b + j - 1);
+        pv += w * node(1, a + i - 1, b + j - 1);
+      }
+    }
+}
+
+// Fit and compose one vector from its coefficient lookup rho(sy, sx).
+template <typename RhoFn>
+__device__ __forceinline__ void finish_vector(const CorrArgs& g, int pair, int a, int b, int sy, int sx,
+                                              bool flat, float pu, float pv, RhoFn rho) {
+  const int R = g.R;
+  uint8_t fl = flat ? PIV_F_FLAT : 0;
+  float c0 = rho(sy, sx);
+  float ex = 0.0f, ey = 0.0f;
+  bool nc;
+  if (!g.fixed && (sx == -R || sx == R)) fl |= PIV_F_BORDER;
+  else {
+    ex = gauss3(rho(sy, sx - 1), c0, rho(sy, sx + 1), nc);
+    if (nc) fl |= PIV_F_NOCURV;
+  }
+  if (!g.fixed && (sy == -R || sy == R)) fl |= PIV_F_BORDER;
+  else {
+    ey = gauss3(rho(sy - 1, sx), c0, rho(sy + 1, sx), nc);
+    if (nc) fl |= PIV_F_NOCURV;
+  }
+  if (g.fixed) {
+    ex = fminf(fmaxf(ex, -1.0f), 1.0f);
+    ey = fminf(fmaxf(ey, -1.0f), 1.0f);
+  }
+  const int np = g.nx * g.ny, i = a * g.nx + b;
+  float* D = g.disp + (int64_t)pair * 2 * np;
+  D[i] = pu + (float)sx + ex;
+  D[np + i] = pv + (float)sy + ey;
+  if (g.peak) g.peak[(int64_t)pair * np + i] = c0;
+  g.flags[(int64_t)pair * np + i] = fl;
+}
+
+// ---------------------------------------------------------------------------
+// Generic: one workgroup per window.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_correct_generic(CorrArgs g) {
+  extern __shared__ float s_mem[];
+  __shared__ float s_red[256];
+  __shared__ int s_key[256];
+  __shared__ float s_K;
+  const int pair = blockIdx.z;
+  if (slot_off(g.mask, pair)) return;
+  const int a = blockIdx.y, b = blockIdx.x, t = threadIdx.x;
+  const int win = g.win, R = g.R, S = 2 * R + 1, BWd = win + 2 * R;
+  float* sA = s_mem;                 // [win][win]
+  float* sB = sA + win * win;        // [BWd][BWd]
+  float* sRho = sB + BWd * BWd;      // [S][S]
+  const uint8_t* Ai = g.A + (int64_t)pair * g.stride;
+  const uint8_t* Bi = g.B + (int64_t)pair * g.stride;
+  const float* Pn = g.pred ? g.pred + (int64_t)pair * 2 * g.nx * g.ny : nullptr;
+  const int np = g.nx * g.ny;
+  auto node = [&](int c, int y, int x) { return Pn[c * np + y * g.nx + x]; };
+  const int h = (win - g.step) / 2, oy = a * g.step - h, ox = b * g.step - h;
+  const float sgnA = -0.5f, sgnB = g.central ? 0.5f : 1.0f;
+
+  float part = 0.0f;
+  for (int idx = t; idx < win * win; idx += 256) {
+    int y = oy + idx / win, x = ox + idx % win;
+    float v;
+    if (g.central && Pn) {
+      float u, w;
+      interp_u((float)x, (float)y, g.nx, g.ny, g.step, node, u, w);
+      v = bilin<T>(Ai, g.pitch, g.W, g.H, x + sgnA * u, y + sgnA * w);
+    } else {
+      v = pixf<T>(Ai, g.pitch, g.W, g.H, y, x);
+    }
+    sA[idx] = v;
+    part += v;
+  }
+  s_red[t] = part;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (t < o) s_red[t] += s_red[t + o];
+    __syncthreads();
+  }
+  if (t == 0) s_K = rintf(s_red[0] / (float)(win * win));
+  __syncthreads();
+  const float K = s_K;
+  for (int idx = t; idx < win * win; idx += 256) sA[idx] -= K;
+  for (int idx = t; idx < BWd * BWd; idx += 256) {
+    int y = oy - R + idx / BWd, x = ox - R + idx % BWd;
+    float v;
+    if (Pn) {
+      float u, w;
+      interp_u((float)x, (float)y, g.nx, g.ny, g.step, node, u, w);
+      v = bilin<T>(Bi, g.pitch, g.W, g.H, x + sgnB * u, y + sgnB * w);
+    } else {
+      v = pixf<T>(Bi, g.pitch, g.W, g.H, y, x);
+    }
+    sB[idx] = v - K;
+  }
+  __syncthreads();
+  // A statistics (every thread, from LDS; small)
+  float sa = 0.0f, saa = 0.0f;
+  for (int i = 0; i < win * win; ++i) {
+    float v = sA[i];
+    sa += v;
+    saa += v * v;
+  }
+  const float n = (float)(win * win);
+  const float mA = sa / n;
+  const float varA = saa - sa * mA;
+  const bool flatA = !(varA > kFlatRel * saa);
+
+  float best = -2.0f;
+  int bkey = 1 << 30, nflat = 0;
+  for (int s = t; s < S * S; s += 256) {
+    int sy = s / S - R, sx = s % S - R;
+    float r = 0.0f;
+    bool used = !g.fixed || sx == 0 || sy == 0;
+    if (used) {
+      float P = 0.0f, Sb = 0.0f, Q = 0.0f;
+      for (int i = 0; i < win; ++i) {
+        const float* arow = sA + i * win;
+        const float* brow = sB + (i + sy + R) * BWd + sx + R;
+        for (int j = 0; j < win; ++j) {
+          float bv = brow[j];
+          P += arow[j] * bv;
+          Sb += bv;
+          Q += bv * bv;
+        }
+      }
+      float num = P - mA * Sb;
+      float varB = Q - Sb * Sb / n;
+      bool flat = flatA || !(varB > kFlatRel * Q);
+      r = flat ? 0.0f : num * rsqrtf(varA * varB);
+      nflat += flat;
+      int key = tie_key(sy, sx);
+      if (!g.fixed && better(r, key, best, bkey)) {
+        best = r;
+        bkey = key;
+      }
+    }
+    sRho[s] = r;
+  }
+  s_red[t] = best;
+  s_key[t] = bkey;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (t < o && better(s_red[t + o], s_key[t + o], s_red[t], s_key[t])) {
+      s_red[t] = s_red[t + o];
+      s_key[t] = s_key[t + o];
+    }
+    __syncthreads();
+  }
+  // count flat shifts
+  __shared__ int s_nflat;
+  if (t == 0) s_nflat = 0;
+  __syncthreads();
+  if (nflat) atomicAdd(&s_nflat, nflat);
+  __syncthreads();
+  if (t == 0) {
+    int sy = 0, sx = 0;
+    if (!g.fixed) {
+      int k = s_key[0];
+      sx = (k & 63) - 32;
+      sy = ((k >> 6) & 63) - 32;
+    }
+    // window mean of the interpolated predictor: per-axis node weights
+    float pu = 0.0f, pv = 0.0f;
+    if (Pn) {
+      float* wx = sA;                     // A tile is no longer needed
+      float* wy = sA + (win / g.step + 3);
+      const float c = 0.5f * (float)(g.step - 1);
+      int bxl, byl;
+      {
+        float tx = fminf(fmaxf(((float)ox - c) / g.step, 0.0f), (float)(g.nx - 1));
+        float ty = fminf(fmaxf(((float)oy - c) / g.step, 0.0f), (float)(g.ny - 1));
+        bxl = min((int)tx, max(g.nx - 2, 0));
+        byl = min((int)ty, max(g.ny - 2, 0));
+      }
+      const int nw = win / g.step + 3;
+      for (int q = 0; q < 2 * nw; ++q) sA[q] = 0.0f;
+      for (int j = 0; j < win; ++j) {
+        float tx = fminf(fmaxf(((float)(ox + j) - c) / g.step, 0.0f), (float)(g.nx - 1));
+        int bx = min((int)tx, max(g.nx - 2, 0));
+        float fx = tx - (float)bx;
+        wx[bx - bxl] += 1.0f - fx;
+        wx[(g.nx > 1 ? bx + 1 : bx) - bxl] += fx;
+        float ty = fminf(fmaxf(((float)(oy + j) - c) / g.step, 0.0f), (float)(g.ny - 1));
+        int by = min((int)ty, max(g.ny - 2, 0));
+        float fy = ty - (float)by;
+        wy[by - byl] += 1.0f - fy;
+        wy[(g.ny > 1 ? by + 1 : by) - byl] += fy;
+      }
+      for (int i = 0; i < nw; ++i)
+        for (int j = 0; j < nw; ++j) {
+          float w = wy[i] * wx[j];
+          if (w != 0.0f) {
+            pu += w * node(0, byl + i, bxl + j);
+            pv += w * node(1, byl + i, bxl + j);
+          }
+        }
+      const float inv = 1.0f / ((float)win * (float)win);
+      pu *= inv;
+      pv *= inv;
+    }
+    const int nev = g.fixed ? 5 : S * S;
+    auto rho = [&](int y, int x) { return sRho[(y + R) * S + x + R]; };
+    finish_vector(g, pair, a, b, sy, sx, s_nflat == nev, pu, pv, rho);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Tiled, cell-shared (win = 2 step).
+// ---------------------------------------------------------------------------
+template <int STEP, int R, int SYG, int TW, int TH>
+struct TileCfg {
+  static constexpr int CW = TW + 1, CH = TH + 1, NC = CW * CH;
+  static constexpr int NSY = 2 * R + 1, NS = NSY * NSY, NG = NSY / SYG;
+  static constexpr int AW = CW * STEP, AH = CH * STEP;
+  static constexpr int BW = AW + 2 * R, BH = AH + 2 * R;
+  static constexpr int AP = AW + 4;   // LDS row pitches (floats)
+  static constexpr int BP = BW + 4;
+  static constexpr int NNX = BW / STEP + 3, NNY = BH / STEP + 3;
+  static constexpr int IN_FLOATS = AH * AP + BH * BP;
+  static constexpr int RES_FLOATS = 3 * NC * NS;
+  static constexpr int UNION = IN_FLOATS > RES_FLOATS ? IN_FLOATS : RES_FLOATS;
+  static constexpr int NWIN = TW * TH;
+  static_assert(NSY % SYG == 0, "shift rows must split evenly");
+  static_assert(STEP % 2 == 0, "50% overlap needs an even step");
+};
+
+template <typename T, int STEP, int R, int SYG, int TW, int TH, int NT>
+__global__ __launch_bounds__(NT) void k_correct_tiled(CorrArgs g) {
+  using C = TileCfg<STEP, R, SYG, TW, TH>;
+  static_assert(C::NG * C::NC <= NT, "one thread per (cell, shift band)");
+  static_assert(4 * C::NWIN <= NT, "four threads per window");
+  __shared__ float s_u[C::UNION];
+  __shared__ float s_node[2][C::NNY][C::NNX];
+  __shared__ float s_wsum[C::NWIN], s_wsq[C::NWIN];
+  __shared__ float s_red[NT / 64];
+  __shared__ float s_K;
+
+  const int pair = blockIdx.z;
+  if (slot_off(g.mask, pair)) return;
+  const int t = threadIdx.x;
+  const int a0 = blockIdx.y * TH, b0 = blockIdx.x * TW;
+  constexpr int h = STEP / 2;
+  const int y0 = a0 * STEP - h, x0 = b0 * STEP - h;      // A tile origin
+  const int yb = y0 - R, xb = x0 - R;                    // B' tile origin
+  const uint8_t* Ai = g.A + (int64_t)pair * g.stride;
+  const uint8_t* Bi = g.B + (int64_t)pair * g.stride;
+  const int np = g.nx * g.ny;
+  const float* Pn = g.pred ? g.pred + (int64_t)pair * 2 * np : nullptr;
+  float* sA = s_u;                   // [AH][AP]
+  float* sB = s_u + C::AH * C::AP;   // [BH][BP]
+
+  // node cache covering the B' tile
+  const float cen = 0.5f * (float)(STEP - 1);
+  const int nlo_y = max(0, (int)floorf(((float)yb - cen) / STEP));
+  const int nlo_x = max(0, (int)floorf(((float)xb - cen) / STEP));
+  if (Pn) {
+    for (int idx = t; idx < 2 * C::NNY * C::NNX; idx += NT) {
+      int c = idx / (C::NNY * C::NNX), r = (idx / C::NNX) % C::NNY, q = idx % C::NNX;
+      int ny_ = min(nlo_y + r, g.ny - 1), nx_ = min(nlo_x + q, g.nx - 1);
+      s_node[c][r][q] = Pn[c * np + ny_ * g.nx + nx_];
+    }
+  }
+  __syncthreads();
+  auto node = [&](int c, int y, int x) { return s_node[c][y - nlo_y][x - nlo_x]; };
+
+  // A tile (deformed by -u/2 in central mode) and its sum for the offset K
+  float part = 0.0f;
+  for (int idx = t; idx < C::AH * C::AW; idx += NT) {
+    int r = idx / C::AW, q = idx % C::AW;
+    int y = y0 + r, x = x0 + q;
+    float v;
+    if (g.central && Pn) {
+      float u, w;
+      interp_u((float)x, (float)y, g.nx, g.ny, STEP, node, u, w);
+      v = bilin<T>(Ai, g.pitch, g.W, g.H, x - 0.5f * u, y - 0.5f * w);
+    } else {
+      v = pixf<T>(Ai, g.pitch, g.W, g.H, y, x);
+    }
+    sA[r * C::AP + q] = v;
+    part += v;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o);
+  if ((t & 63) == 0) s_red[t >> 6] = part;
+  __syncthreads();
+  if (t == 0) {
+    float s = 0.0f;
+#pragma unroll
+    for (int i = 0; i < NT / 64; ++i) s += s_red[i];
+    s_K = rintf(s / (float)(C::AH * C::AW));
+  }
+  __syncthreads();
+  const float K = s_K;
+  for (int idx = t; idx < C::AH * C::AW; idx += NT) {
+    int r = idx / C::AW, q = idx % C::AW;
+    sA[r * C::AP + q] -= K;
+  }
+  // deformed B' tile
+  const float sgnB = g.central ? 0.5f : 1.0f;
+  for (int idx = t; idx < C::BH * C::BW; idx += NT) {
+    int r = idx / C::BW, q = idx % C::BW;
+    int y = yb + r, x = xb + q;
+    float v;
+    if (Pn) {
+      float u, w;
+      interp_u((float)x, (float)y, g.nx, g.ny, STEP, node, u, w);
+      v = bilin<T>(Bi, g.pitch, g.W, g.H, x + sgnB * u, y + sgnB * w);
+    } else {
+      v = pixf<T>(Bi, g.pitch, g.W, g.H, y, x);
+    }
+    sB[r * C::BP + q] = v - K;
+  }
+  __syncthreads();
+  // A window statistics: four threads per window, four rows... of 2 STEP each
+  if (t < 4 * C::NWIN) {
+    int w = t >> 2, p = t & 3;
+    int wi = w / TW, wj = w % TW;
+    float s = 0.0f, ss = 0.0f;
+    for (int r = p; r < 2 * STEP; r += 4) {
+      const float* row = sA + (wi * STEP + r) * C::AP + wj * STEP;
+#pragma unroll
+      for (int q = 0; q < 2 * STEP; ++q) {
+        float v = row[q];
+        s += v;
+        ss += v * v;
+      }
+    }
+    s += __shfl_xor(s, 1);
+    ss += __shfl_xor(ss, 1);
+    s += __shfl_xor(s, 2);
+    ss += __shfl_xor(ss, 2);
+    if (p == 0) {
+      s_wsum[w] = s;
+      s_wsq[w] = ss;
+    }
+  }
+
+  // ---- per cell and shift band: P = sum (A-K)(B'-K), S = sum (B'-K), Q = sum (B'-K)^2
+  constexpr int BRW = STEP + 2 * R;   // B' columns one cell row needs
+  float Pacc[SYG][C::NSY];
+  float Sacc[SYG][C::NSY], Qacc[SYG][C::NSY];
+  const bool worker = t < C::NG * C::NC;
+  const int grp = t / C::NC, cell = t - grp * C::NC;
+  const int ci = cell / C::CW, cj = cell - (cell / C::CW) * C::CW;
+  if (worker) {
+#pragma unroll
+    for (int k = 0; k < SYG; ++k)
+#pragma unroll
+      for (int j = 0; j < C::NSY; ++j) Pacc[k][j] = 0.0f;
+    float cs[BRW], cq[BRW];
+#pragma unroll
+    for (int x = 0; x < BRW; ++x) cs[x] = cq[x] = 0.0f;
+    const float* abase = sA + (ci * STEP) * C::AP + cj * STEP;
+    const float* bbase = sB + (ci * STEP + grp * SYG) * C::BP + cj * STEP;
+    float br[SYG][BRW];
+    // rows of the band for py = 0
+#pragma unroll
+    for (int k = 0; k < SYG; ++k)
+#pragma unroll
+      for (int x = 0; x < BRW; ++x) br[k][x] = bbase[k * C::BP + x];
+#pragma unroll
+    for (int py = 0; py < STEP; ++py) {
+      float ar[STEP];
+#pragma unroll
+      for (int x = 0; x < STEP; ++x) ar[x] = abase[py * C::AP + x];
+#pragma unroll
+      for (int x = 0; x < BRW; ++x) {
+        cs[x] += br[0][x];
+        cq[x] += br[0][x] * br[0][x];
+      }
+#pragma unroll
+      for (int k = 0; k < SYG; ++k)
+#pragma unroll
+        for (int j = 0; j < C::NSY; ++j) {
+          float s = Pacc[k][j];
+#pragma unroll
+          for (int x = 0; x < STEP; ++x) s += ar[x] * br[k][x + j];
+          Pacc[k][j] = s;
+        }
+      if (py + 1 < STEP) {
+        // slide the band one row down
+#pragma unroll
+        for (int k = 0; k + 1 < SYG; ++k)
+#pragma unroll
+          for (int x = 0; x < BRW; ++x) br[k][x] = br[k + 1][x];
+#pragma unroll
+        for (int x = 0; x < BRW; ++x) br[SYG - 1][x] = bbase[(py + SYG) * C::BP + x];
+      }
+    }
+    // column sums for the band's first row -> window-free cell box sums
+#pragma unroll
+    for (int k = 0; k < SYG; ++k) {
+      if (k > 0) {
+        const float* rin = bbase + (STEP + k - 1) * C::BP;
+        const float* rout = bbase + (k - 1) * C::BP;
+#pragma unroll
+        for (int x = 0; x < BRW; ++x) {
+          float vi = rin[x], vo = rout[x];
+          cs[x] += vi - vo;
+          cq[x] += vi * vi - vo * vo;
+        }
+      }
+      float s = 0.0f, q = 0.0f;
+#pragma unroll
+      for (int x = 0; x < STEP; ++x) {
+        s += cs[x];
+        q += cq[x];
+      }
+      Sacc[k][0] = s;
+      Qacc[k][0] = q;
+#pragma unroll
+      for (int j = 1; j < C::NSY; ++j) {
+        s += cs[j + STEP - 1] - cs[j - 1];
+        q += cq[j + STEP - 1] - cq[j - 1];
+        Sacc[k][j] = s;
+        Qacc[k][j] = q;
+      }
+    }
+  }
+  __syncthreads();   // everyone is done with the A and B' tiles
+  float* resP = s_u;
+  float* resS = s_u + C::NC * C::NS;
+  float* resQ = s_u + 2 * C::NC * C::NS;
+  if (worker) {
+#pragma unroll
+    for (int k = 0; k < SYG; ++k)
+#pragma unroll
+      for (int j = 0; j < C::NSY; ++j) {
+        int s = (grp * SYG + k) * C::NSY + j;
+        resP[cell * C::NS + s] = Pacc[k][j];
+        resS[cell * C::NS + s] = Sacc[k][j];
+        resQ[cell * C::NS + s] = Qacc[k][j];
+      }
+  }
+  __syncthreads();
+
+  // ---- windows: four threads each, shifts s = p, p+4, ...
+  constexpr int PER = (C::NS + 3) / 4;
+  float rho[PER];
+  float best = -2.0f;
+  int bkey = 1 << 30, nflat = 0;
+  const int w = t >> 2, p = t & 3;
+  const bool wact = t < 4 * C::NWIN;
+  const int wi = w / TW, wj = w - (w / TW) * TW;
+  const int c00 = wi * C::CW + wj, c01 = c00 + 1, c10 = c00 + C::CW, c11 = c10 + 1;
+  if (wact) {
+    const float n = (float)(4 * STEP * STEP);
+    const float sa = s_wsum[w], saa = s_wsq[w];
+    const float mA = sa / n;
+    const float varA = saa - sa * mA;
+    const bool flatA = !(varA > kFlatRel * saa);
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      int s = p + 4 * i;
+      float r = 0.0f;
+      if (s < C::NS) {
+        int sy = s / C::NSY - R, sx = s % C::NSY - R;
+        float P = resP[c00 * C::NS + s] + resP[c01 * C::NS + s] + resP[c10 * C::NS + s] + resP[c11 * C::NS + s];
+        float S = resS[c00 * C::NS + s] + resS[c01 * C::NS + s] + resS[c10 * C::NS + s] + resS[c11 * C::NS + s];
+        float Q = resQ[c00 * C::NS + s] + resQ[c01 * C::NS + s] + resQ[c10 * C::NS + s] + resQ[c11 * C::NS + s];
+        float num = P - mA * S;
+        float varB = Q - S * S / n;
+        bool flat = flatA || !(varB > kFlatRel * Q);
+        r = flat ? 0.0f : num * rsqrtf(varA * varB);
+        bool used = !g.fixed || sx == 0 || sy == 0;
+        if (used) {
+          nflat += flat;
+          int key = tie_key(sy, sx);
+          if (!g.fixed && better(r, key, best, bkey)) {
+            best = r;
+            bkey = key;
+          }
+        }
+      }
+      rho[i] = r;
+    }
+  }
+  // reduce over the window's four lanes
+#pragma unroll
+  for (int o = 1; o <= 2; o <<= 1) {
+    float ob = __shfl_xor(best, o);
+    int ok = __shfl_xor(bkey, o);
+    nflat += __shfl_xor(nflat, o);
+    if (better(ob, ok, best, bkey)) {
+      best = ob;
+      bkey = ok;
+    }
+  }
+  __syncthreads();   // all window sums read: reuse resP of cell c00 for rho
+  if (wact) {
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      int s = p + 4 * i;
+      if (s < C::NS) resP[c00 * C::NS + s] = rho[i];
+    }
+  }
+  __syncthreads();
+  if (wact && p == 0) {
+    const int a = a0 + wi, b = b0 + wj;
+    if (a < g.ny && b < g.nx) {
+      int sy = 0, sx = 0;
+      if (!g.fixed) {
+        sx = (bkey & 63) - 32;
+        sy = ((bkey >> 6) & 63) - 32;
+      }
+      const float* rr = resP + c00 * C::NS;
+      auto rhof = [&](int y, int x) { return rr[(y + R) * C::NSY + x + R]; };
+      float pu = 0.0f, pv = 0.0f;
+      if (Pn) window_mean_half_overlap(a, b, g.nx, g.ny, node, pu, pv);
+      finish_vector(g, pair, a, b, sy, sx, nflat == (g.fixed ? 5 : C::NS), pu, pv, rhof);
+    }
+  }
+}
+
+template <typename T, int STEP, int R, int SYG, int TW, int TH, int NT>
+hipError_t launch_tiled(const CorrArgs& g, int n, hipStream_t s) {
+  dim3 grid((g.nx + TW - 1) / TW, (g.ny + TH - 1) / TH, n);
+  hipLaunchKernelGGL((k_correct_tiled<T, STEP, R, SYG, TW, TH, NT>), grid, dim3(NT), 0, s, g);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_tiled_t(const CorrArgs& g, int n, hipStream_t s) {
+  if (g.step == 8 && g.R == 4) return launch_tiled<T, 8, 4, 3, 8, 7, 256>(g, n, s);
+  if (g.step == 8 && g.R == 1) return launch_tiled<T, 8, 1, 1, 8, 7, 256>(g, n, s);
+  if (g.step == 12 && g.R == 4) return launch_tiled<T, 12, 4, 3, 6, 5, 128>(g, n, s);
+  if (g.step == 12 && g.R == 1) return launch_tiled<T, 12, 1, 1, 6, 5, 128>(g, n, s);
+  return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+int correct_impl(const Plan& P) {
+  const int R = P.p.peak == PIV_PEAK_FIXED_CENTER ? 1 : P.p.radius;
+  if (P.p.dtype == PIV_F32) return 0;
+  if (P.p.win != 2 * P.p.step) return 0;
+  if ((P.p.step == 8 || P.p.step == 12) && (R == 4 || R == 1)) return 1;
+  return 0;
+}
+
+hipError_t launch_correct(const Plan& P, const void* A, const void* B, int64_t pitch, int n,
+                          const float* pred, float* disp, float* peak, uint8_t* flags, hipStream_t s) {
+  CorrArgs g;
+  g.A = (const uint8_t*)A;
+  g.B = (const uint8_t*)B;
+  g.pitch = pitch;
+  g.stride = pitch * P.p.height;
+  g.W = P.p.width;
+  g.H = P.p.height;
+  g.nx = P.nx;
+  g.ny = P.ny;
+  g.win = P.p.win;
+  g.step = P.p.step;
+  g.fixed = P.p.peak == PIV_PEAK_FIXED_CENTER;
+  g.R = g.fixed ? 1 : P.p.radius;
+  g.central = P.p.warp == PIV_WARP_CENTRAL;
+  g.pred = pred;
+  g.disp = disp;
+  g.peak = peak;
+  g.flags = flags;
+  g.mask = P.slot_mask;
+  if (correct_impl(P) == 1) {
+    return P.p.dtype == PIV_U8 ? launch_tiled_t<uint8_t>(g, n, s) : launch_tiled_t<uint16_t>(g, n, s);
+  }
+  const int BWd = g.win + 2 * g.R, S = 2 * g.R + 1;
+  size_t lds = sizeof(float) * ((size_t)g.win * g.win + (size_t)BWd * BWd + (size_t)S * S);
+  dim3 grid(P.nx, P.ny, n);
+  switch (P.p.dtype) {
+    case PIV_U8: hipLaunchKernelGGL(k_correct_generic<uint8_t>, grid, dim3(256), lds, s, g); break;
+    case PIV_U16: hipLaunchKernelGGL(k_correct_generic<uint16_t>, grid, dim3(256), lds, s, g); break;
+    default: hipLaunchKernelGGL(k_correct_generic<float>, grid, dim3(256), lds, s, g); break;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace piv

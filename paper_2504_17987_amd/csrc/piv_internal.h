@@ -1,0 +1,67 @@
+// Internal plan layout and kernel launchers of libpiv (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/piv.h"
+
+namespace piv {
+
+constexpr int kMaxLevels = 6;
+
+struct Level {
+  int W, H;           // level image size (px)
+  int pitch;          // bytes per row in the workspace (levels >= 1)
+  int nx, ny;         // level node grid
+  size_t off_a, off_b;  // per-pair offset of the level images (levels >= 1)
+  size_t off_d;         // per-pair offset of the level's int32 [2][ny][nx] field
+};
+
+struct Plan {
+  piv_params p;
+  int es;             // bytes per pixel (1, 2, 4)
+  int nx, ny;         // level-0 grid
+  int block;          // predictor block (resolved)
+  int L;
+  Level lv[kMaxLevels];
+  size_t off_mask;    // per-pair offset of the validation mask uint8 [ny][nx]
+  size_t per_pair;    // workspace bytes per pair
+  uint8_t* ws = nullptr;
+  size_t ws_bytes = 0;
+  int ws_pairs = 0;   // pairs the bound workspace can hold
+  const uint8_t* slot_mask = nullptr;
+};
+
+// Image view of one frame batch.
+struct Img {
+  const uint8_t* base;  // pair 0, row 0
+  int64_t pitch;        // bytes per row
+  int64_t stride;       // bytes per pair
+};
+
+// ---- launchers (return hipError_t of the launch) ----
+hipError_t launch_pyramid(const Plan& P, const void* A, const void* B, int64_t pitch, int n,
+                          hipStream_t s);
+hipError_t launch_sad_level(const Plan& P, int l, const void* A, const void* B, int64_t pitch,
+                            int n, hipStream_t s);
+hipError_t launch_pred_out(const Plan& P, int n, float* pred, hipStream_t s);
+hipError_t launch_correct(const Plan& P, const void* A, const void* B, int64_t pitch, int n,
+                          const float* pred, float* disp, float* peak, uint8_t* flags,
+                          hipStream_t s);
+hipError_t launch_validate(const Plan& P, float* field, uint8_t* flags, int n, hipStream_t s);
+hipError_t launch_vorticity(const Plan& P, const float* disp, float* omega, int n, hipStream_t s);
+hipError_t launch_ssd_forward(const Plan& P, const float* A, const float* B, const float* U, int n,
+                              float* loss, hipStream_t s);
+hipError_t launch_ssd_backward(const Plan& P, const float* A, const float* B, const float* U,
+                               const float* g, int n, float* gU, float* D, hipStream_t s);
+
+// Block widths (in 4-byte words) the SAD kernel is built for.
+bool sad_supported(int block_words);
+
+// Which correlation kernel a plan uses (exposed for tests and the bench).
+int correct_impl(const Plan& P);
+
+}  // namespace piv

@@ -1,0 +1,283 @@
+// Host side of libpiv: parameter validation, plan and workspace layout,
+// entry points of the C ABI (declared in include/piv.h).
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "piv_internal.h"
+
+using piv::Plan;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+piv_status fail(piv_status s, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof g_err, fmt, ap);
+  va_end(ap);
+  return s;
+}
+
+piv_status dev(hipError_t e, const char* what) {
+  if (e == hipSuccess) return PIV_OK;
+  return fail(PIV_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+const Plan* cplan(piv_plan_t p) { return reinterpret_cast<const Plan*>(p); }
+Plan* mplan(piv_plan_t p) { return reinterpret_cast<Plan*>(p); }
+
+piv_status check_images(const Plan& P, const void* A, const void* B, int64_t pitch, int32_t n) {
+  if (!A || !B) return fail(PIV_EINVAL, "image pointers must not be NULL");
+  if (n < 0 || n > P.p.max_batch) return fail(PIV_EINVAL, "n=%d outside [0, max_batch=%d]", n, P.p.max_batch);
+  if (pitch < (int64_t)P.p.width * P.es) return fail(PIV_EINVAL, "pitch_bytes %lld < width*elem", (long long)pitch);
+  if (pitch % 4) return fail(PIV_EINVAL, "pitch_bytes must be a multiple of 4");
+  if (((uintptr_t)A | (uintptr_t)B) & 3) return fail(PIV_EINVAL, "image pointers must be 4-byte aligned");
+  return PIV_OK;
+}
+
+piv_status need_ws(const Plan& P, int32_t n) {
+  if (!P.ws) return fail(PIV_ENOWORKSPACE, "no workspace bound");
+  if (n > P.ws_pairs) return fail(PIV_ENOWORKSPACE, "workspace holds %d pairs, n=%d", P.ws_pairs, n);
+  return PIV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void piv_params_default(piv_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof *p);
+  p->width = 1024;
+  p->height = 1024;
+  p->max_batch = 1;
+  p->dtype = PIV_U8;
+  p->bit_depth = 8;
+  p->win = 16;
+  p->step = 8;
+  p->radius = 4;
+  p->levels = 3;
+  p->block = 0;
+  p->radius_coarse = 6;
+  p->radius_fine = 2;
+  p->median = 1;
+  p->warp = PIV_WARP_B;
+  p->peak = PIV_PEAK_ARGMAX;
+  p->uod_threshold = 2.0f;
+  p->uod_epsilon = 0.1f;
+}
+
+piv_status piv_plan(const piv_params* pp, piv_plan_t* out) {
+  if (!out) return fail(PIV_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!pp) return fail(PIV_EINVAL, "params is NULL");
+  const piv_params& p = *pp;
+  if (p.width <= 0 || p.height <= 0) return fail(PIV_EINVAL, "image size must be positive");
+  if (p.max_batch <= 0) return fail(PIV_EINVAL, "max_batch must be positive");
+  int es = p.dtype == PIV_U8 ? 1 : p.dtype == PIV_U16 ? 2 : p.dtype == PIV_F32 ? 4 : 0;
+  if (!es) return fail(PIV_EINVAL, "unknown dtype %d", (int)p.dtype);
+  if (p.dtype == PIV_U16 && p.bit_depth != 12 && p.bit_depth != 16)
+    return fail(PIV_EINVAL, "U16 bit_depth must be 12 or 16");
+  if (p.step <= 0 || p.win <= 0) return fail(PIV_EINVAL, "win and step must be positive");
+  if (p.win < p.step) return fail(PIV_EINVAL, "win (%d) < step (%d)", p.win, p.step);
+  if ((p.win - p.step) % 2) return fail(PIV_EINVAL, "win - step must be even");
+  if (p.win > 64) return fail(PIV_EINVAL, "win > 64");
+  if (p.width % p.step || p.height % p.step)
+    return fail(PIV_EINVAL, "width and height must be multiples of step");
+  if (p.radius < 1 || p.radius > 16) return fail(PIV_EINVAL, "radius outside [1, 16]");
+  if (p.levels < 1 || p.levels > piv::kMaxLevels) return fail(PIV_EINVAL, "levels outside [1, 6]");
+  if (p.warp != PIV_WARP_B && p.warp != PIV_WARP_CENTRAL) return fail(PIV_EINVAL, "bad warp mode");
+  if (p.peak != PIV_PEAK_ARGMAX && p.peak != PIV_PEAK_FIXED_CENTER) return fail(PIV_EINVAL, "bad peak mode");
+  if (!(p.uod_threshold > 0) || !(p.uod_epsilon >= 0)) return fail(PIV_EINVAL, "bad UOD parameters");
+  int block = p.block ? p.block : p.win;
+  if (block < p.step || (block - p.step) % 2) return fail(PIV_EINVAL, "block must be >= step with block - step even");
+  if (block > 64) return fail(PIV_EINVAL, "block > 64");
+  if (p.radius_coarse < 0 || p.radius_coarse > 16 || p.radius_fine < 0 || p.radius_fine > 16)
+    return fail(PIV_EINVAL, "predictor radii outside [0, 16]");
+  // largest predictor displacement: Rc 2^(L-1) + Rf (2^(L-1) - 1); keys hold |d| <= 127
+  long reach = (long)p.radius_coarse * (1L << (p.levels - 1)) + (long)p.radius_fine * ((1L << (p.levels - 1)) - 1);
+  if (reach > 127) return fail(PIV_EINVAL, "predictor reach %ld px exceeds 127", reach);
+  if (p.dtype == PIV_F32 && p.levels > 1)
+    return fail(PIV_EUNSUPPORTED, "the integer predictor takes U8/U16 frames (F32 is for the SSD path)");
+  if ((block * es) % 4) return fail(PIV_EUNSUPPORTED, "block*bytes_per_pixel must be a multiple of 4");
+  if (p.dtype != PIV_F32 && !piv::sad_supported(block * es / 4))
+    return fail(PIV_EUNSUPPORTED, "predictor block of %d bytes per row is not built", block * es);
+
+  Plan* P = new (std::nothrow) Plan();
+  if (!P) return fail(PIV_EINVAL, "out of host memory");
+  P->p = p;
+  P->es = es;
+  P->block = block;
+  P->L = p.levels;
+  P->nx = p.width / p.step;
+  P->ny = p.height / p.step;
+  size_t off = 0;
+  for (int l = 0; l < P->L; ++l) {
+    piv::Level& v = P->lv[l];
+    if (l == 0) {
+      v.W = p.width; v.H = p.height; v.nx = P->nx; v.ny = P->ny; v.pitch = 0;
+      v.off_a = v.off_b = 0;
+    } else {
+      const piv::Level& u = P->lv[l - 1];
+      v.W = (u.W + 1) / 2; v.H = (u.H + 1) / 2;
+      v.nx = (u.nx + 1) / 2; v.ny = (u.ny + 1) / 2;
+      v.pitch = (int)((size_t)(v.W * es + 63) & ~size_t(63));
+      v.off_a = off; off = align256(off + (size_t)v.pitch * v.H);
+      v.off_b = off; off = align256(off + (size_t)v.pitch * v.H);
+    }
+  }
+  for (int l = 0; l < P->L; ++l) {
+    piv::Level& v = P->lv[l];
+    v.off_d = off;
+    off = align256(off + sizeof(int32_t) * 2 * (size_t)v.nx * v.ny);
+  }
+  P->off_mask = off;
+  off = align256(off + (size_t)P->nx * P->ny);
+  P->per_pair = off;
+  *out = reinterpret_cast<piv_plan_t>(P);
+  g_err[0] = 0;
+  return PIV_OK;
+}
+
+piv_status piv_plan_grid(piv_plan_t plan, int32_t* nx, int32_t* ny) {
+  if (!plan) return fail(PIV_EINVAL, "plan is NULL");
+  if (nx) *nx = cplan(plan)->nx;
+  if (ny) *ny = cplan(plan)->ny;
+  return PIV_OK;
+}
+
+size_t piv_plan_workspace_bytes(piv_plan_t plan, int32_t batch) {
+  if (!plan || batch < 0) return 0;
+  return cplan(plan)->per_pair * (size_t)batch;
+}
+
+piv_status piv_plan_bind_workspace(piv_plan_t plan, void* d_ws, size_t bytes) {
+  if (!plan) return fail(PIV_EINVAL, "plan is NULL");
+  Plan* P = mplan(plan);
+  if (d_ws && ((uintptr_t)d_ws & 255)) return fail(PIV_EINVAL, "workspace must be 256-byte aligned");
+  P->ws = static_cast<uint8_t*>(d_ws);
+  P->ws_bytes = d_ws ? bytes : 0;
+  P->ws_pairs = d_ws ? (int)(bytes / P->per_pair) : 0;
+  if (d_ws && P->ws_pairs == 0) {
+    P->ws = nullptr;
+    return fail(PIV_ENOWORKSPACE, "workspace of %zu bytes holds no pair (need %zu)", bytes, P->per_pair);
+  }
+  return PIV_OK;
+}
+
+piv_status piv_plan_bind_slot_mask(piv_plan_t plan, const uint8_t* d_mask) {
+  if (!plan) return fail(PIV_EINVAL, "plan is NULL");
+  mplan(plan)->slot_mask = d_mask;
+  return PIV_OK;
+}
+
+void piv_plan_destroy(piv_plan_t plan) { delete mplan(plan); }
+
+piv_status piv_predict(piv_plan_t plan, const void* A, const void* B, int64_t pitch, int32_t n,
+                       float* pred, hipStream_t stream) {
+  if (!plan) return fail(PIV_EINVAL, "plan is NULL");
+  const Plan& P = *cplan(plan);
+  if (piv_status s = check_images(P, A, B, pitch, n)) return s;
+  if (!pred) return fail(PIV_EINVAL, "pred must not be NULL");
+  if (P.p.dtype == PIV_F32) return fail(PIV_EUNSUPPORTED, "the predictor takes U8/U16 frames");
+  if (piv_status s = need_ws(P, n)) return s;
+  if (n == 0) return PIV_OK;
+  if (P.L > 1)
+    if (piv_status s = dev(piv::launch_pyramid(P, A, B, pitch, n, stream), "pyramid")) return s;
+  for (int l = P.L - 1; l >= 0; --l)
+    if (piv_status s = dev(piv::launch_sad_level(P, l, A, B, pitch, n, stream), "sad_search")) return s;
+  return dev(piv::launch_pred_out(P, n, pred, stream), "pred_out");
+}
+
+piv_status piv_correct(piv_plan_t plan, const void* A, const void* B, int64_t pitch, int32_t n,
+                       const float* pred, float* disp, float* peak, uint8_t* flags,
+                       hipStream_t stream) {
+  if (!plan) return fail(PIV_EINVAL, "plan is NULL");
+  const Plan& P = *cplan(plan);
+  if (piv_status s = check_images(P, A, B, pitch, n)) return s;
+  if (!disp || !flags) return fail(PIV_EINVAL, "disp and flags must not be NULL");
+  if (n == 0) return PIV_OK;
+  return dev(piv::launch_correct(P, A, B, pitch, n, pred, disp, peak, flags, stream), "correct");
+}
+
+piv_status piv_validate(piv_plan_t plan, float* field, uint8_t* flags, int32_t n, hipStream_t stream) {
+  if (!plan) return fail(PIV_EINVAL, "plan is NULL");
+  const Plan& P = *cplan(plan);
+  if (!field) return fail(PIV_EINVAL, "field must not be NULL");
+  if (n < 0 || n > P.p.max_batch) return fail(PIV_EINVAL, "n=%d outside [0, max_batch]", n);
+  if (piv_status s = need_ws(P, n)) return s;
+  if (n == 0) return PIV_OK;
+  return dev(piv::launch_validate(P, field, flags, n, stream), "validate");
+}
+
+piv_status piv_vorticity(piv_plan_t plan, const float* disp, float* omega, int32_t n, hipStream_t stream) {
+  if (!plan) return fail(PIV_EINVAL, "plan is NULL");
+  const Plan& P = *cplan(plan);
+  if (!disp || !omega) return fail(PIV_EINVAL, "disp and omega must not be NULL");
+  if (n < 0 || n > P.p.max_batch) return fail(PIV_EINVAL, "n=%d outside [0, max_batch]", n);
+  if (n == 0) return PIV_OK;
+  return dev(piv::launch_vorticity(P, disp, omega, n, stream), "vorticity");
+}
+
+piv_status piv_run(piv_plan_t plan, const void* A, const void* B, int64_t pitch, int32_t n,
+                   float* pred, float* disp, float* peak, uint8_t* flags, float* omega,
+                   hipStream_t stream) {
+  if (!plan) return fail(PIV_EINVAL, "plan is NULL");
+  const Plan& P = *cplan(plan);
+  if (piv_status s = check_images(P, A, B, pitch, n)) return s;
+  if (!pred || !disp || !flags || !omega) return fail(PIV_EINVAL, "pred, disp, flags, omega must not be NULL");
+  if (piv_status s = need_ws(P, n)) return s;
+  if (piv_status s = piv_predict(plan, A, B, pitch, n, pred, stream)) return s;
+  if (piv_status s = piv_validate(plan, pred, nullptr, n, stream)) return s;
+  if (piv_status s = piv_correct(plan, A, B, pitch, n, pred, disp, peak, flags, stream)) return s;
+  if (piv_status s = piv_validate(plan, disp, flags, n, stream)) return s;
+  return piv_vorticity(plan, disp, omega, n, stream);
+}
+
+piv_status piv_ssd_forward(piv_plan_t plan, const float* A, const float* B, const float* U, int32_t n,
+                           float* loss, hipStream_t stream) {
+  if (!plan) return fail(PIV_EINVAL, "plan is NULL");
+  const Plan& P = *cplan(plan);
+  if (P.p.dtype != PIV_F32) return fail(PIV_EINVAL, "SSD needs a PIV_F32 plan");
+  if (!A || !B || !U || !loss) return fail(PIV_EINVAL, "NULL pointer");
+  if (n < 0 || n > P.p.max_batch) return fail(PIV_EINVAL, "n=%d outside [0, max_batch]", n);
+  if (n == 0) return PIV_OK;
+  return dev(piv::launch_ssd_forward(P, A, B, U, n, loss, stream), "ssd_forward");
+}
+
+piv_status piv_ssd_backward(piv_plan_t plan, const float* A, const float* B, const float* U,
+                            const float* g, int32_t n, float* gU, float* D, hipStream_t stream) {
+  if (!plan) return fail(PIV_EINVAL, "plan is NULL");
+  const Plan& P = *cplan(plan);
+  if (P.p.dtype != PIV_F32) return fail(PIV_EINVAL, "SSD needs a PIV_F32 plan");
+  if (!A || !B || !U || !g || !gU) return fail(PIV_EINVAL, "NULL pointer");
+  if (n < 0 || n > P.p.max_batch) return fail(PIV_EINVAL, "n=%d outside [0, max_batch]", n);
+  if (n == 0) return PIV_OK;
+  return dev(piv::launch_ssd_backward(P, A, B, U, g, n, gU, D, stream), "ssd_backward");
+}
+
+const char* piv_status_string(piv_status s) {
+  switch (s) {
+    case PIV_OK: return "PIV_OK";
+    case PIV_EINVAL: return "PIV_EINVAL";
+    case PIV_EUNSUPPORTED: return "PIV_EUNSUPPORTED";
+    case PIV_ENOWORKSPACE: return "PIV_ENOWORKSPACE";
+    case PIV_EDEVICE: return "PIV_EDEVICE";
+  }
+  return "PIV_UNKNOWN";
+}
+
+const char* piv_last_error(void) { return g_err; }
+
+// Not part of the public header: which correlation kernel a plan selects
+// (0 = generic per-window, 1 = cell-shared tiled).  Used by tests and bench.
+int piv_debug_correct_impl(piv_plan_t plan) { return plan ? piv::correct_impl(*cplan(plan)) : -1; }
+
+}  // extern "C"

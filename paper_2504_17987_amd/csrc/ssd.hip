@@ -1,0 +1,269 @@
+// Differentiable windowed SSD of the deformation (an addition of this
+// library, not in the paper): forward loss per window and its adjoint with
+// respect to the node displacement field, with the Gauss-Newton diagonal.
+//
+// Both kernels work on tiles staged through LDS.  The backward kernel
+// forms each pixel's terms 2 m r dB'/du and 2 m (dB'/du)^2 once per tile
+// and lets every node gather its own weighted terms: no atomics, so the
+// result is bitwise reproducible.
+#include "dev_common.h"
+#include "piv_internal.h"
+
+namespace piv {
+namespace {
+
+struct SsdArgs {
+  const float* A;
+  const float* B;
+  const float* U;
+  int W, H, nx, ny, win, step;
+  float* loss;
+  const float* g;
+  float* gU;
+  float* D;
+  const uint8_t* mask;
+};
+
+__device__ __forceinline__ float ldA(const float* I, int W, int H, int y, int x) {
+  return ((unsigned)x < (unsigned)W && (unsigned)y < (unsigned)H) ? I[(int64_t)y * W + x] : 0.0f;
+}
+
+// clamped bilinear node coordinates of a pixel: base node and fractions
+__device__ __forceinline__ void node_coord(float p, int n, int step, int& b, float& f) {
+  const float c = 0.5f * (float)(step - 1);
+  float t = fminf(fmaxf((p - c) / (float)step, 0.0f), (float)(n - 1));
+  b = min((int)t, max(n - 2, 0));
+  f = t - (float)b;
+}
+
+__device__ __forceinline__ void disp_at(const float* U, int nx, int ny, int step, int x, int y, float& u,
+                                        float& v) {
+  int bx, by;
+  float fx, fy;
+  node_coord((float)x, nx, step, bx, fx);
+  node_coord((float)y, ny, step, by, fy);
+  int bx1 = nx > 1 ? bx + 1 : bx, by1 = ny > 1 ? by + 1 : by;
+  const int np = nx * ny;
+  const float* P = U;
+  u = (1.0f - fy) * ((1.0f - fx) * P[by * nx + bx] + fx * P[by * nx + bx1]) +
+      fy * ((1.0f - fx) * P[by1 * nx + bx] + fx * P[by1 * nx + bx1]);
+  P = U + np;
+  v = (1.0f - fy) * ((1.0f - fx) * P[by * nx + bx] + fx * P[by * nx + bx1]) +
+      fy * ((1.0f - fx) * P[by1 * nx + bx] + fx * P[by1 * nx + bx1]);
+}
+
+// weight of node index `b` in the clamped interpolation of coordinate p
+__device__ __forceinline__ float node_weight(float p, int n, int step, int b) {
+  int bb;
+  float f;
+  node_coord(p, n, step, bb, f);
+  float w = 0.0f;
+  if (b == bb) w += 1.0f - f;
+  if (b == (n > 1 ? bb + 1 : bb)) w += f;
+  return w;
+}
+
+// residual r = B(p+u) - A(p) and the floor-cell gradient of the sample
+__device__ __forceinline__ void residual(const SsdArgs& a, const float* A, const float* B, const float* U,
+                                         int x, int y, float& r, float& gx, float& gy) {
+  float u, v;
+  disp_at(U, a.nx, a.ny, a.step, x, y, u, v);
+  float qx = (float)x + u, qy = (float)y + v;
+  float x0 = floorf(qx), y0 = floorf(qy);
+  float fx = qx - x0, fy = qy - y0;
+  int ix = (int)x0, iy = (int)y0;
+  float p00 = ldA(B, a.W, a.H, iy, ix), p01 = ldA(B, a.W, a.H, iy, ix + 1);
+  float p10 = ldA(B, a.W, a.H, iy + 1, ix), p11 = ldA(B, a.W, a.H, iy + 1, ix + 1);
+  float bs = (1.0f - fy) * ((1.0f - fx) * p00 + fx * p01) + fy * ((1.0f - fx) * p10 + fx * p11);
+  r = bs - ldA(A, a.W, a.H, y, x);
+  gx = (1.0f - fy) * (p01 - p00) + fy * (p11 - p10);
+  gy = (1.0f - fx) * (p10 - p00) + fx * (p11 - p01);
+}
+
+__device__ __forceinline__ int fdiv(int p, int q) { return p >= 0 ? p / q : -((-p + q - 1) / q); }
+
+// Forward: a workgroup owns a TN x TN tile of windows; squared residuals of
+// the tile's pixel region go to LDS, then every window sums its block.
+__global__ __launch_bounds__(256) void k_ssd_forward(SsdArgs a, int TN) {
+  extern __shared__ float s_r2[];
+  const int pair = blockIdx.z;
+  if (slot_off(a.mask, pair)) return;
+  const int t = threadIdx.x;
+  const int np = a.nx * a.ny;
+  const int64_t img = (int64_t)a.W * a.H;
+  const float* A = a.A + pair * img;
+  const float* B = a.B + pair * img;
+  const float* U = a.U + (int64_t)pair * 2 * np;
+  const int h = (a.win - a.step) / 2;
+  const int ta = blockIdx.y * TN, tb = blockIdx.x * TN;
+  const int RW = (TN - 1) * a.step + a.win;
+  const int y0 = ta * a.step - h, x0 = tb * a.step - h;
+  for (int idx = t; idx < RW * RW; idx += 256) {
+    int y = y0 + idx / RW, x = x0 + idx % RW;
+    float r, gx, gy;
+    residual(a, A, B, U, x, y, r, gx, gy);
+    s_r2[idx] = r * r;
+  }
+  __syncthreads();
+  // one window per 4 threads (TN*TN <= 64)
+  const int w = t >> 2, p = t & 3;
+  const int wi = w / TN, wj = w % TN;
+  float s = 0.0f;
+  if (w < TN * TN) {
+    for (int i = p; i < a.win; i += 4) {
+      const float* row = s_r2 + (wi * a.step + i) * RW + wj * a.step;
+      for (int j = 0; j < a.win; ++j) s += row[j];
+    }
+  }
+  s += __shfl_xor(s, 1);
+  s += __shfl_xor(s, 2);
+  if (w < TN * TN && p == 0) {
+    int aa = ta + wi, bb = tb + wj;
+    if (aa < a.ny && bb < a.nx) a.loss[(int64_t)pair * np + aa * a.nx + bb] = s;
+  }
+}
+
+// Backward: a workgroup owns a TN x TN tile of nodes.  Pass 1 writes per
+// pixel of the tile's support region: 2 m r gx, 2 m r gy, 2 m gx^2, 2 m gy^2
+// (m = sum of upstream gradients of the windows holding the pixel).  Pass 2:
+// 16 threads per node gather weight * term over the node's support rows,
+// then reduce over their 16 lanes.
+__global__ __launch_bounds__(256) void k_ssd_backward(SsdArgs a, int TN) {
+  extern __shared__ float s_t[];
+  const int pair = blockIdx.z;
+  if (slot_off(a.mask, pair)) return;
+  const int t = threadIdx.x;
+  const int np = a.nx * a.ny;
+  const int64_t img = (int64_t)a.W * a.H;
+  const float* A = a.A + pair * img;
+  const float* B = a.B + pair * img;
+  const float* U = a.U + (int64_t)pair * 2 * np;
+  const float* G = a.g + (int64_t)pair * np;
+  const int h = (a.win - a.step) / 2;
+  const int ta = blockIdx.y * TN, tb = blockIdx.x * TN;
+  // pixel support of the tile's nodes (clamped interpolation extends the
+  // edge nodes' support to the outermost window pixel)
+  const int lo_all = -h, hi_x = a.nx * a.step + h - 1, hi_y = a.ny * a.step + h - 1;
+  int ylo = ta == 0 ? lo_all : (ta - 1) * a.step + a.step / 2;   // > centre of node ta-1
+  int xlo = tb == 0 ? lo_all : (tb - 1) * a.step + a.step / 2;
+  int tae = min(ta + TN, a.ny) - 1, tbe = min(tb + TN, a.nx) - 1;
+  int yhi = tae == a.ny - 1 ? hi_y : (tae + 1) * a.step + (a.step - 1) / 2;  // < centre of node tae+1
+  int xhi = tbe == a.nx - 1 ? hi_x : (tbe + 1) * a.step + (a.step - 1) / 2;
+  const int RH = yhi - ylo + 1, RW = xhi - xlo + 1;
+  float* T0 = s_t;
+  float* T1 = T0 + RH * RW;
+  float* T2 = T1 + RH * RW;
+  float* T3 = T2 + RH * RW;
+  for (int idx = t; idx < RH * RW; idx += 256) {
+    int y = ylo + idx / RW, x = xlo + idx % RW;
+    // m(p): windows whose block holds the pixel
+    int a0 = max(fdiv(y + h - a.win + 1, a.step), 0), a1 = min(fdiv(y + h, a.step), a.ny - 1);
+    int b0 = max(fdiv(x + h - a.win + 1, a.step), 0), b1 = min(fdiv(x + h, a.step), a.nx - 1);
+    float m = 0.0f;
+    for (int i = a0; i <= a1; ++i)
+      for (int j = b0; j <= b1; ++j) m += G[i * a.nx + j];
+    float r = 0.0f, gx = 0.0f, gy = 0.0f;
+    if (m != 0.0f) residual(a, A, B, U, x, y, r, gx, gy);
+    T0[idx] = 2.0f * m * r * gx;
+    T1[idx] = 2.0f * m * r * gy;
+    T2[idx] = 2.0f * m * gx * gx;
+    T3[idx] = 2.0f * m * gy * gy;
+  }
+  __syncthreads();
+  const int nd = t >> 4, lane = t & 15;
+  const int na = ta + nd / TN, nb = tb + nd % TN;
+  float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;
+  const bool act = nd < TN * TN && na < a.ny && nb < a.nx;
+  if (act) {
+    // node support rows/cols, intersected with the region
+    int sy0 = na == 0 ? lo_all : (na - 1) * a.step + a.step / 2;
+    int sy1 = na == a.ny - 1 ? hi_y : (na + 1) * a.step + (a.step - 1) / 2;
+    int sx0 = nb == 0 ? lo_all : (nb - 1) * a.step + a.step / 2;
+    int sx1 = nb == a.nx - 1 ? hi_x : (nb + 1) * a.step + (a.step - 1) / 2;
+    for (int y = sy0 + lane; y <= sy1; y += 16) {
+      float wy = node_weight((float)y, a.ny, a.step, na);
+      if (wy == 0.0f) continue;
+      const int ro = (y - ylo) * RW - xlo;
+      for (int x = sx0; x <= sx1; ++x) {
+        float wx = node_weight((float)x, a.nx, a.step, nb);
+        float w = wx * wy;
+        s0 += w * T0[ro + x];
+        s1 += w * T1[ro + x];
+        s2 += w * w * T2[ro + x];
+        s3 += w * w * T3[ro + x];
+      }
+    }
+  }
+#pragma unroll
+  for (int o = 1; o < 16; o <<= 1) {
+    s0 += __shfl_xor(s0, o);
+    s1 += __shfl_xor(s1, o);
+    s2 += __shfl_xor(s2, o);
+    s3 += __shfl_xor(s3, o);
+  }
+  if (act && lane == 0) {
+    const int i = na * a.nx + nb;
+    float* gU = a.gU + (int64_t)pair * 2 * np;
+    gU[i] = s0;
+    gU[np + i] = s1;
+    if (a.D) {
+      float* D = a.D + (int64_t)pair * 2 * np;
+      D[i] = s2;
+      D[np + i] = s3;
+    }
+  }
+}
+
+SsdArgs make_args(const Plan& P, const float* A, const float* B, const float* U) {
+  SsdArgs a;
+  a.A = A;
+  a.B = B;
+  a.U = U;
+  a.W = P.p.width;
+  a.H = P.p.height;
+  a.nx = P.nx;
+  a.ny = P.ny;
+  a.win = P.p.win;
+  a.step = P.p.step;
+  a.loss = nullptr;
+  a.g = nullptr;
+  a.gU = nullptr;
+  a.D = nullptr;
+  a.mask = P.slot_mask;
+  return a;
+}
+
+}  // namespace
+
+hipError_t launch_ssd_forward(const Plan& P, const float* A, const float* B, const float* U, int n,
+                              float* loss, hipStream_t s) {
+  SsdArgs a = make_args(P, A, B, U);
+  a.loss = loss;
+  // tile: at most 8 x 8 windows with a pixel region of at most 96 x 96
+  int TN = max(1, min(8, (96 - a.win) / a.step + 1));
+  int RW = (TN - 1) * a.step + a.win;
+  size_t lds = sizeof(float) * (size_t)RW * RW;
+  dim3 grid((a.nx + TN - 1) / TN, (a.ny + TN - 1) / TN, n);
+  hipLaunchKernelGGL(k_ssd_forward, grid, dim3(256), lds, s, a, TN);
+  return hipGetLastError();
+}
+
+hipError_t launch_ssd_backward(const Plan& P, const float* A, const float* B, const float* U,
+                               const float* g, int n, float* gU, float* D, hipStream_t s) {
+  SsdArgs a = make_args(P, A, B, U);
+  a.g = g;
+  a.gU = gU;
+  a.D = D;
+  // 16 threads per node -> 16 nodes per workgroup; support region of a
+  // 4 x 4 node tile spans (TN+1) step + h px plus edge extension
+  const int TN = 4;
+  const int h = (a.win - a.step) / 2;
+  int RWmax = (TN + 1) * a.step + 2 * h + 2;
+  size_t lds = sizeof(float) * 4 * (size_t)RWmax * RWmax;
+  if (lds > 65536) return hipErrorInvalidValue;
+  dim3 grid((a.nx + TN - 1) / TN, (a.ny + TN - 1) / TN, n);
+  hipLaunchKernelGGL(k_ssd_backward, grid, dim3(256), lds, s, a, TN);
+  return hipGetLastError();
+}
+
+}  // namespace piv

@@ -207,3 +207,26 @@ def test_zero_displacement_gives_zero():
     assert (np.rint(disp[:, 1:15, 1:15]) == 0).all()
     assert (peak[inner] > 1 - 1e-12).all()
     assert abs(disp[0][inner].mean()) < 0.01 and np.abs(disp[:, 1:15, 1:15]).max() < 0.1
+
+
+def test_composition_is_window_mean_of_predictor():
+    """Blank frames give no correlation (FLAT, zero shift, no fit), so the
+    result is exactly the base the correction is added to: the mean over the
+    window of the interpolated predictor (scipy's bilinear interpolation
+    averaged over the window's pixels), which for 50% overlap equals the
+    separable (1/4, 1/2, 1/4) node stencil inside and (3/4, 1/4) at edges."""
+    rng = np.random.default_rng(17)
+    P = rng.integers(-5, 6, (2, 6, 7)).astype(float)
+    Z = np.zeros((48, 56))
+    d, pk, fl = oracle.correct(Z, Z, 16, 8, 2, P)
+    assert (fl & oracle.FLAT).all()
+    ys, xs = np.mgrid[-4:12, -4:12].astype(float)
+    w = lambda i, n: ({0: [0, .75, .25], n - 1: [.25, .75, 0]}.get(i, [.25, .5, .25]))
+    for a in range(6):
+        for b in range(7):
+            u, v = brute.displacement_at(P, 8, xs + 8 * b, ys + 8 * a)
+            assert abs(d[0, a, b] - u.mean()) < 1e-12 and abs(d[1, a, b] - v.mean()) < 1e-12
+            st = np.outer(w(a, 6), w(b, 7))
+            Pp = np.pad(P, ((0, 0), (1, 1), (1, 1)))
+            ref = (st * Pp[0, a:a + 3, b:b + 3]).sum()
+            assert abs(d[0, a, b] - ref) < 1e-12
