@@ -156,9 +156,10 @@ __global__ __launch_bounds__(256) void k_ssd_backward(SsdArgs a, int TN) {
   float* T3 = T2 + RH * RW;
   for (int idx = t; idx < RH * RW; idx += 256) {
     int y = ylo + idx / RW, x = xlo + idx % RW;
-    // m(p): windows whose block holds the pixel
-    int a0 = max(fdiv(y + h - a.win + 1, a.step), 0), a1 = min(fdiv(y + h, a.step), a.ny - 1);
-    int b0 = max(fdiv(x + h - a.win + 1, a.step), 0), b1 = min(fdiv(x + h, a.step), a.nx - 1);
+    // m(p): windows whose block holds the pixel, i.e. the a with
+    // a step - h <= y <= a step - h + win - 1 (ceiling for the lower bound)
+    int a0 = max(fdiv(y + h - a.win + a.step, a.step), 0), a1 = min(fdiv(y + h, a.step), a.ny - 1);
+    int b0 = max(fdiv(x + h - a.win + a.step, a.step), 0), b1 = min(fdiv(x + h, a.step), a.nx - 1);
     float m = 0.0f;
     for (int i = a0; i <= a1; ++i)
       for (int j = b0; j <= b1; ++j) m += G[i * a.nx + j];

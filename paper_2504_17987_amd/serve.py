@@ -1,0 +1,435 @@
+"""Batched graph launches and a continuous-batching server for streams of
+image pairs.
+
+The paper pipelines frames so that its fixed-function engine stays busy
+while the compute units pre- and post-process neighbouring frames, and it
+notes that small images are overhead-limited (Sec. 4.1).  Here the same
+concern is met with batching and HIP graphs:
+
+* ``GraphRunner`` captures the whole path (``piv_run``) for a fixed number
+  of slots into one HIP graph (``torch.cuda.CUDAGraph``); a device slot
+  mask lets a replay run a partial batch without recapture.
+* ``Scheduler`` is the host policy of the server (pure Python, clock and
+  executor injected, so it is tested on the CPU): stream admission against
+  an HBM budget, per-size-class FIFO queues, launch when a class's slots
+  are full, when its oldest request has waited ``max_wait`` or when the
+  device is idle; up to ``inflight`` batches per class on the device.
+* ``GpuExecutor`` runs a class's batch as one graph replay on that class's
+  own stream (classes overlap on the device) and polls HIP events for
+  completion.
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import heapq
+import math
+import time
+from typing import Callable, Deque, Dict, List, Optional, Sequence, Tuple
+
+# ----------------------------------------------------------------------------
+# graph runner (device)
+# ----------------------------------------------------------------------------
+
+
+class GraphRunner:
+    """Static slot buffers + one captured graph of the whole path.
+
+    The plan must be dedicated to this runner (its workspace and slot mask
+    are used by the captured kernels), with max_batch >= slots."""
+
+    def __init__(self, plan, slots: int, stream=None):
+        import torch
+        from .api import Plan  # noqa: F401
+        self.torch = torch
+        self.plan = plan
+        self.slots = slots
+        dev = plan.device
+        H, W = plan.height, plan.width
+        self.A = torch.zeros((slots, H, W), dtype=plan.tdtype, device=dev)
+        self.B = torch.zeros((slots, H, W), dtype=plan.tdtype, device=dev)
+        ny, nx = plan.ny, plan.nx
+        self.out = dict(pred=torch.zeros((slots, 2, ny, nx), device=dev),
+                        disp=torch.zeros((slots, 2, ny, nx), device=dev),
+                        peak=torch.zeros((slots, ny, nx), device=dev),
+                        flags=torch.zeros((slots, ny, nx), dtype=torch.uint8, device=dev),
+                        omega=torch.zeros((slots, ny, nx), device=dev))
+        self.mask = torch.ones((slots,), dtype=torch.uint8, device=dev)
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=dev)
+        self.graph = None
+
+    def resident_bytes(self) -> int:
+        t = [self.A, self.B, self.mask] + list(self.out.values())
+        return sum(x.numel() * x.element_size() for x in t) + self.plan.workspace_bytes(self.slots)
+
+    def capture(self) -> None:
+        torch = self.torch
+        self.plan.bind_slot_mask(self.mask)
+        # warm up on the capture stream, then capture
+        self.stream.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(self.stream):
+            self.plan.run(self.A, self.B, self.out)
+        self.stream.synchronize()
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph, stream=self.stream):
+            self.plan.run(self.A, self.B, self.out)
+        self.stream.synchronize()
+
+    def set_active(self, n: int) -> None:
+        """Slots [0, n) run, the rest are skipped (a small fill kernel on the
+        runner's stream; no memset node)."""
+        with self.torch.cuda.stream(self.stream):
+            self.mask[:n].fill_(1)
+            if n < self.slots:
+                self.mask[n:].fill_(0)
+
+    def replay(self, n: Optional[int] = None) -> None:
+        """Replay after all work already queued on the caller's current
+        stream (input copies, for instance)."""
+        if self.graph is None:
+            self.capture()
+        self.stream.wait_stream(self.torch.cuda.current_stream())
+        if n is not None:
+            self.set_active(n)
+        with self.torch.cuda.stream(self.stream):
+            self.graph.replay()
+
+
+# ----------------------------------------------------------------------------
+# host policy (CPU-testable)
+# ----------------------------------------------------------------------------
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    stream: int
+    cls: str
+    item: int            # which of the stream's resident pairs
+    arrival: float
+    start: float = math.nan
+    done: float = math.nan
+
+
+@dataclasses.dataclass
+class ClassSpec:
+    name: str
+    width: int
+    height: int
+    capacity: int        # slots per batch
+    slot_bytes: int      # resident bytes of one runner (plan workspace, slots, outputs)
+    stream_bytes: int    # resident bytes of one admitted stream (its device-resident pairs)
+
+
+class Executor:
+    """What the scheduler needs from the device side."""
+
+    def launch(self, cls: str, reqs: List[Request], now: float) -> object: ...
+
+    def done(self, handle: object) -> bool: ...
+
+    def busy(self) -> bool: ...
+
+
+class Scheduler:
+    """Continuous batching over size classes.
+
+    * admit(stream, cls): reserves the class's runners (first stream of a
+      class) and the stream's resident bytes against ``budget``; a stream
+      that does not fit waits in the admission queue and is admitted as
+      soon as memory is released (``retire``).
+    * submit(req): requests of admitted streams join their class's FIFO.
+    * step(now): completes finished batches, then launches, per class and
+      while that class has fewer than ``inflight`` batches on the device,
+      the oldest ``capacity`` requests when the queue is full, when the
+      oldest has waited ``max_wait``, or when the device is idle.
+    """
+
+    def __init__(self, classes: Sequence[ClassSpec], executor: Executor, budget: int,
+                 max_wait: float = 2e-3, inflight: int = 2):
+        self.classes = {c.name: c for c in classes}
+        self.ex = executor
+        self.budget = budget
+        self.max_wait = max_wait
+        self.inflight = inflight
+        self.used = 0
+        self.admitted: Dict[int, str] = {}
+        self.waiting: Deque[Tuple[int, str]] = collections.deque()
+        self.class_live: Dict[str, int] = collections.Counter()
+        self.queues: Dict[str, Deque[Request]] = {c: collections.deque() for c in self.classes}
+        self.running: Dict[str, List[Tuple[object, List[Request]]]] = {c: [] for c in self.classes}
+        self.finished: List[Request] = []
+        self.refused_submits = 0
+        self.batches = 0
+
+    # -- admission ----------------------------------------------------------
+    def _cost(self, cls: str) -> int:
+        c = self.classes[cls]
+        cost = c.stream_bytes
+        if self.class_live[cls] == 0:
+            cost += self.inflight * c.slot_bytes
+        return cost
+
+    def _try_admit(self, stream: int, cls: str) -> bool:
+        if self.used + self._cost(cls) <= self.budget:
+            self.used += self._cost(cls)
+            self.class_live[cls] += 1
+            self.admitted[stream] = cls
+            return True
+        return False
+
+    def admit(self, stream: int, cls: str) -> bool:
+        if stream in self.admitted:
+            return True
+        if self._try_admit(stream, cls):
+            return True
+        if (stream, cls) not in self.waiting:
+            self.waiting.append((stream, cls))
+        return False
+
+    def retire(self, stream: int) -> None:
+        cls = self.admitted.pop(stream, None)
+        if cls is not None:
+            self.class_live[cls] -= 1
+            self.used -= self.classes[cls].stream_bytes
+            if self.class_live[cls] == 0:
+                self.used -= self.inflight * self.classes[cls].slot_bytes
+        self._drain_waiting()
+
+    def set_budget(self, budget: int) -> None:
+        self.budget = budget
+        self._drain_waiting()
+
+    def _drain_waiting(self) -> None:
+        # admit waiting streams in order while they fit
+        still = collections.deque()
+        while self.waiting:
+            s, c = self.waiting.popleft()
+            if not self._try_admit(s, c):
+                still.append((s, c))
+        self.waiting = still
+
+    # -- requests -----------------------------------------------------------
+    def submit(self, req: Request) -> bool:
+        if self.admitted.get(req.stream) != req.cls:
+            self.refused_submits += 1
+            return False
+        self.queues[req.cls].append(req)
+        return True
+
+    def pending(self) -> int:
+        return sum(len(q) for q in self.queues.values()) + sum(
+            sum(len(r) for _, r in v) for v in self.running.values())
+
+    def step(self, now: float) -> int:
+        """One scheduling round; returns the number of batches launched."""
+        for cls, lst in self.running.items():
+            keep = []
+            for h, reqs in lst:
+                if self.ex.done(h):
+                    for r in reqs:
+                        r.done = now
+                    self.finished.extend(reqs)
+                else:
+                    keep.append((h, reqs))
+            self.running[cls] = keep
+        launched = 0
+        idle = not self.ex.busy()
+        # oldest-first across classes so that no class starves
+        order = sorted((q[0].arrival, cls) for cls, q in self.queues.items() if q)
+        for _, cls in order:
+            q = self.queues[cls]
+            cap = self.classes[cls].capacity
+            while q and len(self.running[cls]) < self.inflight:
+                full = len(q) >= cap
+                late = now - q[0].arrival >= self.max_wait
+                if not (full or late or idle):
+                    break
+                batch = [q.popleft() for _ in range(min(cap, len(q)))]
+                for r in batch:
+                    r.start = now
+                h = self.ex.launch(cls, batch, now)
+                self.running[cls].append((h, batch))
+                self.batches += 1
+                launched += 1
+                idle = False
+        return launched
+
+
+class FakeExecutor(Executor):
+    """Scripted batch durations on a simulated clock (CPU tests)."""
+
+    def __init__(self, duration: Callable[[str, int], float], clock: Callable[[], float]):
+        self.duration = duration
+        self.clock = clock
+        self.live: Dict[int, float] = {}
+        self.n = 0
+        self.log: List[Tuple[str, int, float]] = []
+
+    def launch(self, cls, reqs, now):
+        self.n += 1
+        self.live[self.n] = now + self.duration(cls, len(reqs))
+        self.log.append((cls, len(reqs), now))
+        return self.n
+
+    def done(self, h):
+        if self.live[h] <= self.clock():
+            del self.live[h]
+            return True
+        return False
+
+    def busy(self):
+        t = self.clock()
+        return any(v > t for v in self.live.values())
+
+
+# ----------------------------------------------------------------------------
+# device executor and the server loop
+# ----------------------------------------------------------------------------
+
+
+class GpuExecutor(Executor):
+    """Graph replays on per-class streams; completion by HIP events.
+
+    ``pairs[stream]`` holds each admitted stream's device-resident pairs
+    (A, B tensors of shape [k, H, W]); a launch copies the requested pairs
+    into a free runner's slots (device-to-device, on the runner's stream),
+    sets the active-slot mask and replays the runner's graph."""
+
+    def __init__(self, runners: Dict[str, List[GraphRunner]], pairs: Dict[int, Tuple[object, object]],
+                 keep_results: bool = False):
+        import torch
+        self.torch = torch
+        self.runners = runners
+        self.pairs = pairs
+        self.free = {c: list(r) for c, r in runners.items()}
+        self.live: Dict[int, Tuple[str, GraphRunner, object, List[Request]]] = {}
+        self.n = 0
+        self.keep = keep_results
+        self.results: Dict[int, Dict[str, object]] = {}
+
+    def launch(self, cls, reqs, now):
+        torch = self.torch
+        run = self.free[cls].pop()
+        with torch.cuda.stream(run.stream):
+            for i, r in enumerate(reqs):
+                a, b = self.pairs[r.stream]
+                run.A[i].copy_(a[r.item], non_blocking=True)
+                run.B[i].copy_(b[r.item], non_blocking=True)
+        run.replay(len(reqs))
+        ev = torch.cuda.Event()
+        ev.record(run.stream)
+        self.n += 1
+        self.live[self.n] = (cls, run, ev, reqs)
+        return self.n
+
+    def done(self, h):
+        cls, run, ev, reqs = self.live[h]
+        if not ev.query():
+            return False
+        if self.keep:
+            for i, r in enumerate(reqs):
+                self.results[r.rid] = {k: v[i].clone() for k, v in run.out.items()}
+        del self.live[h]
+        self.free[cls].append(run)
+        return True
+
+    def busy(self):
+        return bool(self.live)
+
+
+def make_gpu_server(classes: Dict[str, Tuple[int, int, int]], pairs: Dict[int, Tuple[object, object]],
+                    stream_class: Dict[int, str], budget: int, plan_kw: Optional[dict] = None,
+                    inflight: int = 2, max_wait: float = 2e-3, keep_results: bool = False):
+    """Build runners (``inflight`` per class, each with its own plan,
+    workspace, HIP stream and captured graph), the executor and the
+    scheduler, and admit the streams in order.  classes: name -> (W, H,
+    slots).  Returns (scheduler, executor)."""
+    from .api import Plan
+    plan_kw = dict(plan_kw or {})
+    runners: Dict[str, List[GraphRunner]] = {}
+    specs = []
+    for name, (W, H, cap) in classes.items():
+        rs = []
+        for _ in range(inflight):
+            r = GraphRunner(Plan(W, H, max_batch=cap, **plan_kw), cap)
+            r.capture()
+            rs.append(r)
+        runners[name] = rs
+        per_stream = 0
+        for s, c in stream_class.items():
+            if c == name:
+                a, b = pairs[s]
+                per_stream = a.numel() * a.element_size() + b.numel() * b.element_size()
+                break
+        specs.append(ClassSpec(name, W, H, cap, rs[0].resident_bytes(), per_stream))
+    ex = GpuExecutor(runners, pairs, keep_results=keep_results)
+    sched = Scheduler(specs, ex, budget, max_wait=max_wait, inflight=inflight)
+    for s, c in stream_class.items():
+        sched.admit(s, c)
+    return sched, ex
+
+
+def poisson_trace(streams: Sequence[Tuple[int, str]], rate: float, duration: float, items: int,
+                  seed: int = 0) -> List[Request]:
+    """Merged Poisson arrivals: each stream at `rate` requests/s for
+    `duration` seconds, cycling through its `items` resident pairs."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for s, cls in streams:
+        t, k = 0.0, 0
+        while True:
+            t += rng.exponential(1.0 / rate)
+            if t >= duration:
+                break
+            reqs.append(Request(0, s, cls, k % items, t))
+            k += 1
+    reqs.sort(key=lambda r: (r.arrival, r.stream))
+    for i, r in enumerate(reqs):
+        r.rid = i
+    return reqs
+
+
+def serve_trace(sched: Scheduler, trace: List[Request], clock: Callable[[], float],
+                poll: float = 20e-6, deadline: float = 60.0) -> None:
+    """Feed `trace` (arrival times relative to the start) into `sched` in
+    real time and run until every request has completed."""
+    t0 = clock()
+    i = 0
+    while i < len(trace) or sched.pending():
+        now = clock() - t0
+        if now > deadline:
+            raise TimeoutError(f"serving did not finish within {deadline} s")
+        while i < len(trace) and trace[i].arrival <= now:
+            sched.submit(trace[i])
+            i += 1
+        if not sched.step(now) and poll > 0:
+            time.sleep(poll)
+
+
+def run_fifo(plan_for: Callable[[str], object], pairs, trace: List[Request], clock,
+             deadline: float = 120.0) -> None:
+    """The plain per-pair form: one request at a time in arrival order, each
+    an ordinary (non-graph) piv_run of one pair; completion synchronously."""
+    import torch
+    t0 = clock()
+    for r in trace:
+        while clock() - t0 < r.arrival:
+            pass
+        r.start = clock() - t0
+        a, b = pairs[r.stream]
+        plan = plan_for(r.cls)
+        plan.run(a[r.item:r.item + 1], b[r.item:r.item + 1], plan._fifo_out)
+        torch.cuda.current_stream().synchronize()
+        r.done = clock() - t0
+        if r.done > deadline:
+            raise TimeoutError("FIFO baseline exceeded its deadline")
+
+
+def latency_stats(reqs: Sequence[Request]) -> Dict[str, float]:
+    import numpy as np
+    lat = np.array([r.done - r.arrival for r in reqs]) * 1e3
+    span = max(r.done for r in reqs) - min(r.arrival for r in reqs)
+    return {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "mean_ms": float(lat.mean()), "pairs_per_s": len(reqs) / span, "n": len(reqs)}
