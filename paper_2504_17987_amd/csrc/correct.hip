@@ -108,6 +108,36 @@ __device__ __forceinline__ void window_mean_half_overlap(int a, int b, int nx, i
     }
 }
 
+// Four consecutive pixels of row y from pixel x on (zero outside the image),
+// with aligned word loads realigned by alignbyte.
+template <typename T>
+__device__ __forceinline__ void load4(const uint8_t* img, int64_t pitch, int H, int rowbytes, int y, int x,
+                                      float (&v)[4]) {
+  if (y < 0 || y >= H) {
+    v[0] = v[1] = v[2] = v[3] = 0.0f;
+    return;
+  }
+  const uint8_t* row = img + (int64_t)y * pitch;
+  if constexpr (sizeof(T) == 1) {
+    const int xb = x, xa = xb & ~3, sh = xb & 3;
+    uint32_t w = __builtin_amdgcn_alignbyte(masked_word(row, rowbytes, xa + 4), masked_word(row, rowbytes, xa), sh);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] = (float)((w >> (8 * k)) & 0xffu);
+  } else if constexpr (sizeof(T) == 2) {
+    const int xb = 2 * x, xa = xb & ~3, sh = xb & 3;
+    uint32_t w0 = masked_word(row, rowbytes, xa), w1 = masked_word(row, rowbytes, xa + 4),
+             w2 = masked_word(row, rowbytes, xa + 8);
+    uint32_t lo = __builtin_amdgcn_alignbyte(w1, w0, sh), hi = __builtin_amdgcn_alignbyte(w2, w1, sh);
+    v[0] = (float)(lo & 0xffffu);
+    v[1] = (float)(lo >> 16);
+    v[2] = (float)(hi & 0xffffu);
+    v[3] = (float)(hi >> 16);
+  } else {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] = pixf<T>(img, pitch, rowbytes / 4, H, y, x + k);
+  }
+}
+
 // Fit and compose one vector from its coefficient lookup rho(sy, sx).
 template <typename RhoFn>
 __device__ __forceinline__ void finish_vector(const CorrArgs& g, int pair, int a, int b, int sy, int sx,
@@ -325,7 +355,10 @@ struct TileCfg {
   static constexpr int NNX = BW / STEP + 3, NNY = BH / STEP + 3;
   static constexpr int IN_FLOATS = AH * AP + BH * BP;
   static constexpr int RES_FLOATS = 3 * NC * NS;
-  static constexpr int UNION = IN_FLOATS > RES_FLOATS ? IN_FLOATS : RES_FLOATS;
+  // room for the raw source tile of B behind the A and B' tiles: what the
+  // result arrays leave free, at least 16 KiB
+  static constexpr int RAW_WORDS = RES_FLOATS - IN_FLOATS > 4096 ? RES_FLOATS - IN_FLOATS : 4096;
+  static constexpr int UNION = IN_FLOATS + RAW_WORDS > RES_FLOATS ? IN_FLOATS + RAW_WORDS : RES_FLOATS;
   static constexpr int NWIN = TW * TH;
   static_assert(NSY % SYG == 0, "shift rows must split evenly");
   static_assert(STEP % 2 == 0, "50% overlap needs an even step");
@@ -340,6 +373,9 @@ __global__ __launch_bounds__(NT) void k_correct_tiled(CorrArgs g) {
   __shared__ float s_node[2][C::NNY][C::NNX];
   __shared__ float s_wsum[C::NWIN], s_wsq[C::NWIN];
   __shared__ float s_red[NT / 64];
+  __shared__ float s_rng[NT / 64][4];
+  __shared__ int s_rb[C::BH], s_cb[C::BW];
+  __shared__ float s_rf[C::BH], s_cf[C::BW];
   __shared__ float s_K;
 
   const int pair = blockIdx.z;
@@ -356,39 +392,125 @@ __global__ __launch_bounds__(NT) void k_correct_tiled(CorrArgs g) {
   float* sA = s_u;                   // [AH][AP]
   float* sB = s_u + C::AH * C::AP;   // [BH][BP]
 
-  // node cache covering the B' tile
+  // node cache covering the B' tile, and the range of the predictor over it
+  // (every interpolated displacement is a convex combination of cached nodes)
   const float cen = 0.5f * (float)(STEP - 1);
   const int nlo_y = max(0, (int)floorf(((float)yb - cen) / STEP));
   const int nlo_x = max(0, (int)floorf(((float)xb - cen) / STEP));
+  float umin = 0.0f, umax = 0.0f, vmin = 0.0f, vmax = 0.0f;
   if (Pn) {
-    for (int idx = t; idx < 2 * C::NNY * C::NNX; idx += NT) {
-      int c = idx / (C::NNY * C::NNX), r = (idx / C::NNX) % C::NNY, q = idx % C::NNX;
+    umin = vmin = 3.0e38f;
+    umax = vmax = -3.0e38f;
+    for (int idx = t; idx < C::NNY * C::NNX; idx += NT) {
+      int r = idx / C::NNX, q = idx % C::NNX;
       int ny_ = min(nlo_y + r, g.ny - 1), nx_ = min(nlo_x + q, g.nx - 1);
-      s_node[c][r][q] = Pn[c * np + ny_ * g.nx + nx_];
+      float u = Pn[ny_ * g.nx + nx_], v = Pn[np + ny_ * g.nx + nx_];
+      s_node[0][r][q] = u;
+      s_node[1][r][q] = v;
+      umin = fminf(umin, u);
+      umax = fmaxf(umax, u);
+      vmin = fminf(vmin, v);
+      vmax = fmaxf(vmax, v);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      umin = fminf(umin, __shfl_xor(umin, o));
+      umax = fmaxf(umax, __shfl_xor(umax, o));
+      vmin = fminf(vmin, __shfl_xor(vmin, o));
+      vmax = fmaxf(vmax, __shfl_xor(vmax, o));
+    }
+    if ((t & 63) == 0) {
+      s_rng[t >> 6][0] = umin;
+      s_rng[t >> 6][1] = umax;
+      s_rng[t >> 6][2] = vmin;
+      s_rng[t >> 6][3] = vmax;
     }
   }
+  // per-row / per-column interpolation tables of the B' tile (the A tile is
+  // the same grid shifted by R): base node (cache index) and fraction, the
+  // same arithmetic as interp_u
+  for (int i = t; i < C::BH + C::BW; i += NT) {
+    const bool row = i < C::BH;
+    const int p = row ? yb + i : xb + (i - C::BH);
+    const int n = row ? g.ny : g.nx;
+    float tt = fminf(fmaxf(((float)p - cen) / (float)STEP, 0.0f), (float)(n - 1));
+    int bb = min((int)tt, max(n - 2, 0));
+    float ff = tt - (float)bb;
+    if (row) { s_rb[i] = bb - nlo_y; s_rf[i] = ff; }
+    else { s_cb[i - C::BH] = bb - nlo_x; s_cf[i - C::BH] = ff; }
+  }
   __syncthreads();
+  if (Pn) {
+    umin = s_rng[0][0]; umax = s_rng[0][1]; vmin = s_rng[0][2]; vmax = s_rng[0][3];
+#pragma unroll
+    for (int i = 1; i < NT / 64; ++i) {
+      umin = fminf(umin, s_rng[i][0]);
+      umax = fmaxf(umax, s_rng[i][1]);
+      vmin = fminf(vmin, s_rng[i][2]);
+      vmax = fmaxf(vmax, s_rng[i][3]);
+    }
+  }
   auto node = [&](int c, int y, int x) { return s_node[c][y - nlo_y][x - nlo_x]; };
+  auto interp_tab = [&](int r, int q, float& u, float& v) {
+    const int rb = s_rb[r], cb = s_cb[q];
+    const float fy = s_rf[r], fx = s_cf[q];
+    u = (1.0f - fy) * ((1.0f - fx) * s_node[0][rb][cb] + fx * s_node[0][rb][cb + 1]) +
+        fy * ((1.0f - fx) * s_node[0][rb + 1][cb] + fx * s_node[0][rb + 1][cb + 1]);
+    v = (1.0f - fy) * ((1.0f - fx) * s_node[1][rb][cb] + fx * s_node[1][rb][cb + 1]) +
+        fy * ((1.0f - fx) * s_node[1][rb + 1][cb] + fx * s_node[1][rb + 1][cb + 1]);
+  };
 
   // A tile (deformed by -u/2 in central mode) and its sum for the offset K
   float part = 0.0f;
-  for (int idx = t; idx < C::AH * C::AW; idx += NT) {
-    int r = idx / C::AW, q = idx % C::AW;
-    int y = y0 + r, x = x0 + q;
-    float v;
-    if (g.central && Pn) {
+  if (g.central && Pn) {
+    for (int idx = t; idx < C::AH * C::AW; idx += NT) {
+      int r = idx / C::AW, q = idx % C::AW;
       float u, w;
-      interp_u((float)x, (float)y, g.nx, g.ny, STEP, node, u, w);
-      v = bilin<T>(Ai, g.pitch, g.W, g.H, x - 0.5f * u, y - 0.5f * w);
-    } else {
-      v = pixf<T>(Ai, g.pitch, g.W, g.H, y, x);
+      interp_tab(r + R, q + R, u, w);
+      float v = bilin<T>(Ai, g.pitch, g.W, g.H, (x0 + q) - 0.5f * u, (y0 + r) - 0.5f * w);
+      sA[r * C::AP + q] = v;
+      part += v;
     }
-    sA[r * C::AP + q] = v;
-    part += v;
+  } else {
+    // straight copy, four pixels per load
+    const int rowbytes = g.W * (int)sizeof(T);
+    for (int idx = t; idx < C::AH * (C::AW / 4); idx += NT) {
+      int r = idx / (C::AW / 4), q = 4 * (idx % (C::AW / 4));
+      int y = y0 + r;
+      float v[4];
+      load4<T>(Ai, g.pitch, g.H, rowbytes, y, x0 + q, v);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        sA[r * C::AP + q + k] = v[k];
+        part += v[k];
+      }
+    }
   }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o);
   if ((t & 63) == 0) s_red[t >> 6] = part;
+
+  // raw source tile of B for the deformation, when its bounding box fits
+  const float sgnB = g.central ? 0.5f : 1.0f;
+  const int ix0 = (int)floorf((float)xb + sgnB * umin) - 1;
+  const int ix1 = (int)floorf((float)(xb + C::BW - 1) + sgnB * umax) + 2;
+  const int iy0 = (int)floorf((float)yb + sgnB * vmin) - 1;
+  const int iy1 = (int)floorf((float)(yb + C::BH - 1) + sgnB * vmax) + 2;
+  const int xw0 = (ix0 * (int)sizeof(T)) >> 2;
+  const int nwords = ((ix1 * (int)sizeof(T) + (int)sizeof(T) - 1) >> 2) - xw0 + 1;
+  const int nrows = iy1 - iy0 + 1;
+  const bool staged = nwords * nrows <= C::RAW_WORDS;
+  uint32_t* sraw = reinterpret_cast<uint32_t*>(s_u + C::IN_FLOATS);
+  if (staged) {
+    const int rowbytes = g.W * (int)sizeof(T);
+    for (int idx = t; idx < nwords * nrows; idx += NT) {
+      int r = idx / nwords, w = idx - (idx / nwords) * nwords;
+      int y = iy0 + r;
+      uint32_t val = 0u;
+      if (y >= 0 && y < g.H) val = masked_word(Bi + (int64_t)y * g.pitch, rowbytes, 4 * (xw0 + w));
+      sraw[idx] = val;
+    }
+  }
   __syncthreads();
   if (t == 0) {
     float s = 0.0f;
@@ -403,19 +525,40 @@ __global__ __launch_bounds__(NT) void k_correct_tiled(CorrArgs g) {
     sA[r * C::AP + q] -= K;
   }
   // deformed B' tile
-  const float sgnB = g.central ? 0.5f : 1.0f;
-  for (int idx = t; idx < C::BH * C::BW; idx += NT) {
-    int r = idx / C::BW, q = idx % C::BW;
-    int y = yb + r, x = xb + q;
-    float v;
-    if (Pn) {
-      float u, w;
-      interp_u((float)x, (float)y, g.nx, g.ny, STEP, node, u, w);
-      v = bilin<T>(Bi, g.pitch, g.W, g.H, x + sgnB * u, y + sgnB * w);
-    } else {
-      v = pixf<T>(Bi, g.pitch, g.W, g.H, y, x);
+  if (staged) {
+    const uint8_t* rawb = reinterpret_cast<const uint8_t*>(sraw);
+    const int rowb = 4 * nwords, xoff = 4 * xw0;
+    auto rawpx = [&](int y, int x) -> float {
+      y = min(max(y, iy0), iy1);
+      x = min(max(x, ix0), ix1);
+      return (float)*reinterpret_cast<const T*>(rawb + (y - iy0) * rowb + (x * (int)sizeof(T) - xoff));
+    };
+    for (int idx = t; idx < C::BH * C::BW; idx += NT) {
+      int r = idx / C::BW, q = idx % C::BW;
+      float u = 0.0f, w = 0.0f;
+      if (Pn) interp_tab(r, q, u, w);
+      float qx = (float)(xb + q) + sgnB * u, qy = (float)(yb + r) + sgnB * w;
+      float fx0 = floorf(qx), fy0 = floorf(qy);
+      float fx = qx - fx0, fy = qy - fy0;
+      int ix = (int)fx0, iy = (int)fy0;
+      float p00 = rawpx(iy, ix), p01 = rawpx(iy, ix + 1), p10 = rawpx(iy + 1, ix), p11 = rawpx(iy + 1, ix + 1);
+      float v = (1.0f - fy) * ((1.0f - fx) * p00 + fx * p01) + fy * ((1.0f - fx) * p10 + fx * p11);
+      sB[r * C::BP + q] = v - K;
     }
-    sB[r * C::BP + q] = v - K;
+  } else {
+    for (int idx = t; idx < C::BH * C::BW; idx += NT) {
+      int r = idx / C::BW, q = idx % C::BW;
+      int y = yb + r, x = xb + q;
+      float v;
+      if (Pn) {
+        float u, w;
+        interp_tab(r, q, u, w);
+        v = bilin<T>(Bi, g.pitch, g.W, g.H, x + sgnB * u, y + sgnB * w);
+      } else {
+        v = pixf<T>(Bi, g.pitch, g.W, g.H, y, x);
+      }
+      sB[r * C::BP + q] = v - K;
+    }
   }
   __syncthreads();
   // A window statistics: four threads per window, four rows... of 2 STEP each

@@ -42,39 +42,70 @@ __device__ __forceinline__ float bilin(const uint8_t* img, int64_t pitch, int W,
   return (1.0f - fy) * ((1.0f - fx) * p00 + fx * p01) + fy * ((1.0f - fx) * p10 + fx * p11);
 }
 
-// Rank selection among the first k of N values (static indexing only):
-// the value whose rank interval holds `idx` (0-based, ascending).
+// Compare-exchange on static indices.
+template <typename V>
+__device__ __forceinline__ void cswap(V& a, V& b) {
+  V lo = a < b ? a : b, hi = a < b ? b : a;
+  a = lo;
+  b = hi;
+}
+
+// Sort the first 8 of N >= 8 values ascending (Batcher's odd-even merge
+// network, 19 exchanges).
 template <int N, typename V>
-__device__ __forceinline__ V select_rank(const V (&v)[N], int k, int idx) {
-  V out = v[0];
-#pragma unroll
-  for (int i = 0; i < N; ++i) {
-    if (i < k) {
-      int lt = 0, le = 0;
-#pragma unroll
-      for (int j = 0; j < N; ++j) {
-        if (j < k) {
-          lt += v[j] < v[i];
-          le += v[j] <= v[i];
-        }
-      }
-      if (lt <= idx && idx < le) out = v[i];
-    }
-  }
-  return out;
+__device__ __forceinline__ void sort8(V (&v)[N]) {
+  static_assert(N >= 8, "needs 8 values");
+  cswap(v[0], v[1]); cswap(v[2], v[3]); cswap(v[4], v[5]); cswap(v[6], v[7]);
+  cswap(v[0], v[2]); cswap(v[1], v[3]); cswap(v[4], v[6]); cswap(v[5], v[7]);
+  cswap(v[1], v[2]); cswap(v[5], v[6]);
+  cswap(v[0], v[4]); cswap(v[1], v[5]); cswap(v[2], v[6]); cswap(v[3], v[7]);
+  cswap(v[2], v[4]); cswap(v[3], v[5]);
+  cswap(v[1], v[2]); cswap(v[3], v[4]); cswap(v[5], v[6]);
 }
 
-// Median of the first k (>= 1) values; even k: mean of the two middle ones.
-template <int N>
-__device__ __forceinline__ float median_f(const float (&v)[N], int k) {
-  if (k & 1) return select_rank<N, float>(v, k, k >> 1);
-  return 0.5f * (select_rank<N, float>(v, k, (k >> 1) - 1) + select_rank<N, float>(v, k, k >> 1));
+// Sort 9 values ascending: sort the first 8, then insert the ninth.
+template <typename V>
+__device__ __forceinline__ void sort9(V (&v)[9]) {
+  sort8<9, V>(v);
+#pragma unroll
+  for (int i = 7; i >= 0; --i) cswap(v[i], v[i + 1]);
 }
 
-// Lower median of the first k (>= 1) integers.
-template <int N>
-__device__ __forceinline__ int median_low_i(const int (&v)[N], int k) {
-  return select_rank<N, int>(v, k, (k - 1) >> 1);
+// Element idx of an array, as a sum of masked elements: written with bit
+// operations so that it stays a register computation (a select chain is
+// turned back into an indexed load from memory by the optimiser).
+__device__ __forceinline__ uint32_t as_u(float x) { return __float_as_uint(x); }
+__device__ __forceinline__ uint32_t as_u(int x) { return (uint32_t)x; }
+__device__ __forceinline__ float from_u(uint32_t x, float) { return __uint_as_float(x); }
+__device__ __forceinline__ int from_u(uint32_t x, int) { return (int)x; }
+
+template <int N, typename V>
+__device__ __forceinline__ V pick(const V (&v)[N], int idx) {
+  uint32_t out = 0u;
+#pragma unroll
+  for (int i = 0; i < N; ++i) out |= as_u(v[i]) & (0u - (uint32_t)(idx == i));
+  return from_u(out, V());
+}
+
+// Sentinels for unused slots: they sort above every real value, so the k
+// real values of a slot array are the first k after sorting.  (Slots stay
+// at static positions: compacting valid values to the front would need a
+// dynamic index.)
+constexpr float kSlotF = 3.0e38f;
+constexpr int kSlotI = 0x7fffffff;
+
+// Median of the k (>= 1) real values among 8 slots; even k: mean of the
+// two middle values.
+__device__ __forceinline__ float median8_f(float (&v)[8], int k) {
+  sort8<8, float>(v);
+  if (k & 1) return pick<8>(v, k >> 1);
+  return 0.5f * (pick<8>(v, (k >> 1) - 1) + pick<8>(v, k >> 1));
+}
+
+// Lower median of the k (>= 1) real values among 9 slots.
+__device__ __forceinline__ int median9_low_i(int (&v)[9], int k) {
+  sort9(v);
+  return pick<9>(v, (k - 1) >> 1);
 }
 
 }  // namespace piv

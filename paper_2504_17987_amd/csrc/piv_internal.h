@@ -12,12 +12,20 @@ namespace piv {
 
 constexpr int kMaxLevels = 6;
 
+// Every pyramid level (level 0 included, as a copy of the input) lives in
+// the workspace with a zero margin of `margin` pixels on all four sides,
+// wide enough for the level's whole search reach, so that the SAD kernels
+// read without bounds checks.
 struct Level {
   int W, H;           // level image size (px)
-  int pitch;          // bytes per row in the workspace (levels >= 1)
+  int margin;         // zero border (px); a multiple of 4
+  int pitch;          // bytes per padded row (multiple of 64)
+  int rows;           // padded rows: H + 2 margin
+  int R;              // search radius on this level
   int nx, ny;         // level node grid
-  size_t off_a, off_b;  // per-pair offset of the level images (levels >= 1)
+  size_t off_a, off_b;  // per-pair offset of the padded images (row 0 of the margin)
   size_t off_d;         // per-pair offset of the level's int32 [2][ny][nx] field
+  size_t origin() const { return (size_t)margin * pitch; }  // + margin * es for the column
 };
 
 struct Plan {

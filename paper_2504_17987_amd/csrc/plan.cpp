@@ -122,16 +122,32 @@ piv_status piv_plan(const piv_params* pp, piv_plan_t* out) {
   for (int l = 0; l < P->L; ++l) {
     piv::Level& v = P->lv[l];
     if (l == 0) {
-      v.W = p.width; v.H = p.height; v.nx = P->nx; v.ny = P->ny; v.pitch = 0;
-      v.off_a = v.off_b = 0;
+      v.W = p.width; v.H = p.height; v.nx = P->nx; v.ny = P->ny;
     } else {
       const piv::Level& u = P->lv[l - 1];
       v.W = (u.W + 1) / 2; v.H = (u.H + 1) / 2;
       v.nx = (u.nx + 1) / 2; v.ny = (u.ny + 1) / 2;
-      v.pitch = (int)((size_t)(v.W * es + 63) & ~size_t(63));
-      v.off_a = off; off = align256(off + (size_t)v.pitch * v.H);
-      v.off_b = off; off = align256(off + (size_t)v.pitch * v.H);
     }
+    v.R = l == P->L - 1 ? p.radius_coarse : p.radius_fine;
+  }
+  // search reach per level: |cand_l| <= 2 maxd_{l+1}, maxd_l = R_l + |cand_l|
+  int maxd = 0;
+  for (int l = P->L - 1; l >= 0; --l) {
+    piv::Level& v = P->lv[l];
+    int cand = l == P->L - 1 ? 0 : 2 * maxd;
+    maxd = cand + v.R;
+    // node grid may overhang the image by < step; block offset (block-step)/2;
+    // word-granular loads read up to 8 bytes past the search span
+    int m = p.step + (block - p.step) / 2 + cand + v.R + 8;
+    v.margin = (m + 3) & ~3;
+    v.pitch = (int)((size_t)((v.W + 2 * v.margin) * es + 63) & ~size_t(63));
+    v.rows = v.H + 2 * v.margin;
+  }
+  for (int l = 0; l < P->L; ++l) {
+    piv::Level& v = P->lv[l];
+    if (p.dtype == PIV_F32) { v.off_a = v.off_b = 0; continue; }   // no predictor on F32 plans
+    v.off_a = off; off = align256(off + (size_t)v.pitch * v.rows);
+    v.off_b = off; off = align256(off + (size_t)v.pitch * v.rows);
   }
   for (int l = 0; l < P->L; ++l) {
     piv::Level& v = P->lv[l];
@@ -189,8 +205,7 @@ piv_status piv_predict(piv_plan_t plan, const void* A, const void* B, int64_t pi
   if (P.p.dtype == PIV_F32) return fail(PIV_EUNSUPPORTED, "the predictor takes U8/U16 frames");
   if (piv_status s = need_ws(P, n)) return s;
   if (n == 0) return PIV_OK;
-  if (P.L > 1)
-    if (piv_status s = dev(piv::launch_pyramid(P, A, B, pitch, n, stream), "pyramid")) return s;
+  if (piv_status s = dev(piv::launch_pyramid(P, A, B, pitch, n, stream), "pyramid")) return s;
   for (int l = P.L - 1; l >= 0; --l)
     if (piv_status s = dev(piv::launch_sad_level(P, l, A, B, pitch, n, stream), "sad_search")) return s;
   return dev(piv::launch_pred_out(P, n, pred, stream), "pred_out");
@@ -279,5 +294,18 @@ const char* piv_last_error(void) { return g_err; }
 // Not part of the public header: which correlation kernel a plan selects
 // (0 = generic per-window, 1 = cell-shared tiled).  Used by tests and bench.
 int piv_debug_correct_impl(piv_plan_t plan) { return plan ? piv::correct_impl(*cplan(plan)) : -1; }
+
+// Not part of the public header: geometry of pyramid level l, for host-side
+// checks of the kernels' read extents.  out: W, H, margin, pitch, rows, R,
+// nx, ny, es, step, block.  Returns 0, or -1 for a bad level.
+int piv_debug_level(piv_plan_t plan, int32_t l, int32_t* out) {
+  if (!plan || !out) return -1;
+  const Plan& P = *cplan(plan);
+  if (l < 0 || l >= P.L) return -1;
+  const piv::Level& v = P.lv[l];
+  int32_t vals[11] = {v.W, v.H, v.margin, v.pitch, v.rows, v.R, v.nx, v.ny, P.es, P.p.step, P.block};
+  for (int i = 0; i < 11; ++i) out[i] = vals[i];
+  return 0;
+}
 
 }  // extern "C"

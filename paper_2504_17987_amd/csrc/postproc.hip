@@ -29,8 +29,9 @@ __global__ __launch_bounds__(256) void k_uod_detect(const float* field, const ui
     mask[i] = 1;
     return;
   }
-  float v[2][8] = {{0, 0, 0, 0, 0, 0, 0, 0}, {0, 0, 0, 0, 0, 0, 0, 0}};
-  int k = 0;
+  // neighbours in static slots; unusable ones hold a sentinel that sorts last
+  float v[2][8];
+  int k = 0, slot = 0;
 #pragma unroll
   for (int di = -1; di <= 1; ++di)
 #pragma unroll
@@ -39,14 +40,10 @@ __global__ __launch_bounds__(256) void k_uod_detect(const float* field, const ui
       int y = a + di, x = b + dj;
       bool ok = y >= 0 && x >= 0 && y < ny && x < nx;
       if (ok && FL) ok = !(FL[y * nx + x] & kInvalid);
-      float u0 = ok ? F[y * nx + x] : 0.0f, v0 = ok ? F[np + y * nx + x] : 0.0f;
-#pragma unroll
-      for (int s = 0; s < 8; ++s)
-        if (ok && s == k) {
-          v[0][s] = u0;
-          v[1][s] = v0;
-        }
+      v[0][slot] = ok ? F[y * nx + x] : kSlotF;
+      v[1][slot] = ok ? F[np + y * nx + x] : kSlotF;
       k += ok;
+      ++slot;
     }
   uint8_t out = 0;
   if (k > 0) {
@@ -56,10 +53,12 @@ __global__ __launch_bounds__(256) void k_uod_detect(const float* field, const ui
       float vals[8], res[8];
 #pragma unroll
       for (int s = 0; s < 8; ++s) vals[s] = v[c][s];
-      float um = median_f<8>(vals, k);
 #pragma unroll
-      for (int s = 0; s < 8; ++s) res[s] = fabsf(vals[s] - um);
-      float rm = median_f<8>(res, k);
+      for (int s = 0; s < 8; ++s) res[s] = v[c][s];
+      float um = median8_f(vals, k);
+#pragma unroll
+      for (int s = 0; s < 8; ++s) res[s] = fabsf(res[s] - um);
+      float rm = median8_f(res, k);
       float r0 = fabsf(F[c * np + i] - um) / (rm + eps);
       worst = fmaxf(worst, r0);
     }
@@ -85,8 +84,8 @@ __global__ __launch_bounds__(256) void k_uod_replace(float* field, uint8_t* flag
   uint8_t* FL = flags ? flags + (int64_t)pair * np : nullptr;
   const uint8_t* mask = ws + (int64_t)pair * ws_stride + off_mask;
   if (!mask[i]) return;
-  float v[2][8] = {{0, 0, 0, 0, 0, 0, 0, 0}, {0, 0, 0, 0, 0, 0, 0, 0}};
-  int k = 0;
+  float v[2][8];
+  int k = 0, slot = 0;
 #pragma unroll
   for (int di = -1; di <= 1; ++di)
 #pragma unroll
@@ -94,14 +93,10 @@ __global__ __launch_bounds__(256) void k_uod_replace(float* field, uint8_t* flag
       if (di == 0 && dj == 0) continue;
       int y = a + di, x = b + dj;
       bool ok = y >= 0 && x >= 0 && y < ny && x < nx && !mask[y * nx + x];
-      float u0 = ok ? F[y * nx + x] : 0.0f, v0 = ok ? F[np + y * nx + x] : 0.0f;
-#pragma unroll
-      for (int s = 0; s < 8; ++s)
-        if (ok && s == k) {
-          v[0][s] = u0;
-          v[1][s] = v0;
-        }
+      v[0][slot] = ok ? F[y * nx + x] : kSlotF;
+      v[1][slot] = ok ? F[np + y * nx + x] : kSlotF;
       k += ok;
+      ++slot;
     }
   uint8_t fl = PIV_F_OUTLIER;
   if (k == 0) {
@@ -113,8 +108,8 @@ __global__ __launch_bounds__(256) void k_uod_replace(float* field, uint8_t* flag
       vu[s] = v[0][s];
       vv[s] = v[1][s];
     }
-    F[i] = median_f<8>(vu, k);
-    F[np + i] = median_f<8>(vv, k);
+    F[i] = median8_f(vu, k);
+    F[np + i] = median8_f(vv, k);
     fl |= PIV_F_REPLACED;
   }
   if (FL) FL[i] |= fl;

@@ -1,9 +1,14 @@
-// Predictor kernels: 2x2 pyramid, per-level integer SAD block search with
+// Predictor kernels: padded pyramid, per-level integer SAD block search with
 // a packed-key argmin, and the final 3x3 median to the float field.
 //
 // The predictor stands where the paper (Sec. 2) uses a fixed-function
 // optical-flow engine: a coarse, integer-accurate displacement estimate
 // that the correlation stage then corrects.
+//
+// Every level, level 0 included (a copy of the input), is stored in the
+// workspace with a zero margin wide enough for the level's whole search
+// reach (see Level in piv_internal.h): the SAD kernels read aligned words
+// with no bounds checks, and zero outside the image comes from the margin.
 #include "dev_common.h"
 #include "piv_internal.h"
 
@@ -11,58 +16,82 @@ namespace piv {
 namespace {
 
 // ---------------------------------------------------------------------------
-// Pyramid: out(y,x) = floor((in(2y,2x) + in(2y,2x+1) + in(2y+1,2x) + in(2y+1,2x+1) + 2) / 4),
-// zero outside the input.  One thread writes 4 consecutive output pixels of
-// one frame; the grid covers the output pitch so that the pad columns are
-// written (as zeros).
+// Padded copy of level 0: one thread per 4-byte word of the padded image;
+// words outside the image core are zero.
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(256) void k_pyr_down(const uint8_t* __restrict__ srcA,
-                                                  const uint8_t* __restrict__ srcB, int64_t spitch,
-                                                  int64_t sstride, int sW, int sH, uint8_t* dst,
-                                                  int64_t dA, int64_t dB, int dpitch, int64_t dstride,
-                                                  int dH, const uint8_t* mask) {
+__global__ __launch_bounds__(256) void k_pad_copy(const uint8_t* __restrict__ A, const uint8_t* __restrict__ B,
+                                                  int64_t spitch, int64_t sstride, int rowbytes, int H,
+                                                  uint8_t* ws, int64_t offA, int64_t offB, int dpitch,
+                                                  int drows, int mbytes, int mrows, int64_t dstride,
+                                                  const uint8_t* mask) {
   const int pair = blockIdx.z >> 1, frame = blockIdx.z & 1;
   if (slot_off(mask, pair)) return;
-  const int y = blockIdx.y * blockDim.y + threadIdx.y;
-  const int x0 = (blockIdx.x * blockDim.x + threadIdx.x) * 4;
-  const int dcols = dpitch / (int)sizeof(T);
-  if (y >= dH || x0 >= dcols) return;
-  const uint8_t* src = (frame ? srcB : srcA) + (int64_t)pair * sstride;
-  T* out = reinterpret_cast<T*>(dst + (int64_t)pair * dstride + (frame ? dB : dA) + (int64_t)y * dpitch);
+  const int nq = dpitch / 16;                     // 16-byte chunks per padded row
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = idx / nq;                         // padded row
+  const int q = idx - y * nq;
+  if (y >= drows) return;
+  const int sy = y - mrows;
+  uint4 v = make_uint4(0u, 0u, 0u, 0u);
+  if (sy >= 0 && sy < H) {
+    const uint8_t* row = (frame ? B : A) + (int64_t)pair * sstride + (int64_t)sy * spitch;
+    const int xb = q * 16 - mbytes;                // byte offset in the source row
+    const int xa = xb & ~3, sh = xb & 3;
+    uint32_t w[5];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    int x = x0 + i;
-    if (x >= dcols) break;
-    uint32_t s = 0;
-#pragma unroll
-    for (int dy = 0; dy < 2; ++dy)
-#pragma unroll
-      for (int dx = 0; dx < 2; ++dx) {
-        int sy = 2 * y + dy, sx = 2 * x + dx;
-        if (sy < sH && sx < sW) s += reinterpret_cast<const T*>(src + (int64_t)sy * spitch)[sx];
-      }
-    out[x] = (T)((s + 2u) >> 2);
+    for (int i = 0; i < 5; ++i) w[i] = masked_word(row, rowbytes, xa + 4 * i);
+    v.x = __builtin_amdgcn_alignbyte(w[1], w[0], sh);
+    v.y = __builtin_amdgcn_alignbyte(w[2], w[1], sh);
+    v.z = __builtin_amdgcn_alignbyte(w[3], w[2], sh);
+    v.w = __builtin_amdgcn_alignbyte(w[4], w[3], sh);
   }
+  uint8_t* out = ws + (int64_t)pair * dstride + (frame ? offB : offA) + (int64_t)y * dpitch;
+  reinterpret_cast<uint4*>(out)[q] = v;
 }
 
 // ---------------------------------------------------------------------------
-// SAD block search on one level.
-//
-// Lanes: a group of G = 2R+1 lanes per node, lane k owning the column of
-// candidates dx = cand_x - R + k; NPW = 256/G nodes of one node row per
-// workgroup.  The node's A block is staged in LDS as packed words; every
-// lane streams the rows of frame B its column needs (aligned 4-byte loads,
-// realigned once per row with alignbyte), and accumulates, for each of its
-// G candidates dy, v_sad_u8 / v_sad_u16 over the row pairs.  The winner
-// minimises the packed key (SAD, |dx|+|dy|, dy, dx) -- a plain u64 min, so
-// the result does not depend on the reduction order.
+// Pyramid level from the padded level below:
+// out(y,x) = floor((in(2y,2x) + in(2y,2x+1) + in(2y+1,2x) + in(2y+1,2x+1) + 2) / 4)
+// with zero outside the input (its margin); the output margin is written as
+// zero.  One thread per pixel of the padded output.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_pyr_down(uint8_t* ws, int64_t stride, int64_t sA, int64_t sB,
+                                                  int spitch, int smargin, int64_t dA, int64_t dB, int dpitch,
+                                                  int dmargin, int dW, int dH, const uint8_t* mask) {
+  const int pair = blockIdx.z >> 1, frame = blockIdx.z & 1;
+  if (slot_off(mask, pair)) return;
+  const int Y = blockIdx.y * blockDim.y + threadIdx.y;      // padded output row
+  const int X = 4 * (blockIdx.x * blockDim.x + threadIdx.x);  // first of 4 padded output columns
+  const int dcols = dpitch / (int)sizeof(T);
+  if (Y >= dH + 2 * dmargin || X >= dcols) return;
+  uint8_t* base = ws + (int64_t)pair * stride;
+  const int y = Y - dmargin, x = X - dmargin;   // x is a multiple of 4 (margins are)
+  T v[4] = {0, 0, 0, 0};
+  if (y >= 0 && y < dH && x + 3 >= 0 && x < dW) {
+    // the 8 source pixels 2x .. 2x+7 of rows 2y, 2y+1 lie inside the
+    // source's padded extent (past its image they read its zero margin)
+    const uint8_t* src = base + (frame ? sB : sA) + (int64_t)smargin * spitch + (int64_t)smargin * sizeof(T);
+    const T* r0 = reinterpret_cast<const T*>(src + (int64_t)(2 * y) * spitch) + 2 * x;
+    const T* r1 = reinterpret_cast<const T*>(src + (int64_t)(2 * y + 1) * spitch) + 2 * x;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      uint32_t s = (uint32_t)r0[2 * i] + r0[2 * i + 1] + r1[2 * i] + r1[2 * i + 1];
+      v[i] = (x + i >= 0 && x + i < dW) ? (T)((s + 2u) >> 2) : (T)0;
+    }
+  }
+  T* out = reinterpret_cast<T*>(base + (frame ? dB : dA) + (int64_t)Y * dpitch) + X;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) out[i] = v[i];
+}
+
+// ---------------------------------------------------------------------------
+// Shared by the SAD kernels
 // ---------------------------------------------------------------------------
 struct SadArgs {
-  const uint8_t* A;   // level image base (pair 0)
+  const uint8_t* A;   // padded level image, pair 0, at the core origin (0, 0)
   const uint8_t* B;
   int64_t pitch, stride;
-  int W, H;           // level image size (px)
   int nx, ny;         // level grid
   int step, block, R;
   const int32_t* parent;  // parent level field [.][2][pny][pnx] or null (coarsest)
@@ -72,7 +101,7 @@ struct SadArgs {
   int32_t* out;           // this level's field
   int64_t ostride;        // int32 elements per pair
   const uint8_t* mask;
-  int npw;                // nodes per workgroup
+  int npw;                // nodes per workgroup (k_sad)
 };
 
 template <int ES>
@@ -81,11 +110,20 @@ __device__ __forceinline__ uint32_t sad_word(uint32_t a, uint32_t b, uint32_t c)
   else return __builtin_amdgcn_sad_u16(a, b, c);
 }
 
-__device__ __forceinline__ int parent_value(const SadArgs& g, const int32_t* par, int comp, int pa,
-                                            int pb) {
+// 4-byte word of a padded row at a (possibly unaligned) byte offset
+__device__ __forceinline__ uint32_t word_at(const uint8_t* row, int xb) {
+  const int xa = xb & ~3, sh = xb & 3;
+  const uint32_t* p = reinterpret_cast<const uint32_t*>(row + xa);
+  return __builtin_amdgcn_alignbyte(p[1], p[0], sh);
+}
+
+// Candidate centre component: twice the parent node's result, through the
+// 3x3 median of the parent level when enabled (the median after the parent
+// level, taken where it is read).
+__device__ __forceinline__ int parent_value(const SadArgs& g, const int32_t* par, int comp, int pa, int pb) {
   const int32_t* P = par + (int64_t)comp * g.pnx * g.pny;
   if (!g.median) return P[pa * g.pnx + pb];
-  int v[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  int v[9];
   int k = 0;
 #pragma unroll
   for (int i = -1; i <= 1; ++i)
@@ -93,19 +131,30 @@ __device__ __forceinline__ int parent_value(const SadArgs& g, const int32_t* par
     for (int j = -1; j <= 1; ++j) {
       int y = pa + i, x = pb + j;
       bool in = y >= 0 && x >= 0 && y < g.pny && x < g.pnx;
-      int val = in ? P[y * g.pnx + x] : 0;
-      // pack the in-bounds values to the front (static indices)
-#pragma unroll
-      for (int s = 0; s < 9; ++s)
-        if (in && s == k) v[s] = val;
+      v[(i + 1) * 3 + j + 1] = in ? P[y * g.pnx + x] : kSlotI;
       k += in;
     }
-  return median_low_i<9>(v, k);
+  return median9_low_i(v, k);
 }
 
+__device__ __forceinline__ unsigned long long sad_key(uint32_t sad, int dy, int dx) {
+  const unsigned l1 = (unsigned)(abs(dx) + abs(dy));
+  return ((unsigned long long)sad << 25) | ((unsigned long long)l1 << 16) |
+         ((unsigned long long)(dy + 128) << 8) | (unsigned long long)(dx + 128);
+}
+
+// ---------------------------------------------------------------------------
+// SAD block search, general form: a group of G = 2R+1 lanes per node, lane k
+// owning the candidate column dx = cand_x - R + k; npw nodes of one node row
+// per workgroup.  The node's A block is staged in LDS as packed words; every
+// lane streams the rows of B its column needs (realigned to its dx), and
+// accumulates, for each of its G candidates dy, v_sad_u8 / v_sad_u16.  The
+// winner minimises the packed key (SAD, |dx|+|dy|, dy, dx): a plain u64
+// min, independent of the reduction order.
+// ---------------------------------------------------------------------------
 template <int ES, int NW, int KMAX>
 __global__ __launch_bounds__(256) void k_sad(SadArgs g) {
-  extern __shared__ uint32_t s_ablk[];        // [NPW][block][NW]
+  extern __shared__ uint32_t s_ablk[];        // [npw][block][NW]
   __shared__ unsigned long long s_key[256];
 
   const int pair = blockIdx.z;
@@ -120,29 +169,17 @@ __global__ __launch_bounds__(256) void k_sad(SadArgs g) {
   const bool active = j < npw && b < g.nx;
   const int off = (g.step - g.block) / 2;
   const int oy = a * g.step + off;
-  const int rowbytes = g.W * ES;
   const uint8_t* Ab = g.A + (int64_t)pair * g.stride;
   const uint8_t* Bb = g.B + (int64_t)pair * g.stride;
 
-  // stage the A blocks of this workgroup's nodes (unaligned spans -> words)
   const int nblk = min(npw, g.nx - b0);
   const int words = g.block * NW;
   for (int idx = t; idx < nblk * words; idx += 256) {
     int jj = idx / words, r = (idx / NW) % g.block, w = idx % NW;
-    int y = oy + r;
-    uint32_t val = 0;
-    if (y >= 0 && y < g.H) {
-      const uint8_t* row = Ab + (int64_t)y * g.pitch;
-      int xb = ((b0 + jj) * g.step + off) * ES + 4 * w;
-      int xa = xb & ~3, sh = xb & 3;
-      uint32_t lo = masked_word(row, rowbytes, xa);
-      uint32_t hi = sh ? masked_word(row, rowbytes, xa + 4) : 0u;
-      val = sh ? __builtin_amdgcn_alignbyte(hi, lo, sh) : lo;
-    }
-    s_ablk[idx] = val;
+    const uint8_t* row = Ab + (int64_t)(oy + r) * g.pitch;
+    s_ablk[idx] = word_at(row, ((b0 + jj) * g.step + off) * ES + 4 * w);
   }
 
-  // candidate centre: twice the (median-filtered) parent result
   int cx = 0, cy = 0;
   if (g.parent && active) {
     const int32_t* par = g.parent + (int64_t)pair * g.pstride;
@@ -164,19 +201,13 @@ __global__ __launch_bounds__(256) void k_sad(SadArgs g) {
     const uint32_t* ablk = s_ablk + j * words;
     const int nrows = g.block + 2 * g.R;
     for (int rb = 0; rb < nrows; ++rb) {
-      const int y = by0 + rb;
+      const uint32_t* row = reinterpret_cast<const uint32_t*>(Bb + (int64_t)(by0 + rb) * g.pitch + xa);
+      uint32_t w[NW + 1];
+#pragma unroll
+      for (int i = 0; i <= NW; ++i) w[i] = row[i];
       uint32_t bw[NW];
-      if (y >= 0 && y < g.H) {
-        const uint8_t* row = Bb + (int64_t)y * g.pitch;
-        uint32_t w[NW + 1];
 #pragma unroll
-        for (int i = 0; i <= NW; ++i) w[i] = masked_word(row, rowbytes, xa + 4 * i);
-#pragma unroll
-        for (int i = 0; i < NW; ++i) bw[i] = sh ? __builtin_amdgcn_alignbyte(w[i + 1], w[i], sh) : w[i];
-      } else {
-#pragma unroll
-        for (int i = 0; i < NW; ++i) bw[i] = 0u;
-      }
+      for (int i = 0; i < NW; ++i) bw[i] = __builtin_amdgcn_alignbyte(w[i + 1], w[i], sh);
 #pragma unroll
       for (int q = 0; q < KMAX; ++q) {
         const int ar = rb - q;
@@ -192,10 +223,7 @@ __global__ __launch_bounds__(256) void k_sad(SadArgs g) {
 #pragma unroll
     for (int q = 0; q < KMAX; ++q) {
       if (q < G) {
-        const int dy = cy - g.R + q;
-        const unsigned l1 = (unsigned)(abs(dx) + abs(dy));
-        unsigned long long key = ((unsigned long long)acc[q] << 25) | ((unsigned long long)l1 << 16) |
-                                 ((unsigned long long)(dy + 128) << 8) | (unsigned long long)(dx + 128);
+        unsigned long long key = sad_key(acc[q], cy - g.R + q, dx);
         best = key < best ? key : best;
       }
     }
@@ -209,6 +237,94 @@ __global__ __launch_bounds__(256) void k_sad(SadArgs g) {
     out[a * g.nx + b] = (int)(m & 0xff) - 128;
     out[g.nx * g.ny + a * g.nx + b] = (int)((m >> 8) & 0xff) - 128;
   }
+}
+
+// ---------------------------------------------------------------------------
+// SAD block search, one node per lane (small radii, u8 blocks of NW words).
+// The lane keeps (2R+1)^2 sums in registers and streams the block + 2R rows
+// of B once, fully unrolled so that the pairing of B rows with A rows is
+// static.  A row r is loaded just before B row r first needs it and dies
+// after B row r + 2R; each B row is realigned to the search origin once and
+// every shift dx is a further static alignbyte of the realigned words.
+// ---------------------------------------------------------------------------
+template <int NW, int R>
+__global__ __launch_bounds__(256) void k_sad_lane(SadArgs g) {
+  constexpr int BLK = 4 * NW, G = 2 * R + 1;
+  constexpr int RW = NW + (2 * R + 3) / 4 + 1;   // realigned words covering BLK + 2R bytes
+  const int pair = blockIdx.y;
+  if (slot_off(g.mask, pair)) return;
+  const int node = blockIdx.x * blockDim.x + threadIdx.x;
+  if (node >= g.nx * g.ny) return;
+  const int a = node / g.nx, b = node - a * g.nx;
+  const int off = (g.step - BLK) / 2;
+  const int oy = a * g.step + off, ox = b * g.step + off;
+  const uint8_t* Ab = g.A + (int64_t)pair * g.stride;
+  const uint8_t* Bb = g.B + (int64_t)pair * g.stride;
+  int cx = 0, cy = 0;
+  if (g.parent) {
+    const int32_t* par = g.parent + (int64_t)pair * g.pstride;
+    int pa = min(a >> 1, g.pny - 1), pb = min(b >> 1, g.pnx - 1);
+    cx = 2 * parent_value(g, par, 0, pa, pb);
+    cy = 2 * parent_value(g, par, 1, pa, pb);
+  }
+  uint32_t acc[G][G];
+#pragma unroll
+  for (int q = 0; q < G; ++q)
+#pragma unroll
+    for (int k = 0; k < G; ++k) acc[q][k] = 0u;
+  const int y0 = oy + cy - R, xs = ox + cx - R;
+  const int xa = xs & ~3, sh = xs & 3;
+  const int axa = ox & ~3, ash = ox & 3;
+  uint32_t av[BLK][NW];
+#pragma unroll
+  for (int rb = 0; rb < BLK + 2 * R; ++rb) {
+    if (rb < BLK) {
+      const uint32_t* row = reinterpret_cast<const uint32_t*>(Ab + (int64_t)(oy + rb) * g.pitch + axa);
+      uint32_t w[NW + 1];
+#pragma unroll
+      for (int i = 0; i <= NW; ++i) w[i] = row[i];
+#pragma unroll
+      for (int i = 0; i < NW; ++i) av[rb][i] = __builtin_amdgcn_alignbyte(w[i + 1], w[i], ash);
+    }
+    const uint32_t* row = reinterpret_cast<const uint32_t*>(Bb + (int64_t)(y0 + rb) * g.pitch + xa);
+    uint32_t w[RW + 1];
+#pragma unroll
+    for (int i = 0; i <= RW; ++i) w[i] = row[i];
+    uint32_t rw[RW];
+#pragma unroll
+    for (int i = 0; i < RW; ++i) rw[i] = __builtin_amdgcn_alignbyte(w[i + 1], w[i], sh);
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+      uint32_t bw[NW];
+#pragma unroll
+      for (int i = 0; i < NW; ++i) {
+        const int jj = (k >> 2) + i;
+        bw[i] = (k & 3) ? __builtin_amdgcn_alignbyte(rw[jj + 1], rw[jj], k & 3) : rw[jj];
+      }
+#pragma unroll
+      for (int q = 0; q < G; ++q) {
+        const int ar = rb - q;
+        if (ar >= 0 && ar < BLK) {
+          uint32_t s = acc[q][k];
+#pragma unroll
+          for (int i = 0; i < NW; ++i) s = __builtin_amdgcn_sad_u8(av[ar][i], bw[i], s);
+          acc[q][k] = s;
+        }
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  unsigned long long best = ~0ull;
+#pragma unroll
+  for (int q = 0; q < G; ++q)
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+      unsigned long long key = sad_key(acc[q][k], cy - R + q, cx - R + k);
+      best = key < best ? key : best;
+    }
+  int32_t* out = g.out + (int64_t)pair * g.ostride;
+  out[a * g.nx + b] = (int)(best & 0xff) - 128;
+  out[g.nx * g.ny + a * g.nx + b] = (int)((best >> 8) & 0xff) - 128;
 }
 
 // final level-0 field -> float predictor, through the 3x3 median when enabled
@@ -227,7 +343,7 @@ __global__ __launch_bounds__(256) void k_pred_out(const int32_t* d, int64_t dstr
     if (!median) {
       val = P[i];
     } else {
-      int v[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+      int v[9];
       int k = 0;
 #pragma unroll
       for (int di = -1; di <= 1; ++di)
@@ -235,13 +351,10 @@ __global__ __launch_bounds__(256) void k_pred_out(const int32_t* d, int64_t dstr
         for (int dj = -1; dj <= 1; ++dj) {
           int y = a + di, x = b + dj;
           bool in = y >= 0 && x >= 0 && y < ny && x < nx;
-          int w = in ? P[y * nx + x] : 0;
-#pragma unroll
-          for (int s = 0; s < 9; ++s)
-            if (in && s == k) v[s] = w;
+          v[(di + 1) * 3 + dj + 1] = in ? P[y * nx + x] : kSlotI;
           k += in;
         }
-      val = median_low_i<9>(v, k);
+      val = median9_low_i(v, k);
     }
     out[c * nx * ny + i] = (float)val;
   }
@@ -286,42 +399,47 @@ bool sad_supported(int block_words) {
 
 hipError_t launch_pyramid(const Plan& P, const void* A, const void* B, int64_t pitch, int n,
                           hipStream_t s) {
+  const Level& v0 = P.lv[0];
+  {
+    // one thread per 16-byte chunk of the padded image, rows x chunks flattened
+    dim3 grid(((v0.pitch / 16) * v0.rows + 255) / 256, 1, 2 * n);
+    hipLaunchKernelGGL(k_pad_copy, grid, dim3(256), 0, s, (const uint8_t*)A, (const uint8_t*)B, pitch,
+                       pitch * P.p.height, v0.W * P.es, v0.H, P.ws, (int64_t)v0.off_a, (int64_t)v0.off_b,
+                       v0.pitch, v0.rows, v0.margin * P.es, v0.margin, (int64_t)P.per_pair, P.slot_mask);
+    if (hipError_t e = hipGetLastError()) return e;
+  }
   for (int l = 1; l < P.L; ++l) {
     const Level& u = P.lv[l - 1];
     const Level& v = P.lv[l];
-    const uint8_t* sA = l == 1 ? (const uint8_t*)A : P.ws + u.off_a;
-    const uint8_t* sB = l == 1 ? (const uint8_t*)B : P.ws + u.off_b;
-    int64_t sp = l == 1 ? pitch : u.pitch;
-    int64_t ss = l == 1 ? pitch * P.p.height : (int64_t)P.per_pair;
-    int dcols = v.pitch / P.es;
+    const int dcols = v.pitch / P.es;
     dim3 blk(64, 4);
-    dim3 grid(((dcols + 3) / 4 + 63) / 64, (v.H + 3) / 4, 2 * n);
+    dim3 grid((dcols / 4 + 63) / 64, (v.rows + 3) / 4, 2 * n);
     if (P.es == 1)
-      hipLaunchKernelGGL(k_pyr_down<uint8_t>, grid, blk, 0, s, sA, sB, sp, ss, u.W, u.H, P.ws,
-                         (int64_t)v.off_a, (int64_t)v.off_b, v.pitch, (int64_t)P.per_pair, v.H, P.slot_mask);
+      hipLaunchKernelGGL(k_pyr_down<uint8_t>, grid, blk, 0, s, P.ws, (int64_t)P.per_pair, (int64_t)u.off_a,
+                         (int64_t)u.off_b, u.pitch, u.margin, (int64_t)v.off_a, (int64_t)v.off_b, v.pitch,
+                         v.margin, v.W, v.H, P.slot_mask);
     else
-      hipLaunchKernelGGL(k_pyr_down<uint16_t>, grid, blk, 0, s, sA, sB, sp, ss, u.W, u.H, P.ws,
-                         (int64_t)v.off_a, (int64_t)v.off_b, v.pitch, (int64_t)P.per_pair, v.H, P.slot_mask);
+      hipLaunchKernelGGL(k_pyr_down<uint16_t>, grid, blk, 0, s, P.ws, (int64_t)P.per_pair, (int64_t)u.off_a,
+                         (int64_t)u.off_b, u.pitch, u.margin, (int64_t)v.off_a, (int64_t)v.off_b, v.pitch,
+                         v.margin, v.W, v.H, P.slot_mask);
     if (hipError_t e = hipGetLastError()) return e;
   }
   return hipSuccess;
 }
 
-hipError_t launch_sad_level(const Plan& P, int l, const void* A, const void* B, int64_t pitch, int n,
-                            hipStream_t s) {
+hipError_t launch_sad_level(const Plan& P, int l, const void*, const void*, int64_t, int n, hipStream_t s) {
   const Level& v = P.lv[l];
   SadArgs g;
-  g.A = l == 0 ? (const uint8_t*)A : P.ws + v.off_a;
-  g.B = l == 0 ? (const uint8_t*)B : P.ws + v.off_b;
-  g.pitch = l == 0 ? pitch : v.pitch;
-  g.stride = l == 0 ? pitch * P.p.height : (int64_t)P.per_pair;
-  g.W = v.W;
-  g.H = v.H;
+  const size_t origin = (size_t)v.margin * v.pitch + (size_t)v.margin * P.es;
+  g.A = P.ws + v.off_a + origin;
+  g.B = P.ws + v.off_b + origin;
+  g.pitch = v.pitch;
+  g.stride = (int64_t)P.per_pair;
   g.nx = v.nx;
   g.ny = v.ny;
   g.step = P.p.step;
   g.block = P.block;
-  g.R = l == P.L - 1 ? P.p.radius_coarse : P.p.radius_fine;
+  g.R = v.R;
   if (l == P.L - 1) {
     g.parent = nullptr;
     g.pstride = 0;
@@ -337,8 +455,18 @@ hipError_t launch_sad_level(const Plan& P, int l, const void* A, const void* B, 
   g.out = reinterpret_cast<int32_t*>(P.ws + v.off_d);
   g.ostride = (int64_t)(P.per_pair / sizeof(int32_t));
   g.mask = P.slot_mask;
+  g.npw = 0;
   const int G = 2 * g.R + 1;
   const int NW = P.block * P.es / 4;
+  if (P.es == 1 && g.R <= 2 && (NW == 2 || NW == 3 || NW == 4)) {
+    dim3 grid((v.nx * v.ny + 255) / 256, n);
+#define PIV_SAD_LANE(NW_, R_) \
+  if (NW == NW_ && g.R == R_) { hipLaunchKernelGGL((k_sad_lane<NW_, R_>), grid, dim3(256), 0, s, g); return hipGetLastError(); }
+    PIV_SAD_LANE(4, 2) PIV_SAD_LANE(4, 1) PIV_SAD_LANE(4, 0)
+    PIV_SAD_LANE(3, 2) PIV_SAD_LANE(3, 1) PIV_SAD_LANE(3, 0)
+    PIV_SAD_LANE(2, 2) PIV_SAD_LANE(2, 1) PIV_SAD_LANE(2, 0)
+#undef PIV_SAD_LANE
+  }
   // nodes per workgroup: G lanes each, A blocks within 64 KiB of LDS
   const int npw = min(256 / G, 65536 / (P.block * NW * 4));
   g.npw = npw;

@@ -87,3 +87,72 @@ def test_workspace_and_argument_errors(L):
     # n = 0 is a no-op that succeeds
     assert lib.piv_vorticity(h, fake, fake, 0, None) == 0
     lib.piv_plan_destroy(h)
+
+
+def _levels(L, **kw):
+    s, h = plan(L, **kw)
+    assert s == 0, L.lib().piv_last_error()
+    lib = L.lib()
+    lib.piv_debug_level.argtypes = [C.c_void_p, C.c_int32, C.POINTER(C.c_int32)]
+    out = []
+    l = 0
+    while True:
+        buf = (C.c_int32 * 11)()
+        if lib.piv_debug_level(h, l, buf) != 0:
+            break
+        out.append(dict(zip("W H margin pitch rows R nx ny es step block".split(), list(buf))))
+        l += 1
+    lib.piv_plan_destroy(h)
+    return out
+
+
+PLANS = [
+    dict(),                                                                   # 1 MP, 16/8, L3, 6/2
+    dict(width=256, height=256, win=32, step=16, radius=8, levels=1, radius_coarse=8),
+    dict(width=3840, height=2160, dtype=2, bit_depth=12, win=24, step=12, levels=3),
+    dict(width=200, height=136, levels=3, radius_coarse=5),
+    dict(width=2048, height=2048),
+    dict(width=1000, height=504, levels=4, radius_coarse=4, radius_fine=3),
+    dict(width=96, height=40, win=24, step=8, block=16, levels=2, radius_coarse=16, radius_fine=16),
+    dict(width=512, height=512, levels=6, radius_coarse=3, radius_fine=1),
+    dict(width=64, height=64, win=8, step=8, block=8, levels=1, radius_coarse=0),
+]
+
+
+@pytest.mark.parametrize("kw", PLANS)
+def test_padded_pyramid_holds_every_sad_read(L, kw):
+    """Every byte the SAD kernels and the pyramid read lies inside the padded
+    level buffer, for the largest candidate centre the level can see."""
+    lv = _levels(L, **kw)
+    maxd_parent = 0
+    for l in range(len(lv) - 1, -1, -1):
+        v = lv[l]
+        es, step, blk, R, M = v["es"], v["step"], v["block"], v["R"], v["margin"]
+        cand = 0 if l == len(lv) - 1 else 2 * maxd_parent
+        maxd_parent = cand + R
+        off = (step - blk) // 2
+        NW = blk * es // 4
+        # rows: A block rows and B search rows over all nodes and candidates
+        rmin = off - cand - R
+        rmax = (v["ny"] - 1) * step + off + blk - 1 + cand + R
+        assert rmin + M >= 0 and rmax + M < v["rows"], (l, v)
+        # columns in bytes; word loads start at the floor multiple of 4
+        xmin = (off - cand - R) * es
+        assert (xmin + M * es) - 3 >= 0, (l, v)
+        if es == 1 and R <= 2 and NW in (2, 3, 4):
+            # one node per lane: from the floor word of the leftmost shift,
+            # RW + 1 words with RW = NW + (2R+3)//4 + 1
+            start = ((v["nx"] - 1) * step + off + cand - R) * es
+            span = 4 * (NW + (2 * R + 3) // 4 + 2)
+        else:
+            # G lanes per node: each from the floor word of its own shift, NW + 1 words
+            start = ((v["nx"] - 1) * step + off + cand + R) * es
+            span = 4 * (NW + 1)
+        assert ((start + M * es) & ~3) + span <= v["pitch"], (l, v)
+        # the A block itself (k_sad word_at reads 8 bytes from its floor word)
+        assert ((((v["nx"] - 1) * step + off) * es + 4 * (NW - 1) + M * es) & ~3) + 8 <= v["pitch"]
+        # pyramid: level l reads rows/cols up to 2*size - 1 of level l-1 (one into the margin)
+        if l > 0:
+            u = lv[l - 1]
+            assert 2 * v["H"] - 1 < u["H"] + u["margin"] and 2 * v["W"] - 1 < u["W"] + u["margin"]
+        assert v["pitch"] % 64 == 0 and M % 4 == 0
