@@ -9,8 +9,11 @@ vectors; +-4 px correction search; 3-level predictor with radii 6/2).
 Prints ONE JSON line with pairs/s (value), Mvectors/s, p50/p99 latency of
 the batched step and of a single pair, the HBM-roofline fraction of the
 whole step, the roofline of the dominant kernel (the correlation stage)
-measured with HIP events on its stream, and the FP64 CPU oracle timed on
-a bounded sample of the same workload.
+measured with HIP events on its stream, the FP64 CPU oracle timed on a
+bounded sample of the same workload, and the other forms of the path:
+HIP-graph batches of 8, continuous batching of a served mix of sizes
+against the plain per-pair FIFO form on the same arrival trace, a stream
+of 4K u16 pairs in graph batches of 8, and the differentiable SSD.
 """
 from __future__ import annotations
 
@@ -38,6 +41,8 @@ def parse():
     ap.add_argument("--distinct", type=int, default=8, help="distinct rendered pairs in the batch")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-latency", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the graph/serving/stream/SSD forms")
+    ap.add_argument("--serve-seconds", type=float, default=3.0)
     ap.add_argument("--quiet", action="store_true")
     return ap.parse_args()
 
@@ -56,12 +61,11 @@ def algorithmic(W, H, nx, ny, r):
     combine_flop = 25.0 * S * nx * ny       # window sums -> coefficient, argmax
     warp_flop = 20.0 * W * H                # bilinear deformation of B
     corr_flop = xcorr_flop + combine_flop + warp_flop
-    corr_bytes = 2.0 * W * H + nx * ny * (2 * 4 + 2 * 4 + 4 + 1)   # A, B, pred in, disp, peak, flags
     path_bytes = 2.0 * W * H + nx * ny * 17.0  # A, B in; disp 8, flags 1, omega 4, peak 4 out
-    return dict(corr_flop=corr_flop, corr_bytes=corr_bytes, path_bytes=path_bytes)
+    return dict(corr_flop=corr_flop, path_bytes=path_bytes)
 
 
-def cpu_baseline(A, B, plan_kw, log_fn):
+def cpu_baseline(A, B, log_fn):
     """The FP64 oracle (as it stands) on a bounded sample of one pair: the
     full predictor, then the correction on a 512-row strip (8192 of the
     16384 windows), validation and vorticity on the full grid; seconds per
@@ -74,12 +78,10 @@ def cpu_baseline(A, B, plan_kw, log_fn):
     t_pred = time.perf_counter() - t0
     rows = 64
     strip = slice(256, 768)
-    # a strip of the image with its predictor rows; windows of the strip see
-    # their true neighbours except at the strip's top and bottom rows
     As, Bs = A[strip], B[strip]
     ps = np.ascontiguousarray(pred[:, 32:32 + rows])
     t0 = time.perf_counter()
-    disp, peak, flags = oracle.correct(As, Bs, 16, 8, 4, ps)
+    oracle.correct(As, Bs, 16, 8, 4, ps)
     t_corr = (time.perf_counter() - t0) * (A.shape[0] // 8) / rows
     t0 = time.perf_counter()
     full = np.zeros((2, A.shape[0] // 8, W // 8))
@@ -93,6 +95,146 @@ def cpu_baseline(A, B, plan_kw, log_fn):
     return {"value": round(1.0 / sec, 5), "unit": "pairs/s", "cores": cores, "kind": "oracle",
             "sample": "one 1024x1024 pair: full predictor + validation + vorticity; correction on a "
                       "512-row strip (8192 of 16384 windows) scaled x2"}
+
+
+def events(torch, n):
+    return [torch.cuda.Event(enable_timing=True) for _ in range(n)]
+
+
+def graph_batched(torch, api, A, B, kw, args):
+    """Config-2 pairs through one captured HIP graph of 8 slots."""
+    from paper_2504_17987_amd.serve import GraphRunner
+    run = GraphRunner(api.Plan(1024, 1024, max_batch=8, **kw), 8)
+    run.capture()
+    n = A.shape[0]
+    reps = max(8, args.steps)
+    for _ in range(3):
+        run.replay(8)
+    torch.cuda.synchronize()
+    ev = events(torch, reps + 1)
+    ev[0].record(run.stream)
+    for k in range(reps):
+        lo = (8 * k) % n
+        with torch.cuda.stream(run.stream):
+            run.A.copy_(A[lo:lo + 8])
+            run.B.copy_(B[lo:lo + 8])
+        run.replay(8)
+        ev[k + 1].record(run.stream)
+    torch.cuda.synchronize()
+    ms = np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(reps)])
+    return {"slots": 8, "pairs_per_s": round(8 * reps / (ev[0].elapsed_time(ev[-1]) / 1e3), 1),
+            "replay_p50_ms": round(float(np.percentile(ms, 50)), 4),
+            "replay_p99_ms": round(float(np.percentile(ms, 99)), 4),
+            "includes": "device-to-device copy of the 8 input pairs into the graph's slots"}
+
+
+def served(torch, api, synth, kw, args, log_fn):
+    """The serving mix: 12 streams (4 x 512^2, 4 x 1024^2, 4 x 2048^2 u8;
+    solid-body or shear flows, 0.03 ppp), Poisson arrivals at 250/s each
+    (3,000 pairs/s offered), device-resident pairs; continuous batching with
+    per-class graphs on their own streams, against the plain per-pair form
+    (one eager run at a time in arrival order) on the same trace."""
+    from paper_2504_17987_amd.serve import latency_stats, make_gpu_server, poisson_trace, run_fifo, serve_trace
+    per = 2
+    sizes = {"s": (512, 512, 16), "m": (1024, 1024, 8), "l": (2048, 2048, 4)}
+    cls_of = {512: "s", 1024: "m", 2048: "l"}
+    stream_class, pairs = {}, {}
+    for s in range(12):
+        W = synth.CFG5_SIZES[s]
+        stream_class[s] = cls_of[W]
+        a, b = zip(*[synth.cfg5_pair(s, k)[:2] for k in range(per)])
+        pairs[s] = (torch.from_numpy(np.stack(a)).cuda(), torch.from_numpy(np.stack(b)).cuda())
+    free, _ = torch.cuda.mem_get_info()
+    sched, ex = make_gpu_server(sizes, pairs, stream_class, budget=int(0.5 * free), plan_kw=kw)
+    trace = poisson_trace(list(stream_class.items()), 250.0, args.serve_seconds, per, seed=5)
+    warm = poisson_trace(list(stream_class.items()), 250.0, 0.3, per, seed=6)
+    serve_trace(sched, warm, time.perf_counter, poll=0)
+    sched.finished.clear()
+    t0 = time.perf_counter()
+    serve_trace(sched, trace, time.perf_counter, poll=0, deadline=60.0 + 4 * args.serve_seconds)
+    torch.cuda.synchronize()
+    st = latency_stats(trace)
+    log_fn(f"served: {st['n']} pairs, p50 {st['p50_ms']:.3f} ms, p99 {st['p99_ms']:.3f} ms, "
+           f"{sched.batches} batches in {time.perf_counter() - t0:.2f} s")
+    # plain per-pair form on the same trace
+    plans = {c: api.Plan(W, H, max_batch=1, **kw) for c, (W, H, _) in sizes.items()}
+    for c, p in plans.items():
+        W, H, _ = sizes[c]
+        p._fifo_out = dict(pred=torch.empty((1, 2, p.ny, p.nx), device="cuda"),
+                           disp=torch.empty((1, 2, p.ny, p.nx), device="cuda"),
+                           peak=torch.empty((1, p.ny, p.nx), device="cuda"),
+                           flags=torch.empty((1, p.ny, p.nx), dtype=torch.uint8, device="cuda"),
+                           omega=torch.empty((1, p.ny, p.nx), device="cuda"))
+    fifo = [type(r)(r.rid, r.stream, r.cls, r.item, r.arrival) for r in trace]
+    run_fifo(lambda c: plans[c], pairs, fifo[: min(len(fifo), 50)], time.perf_counter)   # warm-up
+    fifo = [type(r)(r.rid, r.stream, r.cls, r.item, r.arrival) for r in trace]
+    run_fifo(lambda c: plans[c], pairs, fifo, time.perf_counter, deadline=120.0 + 10 * args.serve_seconds)
+    sf = latency_stats(fifo)
+    log_fn(f"plain FIFO: p50 {sf['p50_ms']:.3f} ms, p99 {sf['p99_ms']:.3f} ms")
+    r4 = lambda d: {k: (round(v, 4) if isinstance(v, float) else v) for k, v in d.items()}
+    return {"offered_pairs_per_s": 3000, "seconds": args.serve_seconds, "mix": "4x512^2, 4x1024^2, 4x2048^2 u8",
+            "continuous_batching": r4(st), "plain_per_pair_fifo": r4(sf), "batches": sched.batches}
+
+
+def stream_cfg3(torch, api, synth, log_fn, npairs=64, distinct=4):
+    """3840x2160 u16 (12-bit) pairs, 24/12 windows, graph batches of 8."""
+    from paper_2504_17987_amd.serve import GraphRunner
+    kw = dict(dtype="u16", win=24, step=12, radius=4, levels=3, radius_coarse=6, radius_fine=2)
+    prs = [synth.cfg3_pair(k) for k in range(distinct)]
+    A = torch.stack([torch.from_numpy(p[0].view(np.int16)) for p in prs]).cuda().view(torch.uint16)
+    B = torch.stack([torch.from_numpy(p[1].view(np.int16)) for p in prs]).cuda().view(torch.uint16)
+    run = GraphRunner(api.Plan(3840, 2160, max_batch=8, **kw), 8)
+    run.capture()
+    for i in range(8):
+        run.A[i].copy_(A[i % distinct])
+        run.B[i].copy_(B[i % distinct])
+    run.replay(8)
+    torch.cuda.synchronize()
+    reps = npairs // 8
+    ev = events(torch, reps + 1)
+    ev[0].record(run.stream)
+    for k in range(reps):
+        run.replay(8)
+        ev[k + 1].record(run.stream)
+    torch.cuda.synchronize()
+    ms = np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(reps)])
+    pps = 8 * reps / (ev[0].elapsed_time(ev[-1]) / 1e3)
+    log_fn(f"cfg3 stream: {pps:.0f} pairs/s, replay p50 {np.percentile(ms, 50):.3f} ms")
+    return {"pairs_per_s": round(pps, 1), "replay_p50_ms": round(float(np.percentile(ms, 50)), 4),
+            "replay_p99_ms": round(float(np.percentile(ms, 99)), 4), "slots": 8,
+            "mvec_per_s": round(pps * 320 * 180 / 1e6, 2)}
+
+
+def ssd_cfg4(torch, api, synth, log_fn, n=64, distinct=8):
+    """64 pairs of 512x512 f32, forward + backward of the windowed SSD."""
+    prs = [synth.cfg4_pair(k) for k in range(distinct)]
+    A = torch.stack([torch.from_numpy(prs[i % distinct][0]) for i in range(n)]).cuda()
+    B = torch.stack([torch.from_numpy(prs[i % distinct][1]) for i in range(n)]).cuda()
+    U = torch.stack([torch.from_numpy(synth.truth(prs[i % distinct][2], 512, 512, 8).astype(np.float32))
+                     for i in range(n)]).cuda()
+    P = api.Plan(512, 512, max_batch=n, dtype="f32", levels=1)
+    g = torch.ones((n, 64, 64), device="cuda")
+    loss = P.ssd_forward(A, B, U)
+    gU, D = P.ssd_backward(A, B, U, g)
+    torch.cuda.synchronize()
+    e = events(torch, 3)
+    reps = 20
+    e[0].record()
+    for _ in range(reps):
+        P.ssd_forward(A, B, U, loss)
+    e[1].record()
+    for _ in range(reps):
+        P.ssd_backward(A, B, U, g, gU, D)
+    e[2].record()
+    torch.cuda.synchronize()
+    f_ms, b_ms = e[0].elapsed_time(e[1]) / reps, e[1].elapsed_time(e[2]) / reps
+    img = 512 * 512 * 4
+    fwd_bytes = n * (2 * img + 2 * 64 * 64 * 4 + 64 * 64 * 4)
+    bwd_bytes = n * (2 * img + 2 * 64 * 64 * 4 + 64 * 64 * 4 + 4 * 64 * 64 * 4)
+    gbs = (fwd_bytes + bwd_bytes) / ((f_ms + b_ms) / 1e3) / 1e9
+    log_fn(f"ssd: forward {f_ms:.3f} ms, backward {b_ms:.3f} ms, {gbs:.0f} GB/s algorithmic")
+    return {"batch": n, "forward_ms": round(f_ms, 4), "backward_ms": round(b_ms, 4),
+            "achieved_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
 
 
 def main():
@@ -127,7 +269,7 @@ def main():
     for _ in range(args.warmup):
         plan.run(A, B, out)
     torch.cuda.synchronize()
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    ev = events(torch, args.steps + 1)
     t0 = time.perf_counter()
     ev[0].record(stream)
     for k in range(args.steps):
@@ -147,7 +289,7 @@ def main():
     for _ in range(3):
         plan.correct(A, B, pred, disp, peakb, flags)
     torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0, e1 = events(torch, 2)
     e0.record(stream)
     for _ in range(args.steps):
         plan.correct(A, B, pred, disp, peakb, flags)
@@ -169,7 +311,7 @@ def main():
         torch.cuda.synchronize()
         xs = []
         for _ in range(100):
-            s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            s0, s1 = events(torch, 2)
             s0.record(stream)
             p1.run(a1, b1, o1)
             s1.record(stream)
@@ -181,9 +323,18 @@ def main():
     lat.update({"batch_p50_ms": round(float(np.percentile(step_ms, 50)), 4),
                 "batch_p99_ms": round(float(np.percentile(step_ms, 99)), 4)})
 
+    forms = {}
+    if not args.no_extras:
+        lg = lambda *a: log(args, *a)
+        forms["graph_batched_cfg2"] = graph_batched(torch, api, A, B, kw, args)
+        lg(f"graph batches of 8: {forms['graph_batched_cfg2']['pairs_per_s']:.0f} pairs/s")
+        forms["served_cfg5"] = served(torch, api, synth, kw, args, lg)
+        forms["stream_cfg3"] = stream_cfg3(torch, api, synth, lg)
+        forms["ssd_cfg4"] = ssd_cfg4(torch, api, synth, lg)
+
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(pairs[0][0], pairs[0][1], kw, lambda *a: log(args, *a))
+        cpu = cpu_baseline(pairs[0][0], pairs[0][1], lambda *a: log(args, *a))
 
     path_gbs = alg["path_bytes"] * nb / (ms_per_step / 1e3) / 1e9
     line = {
@@ -211,7 +362,9 @@ def main():
         "roofline": {"kernel": "k_correct_tiled (deformation + correlation + fit)", "bound": "alu",
                      "achieved": round(corr_tflops, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(corr_tflops / FP32_PEAK_TFLOPS, 5), "traffic": None,
-                     "ms_per_launch": round(corr_ms, 4), "flop_per_pair": alg["corr_flop"]},
+                     "ms_per_launch": round(corr_ms, 4), "flop_per_pair": alg["corr_flop"],
+                     "pairs_per_launch": nb},
+        "forms": forms,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
