@@ -351,10 +351,12 @@ struct TileCfg {
   static constexpr int AW = CW * STEP, AH = CH * STEP;
   static constexpr int BW = AW + 2 * R, BH = AH + 2 * R;
   static constexpr int AP = AW + 4;   // LDS row pitches (floats)
-  static constexpr int BP = BW + 4;
-  static constexpr int NNX = BW / STEP + 3, NNY = BH / STEP + 3;
+  static constexpr int BP = (BW + 3) / 4 * 4 + 4;
+  static constexpr int NNX = BW / STEP + 4, NNY = BH / STEP + 3;
   static constexpr int IN_FLOATS = AH * AP + BH * BP;
-  static constexpr int RES_FLOATS = 3 * NC * NS;
+  static constexpr int BAND = (SYG * NSY + 3) / 4 * 4;   // shift band padded to 16 bytes
+  static constexpr int NSP = NG * BAND;                   // result slots per cell
+  static constexpr int RES_FLOATS = 3 * NC * NSP;
   // room for the raw source tile of B behind the A and B' tiles: what the
   // result arrays leave free, at least 16 KiB
   static constexpr int RAW_WORDS = RES_FLOATS - IN_FLOATS > 4096 ? RES_FLOATS - IN_FLOATS : 4096;
@@ -362,6 +364,7 @@ struct TileCfg {
   static constexpr int NWIN = TW * TH;
   static_assert(NSY % SYG == 0, "shift rows must split evenly");
   static_assert(STEP % 2 == 0, "50% overlap needs an even step");
+  static_assert(STEP >= 4, "a group of four pixels spans at most two node columns");
 };
 
 template <typename T, int STEP, int R, int SYG, int TW, int TH, int NT>
@@ -369,14 +372,13 @@ __global__ __launch_bounds__(NT) void k_correct_tiled(CorrArgs g) {
   using C = TileCfg<STEP, R, SYG, TW, TH>;
   static_assert(C::NG * C::NC <= NT, "one thread per (cell, shift band)");
   static_assert(4 * C::NWIN <= NT, "four threads per window");
-  __shared__ float s_u[C::UNION];
+  __shared__ __align__(16) float s_u[C::UNION];
   __shared__ float s_node[2][C::NNY][C::NNX];
   __shared__ float s_wsum[C::NWIN], s_wsq[C::NWIN];
   __shared__ float s_red[NT / 64];
   __shared__ float s_rng[NT / 64][4];
   __shared__ int s_rb[C::BH], s_cb[C::BW];
   __shared__ float s_rf[C::BH], s_cf[C::BW];
-  __shared__ float s_K;
 
   const int pair = blockIdx.z;
   if (slot_off(g.mask, pair)) return;
@@ -460,29 +462,31 @@ __global__ __launch_bounds__(NT) void k_correct_tiled(CorrArgs g) {
         fy * ((1.0f - fx) * s_node[1][rb + 1][cb] + fx * s_node[1][rb + 1][cb + 1]);
   };
 
-  // A tile (deformed by -u/2 in central mode) and its sum for the offset K
+  // A tile (deformed by -u/2 in central mode) in groups of four pixels,
+  // held in registers until the tile offset K is known
+  constexpr int AQ = C::AW / 4;
+  constexpr int NA = (C::AH * AQ + NT - 1) / NT;
+  float av[NA][4];
   float part = 0.0f;
-  if (g.central && Pn) {
-    for (int idx = t; idx < C::AH * C::AW; idx += NT) {
-      int r = idx / C::AW, q = idx % C::AW;
-      float u, w;
-      interp_tab(r + R, q + R, u, w);
-      float v = bilin<T>(Ai, g.pitch, g.W, g.H, (x0 + q) - 0.5f * u, (y0 + r) - 0.5f * w);
-      sA[r * C::AP + q] = v;
-      part += v;
-    }
-  } else {
-    // straight copy, four pixels per load
+  {
     const int rowbytes = g.W * (int)sizeof(T);
-    for (int idx = t; idx < C::AH * (C::AW / 4); idx += NT) {
-      int r = idx / (C::AW / 4), q = 4 * (idx % (C::AW / 4));
-      int y = y0 + r;
-      float v[4];
-      load4<T>(Ai, g.pitch, g.H, rowbytes, y, x0 + q, v);
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        sA[r * C::AP + q + k] = v[k];
-        part += v[k];
+    for (int i = 0; i < NA; ++i) {
+      const int idx = t + i * NT;
+      av[i][0] = av[i][1] = av[i][2] = av[i][3] = 0.0f;
+      if (idx < C::AH * AQ) {
+        const int r = idx / AQ, q = 4 * (idx - (idx / AQ) * AQ);
+        if (g.central && Pn) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            float u, w;
+            interp_tab(r + R, q + e + R, u, w);
+            av[i][e] = bilin<T>(Ai, g.pitch, g.W, g.H, (x0 + q + e) - 0.5f * u, (y0 + r) - 0.5f * w);
+          }
+        } else {
+          load4<T>(Ai, g.pitch, g.H, rowbytes, y0 + r, x0 + q, av[i]);
+        }
+        part += (av[i][0] + av[i][1]) + (av[i][2] + av[i][3]);
       }
     }
   }
@@ -512,38 +516,71 @@ __global__ __launch_bounds__(NT) void k_correct_tiled(CorrArgs g) {
     }
   }
   __syncthreads();
-  if (t == 0) {
-    float s = 0.0f;
+  // the tile offset K (every thread sums the per-wave partials itself)
+  float ksum = 0.0f;
 #pragma unroll
-    for (int i = 0; i < NT / 64; ++i) s += s_red[i];
-    s_K = rintf(s / (float)(C::AH * C::AW));
-  }
-  __syncthreads();
-  const float K = s_K;
-  for (int idx = t; idx < C::AH * C::AW; idx += NT) {
-    int r = idx / C::AW, q = idx % C::AW;
-    sA[r * C::AP + q] -= K;
+  for (int i = 0; i < NT / 64; ++i) ksum += s_red[i];
+  const float K = rintf(ksum / (float)(C::AH * C::AW));
+#pragma unroll
+  for (int i = 0; i < NA; ++i) {
+    const int idx = t + i * NT;
+    if (idx < C::AH * AQ) {
+      const int r = idx / AQ, q = 4 * (idx - (idx / AQ) * AQ);
+      *reinterpret_cast<float4*>(sA + r * C::AP + q) =
+          make_float4(av[i][0] - K, av[i][1] - K, av[i][2] - K, av[i][3] - K);
+    }
   }
   // deformed B' tile
   if (staged) {
+    // groups of four pixels of one row: the node row and its fraction are
+    // shared, and the group spans at most two node columns (STEP > 4), so
+    // the displacement is interpolated vertically at three node columns and
+    // then horizontally per pixel.  The deformed coordinates stay inside the
+    // raw box by its construction (a convex combination of cached nodes plus
+    // a one-pixel margin); the clamps only keep the padding columns of a
+    // ragged last group inside it.
+    constexpr int BQ = (C::BW + 3) / 4;
     const uint8_t* rawb = reinterpret_cast<const uint8_t*>(sraw);
     const int rowb = 4 * nwords, xoff = 4 * xw0;
-    auto rawpx = [&](int y, int x) -> float {
-      y = min(max(y, iy0), iy1);
-      x = min(max(x, ix0), ix1);
-      return (float)*reinterpret_cast<const T*>(rawb + (y - iy0) * rowb + (x * (int)sizeof(T) - xoff));
-    };
-    for (int idx = t; idx < C::BH * C::BW; idx += NT) {
-      int r = idx / C::BW, q = idx % C::BW;
-      float u = 0.0f, w = 0.0f;
-      if (Pn) interp_tab(r, q, u, w);
-      float qx = (float)(xb + q) + sgnB * u, qy = (float)(yb + r) + sgnB * w;
-      float fx0 = floorf(qx), fy0 = floorf(qy);
-      float fx = qx - fx0, fy = qy - fy0;
-      int ix = (int)fx0, iy = (int)fy0;
-      float p00 = rawpx(iy, ix), p01 = rawpx(iy, ix + 1), p10 = rawpx(iy + 1, ix), p11 = rawpx(iy + 1, ix + 1);
-      float v = (1.0f - fy) * ((1.0f - fx) * p00 + fx * p01) + fy * ((1.0f - fx) * p10 + fx * p11);
-      sB[r * C::BP + q] = v - K;
+    constexpr int ES = (int)sizeof(T);
+    auto rawv = [&](const uint8_t* p) -> float { return (float)*reinterpret_cast<const T*>(p); };
+    for (int idx = t; idx < C::BH * BQ; idx += NT) {
+      const int r = idx / BQ, q = 4 * (idx - (idx / BQ) * BQ);
+      float uu[4] = {0.0f, 0.0f, 0.0f, 0.0f}, vv[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+      if (Pn) {
+        const int rb = s_rb[r];
+        const float fy = s_rf[r];
+        const int cb0 = s_cb[q];
+        float Vu[3], Vv[3];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+          Vu[j] = (1.0f - fy) * s_node[0][rb][cb0 + j] + fy * s_node[0][rb + 1][cb0 + j];
+          Vv[j] = (1.0f - fy) * s_node[1][rb][cb0 + j] + fy * s_node[1][rb + 1][cb0 + j];
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int qq = min(q + e, C::BW - 1);
+          const bool nxt = s_cb[qq] != cb0;
+          const float fx = s_cf[qq];
+          const float ul = nxt ? Vu[1] : Vu[0], ur = nxt ? Vu[2] : Vu[1];
+          const float vl = nxt ? Vv[1] : Vv[0], vr = nxt ? Vv[2] : Vv[1];
+          uu[e] = (1.0f - fx) * ul + fx * ur;
+          vv[e] = (1.0f - fx) * vl + fx * vr;
+        }
+      }
+      float out[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const float qx = (float)(xb + q + e) + sgnB * uu[e], qy = (float)(yb + r) + sgnB * vv[e];
+        const float fx0 = floorf(qx), fy0 = floorf(qy);
+        const float fx = qx - fx0, fy = qy - fy0;
+        const int ix = min(max((int)fx0, ix0), ix1 - 1), iy = min(max((int)fy0, iy0), iy1 - 1);
+        const uint8_t* p0 = rawb + (iy - iy0) * rowb + (ix * ES - xoff);
+        const float p00 = rawv(p0), p01 = rawv(p0 + ES), p10 = rawv(p0 + rowb), p11 = rawv(p0 + rowb + ES);
+        const float top = (1.0f - fx) * p00 + fx * p01, bot = (1.0f - fx) * p10 + fx * p11;
+        out[e] = ((1.0f - fy) * top + fy * bot) - K;
+      }
+      *reinterpret_cast<float4*>(sB + r * C::BP + q) = make_float4(out[0], out[1], out[2], out[3]);
     }
   } else {
     for (int idx = t; idx < C::BH * C::BW; idx += NT) {
@@ -668,61 +705,88 @@ __global__ __launch_bounds__(NT) void k_correct_tiled(CorrArgs g) {
     }
   }
   __syncthreads();   // everyone is done with the A and B' tiles
+  // cell results in bands: band b holds the SYG*NSY shifts of shift rows
+  // [b SYG, (b+1) SYG), padded to BAND slots so that a band is written and
+  // read with 16-byte LDS operations
+  constexpr int BAND = C::BAND, NSP = C::NSP;
   float* resP = s_u;
-  float* resS = s_u + C::NC * C::NS;
-  float* resQ = s_u + 2 * C::NC * C::NS;
+  float* resS = s_u + C::NC * NSP;
+  float* resQ = s_u + 2 * C::NC * NSP;
   if (worker) {
+    float4* dP = reinterpret_cast<float4*>(resP + cell * NSP + grp * BAND);
+    float4* dS = reinterpret_cast<float4*>(resS + cell * NSP + grp * BAND);
+    float4* dQ = reinterpret_cast<float4*>(resQ + cell * NSP + grp * BAND);
 #pragma unroll
-    for (int k = 0; k < SYG; ++k)
+    for (int v4 = 0; v4 < BAND / 4; ++v4) {
+      float p4[4], s4[4], q4[4];
 #pragma unroll
-      for (int j = 0; j < C::NSY; ++j) {
-        int s = (grp * SYG + k) * C::NSY + j;
-        resP[cell * C::NS + s] = Pacc[k][j];
-        resS[cell * C::NS + s] = Sacc[k][j];
-        resQ[cell * C::NS + s] = Qacc[k][j];
+      for (int e = 0; e < 4; ++e) {
+        const int o = 4 * v4 + e;               // offset in the band
+        const bool real = o < SYG * C::NSY;
+        p4[e] = real ? Pacc[o / C::NSY][o % C::NSY] : 0.0f;
+        s4[e] = real ? Sacc[o / C::NSY][o % C::NSY] : 0.0f;
+        q4[e] = real ? Qacc[o / C::NSY][o % C::NSY] : 1.0f;
       }
+      dP[v4] = make_float4(p4[0], p4[1], p4[2], p4[3]);
+      dS[v4] = make_float4(s4[0], s4[1], s4[2], s4[3]);
+      dQ[v4] = make_float4(q4[0], q4[1], q4[2], q4[3]);
+    }
   }
   __syncthreads();
 
-  // ---- windows: four threads each, shifts s = p, p+4, ...
-  constexpr int PER = (C::NS + 3) / 4;
-  float rho[PER];
+  // ---- windows: four threads each; thread p < NG takes band p
+  float rho[BAND];
   float best = -2.0f;
   int bkey = 1 << 30, nflat = 0;
   const int w = t >> 2, p = t & 3;
   const bool wact = t < 4 * C::NWIN;
+  const bool bact = wact && p < C::NG;
   const int wi = w / TW, wj = w - (w / TW) * TW;
   const int c00 = wi * C::CW + wj, c01 = c00 + 1, c10 = c00 + C::CW, c11 = c10 + 1;
-  if (wact) {
+#pragma unroll
+  for (int o = 0; o < BAND; ++o) rho[o] = 0.0f;
+  if (bact) {
     const float n = (float)(4 * STEP * STEP);
     const float sa = s_wsum[w], saa = s_wsq[w];
     const float mA = sa / n;
     const float varA = saa - sa * mA;
     const bool flatA = !(varA > kFlatRel * saa);
+    const int boff = p * BAND;
 #pragma unroll
-    for (int i = 0; i < PER; ++i) {
-      int s = p + 4 * i;
-      float r = 0.0f;
-      if (s < C::NS) {
-        int sy = s / C::NSY - R, sx = s % C::NSY - R;
-        float P = resP[c00 * C::NS + s] + resP[c01 * C::NS + s] + resP[c10 * C::NS + s] + resP[c11 * C::NS + s];
-        float S = resS[c00 * C::NS + s] + resS[c01 * C::NS + s] + resS[c10 * C::NS + s] + resS[c11 * C::NS + s];
-        float Q = resQ[c00 * C::NS + s] + resQ[c01 * C::NS + s] + resQ[c10 * C::NS + s] + resQ[c11 * C::NS + s];
-        float num = P - mA * S;
-        float varB = Q - S * S / n;
-        bool flat = flatA || !(varB > kFlatRel * Q);
-        r = flat ? 0.0f : num * rsqrtf(varA * varB);
-        bool used = !g.fixed || sx == 0 || sy == 0;
-        if (used) {
-          nflat += flat;
-          int key = tie_key(sy, sx);
-          if (!g.fixed && better(r, key, best, bkey)) {
-            best = r;
-            bkey = key;
+    for (int v4 = 0; v4 < BAND / 4; ++v4) {
+      auto ld = [&](const float* base, int c) {
+        return reinterpret_cast<const float4*>(base + c * NSP + boff)[v4];
+      };
+      const float4 P0 = ld(resP, c00), P1 = ld(resP, c01), P2 = ld(resP, c10), P3 = ld(resP, c11);
+      const float4 S0 = ld(resS, c00), S1 = ld(resS, c01), S2 = ld(resS, c10), S3 = ld(resS, c11);
+      const float4 Q0 = ld(resQ, c00), Q1 = ld(resQ, c01), Q2 = ld(resQ, c10), Q3 = ld(resQ, c11);
+      const float Pv[4] = {P0.x + P1.x + P2.x + P3.x, P0.y + P1.y + P2.y + P3.y, P0.z + P1.z + P2.z + P3.z,
+                           P0.w + P1.w + P2.w + P3.w};
+      const float Sv[4] = {S0.x + S1.x + S2.x + S3.x, S0.y + S1.y + S2.y + S3.y, S0.z + S1.z + S2.z + S3.z,
+                           S0.w + S1.w + S2.w + S3.w};
+      const float Qv[4] = {Q0.x + Q1.x + Q2.x + Q3.x, Q0.y + Q1.y + Q2.y + Q3.y, Q0.z + Q1.z + Q2.z + Q3.z,
+                           Q0.w + Q1.w + Q2.w + Q3.w};
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int o = 4 * v4 + e;
+        if (o < SYG * C::NSY) {
+          const int sy = p * SYG + o / C::NSY - R, sx = o % C::NSY - R;
+          float num = Pv[e] - mA * Sv[e];
+          float varB = Qv[e] - Sv[e] * Sv[e] / n;
+          bool flat = flatA || !(varB > kFlatRel * Qv[e]);
+          float r = flat ? 0.0f : num * rsqrtf(varA * varB);
+          bool used = !g.fixed || sx == 0 || sy == 0;
+          if (used) {
+            nflat += flat;
+            int key = tie_key(sy, sx);
+            if (!g.fixed && better(r, key, best, bkey)) {
+              best = r;
+              bkey = key;
+            }
           }
+          rho[o] = r;
         }
       }
-      rho[i] = r;
     }
   }
   // reduce over the window's four lanes
@@ -737,12 +801,10 @@ __global__ __launch_bounds__(NT) void k_correct_tiled(CorrArgs g) {
     }
   }
   __syncthreads();   // all window sums read: reuse resP of cell c00 for rho
-  if (wact) {
+  if (bact) {
+    float4* d = reinterpret_cast<float4*>(resP + c00 * NSP + p * BAND);
 #pragma unroll
-    for (int i = 0; i < PER; ++i) {
-      int s = p + 4 * i;
-      if (s < C::NS) resP[c00 * C::NS + s] = rho[i];
-    }
+    for (int v4 = 0; v4 < BAND / 4; ++v4) d[v4] = make_float4(rho[4 * v4], rho[4 * v4 + 1], rho[4 * v4 + 2], rho[4 * v4 + 3]);
   }
   __syncthreads();
   if (wact && p == 0) {
@@ -753,8 +815,11 @@ __global__ __launch_bounds__(NT) void k_correct_tiled(CorrArgs g) {
         sx = (bkey & 63) - 32;
         sy = ((bkey >> 6) & 63) - 32;
       }
-      const float* rr = resP + c00 * C::NS;
-      auto rhof = [&](int y, int x) { return rr[(y + R) * C::NSY + x + R]; };
+      const float* rr = resP + c00 * NSP;
+      auto rhof = [&](int y, int x) {
+        const int yi = y + R;
+        return rr[(yi / SYG) * BAND + (yi % SYG) * C::NSY + x + R];
+      };
       float pu = 0.0f, pv = 0.0f;
       if (Pn) window_mean_half_overlap(a, b, g.nx, g.ny, node, pu, pv);
       finish_vector(g, pair, a, b, sy, sx, nflat == (g.fixed ? 5 : C::NS), pu, pv, rhof);
