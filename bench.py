@@ -44,6 +44,9 @@ def parse():
     ap.add_argument("--no-extras", action="store_true", help="skip the graph/serving/stream/SSD forms")
     ap.add_argument("--serve-seconds", type=float, default=3.0)
     ap.add_argument("--quiet", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="first run three plain device-to-device copies of MIB MiB (a known-size "
+                         "reference for memory counters)")
     return ap.parse_args()
 
 
@@ -95,6 +98,32 @@ def cpu_baseline(A, B, log_fn):
     return {"value": round(1.0 / sec, 5), "unit": "pairs/s", "cores": cores, "kind": "oracle",
             "sample": "one 1024x1024 pair: full predictor + validation + vorticity; correction on a "
                       "512-row strip (8192 of 16384 windows) scaled x2"}
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_correct_tiled_cfg2_b64_traffic.txt")
+CORR_SRC = os.path.join(ROOT, "paper_2504_17987_amd", "csrc", "correct.hip")
+
+
+def measured_traffic():
+    """Bytes per launch of the correlation kernel beyond L2 (fetch + write),
+    from the committed counter summary, scaled there by a plain copy of known
+    size; None when the summary is missing or was taken on another version of
+    the kernel source."""
+    import hashlib
+    try:
+        kv = {}
+        with open(TRAFFIC_FILE) as f:
+            for ln in f:
+                if ":" in ln and not ln.startswith("#"):
+                    k, v = ln.split(":", 1)
+                    kv[k.strip()] = v.strip()
+        with open(CORR_SRC, "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+        if kv.get("source_sha256") != sha:
+            return None
+        return float(kv["fetch_bytes_per_launch"]) + float(kv["write_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def events(torch, n):
@@ -265,6 +294,13 @@ def main():
                peak=torch.empty((nb, ny, nx), device=dev), flags=torch.empty((nb, ny, nx), dtype=torch.uint8, device=dev),
                omega=torch.empty((nb, ny, nx), device=dev))
     stream = torch.cuda.current_stream(dev)
+    if args.copy_probe > 0:
+        src = torch.zeros(args.copy_probe << 20, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     for _ in range(args.warmup):
         plan.run(A, B, out)
@@ -361,7 +397,7 @@ def main():
                          "bytes_per_pair": alg["path_bytes"]},
         "roofline": {"kernel": "k_correct_tiled (deformation + correlation + fit)", "bound": "alu",
                      "achieved": round(corr_tflops, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(corr_tflops / FP32_PEAK_TFLOPS, 5), "traffic": None,
+                     "frac": round(corr_tflops / FP32_PEAK_TFLOPS, 5), "traffic": measured_traffic(),
                      "ms_per_launch": round(corr_ms, 4), "flop_per_pair": alg["corr_flop"],
                      "pairs_per_launch": nb},
         "forms": forms,

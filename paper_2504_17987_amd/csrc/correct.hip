@@ -110,29 +110,42 @@ __device__ __forceinline__ void window_mean_half_overlap(int a, int b, int nx, i
 
 // Four consecutive pixels of row y from pixel x on (zero outside the image),
 // with aligned word loads realigned by alignbyte.
-template <typename T>
+template <typename T, bool kAligned = false>
 __device__ __forceinline__ void load4(const uint8_t* img, int64_t pitch, int H, int rowbytes, int y, int x,
                                       float (&v)[4]) {
-  if (y < 0 || y >= H) {
-    v[0] = v[1] = v[2] = v[3] = 0.0f;
-    return;
-  }
-  const uint8_t* row = img + (int64_t)y * pitch;
-  if constexpr (sizeof(T) == 1) {
+  // rows outside the image read row 0 or H-1 and are zeroed afterwards
+  const uint32_t rowok = (unsigned)y < (unsigned)H ? 0xffffffffu : 0u;
+  const uint8_t* row = img + (int64_t)min(max(y, 0), H - 1) * pitch;
+  if constexpr (sizeof(T) == 1 && kAligned) {
+    const uint32_t w = masked_word(row, rowbytes, x) & rowok;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] = (float)((w >> (8 * k)) & 0xffu);
+  } else if constexpr (sizeof(T) == 2 && kAligned) {
+    const uint32_t lo = masked_word(row, rowbytes, 2 * x) & rowok, hi = masked_word(row, rowbytes, 2 * x + 4) & rowok;
+    v[0] = (float)(lo & 0xffffu);
+    v[1] = (float)(lo >> 16);
+    v[2] = (float)(hi & 0xffffu);
+    v[3] = (float)(hi >> 16);
+  } else if constexpr (sizeof(T) == 1) {
     const int xb = x, xa = xb & ~3, sh = xb & 3;
     uint32_t w = __builtin_amdgcn_alignbyte(masked_word(row, rowbytes, xa + 4), masked_word(row, rowbytes, xa), sh);
+    w &= rowok;
 #pragma unroll
     for (int k = 0; k < 4; ++k) v[k] = (float)((w >> (8 * k)) & 0xffu);
   } else if constexpr (sizeof(T) == 2) {
     const int xb = 2 * x, xa = xb & ~3, sh = xb & 3;
     uint32_t w0 = masked_word(row, rowbytes, xa), w1 = masked_word(row, rowbytes, xa + 4),
              w2 = masked_word(row, rowbytes, xa + 8);
-    uint32_t lo = __builtin_amdgcn_alignbyte(w1, w0, sh), hi = __builtin_amdgcn_alignbyte(w2, w1, sh);
+    uint32_t lo = __builtin_amdgcn_alignbyte(w1, w0, sh) & rowok, hi = __builtin_amdgcn_alignbyte(w2, w1, sh) & rowok;
     v[0] = (float)(lo & 0xffffu);
     v[1] = (float)(lo >> 16);
     v[2] = (float)(hi & 0xffffu);
     v[3] = (float)(hi >> 16);
   } else {
+    if (y < 0 || y >= H) {
+      v[0] = v[1] = v[2] = v[3] = 0.0f;
+      return;
+    }
 #pragma unroll
     for (int k = 0; k < 4; ++k) v[k] = pixf<T>(img, pitch, rowbytes / 4, H, y, x + k);
   }
@@ -376,14 +389,15 @@ __global__ __launch_bounds__(NT) void k_correct_tiled(CorrArgs g) {
   __shared__ float s_node[2][C::NNY][C::NNX];
   __shared__ float s_wsum[C::NWIN], s_wsq[C::NWIN];
   __shared__ float s_red[NT / 64];
-  __shared__ float s_rng[NT / 64][4];
+  __shared__ float s_rng[NT / 64][5];
   __shared__ int s_rb[C::BH], s_cb[C::BW];
   __shared__ float s_rf[C::BH], s_cf[C::BW];
 
-  const int pair = blockIdx.z;
+  const WgIdx wg = xcd_order();
+  const int pair = wg.z;
   if (slot_off(g.mask, pair)) return;
   const int t = threadIdx.x;
-  const int a0 = blockIdx.y * TH, b0 = blockIdx.x * TW;
+  const int a0 = wg.y * TH, b0 = wg.x * TW;
   constexpr int h = STEP / 2;
   const int y0 = a0 * STEP - h, x0 = b0 * STEP - h;      // A tile origin
   const int yb = y0 - R, xb = x0 - R;                    // B' tile origin
@@ -394,12 +408,45 @@ __global__ __launch_bounds__(NT) void k_correct_tiled(CorrArgs g) {
   float* sA = s_u;                   // [AH][AP]
   float* sB = s_u + C::AH * C::AP;   // [BH][BP]
 
+  constexpr int AQ = C::AW / 4;
+  constexpr int NA = (C::AH * AQ + NT - 1) / NT;
+  // plain A tile: when the tile origin is 4-byte aligned (STEP/2 pixels
+  // are), its words are read here, all in flight together ahead of the node
+  // cache, and unpacked after the first barrier
+  constexpr bool kAlignedA = ((STEP / 2) * (int)sizeof(T)) % 4 == 0;
+  constexpr int NWA = kAlignedA ? (int)sizeof(T) : 1;
+  const bool plainA = !(g.central && Pn);
+  uint32_t aw[NA][NWA], ak[NA][NWA];   // raw words and their keep masks
+  if (kAlignedA && plainA) {
+    const int rowbytes = g.W * (int)sizeof(T);
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      const int idx0 = t + i * NT;
+      const bool in = idx0 < C::AH * AQ;
+      const int idx = in ? idx0 : 0;
+      const int r = idx / AQ, q = 4 * (idx - (idx / AQ) * AQ);
+      const int y = y0 + r;
+      const uint32_t ok = (in && (unsigned)y < (unsigned)g.H) ? 0xffffffffu : 0u;
+      const uint8_t* row = Ai + (int64_t)min(max(y, 0), g.H - 1) * g.pitch;
+#pragma unroll
+      for (int k = 0; k < NWA; ++k) {
+        // masked_word, with the mask applied after the first barrier so that
+        // nothing waits for these reads before the node cache is requested
+        const int xa = (x0 + q) * (int)sizeof(T) + 4 * k;
+        aw[i][k] = *reinterpret_cast<const uint32_t*>(row + min(max(xa, 0), (rowbytes - 1) & ~3));
+        const int valid = rowbytes - xa;
+        const uint32_t part = (1u << (8 * (valid & 3))) - 1u;
+        ak[i][k] = ((xa < 0 || valid <= 0) ? 0u : (valid >= 4 ? 0xffffffffu : part)) & ok;
+      }
+    }
+  }
+
   // node cache covering the B' tile, and the range of the predictor over it
   // (every interpolated displacement is a convex combination of cached nodes)
   const float cen = 0.5f * (float)(STEP - 1);
   const int nlo_y = max(0, (int)floorf(((float)yb - cen) / STEP));
   const int nlo_x = max(0, (int)floorf(((float)xb - cen) / STEP));
-  float umin = 0.0f, umax = 0.0f, vmin = 0.0f, vmax = 0.0f;
+  float umin = 0.0f, umax = 0.0f, vmin = 0.0f, vmax = 0.0f, bad = 0.0f;
   if (Pn) {
     umin = vmin = 3.0e38f;
     umax = vmax = -3.0e38f;
@@ -413,9 +460,11 @@ __global__ __launch_bounds__(NT) void k_correct_tiled(CorrArgs g) {
       umax = fmaxf(umax, u);
       vmin = fminf(vmin, v);
       vmax = fmaxf(vmax, v);
+      if (!(fabsf(u) < 1.0e6f && fabsf(v) < 1.0e6f)) bad = 1.0f;   // also NaN
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
+      bad = fmaxf(bad, __shfl_xor(bad, o));
       umin = fminf(umin, __shfl_xor(umin, o));
       umax = fmaxf(umax, __shfl_xor(umax, o));
       vmin = fminf(vmin, __shfl_xor(vmin, o));
@@ -426,6 +475,7 @@ __global__ __launch_bounds__(NT) void k_correct_tiled(CorrArgs g) {
       s_rng[t >> 6][1] = umax;
       s_rng[t >> 6][2] = vmin;
       s_rng[t >> 6][3] = vmax;
+      s_rng[t >> 6][4] = bad;
     }
   }
   // per-row / per-column interpolation tables of the B' tile (the A tile is
@@ -443,9 +493,10 @@ __global__ __launch_bounds__(NT) void k_correct_tiled(CorrArgs g) {
   }
   __syncthreads();
   if (Pn) {
-    umin = s_rng[0][0]; umax = s_rng[0][1]; vmin = s_rng[0][2]; vmax = s_rng[0][3];
+    umin = s_rng[0][0]; umax = s_rng[0][1]; vmin = s_rng[0][2]; vmax = s_rng[0][3]; bad = s_rng[0][4];
 #pragma unroll
     for (int i = 1; i < NT / 64; ++i) {
+      bad = fmaxf(bad, s_rng[i][4]);
       umin = fminf(umin, s_rng[i][0]);
       umax = fmaxf(umax, s_rng[i][1]);
       vmin = fminf(vmin, s_rng[i][2]);
@@ -462,34 +513,58 @@ __global__ __launch_bounds__(NT) void k_correct_tiled(CorrArgs g) {
         fy * ((1.0f - fx) * s_node[1][rb + 1][cb] + fx * s_node[1][rb + 1][cb + 1]);
   };
 
-  // A tile (deformed by -u/2 in central mode) in groups of four pixels,
-  // held in registers until the tile offset K is known
-  constexpr int AQ = C::AW / 4;
-  constexpr int NA = (C::AH * AQ + NT - 1) / NT;
+  // A tile in groups of four pixels (deformed by -u/2 in central mode), held
+  // in registers until the tile offset K is known
   float av[NA][4];
+#pragma unroll
+  for (int i = 0; i < NA; ++i) av[i][0] = av[i][1] = av[i][2] = av[i][3] = 0.0f;
   float part = 0.0f;
-  {
-    const int rowbytes = g.W * (int)sizeof(T);
+  if (plainA) {
+    if constexpr (kAlignedA) {
+#pragma unroll
+      for (int i = 0; i < NA; ++i) {
+        const uint32_t w0 = aw[i][0] & ak[i][0], w1 = aw[i][NWA - 1] & ak[i][NWA - 1];
+        if constexpr (sizeof(T) == 1) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) av[i][e] = (float)((w0 >> (8 * e)) & 0xffu);
+        } else {
+          av[i][0] = (float)(w0 & 0xffffu);
+          av[i][1] = (float)(w0 >> 16);
+          av[i][2] = (float)(w1 & 0xffffu);
+          av[i][3] = (float)(w1 >> 16);
+        }
+      }
+    } else {
+      const int rowbytes = g.W * (int)sizeof(T);
+#pragma unroll
+      for (int i = 0; i < NA; ++i) {
+        const int idx0 = t + i * NT;
+        const bool in = idx0 < C::AH * AQ;
+        const int idx = in ? idx0 : 0;
+        const int r = idx / AQ, q = 4 * (idx - (idx / AQ) * AQ);
+        float v[4];
+        load4<T>(Ai, g.pitch, g.H, rowbytes, y0 + r, x0 + q, v);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) av[i][e] = in ? v[e] : 0.0f;
+      }
+    }
+  } else {
 #pragma unroll
     for (int i = 0; i < NA; ++i) {
       const int idx = t + i * NT;
-      av[i][0] = av[i][1] = av[i][2] = av[i][3] = 0.0f;
       if (idx < C::AH * AQ) {
         const int r = idx / AQ, q = 4 * (idx - (idx / AQ) * AQ);
-        if (g.central && Pn) {
 #pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            float u, w;
-            interp_tab(r + R, q + e + R, u, w);
-            av[i][e] = bilin<T>(Ai, g.pitch, g.W, g.H, (x0 + q + e) - 0.5f * u, (y0 + r) - 0.5f * w);
-          }
-        } else {
-          load4<T>(Ai, g.pitch, g.H, rowbytes, y0 + r, x0 + q, av[i]);
+        for (int e = 0; e < 4; ++e) {
+          float u, w;
+          interp_tab(r + R, q + e + R, u, w);
+          av[i][e] = bilin<T>(Ai, g.pitch, g.W, g.H, (x0 + q + e) - 0.5f * u, (y0 + r) - 0.5f * w);
         }
-        part += (av[i][0] + av[i][1]) + (av[i][2] + av[i][3]);
       }
     }
   }
+#pragma unroll
+  for (int i = 0; i < NA; ++i) part += (av[i][0] + av[i][1]) + (av[i][2] + av[i][3]);
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o);
   if ((t & 63) == 0) s_red[t >> 6] = part;
@@ -503,16 +578,31 @@ __global__ __launch_bounds__(NT) void k_correct_tiled(CorrArgs g) {
   const int xw0 = (ix0 * (int)sizeof(T)) >> 2;
   const int nwords = ((ix1 * (int)sizeof(T) + (int)sizeof(T) - 1) >> 2) - xw0 + 1;
   const int nrows = iy1 - iy0 + 1;
-  const bool staged = nwords * nrows <= C::RAW_WORDS;
+  // (a displacement range that is not finite or wider than a window takes
+  // the unstaged path, whose reads are checked one by one)
+  const bool sane = bad == 0.0f && (umax - umin) < 64.0f && (vmax - vmin) < 64.0f;
+  const bool staged = sane && nwords <= NT && nwords * nrows <= C::RAW_WORDS;
   uint32_t* sraw = reinterpret_cast<uint32_t*>(s_u + C::IN_FLOATS);
   if (staged) {
+    // thread -> (word column, first row); rows advance by rstep, U reads in
+    // flight per thread
     const int rowbytes = g.W * (int)sizeof(T);
-    for (int idx = t; idx < nwords * nrows; idx += NT) {
-      int r = idx / nwords, w = idx - (idx / nwords) * nwords;
-      int y = iy0 + r;
-      uint32_t val = 0u;
-      if (y >= 0 && y < g.H) val = masked_word(Bi + (int64_t)y * g.pitch, rowbytes, 4 * (xw0 + w));
-      sraw[idx] = val;
+    const int rstep = NT / nwords;
+    const int r0 = t / nwords, w = t - r0 * nwords;
+    constexpr int U = 8;
+    if (r0 < rstep) {
+      for (int rb = r0; rb < nrows; rb += U * rstep) {
+        uint32_t val[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int y = iy0 + rb + u * rstep;
+          const uint32_t ok = (unsigned)y < (unsigned)g.H ? 0xffffffffu : 0u;
+          val[u] = masked_word(Bi + (int64_t)min(max(y, 0), g.H - 1) * g.pitch, rowbytes, 4 * (xw0 + w)) & ok;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+          if (rb + u * rstep < nrows) sraw[(rb + u * rstep) * nwords + w] = val[u];
+      }
     }
   }
   __syncthreads();
@@ -540,45 +630,69 @@ __global__ __launch_bounds__(NT) void k_correct_tiled(CorrArgs g) {
     // a one-pixel margin); the clamps only keep the padding columns of a
     // ragged last group inside it.
     constexpr int BQ = (C::BW + 3) / 4;
+    constexpr int RPI = NT / BQ;              // rows per pass
+    // groups never straddle a node-column boundary when the tile origin and
+    // the boundaries agree modulo 4
+    constexpr bool kUniformCols = (STEP + R) % 4 == 0;
     const uint8_t* rawb = reinterpret_cast<const uint8_t*>(sraw);
     const int rowb = 4 * nwords, xoff = 4 * xw0;
     constexpr int ES = (int)sizeof(T);
     auto rawv = [&](const uint8_t* p) -> float { return (float)*reinterpret_cast<const T*>(p); };
-    for (int idx = t; idx < C::BH * BQ; idx += NT) {
-      const int r = idx / BQ, q = 4 * (idx - (idx / BQ) * BQ);
+    const int r_t = t / BQ, q = 4 * (t - (t / BQ) * BQ);
+    const float fxlo = (float)ix0, fxhi = (float)(ix1 - 1), fylo = (float)iy0, fyhi = (float)(iy1 - 1);
+    const int rbase = iy0 * rowb + xoff;
+    const bool lane_on = t < RPI * BQ;
+    const float xq = (float)(xb + q);
+    for (int r = r_t; lane_on && r < C::BH; r += RPI) {
       float uu[4] = {0.0f, 0.0f, 0.0f, 0.0f}, vv[4] = {0.0f, 0.0f, 0.0f, 0.0f};
       if (Pn) {
         const int rb = s_rb[r];
         const float fy = s_rf[r];
         const int cb0 = s_cb[q];
-        float Vu[3], Vv[3];
+        if constexpr (kUniformCols) {
+          const float u0 = s_node[0][rb][cb0] + fy * (s_node[0][rb + 1][cb0] - s_node[0][rb][cb0]);
+          const float u1 = s_node[0][rb][cb0 + 1] + fy * (s_node[0][rb + 1][cb0 + 1] - s_node[0][rb][cb0 + 1]);
+          const float v0 = s_node[1][rb][cb0] + fy * (s_node[1][rb + 1][cb0] - s_node[1][rb][cb0]);
+          const float v1 = s_node[1][rb][cb0 + 1] + fy * (s_node[1][rb + 1][cb0 + 1] - s_node[1][rb][cb0 + 1]);
+          const float du = u1 - u0, dv = v1 - v0;
 #pragma unroll
-        for (int j = 0; j < 3; ++j) {
-          Vu[j] = (1.0f - fy) * s_node[0][rb][cb0 + j] + fy * s_node[0][rb + 1][cb0 + j];
-          Vv[j] = (1.0f - fy) * s_node[1][rb][cb0 + j] + fy * s_node[1][rb + 1][cb0 + j];
-        }
+          for (int e = 0; e < 4; ++e) {
+            const float fx = s_cf[min(q + e, C::BW - 1)];
+            uu[e] = u0 + fx * du;
+            vv[e] = v0 + fx * dv;
+          }
+        } else {
+          float Vu[3], Vv[3];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int qq = min(q + e, C::BW - 1);
-          const bool nxt = s_cb[qq] != cb0;
-          const float fx = s_cf[qq];
-          const float ul = nxt ? Vu[1] : Vu[0], ur = nxt ? Vu[2] : Vu[1];
-          const float vl = nxt ? Vv[1] : Vv[0], vr = nxt ? Vv[2] : Vv[1];
-          uu[e] = (1.0f - fx) * ul + fx * ur;
-          vv[e] = (1.0f - fx) * vl + fx * vr;
+          for (int j = 0; j < 3; ++j) {
+            Vu[j] = s_node[0][rb][cb0 + j] + fy * (s_node[0][rb + 1][cb0 + j] - s_node[0][rb][cb0 + j]);
+            Vv[j] = s_node[1][rb][cb0 + j] + fy * (s_node[1][rb + 1][cb0 + j] - s_node[1][rb][cb0 + j]);
+          }
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int qq = min(q + e, C::BW - 1);
+            const bool nxt = s_cb[qq] != cb0;
+            const float fx = s_cf[qq];
+            const float ul = nxt ? Vu[1] : Vu[0], ur = nxt ? Vu[2] : Vu[1];
+            const float vl = nxt ? Vv[1] : Vv[0], vr = nxt ? Vv[2] : Vv[1];
+            uu[e] = ul + fx * (ur - ul);
+            vv[e] = vl + fx * (vr - vl);
+          }
         }
       }
+      const float yr = (float)(yb + r);
       float out[4];
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const float qx = (float)(xb + q + e) + sgnB * uu[e], qy = (float)(yb + r) + sgnB * vv[e];
+        const float qx = (xq + (float)e) + sgnB * uu[e], qy = yr + sgnB * vv[e];
         const float fx0 = floorf(qx), fy0 = floorf(qy);
         const float fx = qx - fx0, fy = qy - fy0;
-        const int ix = min(max((int)fx0, ix0), ix1 - 1), iy = min(max((int)fy0, iy0), iy1 - 1);
-        const uint8_t* p0 = rawb + (iy - iy0) * rowb + (ix * ES - xoff);
+        const int ix = (int)__builtin_amdgcn_fmed3f(fx0, fxlo, fxhi);
+        const int iy = (int)__builtin_amdgcn_fmed3f(fy0, fylo, fyhi);
+        const uint8_t* p0 = rawb + (iy * rowb + ix * ES) - rbase;
         const float p00 = rawv(p0), p01 = rawv(p0 + ES), p10 = rawv(p0 + rowb), p11 = rawv(p0 + rowb + ES);
-        const float top = (1.0f - fx) * p00 + fx * p01, bot = (1.0f - fx) * p10 + fx * p11;
-        out[e] = ((1.0f - fy) * top + fy * bot) - K;
+        const float top = p00 + fx * (p01 - p00), bot = p10 + fx * (p11 - p10);
+        out[e] = (top + fy * (bot - top)) - K;
       }
       *reinterpret_cast<float4*>(sB + r * C::BP + q) = make_float4(out[0], out[1], out[2], out[3]);
     }
@@ -752,6 +866,12 @@ __global__ __launch_bounds__(NT) void k_correct_tiled(CorrArgs g) {
     const float varA = saa - sa * mA;
     const bool flatA = !(varA > kFlatRel * saa);
     const int boff = p * BAND;
+    int krow[SYG];   // shift-row part of the tie key of each row of the band
+#pragma unroll
+    for (int k = 0; k < SYG; ++k) {
+      const int sy = p * SYG + k - R;
+      krow[k] = (abs(sy) << 12) | ((sy + 32) << 6);
+    }
 #pragma unroll
     for (int v4 = 0; v4 < BAND / 4; ++v4) {
       auto ld = [&](const float* base, int c) {
@@ -778,7 +898,7 @@ __global__ __launch_bounds__(NT) void k_correct_tiled(CorrArgs g) {
           bool used = !g.fixed || sx == 0 || sy == 0;
           if (used) {
             nflat += flat;
-            int key = tie_key(sy, sx);
+            const int key = krow[o / C::NSY] + ((abs(sx) << 12) | (sx + 32));   // == tie_key(sy, sx)
             if (!g.fixed && better(r, key, best, bkey)) {
               best = r;
               bkey = key;

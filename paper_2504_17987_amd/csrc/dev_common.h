@@ -13,13 +13,37 @@ __device__ __forceinline__ bool slot_off(const uint8_t* mask, int pair) {
 }
 
 // Aligned 4-byte word of a row at byte offset xa (a multiple of 4, may be
-// negative), with zero for bytes outside [0, rowbytes).  Reading the word is
-// in bounds because row pitches are multiples of 4 and rowbytes <= pitch.
+// negative or past the row), with zero for bytes outside [0, rowbytes).  The
+// read is clamped into the row and always issued, so that a run of such
+// reads is not serialised behind branches; it is in bounds because row
+// pitches are multiples of 4 and rowbytes <= pitch.
 __device__ __forceinline__ uint32_t masked_word(const uint8_t* row, int rowbytes, int xa) {
-  if (xa < 0 || xa >= rowbytes) return 0u;
-  uint32_t w = *reinterpret_cast<const uint32_t*>(row + xa);
-  int valid = rowbytes - xa;
-  if (valid < 4) w &= (1u << (8 * valid)) - 1u;
+  const int xc = min(max(xa, 0), (rowbytes - 1) & ~3);
+  const uint32_t w = *reinterpret_cast<const uint32_t*>(row + xc);
+  const int valid = rowbytes - xa;
+  const uint32_t part = (1u << (8 * (valid & 3))) - 1u;
+  const uint32_t keep = (xa < 0 || valid <= 0) ? 0u : (valid >= 4 ? 0xffffffffu : part);
+  return w & keep;
+}
+
+// Workgroups are dealt round-robin to the 8 XCDs, each with its own L2.
+// xcd_order() renumbers them so that each XCD takes one contiguous run of
+// the linear grid order (x fastest, then y, then z): neighbouring tiles,
+// which read the same cache lines, then meet in the same L2.
+struct WgIdx {
+  int x, y, z;
+};
+__device__ __forceinline__ WgIdx xcd_order() {
+  const int gx = gridDim.x, gy = gridDim.y;
+  const int n = gx * gy * gridDim.z;
+  int p = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+  const int full = n & ~7;
+  if (p < full) p = (p & 7) * (full >> 3) + (p >> 3);
+  WgIdx w;
+  w.x = p % gx;
+  p /= gx;
+  w.y = p % gy;
+  w.z = p / gy;
   return w;
 }
 
