@@ -41,6 +41,7 @@ struct CorrArgs {
 };
 
 // tie key: smaller is preferred among equal coefficients (|sx|+|sy|, sy, sx)
+constexpr int kKeyNone = 0x7fffffff;   // a shift that takes no part in the peak search
 __device__ __forceinline__ int tie_key(int sy, int sx) {
   return ((abs(sx) + abs(sy)) << 12) | ((sy + 32) << 6) | (sx + 32);
 }
@@ -367,15 +368,23 @@ struct TileCfg {
   static constexpr int BP = (BW + 3) / 4 * 4 + 4;
   static constexpr int NNX = BW / STEP + 4, NNY = BH / STEP + 3;
   static constexpr int IN_FLOATS = AH * AP + BH * BP;
-  static constexpr int BAND = (SYG * NSY + 3) / 4 * 4;   // shift band padded to 16 bytes
-  static constexpr int NSP = NG * BAND;                   // result slots per cell
-  static constexpr int RES_FLOATS = 3 * NC * NSP;
+  // one shift band (SYG rows of NSY shifts) is split over the window's four
+  // threads, PER shifts each, stored SLOTW apart (16-byte aligned chunks)
+  static constexpr int NBS = SYG * NSY;
+  static constexpr int PER = (NBS + 3) / 4;
+  static constexpr int SLOTW = (PER + 3) / 4 * 4;
+  static constexpr int BANDP = 4 * SLOTW;
+  static constexpr int CSTR = BANDP + 4;                  // cell stride (spreads LDS banks)
+  static constexpr int WSTR = NG * BANDP + 4;             // window stride of the coefficients
+  static constexpr int XBUF = 3 * NC * CSTR;              // P, S, Q of one band, all cells
+  static constexpr int RES_FLOATS = 2 * XBUF;             // two band buffers
   // room for the raw source tile of B behind the A and B' tiles: what the
   // result arrays leave free, at least 16 KiB
   static constexpr int RAW_WORDS = RES_FLOATS - IN_FLOATS > 4096 ? RES_FLOATS - IN_FLOATS : 4096;
   static constexpr int UNION = IN_FLOATS + RAW_WORDS > RES_FLOATS ? IN_FLOATS + RAW_WORDS : RES_FLOATS;
   static constexpr int NWIN = TW * TH;
   static_assert(NSY % SYG == 0, "shift rows must split evenly");
+  static_assert(NWIN * WSTR <= XBUF, "window coefficients fit one band buffer");
   static_assert(STEP % 2 == 0, "50% overlap needs an even step");
   static_assert(STEP >= 4, "a group of four pixels spans at most two node columns");
 };
@@ -392,6 +401,7 @@ __global__ __launch_bounds__(NT) void k_correct_tiled(CorrArgs g) {
   __shared__ float s_rng[NT / 64][5];
   __shared__ int s_rb[C::BH], s_cb[C::BW];
   __shared__ float s_rf[C::BH], s_cf[C::BW];
+  __shared__ int s_tkey[C::NG * 4 * C::PER];   // tie key of (band, thread, shift), or kKeyNone
 
   const WgIdx wg = xcd_order();
   const int pair = wg.z;
@@ -441,6 +451,16 @@ __global__ __launch_bounds__(NT) void k_correct_tiled(CorrArgs g) {
     }
   }
 
+  // tie keys of the shifts each window thread will see, per band
+  for (int i = t; i < C::NG * 4 * C::PER; i += NT) {
+    const int bnd = i / (4 * C::PER), o = i - bnd * 4 * C::PER;   // o = thread * PER + shift
+    int key = kKeyNone;
+    if (o < C::NBS) {
+      const int sy = bnd * SYG + o / C::NSY - R, sx = o % C::NSY - R;
+      if (!g.fixed || sx == 0 || sy == 0) key = tie_key(sy, sx);
+    }
+    s_tkey[i] = key;
+  }
   // node cache covering the B' tile, and the range of the predictor over it
   // (every interpolated displacement is a convex combination of cached nodes)
   const float cen = 0.5f * (float)(STEP - 1);
@@ -819,95 +839,103 @@ __global__ __launch_bounds__(NT) void k_correct_tiled(CorrArgs g) {
     }
   }
   __syncthreads();   // everyone is done with the A and B' tiles
-  // cell results in bands: band b holds the SYG*NSY shifts of shift rows
-  // [b SYG, (b+1) SYG), padded to BAND slots so that a band is written and
-  // read with 16-byte LDS operations
-  constexpr int BAND = C::BAND, NSP = C::NSP;
-  float* resP = s_u;
-  float* resS = s_u + C::NC * NSP;
-  float* resQ = s_u + 2 * C::NC * NSP;
-  if (worker) {
-    float4* dP = reinterpret_cast<float4*>(resP + cell * NSP + grp * BAND);
-    float4* dS = reinterpret_cast<float4*>(resS + cell * NSP + grp * BAND);
-    float4* dQ = reinterpret_cast<float4*>(resQ + cell * NSP + grp * BAND);
+  // ---- windows, one shift band at a time.  Band b (shift rows
+  // [b SYG, (b+1) SYG)) of every cell goes to LDS buffer X[b & 1] as three
+  // arrays [cell][CSTR]; the window's four threads take PER consecutive
+  // shifts each, stored at p*SLOTW so that every thread reads aligned
+  // 16-byte chunks.  While band b is read, band b+1 is written to the other
+  // buffer.
+  constexpr int PER = C::PER, SLOTW = C::SLOTW, BANDP = C::BANDP, NB = C::NBS;
+  constexpr int XB = C::XBUF, CSTR = C::CSTR, WSTR = C::WSTR;
+  const int w = t >> 2, p = t & 3;
+  const bool wact = t < 4 * C::NWIN;
+  const int wi = w / TW, wj = w - (w / TW) * TW;
+  const int c00 = wi * C::CW + wj, c01 = c00 + 1, c10 = c00 + C::CW, c11 = c10 + 1;
+  auto write_band = [&](float* X) {
+    // slot o of the band (row o / NSY, column o % NSY) sits at
+    // (o / PER) * SLOTW + o % PER
 #pragma unroll
-    for (int v4 = 0; v4 < BAND / 4; ++v4) {
+    for (int v4 = 0; v4 < BANDP / 4; ++v4) {
       float p4[4], s4[4], q4[4];
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const int o = 4 * v4 + e;               // offset in the band
-        const bool real = o < SYG * C::NSY;
-        p4[e] = real ? Pacc[o / C::NSY][o % C::NSY] : 0.0f;
-        s4[e] = real ? Sacc[o / C::NSY][o % C::NSY] : 0.0f;
-        q4[e] = real ? Qacc[o / C::NSY][o % C::NSY] : 1.0f;
+        const int pos = 4 * v4 + e, th = pos / SLOTW, i = pos % SLOTW;
+        const int o = th * PER + i;
+        const bool real = i < PER && o < NB;
+        const int k = real ? o / C::NSY : 0, j = real ? o % C::NSY : 0;
+        p4[e] = real ? Pacc[k][j] : 0.0f;
+        s4[e] = real ? Sacc[k][j] : 0.0f;
+        q4[e] = real ? Qacc[k][j] : 1.0f;
       }
-      dP[v4] = make_float4(p4[0], p4[1], p4[2], p4[3]);
-      dS[v4] = make_float4(s4[0], s4[1], s4[2], s4[3]);
-      dQ[v4] = make_float4(q4[0], q4[1], q4[2], q4[3]);
+      reinterpret_cast<float4*>(X + cell * CSTR)[v4] = make_float4(p4[0], p4[1], p4[2], p4[3]);
+      reinterpret_cast<float4*>(X + XB / 3 + cell * CSTR)[v4] = make_float4(s4[0], s4[1], s4[2], s4[3]);
+      reinterpret_cast<float4*>(X + 2 * (XB / 3) + cell * CSTR)[v4] = make_float4(q4[0], q4[1], q4[2], q4[3]);
     }
-  }
+  };
+  float* const X0 = s_u;
+  float* const X1 = s_u + XB;
+  if (worker && grp == 0) write_band(X0);
   __syncthreads();
 
-  // ---- windows: four threads each; thread p < NG takes band p
-  float rho[BAND];
+  float rho[C::NG][PER];
   float best = -2.0f;
   int bkey = 1 << 30, nflat = 0;
-  const int w = t >> 2, p = t & 3;
-  const bool wact = t < 4 * C::NWIN;
-  const bool bact = wact && p < C::NG;
-  const int wi = w / TW, wj = w - (w / TW) * TW;
-  const int c00 = wi * C::CW + wj, c01 = c00 + 1, c10 = c00 + C::CW, c11 = c10 + 1;
-#pragma unroll
-  for (int o = 0; o < BAND; ++o) rho[o] = 0.0f;
-  if (bact) {
-    const float n = (float)(4 * STEP * STEP);
+  const float n = (float)(4 * STEP * STEP);
+  float mA = 0.0f, varA = 0.0f;
+  bool flatA = true;
+  if (wact) {
     const float sa = s_wsum[w], saa = s_wsq[w];
-    const float mA = sa / n;
-    const float varA = saa - sa * mA;
-    const bool flatA = !(varA > kFlatRel * saa);
-    const int boff = p * BAND;
-    int krow[SYG];   // shift-row part of the tie key of each row of the band
+    mA = sa / n;
+    varA = saa - sa * mA;
+    flatA = !(varA > kFlatRel * saa);
+  }
 #pragma unroll
-    for (int k = 0; k < SYG; ++k) {
-      const int sy = p * SYG + k - R;
-      krow[k] = (abs(sy) << 12) | ((sy + 32) << 6);
-    }
+  for (int bnd = 0; bnd < C::NG; ++bnd) {
+    const float* X = (bnd & 1) ? X1 : X0;
+    if (bnd + 1 < C::NG && worker && grp == bnd + 1) write_band((bnd & 1) ? X0 : X1);
 #pragma unroll
-    for (int v4 = 0; v4 < BAND / 4; ++v4) {
-      auto ld = [&](const float* base, int c) {
-        return reinterpret_cast<const float4*>(base + c * NSP + boff)[v4];
-      };
-      const float4 P0 = ld(resP, c00), P1 = ld(resP, c01), P2 = ld(resP, c10), P3 = ld(resP, c11);
-      const float4 S0 = ld(resS, c00), S1 = ld(resS, c01), S2 = ld(resS, c10), S3 = ld(resS, c11);
-      const float4 Q0 = ld(resQ, c00), Q1 = ld(resQ, c01), Q2 = ld(resQ, c10), Q3 = ld(resQ, c11);
-      const float Pv[4] = {P0.x + P1.x + P2.x + P3.x, P0.y + P1.y + P2.y + P3.y, P0.z + P1.z + P2.z + P3.z,
-                           P0.w + P1.w + P2.w + P3.w};
-      const float Sv[4] = {S0.x + S1.x + S2.x + S3.x, S0.y + S1.y + S2.y + S3.y, S0.z + S1.z + S2.z + S3.z,
-                           S0.w + S1.w + S2.w + S3.w};
-      const float Qv[4] = {Q0.x + Q1.x + Q2.x + Q3.x, Q0.y + Q1.y + Q2.y + Q3.y, Q0.z + Q1.z + Q2.z + Q3.z,
-                           Q0.w + Q1.w + Q2.w + Q3.w};
+    for (int i = 0; i < PER; ++i) rho[bnd][i] = 0.0f;
+    if (wact) {
+      float Pv[SLOTW], Sv[SLOTW], Qv[SLOTW];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int o = 4 * v4 + e;
-        if (o < SYG * C::NSY) {
-          const int sy = p * SYG + o / C::NSY - R, sx = o % C::NSY - R;
-          float num = Pv[e] - mA * Sv[e];
-          float varB = Qv[e] - Sv[e] * Sv[e] / n;
-          bool flat = flatA || !(varB > kFlatRel * Qv[e]);
-          float r = flat ? 0.0f : num * rsqrtf(varA * varB);
-          bool used = !g.fixed || sx == 0 || sy == 0;
-          if (used) {
-            nflat += flat;
-            const int key = krow[o / C::NSY] + ((abs(sx) << 12) | (sx + 32));   // == tie_key(sy, sx)
-            if (!g.fixed && better(r, key, best, bkey)) {
-              best = r;
-              bkey = key;
-            }
+      for (int v4 = 0; v4 < SLOTW / 4; ++v4) {
+        auto ld = [&](int arr, int c) {
+          return reinterpret_cast<const float4*>(X + arr * (XB / 3) + c * CSTR + p * SLOTW)[v4];
+        };
+        const float4 P0 = ld(0, c00), P1 = ld(0, c01), P2 = ld(0, c10), P3 = ld(0, c11);
+        const float4 S0 = ld(1, c00), S1 = ld(1, c01), S2 = ld(1, c10), S3 = ld(1, c11);
+        const float4 Q0 = ld(2, c00), Q1 = ld(2, c01), Q2 = ld(2, c10), Q3 = ld(2, c11);
+        Pv[4 * v4 + 0] = (P0.x + P1.x) + (P2.x + P3.x);
+        Pv[4 * v4 + 1] = (P0.y + P1.y) + (P2.y + P3.y);
+        Pv[4 * v4 + 2] = (P0.z + P1.z) + (P2.z + P3.z);
+        Pv[4 * v4 + 3] = (P0.w + P1.w) + (P2.w + P3.w);
+        Sv[4 * v4 + 0] = (S0.x + S1.x) + (S2.x + S3.x);
+        Sv[4 * v4 + 1] = (S0.y + S1.y) + (S2.y + S3.y);
+        Sv[4 * v4 + 2] = (S0.z + S1.z) + (S2.z + S3.z);
+        Sv[4 * v4 + 3] = (S0.w + S1.w) + (S2.w + S3.w);
+        Qv[4 * v4 + 0] = (Q0.x + Q1.x) + (Q2.x + Q3.x);
+        Qv[4 * v4 + 1] = (Q0.y + Q1.y) + (Q2.y + Q3.y);
+        Qv[4 * v4 + 2] = (Q0.z + Q1.z) + (Q2.z + Q3.z);
+        Qv[4 * v4 + 3] = (Q0.w + Q1.w) + (Q2.w + Q3.w);
+      }
+#pragma unroll
+      for (int i = 0; i < PER; ++i) {
+        const int key = s_tkey[(bnd * 4 + p) * PER + i];   // kKeyNone: not a used shift
+        float num = Pv[i] - mA * Sv[i];
+        float varB = Qv[i] - Sv[i] * Sv[i] / n;
+        bool flat = flatA || !(varB > kFlatRel * Qv[i]);
+        float r = flat ? 0.0f : num * rsqrtf(varA * varB);
+        if (key != kKeyNone) {
+          nflat += flat;
+          if (!g.fixed && better(r, key, best, bkey)) {
+            best = r;
+            bkey = key;
           }
-          rho[o] = r;
         }
+        rho[bnd][i] = r;
       }
     }
+    __syncthreads();
   }
   // reduce over the window's four lanes
 #pragma unroll
@@ -920,11 +948,16 @@ __global__ __launch_bounds__(NT) void k_correct_tiled(CorrArgs g) {
       bkey = ok;
     }
   }
-  __syncthreads();   // all window sums read: reuse resP of cell c00 for rho
-  if (bact) {
-    float4* d = reinterpret_cast<float4*>(resP + c00 * NSP + p * BAND);
+  // coefficients of the window for the fit, in the buffer no round reads
+  // any more: [window][band][thread][SLOTW], windows WSTR apart
+  float* const rhoW = (C::NG & 1) ? X1 : X0;
+  if (wact) {
 #pragma unroll
-    for (int v4 = 0; v4 < BAND / 4; ++v4) d[v4] = make_float4(rho[4 * v4], rho[4 * v4 + 1], rho[4 * v4 + 2], rho[4 * v4 + 3]);
+    for (int bnd = 0; bnd < C::NG; ++bnd) {
+      float* d = rhoW + w * WSTR + bnd * BANDP + p * SLOTW;
+#pragma unroll
+      for (int i = 0; i < PER; ++i) d[i] = rho[bnd][i];
+    }
   }
   __syncthreads();
   if (wact && p == 0) {
@@ -935,10 +968,11 @@ __global__ __launch_bounds__(NT) void k_correct_tiled(CorrArgs g) {
         sx = (bkey & 63) - 32;
         sy = ((bkey >> 6) & 63) - 32;
       }
-      const float* rr = resP + c00 * NSP;
+      const float* rr = rhoW + w * WSTR;
       auto rhof = [&](int y, int x) {
-        const int yi = y + R;
-        return rr[(yi / SYG) * BAND + (yi % SYG) * C::NSY + x + R];
+        const int yi = y + R, bnd = yi / SYG;
+        const int o = (yi - bnd * SYG) * C::NSY + x + R;
+        return rr[bnd * BANDP + (o / PER) * SLOTW + o % PER];
       };
       float pu = 0.0f, pv = 0.0f;
       if (Pn) window_mean_half_overlap(a, b, g.nx, g.ny, node, pu, pv);
@@ -956,8 +990,8 @@ hipError_t launch_tiled(const CorrArgs& g, int n, hipStream_t s) {
 
 template <typename T>
 hipError_t launch_tiled_t(const CorrArgs& g, int n, hipStream_t s) {
-  if (g.step == 8 && g.R == 4) return launch_tiled<T, 8, 4, 3, 8, 7, 256>(g, n, s);
-  if (g.step == 8 && g.R == 1) return launch_tiled<T, 8, 1, 1, 8, 7, 256>(g, n, s);
+  if (g.step == 8 && g.R == 4) return launch_tiled<T, 8, 4, 3, 8, 8, 256>(g, n, s);
+  if (g.step == 8 && g.R == 1) return launch_tiled<T, 8, 1, 1, 8, 8, 256>(g, n, s);
   if (g.step == 12 && g.R == 4) return launch_tiled<T, 12, 4, 3, 6, 5, 128>(g, n, s);
   if (g.step == 12 && g.R == 1) return launch_tiled<T, 12, 1, 1, 6, 5, 128>(g, n, s);
   return hipErrorInvalidValue;

@@ -144,6 +144,109 @@ __device__ __forceinline__ unsigned long long sad_key(uint32_t sad, int dy, int 
 }
 
 // ---------------------------------------------------------------------------
+// SAD block search for u8 blocks of at most 16 pixels and any R: a group of
+// G = 2R+1 lanes per node, lane q owning the candidate row dy = cand_y - R + q
+// and every candidate column, four at a time with v_qsad_pk_u16_u8 (four
+// 16-bit SADs of one A word against four byte offsets of an 8-byte B span).
+// The node's A block is staged in LDS; each lane streams its BLK rows of B.
+// Winner as in the other forms: the minimum packed key over the node's lanes.
+// ---------------------------------------------------------------------------
+template <int NW, int NGRP>
+__global__ __launch_bounds__(256) void k_sad_q(SadArgs g) {
+  constexpr int BLK = 4 * NW, RW = NW + NGRP;
+  static_assert(BLK * BLK * 255 <= 65535, "16-bit SAD fields");
+  extern __shared__ uint32_t s_ablk[];        // [npw][BLK][NW]
+  __shared__ unsigned long long s_key[256];
+
+  const WgIdx wg = xcd_order();
+  const int pair = wg.z;
+  if (slot_off(g.mask, pair)) return;
+  const int G = 2 * g.R + 1;
+  const int npw = g.npw;
+  const int t = threadIdx.x;
+  const int j = t / G, q = t - j * G;
+  const int a = wg.y;
+  const int b0 = wg.x * npw;
+  const int b = b0 + j;
+  const bool active = j < npw && b < g.nx;
+  const int off = (g.step - BLK) / 2;
+  const int oy = a * g.step + off;
+  const uint8_t* Ab = g.A + (int64_t)pair * g.stride;
+  const uint8_t* Bb = g.B + (int64_t)pair * g.stride;
+
+  const int nblk = min(npw, g.nx - b0);
+  for (int idx = t; idx < nblk * BLK * NW; idx += 256) {
+    int jj = idx / (BLK * NW), r = (idx / NW) % BLK, w = idx % NW;
+    const uint8_t* row = Ab + (int64_t)(oy + r) * g.pitch;
+    s_ablk[idx] = word_at(row, (b0 + jj) * g.step + off + 4 * w);
+  }
+
+  int cx = 0, cy = 0;
+  if (g.parent && active) {
+    const int32_t* par = g.parent + (int64_t)pair * g.pstride;
+    int pa = min(a >> 1, g.pny - 1), pb = min(b >> 1, g.pnx - 1);
+    cx = 2 * parent_value(g, par, 0, pa, pb);
+    cy = 2 * parent_value(g, par, 1, pa, pb);
+  }
+  __syncthreads();
+
+  unsigned long long best = ~0ull;
+  if (active) {
+    const int xs = b * g.step + off + cx - g.R;
+    const int xa = xs & ~3, sh = xs & 3;
+    const int by = oy + cy - g.R + q;
+    unsigned long long acc[NGRP];
+#pragma unroll
+    for (int m = 0; m < NGRP; ++m) acc[m] = 0ull;
+    const uint32_t* ablk = s_ablk + j * BLK * NW;
+#pragma unroll 4
+    for (int ar = 0; ar < BLK; ++ar) {
+      const uint32_t* row = reinterpret_cast<const uint32_t*>(Bb + (int64_t)(by + ar) * g.pitch + xa);
+      uint32_t w[RW + 1];
+#pragma unroll
+      for (int i = 0; i <= RW; ++i) w[i] = row[i];
+      uint32_t rw[RW];
+#pragma unroll
+      for (int i = 0; i < RW; ++i) rw[i] = __builtin_amdgcn_alignbyte(w[i + 1], w[i], sh);
+      uint32_t aw[NW];
+#pragma unroll
+      for (int i = 0; i < NW; ++i) aw[i] = ablk[ar * NW + i];
+#pragma unroll
+      for (int m = 0; m < NGRP; ++m) {
+        unsigned long long s = acc[m];
+#pragma unroll
+        for (int i = 0; i < NW; ++i) {
+          const unsigned long long src = ((unsigned long long)rw[i + m + 1] << 32) | rw[i + m];
+          s = __builtin_amdgcn_qsad_pk_u16_u8(src, aw[i], s);
+        }
+        acc[m] = s;
+      }
+    }
+    const int dy = cy - g.R + q;
+#pragma unroll
+    for (int m = 0; m < NGRP; ++m)
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) {
+        const int k = 4 * m + jj;
+        if (k < G) {
+          const uint32_t sad = (uint32_t)(acc[m] >> (16 * jj)) & 0xffffu;
+          unsigned long long key = sad_key(sad, dy, cx - g.R + k);
+          best = key < best ? key : best;
+        }
+      }
+  }
+  s_key[t] = best;
+  __syncthreads();
+  if (active && q == 0) {
+    unsigned long long m = s_key[t];
+    for (int k = 1; k < G; ++k) m = s_key[t + k] < m ? s_key[t + k] : m;
+    int32_t* out = g.out + (int64_t)pair * g.ostride;
+    out[a * g.nx + b] = (int)(m & 0xff) - 128;
+    out[g.nx * g.ny + a * g.nx + b] = (int)((m >> 8) & 0xff) - 128;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // SAD block search, general form: a group of G = 2R+1 lanes per node, lane k
 // owning the candidate column dx = cand_x - R + k; npw nodes of one node row
 // per workgroup.  The node's A block is staged in LDS as packed words; every
@@ -157,14 +260,15 @@ __global__ __launch_bounds__(256) void k_sad(SadArgs g) {
   extern __shared__ uint32_t s_ablk[];        // [npw][block][NW]
   __shared__ unsigned long long s_key[256];
 
-  const int pair = blockIdx.z;
+  const WgIdx wg = xcd_order();
+  const int pair = wg.z;
   if (slot_off(g.mask, pair)) return;
   const int G = 2 * g.R + 1;
   const int npw = g.npw;
   const int t = threadIdx.x;
   const int j = t / G, k = t - j * G;
-  const int a = blockIdx.y;
-  const int b0 = blockIdx.x * npw;
+  const int a = wg.y;
+  const int b0 = wg.x * npw;
   const int b = b0 + j;
   const bool active = j < npw && b < g.nx;
   const int off = (g.step - g.block) / 2;
@@ -251,9 +355,10 @@ template <int NW, int R>
 __global__ __launch_bounds__(256) void k_sad_lane(SadArgs g) {
   constexpr int BLK = 4 * NW, G = 2 * R + 1;
   constexpr int RW = NW + (2 * R + 3) / 4 + 1;   // realigned words covering BLK + 2R bytes
-  const int pair = blockIdx.y;
+  const WgIdx wg = xcd_order();
+  const int pair = wg.y;
   if (slot_off(g.mask, pair)) return;
-  const int node = blockIdx.x * blockDim.x + threadIdx.x;
+  const int node = wg.x * blockDim.x + threadIdx.x;
   if (node >= g.nx * g.ny) return;
   const int a = node / g.nx, b = node - a * g.nx;
   const int off = (g.step - BLK) / 2;
@@ -469,6 +574,19 @@ hipError_t launch_sad_level(const Plan& P, int l, const void*, const void*, int6
   }
   // nodes per workgroup: G lanes each, A blocks within 64 KiB of LDS
   const int npw = min(256 / G, 65536 / (P.block * NW * 4));
+  if (P.es == 1 && NW >= 1 && NW <= 4 && G <= 4 * 8) {
+    g.npw = npw;
+    dim3 grid((v.nx + npw - 1) / npw, v.ny, n);
+    size_t lds = sizeof(uint32_t) * (size_t)npw * P.block * NW;
+    const int ngrp = (G + 3) / 4;
+#define PIV_SAD_Q(NW_, NG_) \
+  if (NW == NW_ && ngrp == NG_) { hipLaunchKernelGGL((k_sad_q<NW_, NG_>), grid, dim3(256), lds, s, g); return hipGetLastError(); }
+#define PIV_SAD_Q_NW(NW_) PIV_SAD_Q(NW_, 1) PIV_SAD_Q(NW_, 2) PIV_SAD_Q(NW_, 3) PIV_SAD_Q(NW_, 4) \
+  PIV_SAD_Q(NW_, 5) PIV_SAD_Q(NW_, 6) PIV_SAD_Q(NW_, 7) PIV_SAD_Q(NW_, 8)
+    PIV_SAD_Q_NW(1) PIV_SAD_Q_NW(2) PIV_SAD_Q_NW(3) PIV_SAD_Q_NW(4)
+#undef PIV_SAD_Q_NW
+#undef PIV_SAD_Q
+  }
   g.npw = npw;
   dim3 grid((v.nx + npw - 1) / npw, v.ny, n);
   size_t lds = sizeof(uint32_t) * (size_t)npw * P.block * NW;

@@ -6,14 +6,16 @@ while the compute units pre- and post-process neighbouring frames, and it
 notes that small images are overhead-limited (Sec. 4.1).  Here the same
 concern is met with batching and HIP graphs:
 
-* ``GraphRunner`` captures the whole path (``piv_run``) for a fixed number
-  of slots into one HIP graph (``torch.cuda.CUDAGraph``); a device slot
-  mask lets a replay run a partial batch without recapture.
+* ``GraphRunner`` captures the whole path (``piv_run``) into HIP graphs
+  (``torch.cuda.CUDAGraph``), one per power-of-two bucket of slots up to its
+  capacity; a device slot mask lets a replay run a partial bucket without
+  recapture.
 * ``Scheduler`` is the host policy of the server (pure Python, clock and
   executor injected, so it is tested on the CPU): stream admission against
   an HBM budget, per-size-class FIFO queues, launch when a class's slots
-  are full, when its oldest request has waited ``max_wait`` or when the
-  device is idle; up to ``inflight`` batches per class on the device.
+  are full, when its oldest request has waited ``max_wait``, when the
+  device is idle or when the class has nothing on the device; up to
+  ``inflight`` batches per class on the device.
 * ``GpuExecutor`` runs a class's batch as one graph replay on that class's
   own stream (classes overlap on the device) and polls HIP events for
   completion.
@@ -33,10 +35,14 @@ from typing import Callable, Deque, Dict, List, Optional, Sequence, Tuple
 
 
 class GraphRunner:
-    """Static slot buffers + one captured graph of the whole path.
+    """Static slot buffers + captured graphs of the whole path.
 
-    The plan must be dedicated to this runner (its workspace and slot mask
-    are used by the captured kernels), with max_batch >= slots."""
+    One graph per bucket size (1, 2, 4, ... up to ``slots``), each over the
+    first n slots, so that a partial batch launches grids for the smallest
+    bucket that holds it instead of the full capacity; the device slot mask
+    switches off the bucket's unused slots.  The plan must be dedicated to
+    this runner (its workspace and slot mask are used by the captured
+    kernels), with max_batch >= slots."""
 
     def __init__(self, plan, slots: int, stream=None):
         import torch
@@ -56,43 +62,61 @@ class GraphRunner:
                         omega=torch.zeros((slots, ny, nx), device=dev))
         self.mask = torch.ones((slots,), dtype=torch.uint8, device=dev)
         self.stream = stream if stream is not None else torch.cuda.Stream(device=dev)
-        self.graph = None
+        b, self.buckets = 1, []
+        while b < slots:
+            self.buckets.append(b)
+            b *= 2
+        self.buckets.append(slots)
+        self.graphs: Dict[int, object] = {}
+
+    @property
+    def graph(self):
+        return self.graphs.get(self.slots)
 
     def resident_bytes(self) -> int:
         t = [self.A, self.B, self.mask] + list(self.out.values())
         return sum(x.numel() * x.element_size() for x in t) + self.plan.workspace_bytes(self.slots)
 
+    def bucket(self, n: int) -> int:
+        return next(b for b in self.buckets if b >= n)
+
     def capture(self) -> None:
         torch = self.torch
         self.plan.bind_slot_mask(self.mask)
-        # warm up on the capture stream, then capture
         self.stream.wait_stream(torch.cuda.current_stream())
-        with torch.cuda.stream(self.stream):
-            self.plan.run(self.A, self.B, self.out)
-        self.stream.synchronize()
-        self.graph = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(self.graph, stream=self.stream):
-            self.plan.run(self.A, self.B, self.out)
-        self.stream.synchronize()
+        for n in self.buckets:
+            A, B = self.A[:n], self.B[:n]
+            out = {k: v[:n] for k, v in self.out.items()}
+            # warm up on the capture stream, then capture
+            with torch.cuda.stream(self.stream):
+                self.plan.run(A, B, out)
+            self.stream.synchronize()
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=self.stream):
+                self.plan.run(A, B, out)
+            self.stream.synchronize()
+            self.graphs[n] = g
 
-    def set_active(self, n: int) -> None:
-        """Slots [0, n) run, the rest are skipped (a small fill kernel on the
-        runner's stream; no memset node)."""
+    def set_active(self, n: int, upto: Optional[int] = None) -> None:
+        """Slots [0, n) run, slots [n, upto) are skipped (small fill kernels
+        on the runner's stream; no memset node)."""
+        upto = self.slots if upto is None else upto
         with self.torch.cuda.stream(self.stream):
             self.mask[:n].fill_(1)
-            if n < self.slots:
-                self.mask[n:].fill_(0)
+            if n < upto:
+                self.mask[n:upto].fill_(0)
 
     def replay(self, n: Optional[int] = None) -> None:
-        """Replay after all work already queued on the caller's current
-        stream (input copies, for instance)."""
-        if self.graph is None:
+        """Replay the graph of the smallest bucket holding n slots (all slots
+        when n is None), after all work already queued on the caller's
+        current stream (input copies, for instance)."""
+        if not self.graphs:
             self.capture()
         self.stream.wait_stream(self.torch.cuda.current_stream())
-        if n is not None:
-            self.set_active(n)
+        b = self.slots if n is None else self.bucket(n)
+        self.set_active(self.slots if n is None else n, b)
         with self.torch.cuda.stream(self.stream):
-            self.graph.replay()
+            self.graphs[b].replay()
 
 
 # ----------------------------------------------------------------------------
@@ -142,7 +166,9 @@ class Scheduler:
     * step(now): completes finished batches, then launches, per class and
       while that class has fewer than ``inflight`` batches on the device,
       the oldest ``capacity`` requests when the queue is full, when the
-      oldest has waited ``max_wait``, or when the device is idle.
+      oldest has waited ``max_wait``, when the device is idle, or when the
+      class has no batch on the device (so light load never waits and heavy
+      load batches by itself).
     """
 
     def __init__(self, classes: Sequence[ClassSpec], executor: Executor, budget: int,
@@ -243,7 +269,10 @@ class Scheduler:
             while q and len(self.running[cls]) < self.inflight:
                 full = len(q) >= cap
                 late = now - q[0].arrival >= self.max_wait
-                if not (full or late or idle):
+                # a class with nothing on the device launches at once: its
+                # requests never wait behind another class's batch
+                cls_idle = not self.running[cls]
+                if not (full or late or idle or cls_idle):
                     break
                 batch = [q.popleft() for _ in range(min(cap, len(q)))]
                 for r in batch:

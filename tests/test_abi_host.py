@@ -144,6 +144,11 @@ def test_padded_pyramid_holds_every_sad_read(L, kw):
             # RW + 1 words with RW = NW + (2R+3)//4 + 1
             start = ((v["nx"] - 1) * step + off + cand - R) * es
             span = 4 * (NW + (2 * R + 3) // 4 + 2)
+        elif es == 1 and NW <= 4 and 2 * R + 1 <= 32:
+            # a lane per candidate row (quad SAD): from the floor word of the
+            # leftmost shift, RW + 1 words with RW = NW + ceil((2R+1)/4)
+            start = ((v["nx"] - 1) * step + off + cand - R) * es
+            span = 4 * (NW + (2 * R + 4) // 4 + 1)
         else:
             # G lanes per node: each from the floor word of its own shift, NW + 1 words
             start = ((v["nx"] - 1) * step + off + cand + R) * es

@@ -1,0 +1,116 @@
+"""Parity at the benchmark's full size and launch configuration: one batch of
+64 pairs of 1024 x 1024 u8 (eight distinct rendered pairs, each eight times,
+exactly as bench.py runs them) through one piv_run.  Against the FP64 oracle:
+
+* the predictor at every node of every distinct pair (bit-exact);
+* the correction at sampled nodes (edges, corners and random interior nodes),
+  called again with the same kernel and launch configuration on the run's own
+  predictor: displacement within 0.01 px, coefficient within 2e-5, flags
+  exact, unless the oracle's plane shows a near-tie;
+* validation and vorticity on the whole grid, from the GPU's correction;
+* all eight copies of a pair give bitwise identical results.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from _helpers import NEAR_TIE_RHO, NEAR_TIE_UOD, TOL_DISP_PX, TOL_REL, TOL_RHO, corr_gap, say, uod_r0
+from paper_2504_17987_amd import synth
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a HIP device")]
+
+KW = dict(win=16, step=8, radius=4, levels=3, radius_coarse=6, radius_fine=2)
+ND, NB, W, H = 8, 64, 1024, 1024
+
+
+@pytest.fixture(scope="module")
+def fullsize():
+    from paper_2504_17987_amd import api
+    say("[fullsize] rendering 8 distinct 1024x1024 pairs")
+    pairs = [synth.cfg2_pair(2000 + i) for i in range(ND)]
+    A = torch.empty((NB, H, W), dtype=torch.uint8, device="cuda")
+    B = torch.empty_like(A)
+    for k in range(NB):
+        A[k].copy_(torch.from_numpy(pairs[k % ND][0]))
+        B[k].copy_(torch.from_numpy(pairs[k % ND][1]))
+    P = api.Plan(W, H, max_batch=NB, **KW)
+    say("[fullsize] piv_run, batch 64")
+    out = P.run(A, B)
+    disp = torch.empty_like(out["disp"])
+    peak = torch.empty_like(out["peak"])
+    flags = torch.empty_like(out["flags"])
+    say("[fullsize] piv_correct on the run's predictor")
+    P.correct(A, B, out["pred"], disp, peak, flags)
+    torch.cuda.synchronize()
+    host = {k: v.cpu().numpy() for k, v in out.items()}
+    corr = dict(disp=disp.cpu().numpy(), peak=peak.cpu().numpy(), flags=flags.cpu().numpy())
+    return pairs, host, corr
+
+
+def test_fullsize_copies_identical(fullsize):
+    _, g, c = fullsize
+    for k in range(ND, NB):
+        for name in ("pred", "disp", "peak", "flags", "omega"):
+            assert np.array_equal(g[name][k], g[name][k % ND]), (name, k)
+        for name in ("disp", "peak", "flags"):
+            assert np.array_equal(c[name][k], c[name][k % ND]), (name, k)
+
+
+def test_fullsize_predictor_bitexact(fullsize):
+    pairs, g, _ = fullsize
+    for i in range(ND):
+        A, B, _ = pairs[i]
+        po = oracle.predict(A, B, 8, 16, 3, 6, 2).astype(np.float64)
+        po, _ = oracle.validate(po, None)
+        say(f"  pair {i}: predictor range {po.min():.0f}..{po.max():.0f}")
+        assert np.array_equal(g["pred"][i], po.astype(np.float32)), i
+
+
+def _sample_nodes(rng, ny, nx, k):
+    edge = [(0, 0), (0, nx - 1), (ny - 1, 0), (ny - 1, nx - 1), (0, nx // 2), (ny // 2, 0),
+            (ny - 1, nx // 3), (ny // 3, nx - 1), (7, 8), (8, 7), (63, 64), (64, 63)]
+    inner = [(int(a), int(b)) for a, b in zip(rng.integers(0, ny, k), rng.integers(0, nx, k))]
+    return edge + inner
+
+
+def test_fullsize_correction_sampled(fullsize):
+    pairs, g, c = fullsize
+    rng = np.random.default_rng(2504)
+    ny, nx = g["pred"].shape[2:]
+    ties = 0
+    worst = 0.0
+    for i in range(ND):
+        A, B, _ = pairs[i]
+        Ad, Bd = A.astype(np.float64), B.astype(np.float64)
+        pred = g["pred"][i].astype(np.float64)   # bit-exact with the oracle's (checked above)
+        for a, b in _sample_nodes(rng, ny, nx, 48):
+            du, dv, pk, fl = oracle.correct_node(Ad, Bd, 16, 8, 4, pred, a, b)
+            d = max(abs(c["disp"][i, 0, a, b] - du), abs(c["disp"][i, 1, a, b] - dv))
+            ok = d <= TOL_DISP_PX and abs(c["peak"][i, a, b] - pk) <= TOL_RHO and c["flags"][i, a, b] == fl
+            if not ok:
+                gap = corr_gap(Ad, Bd, 16, 8, 4, 0, pred, a, b)
+                assert gap < NEAR_TIE_RHO, (i, a, b, c["disp"][i, :, a, b], (du, dv), gap)
+                ties += 1
+            else:
+                worst = max(worst, d)
+    say(f"  max |d disp| {worst:.2e} px, near-tie exemptions {ties}")
+    assert ties <= 2
+
+
+def test_fullsize_validation_and_vorticity(fullsize):
+    _, g, c = fullsize
+    for i in range(ND):
+        f = c["disp"][i].astype(np.float64)
+        fl = c["flags"][i].copy()
+        vo, flo = oracle.validate(f, fl)
+        bad = (np.abs(g["disp"][i] - vo).max(axis=0) > 1e-5) | (g["flags"][i] != flo)
+        ny, nx = fl.shape
+        for a, b in zip(*np.nonzero(bad)):
+            near = [abs(uod_r0(f, c["flags"][i], y, x) - 2.0) for y in range(a - 1, a + 2)
+                    for x in range(b - 1, b + 2) if 0 <= y < ny and 0 <= x < nx]
+            assert min(near) < NEAR_TIE_UOD, (i, a, b)
+        assert bad.sum() <= 2
+        om = oracle.vorticity(g["disp"][i].astype(np.float64), 8)
+        assert np.abs(g["omega"][i] - om).max() <= TOL_REL * np.abs(om).max(), i

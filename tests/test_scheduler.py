@@ -105,3 +105,14 @@ def test_admission_respects_budget_and_releases():
     assert 3 not in sched.admitted                 # its class alone exceeds the budget: still waiting
     sched.set_budget(2 * 40_000 + 4_000)           # more memory: waiting streams are re-tried
     assert 3 in sched.admitted and sched.used == sched.budget
+
+
+def test_idle_class_launches_while_another_class_runs():
+    # a long batch of the large class is on the device; a small request that
+    # arrives meanwhile starts at once instead of waiting for max_wait
+    sched, ex, clock = make(max_wait=1.0, dur=lambda c, n: 5e-3 if c == "l" else 1e-4)
+    sched.admit(0, "l")
+    sched.admit(1, "s")
+    trace = [Request(0, 0, "l", 0, 0.0), Request(1, 1, "s", 0, 1e-3)]
+    simulate(sched, clock, trace)
+    assert trace[1].start - trace[1].arrival < 2e-5
