@@ -392,7 +392,10 @@ struct TileCfg {
 template <typename T, int STEP, int R, int SYG, int TW, int TH, int NT>
 __global__ __launch_bounds__(NT) void k_correct_tiled(CorrArgs g) {
   using C = TileCfg<STEP, R, SYG, TW, TH>;
-  static_assert(C::NG * C::NC <= NT, "one thread per (cell, shift band)");
+  // workers: whole cell rows per wave (lane = row-in-wave * CW + column),
+  // so that a cell's right-hand neighbour is the next lane of its wave
+  constexpr int RPW = 64 / C::CW;
+  static_assert((NT / 64) * RPW >= C::NG * C::CH, "one thread per (cell, shift band)");
   static_assert(4 * C::NWIN <= NT, "four threads per window");
   __shared__ __align__(16) float s_u[C::UNION];
   __shared__ float s_node[2][C::NNY][C::NNX];
@@ -760,9 +763,12 @@ __global__ __launch_bounds__(NT) void k_correct_tiled(CorrArgs g) {
   constexpr int BRW = STEP + 2 * R;   // B' columns one cell row needs
   float Pacc[SYG][C::NSY];
   float Sacc[SYG][C::NSY], Qacc[SYG][C::NSY];
-  const bool worker = t < C::NG * C::NC;
-  const int grp = t / C::NC, cell = t - grp * C::NC;
-  const int ci = cell / C::CW, cj = cell - (cell / C::CW) * C::CW;
+  const int lrow = (t & 63) / C::CW;
+  const int cj = (t & 63) - lrow * C::CW;
+  const int grow = (t >> 6) * RPW + lrow;                // over (band, cell row)
+  const bool worker = lrow < RPW && grow < C::NG * C::CH;
+  const int grp = grow / C::CH, ci = grow - grp * C::CH;
+  const int cell = ci * C::CW + cj;
   if (worker) {
 #pragma unroll
     for (int k = 0; k < SYG; ++k)
@@ -850,10 +856,16 @@ __global__ __launch_bounds__(NT) void k_correct_tiled(CorrArgs g) {
   const int w = t >> 2, p = t & 3;
   const bool wact = t < 4 * C::NWIN;
   const int wi = w / TW, wj = w - (w / TW) * TW;
-  const int c00 = wi * C::CW + wj, c01 = c00 + 1, c10 = c00 + C::CW, c11 = c10 + 1;
+  const int c00 = wi * C::CW + wj, c10 = c00 + C::CW;
+  // a cell plus its right-hand neighbour (the next lane: wave_shl:1 DPP);
+  // the sum is garbage only in the last column, which no window uses
+  auto hpair = [](float x) {
+    return x + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x130, 0xF, 0xF, false));
+  };
   auto write_band = [&](float* X) {
     // slot o of the band (row o / NSY, column o % NSY) sits at
-    // (o / PER) * SLOTW + o % PER
+    // (o / PER) * SLOTW + o % PER; what is stored is the sum over the cell
+    // and its right-hand neighbour
 #pragma unroll
     for (int v4 = 0; v4 < BANDP / 4; ++v4) {
       float p4[4], s4[4], q4[4];
@@ -863,9 +875,9 @@ __global__ __launch_bounds__(NT) void k_correct_tiled(CorrArgs g) {
         const int o = th * PER + i;
         const bool real = i < PER && o < NB;
         const int k = real ? o / C::NSY : 0, j = real ? o % C::NSY : 0;
-        p4[e] = real ? Pacc[k][j] : 0.0f;
-        s4[e] = real ? Sacc[k][j] : 0.0f;
-        q4[e] = real ? Qacc[k][j] : 1.0f;
+        p4[e] = real ? hpair(Pacc[k][j]) : 0.0f;
+        s4[e] = real ? hpair(Sacc[k][j]) : 0.0f;
+        q4[e] = real ? hpair(Qacc[k][j]) : 1.0f;
       }
       reinterpret_cast<float4*>(X + cell * CSTR)[v4] = make_float4(p4[0], p4[1], p4[2], p4[3]);
       reinterpret_cast<float4*>(X + XB / 3 + cell * CSTR)[v4] = make_float4(s4[0], s4[1], s4[2], s4[3]);
@@ -902,21 +914,23 @@ __global__ __launch_bounds__(NT) void k_correct_tiled(CorrArgs g) {
         auto ld = [&](int arr, int c) {
           return reinterpret_cast<const float4*>(X + arr * (XB / 3) + c * CSTR + p * SLOTW)[v4];
         };
-        const float4 P0 = ld(0, c00), P1 = ld(0, c01), P2 = ld(0, c10), P3 = ld(0, c11);
-        const float4 S0 = ld(1, c00), S1 = ld(1, c01), S2 = ld(1, c10), S3 = ld(1, c11);
-        const float4 Q0 = ld(2, c00), Q1 = ld(2, c01), Q2 = ld(2, c10), Q3 = ld(2, c11);
-        Pv[4 * v4 + 0] = (P0.x + P1.x) + (P2.x + P3.x);
-        Pv[4 * v4 + 1] = (P0.y + P1.y) + (P2.y + P3.y);
-        Pv[4 * v4 + 2] = (P0.z + P1.z) + (P2.z + P3.z);
-        Pv[4 * v4 + 3] = (P0.w + P1.w) + (P2.w + P3.w);
-        Sv[4 * v4 + 0] = (S0.x + S1.x) + (S2.x + S3.x);
-        Sv[4 * v4 + 1] = (S0.y + S1.y) + (S2.y + S3.y);
-        Sv[4 * v4 + 2] = (S0.z + S1.z) + (S2.z + S3.z);
-        Sv[4 * v4 + 3] = (S0.w + S1.w) + (S2.w + S3.w);
-        Qv[4 * v4 + 0] = (Q0.x + Q1.x) + (Q2.x + Q3.x);
-        Qv[4 * v4 + 1] = (Q0.y + Q1.y) + (Q2.y + Q3.y);
-        Qv[4 * v4 + 2] = (Q0.z + Q1.z) + (Q2.z + Q3.z);
-        Qv[4 * v4 + 3] = (Q0.w + Q1.w) + (Q2.w + Q3.w);
+        // stored values already hold (cell + right neighbour): the window
+        // is its top pair plus its bottom pair
+        const float4 P0 = ld(0, c00), P2 = ld(0, c10);
+        const float4 S0 = ld(1, c00), S2 = ld(1, c10);
+        const float4 Q0 = ld(2, c00), Q2 = ld(2, c10);
+        Pv[4 * v4 + 0] = P0.x + P2.x;
+        Pv[4 * v4 + 1] = P0.y + P2.y;
+        Pv[4 * v4 + 2] = P0.z + P2.z;
+        Pv[4 * v4 + 3] = P0.w + P2.w;
+        Sv[4 * v4 + 0] = S0.x + S2.x;
+        Sv[4 * v4 + 1] = S0.y + S2.y;
+        Sv[4 * v4 + 2] = S0.z + S2.z;
+        Sv[4 * v4 + 3] = S0.w + S2.w;
+        Qv[4 * v4 + 0] = Q0.x + Q2.x;
+        Qv[4 * v4 + 1] = Q0.y + Q2.y;
+        Qv[4 * v4 + 2] = Q0.z + Q2.z;
+        Qv[4 * v4 + 3] = Q0.w + Q2.w;
       }
 #pragma unroll
       for (int i = 0; i < PER; ++i) {
