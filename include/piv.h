@@ -120,7 +120,11 @@ size_t piv_plan_workspace_bytes(piv_plan_t plan, int32_t batch);
 
 /* Bind caller-owned device workspace (e.g. a torch tensor) to the plan.
  * The plan remembers how many pairs it can hold; later calls with a larger
- * n fail with PIV_ENOWORKSPACE.  The memory must outlive its use. */
+ * n fail with PIV_ENOWORKSPACE.  The memory must outlive its use.  The
+ * first piv_predict after binding also zeroes the pyramid margins in the
+ * whole workspace (on that call's stream) and later calls rely on them:
+ * the caller must not write to bound workspace; binding again (the same
+ * pointer included) repeats the zeroing. */
 piv_status piv_plan_bind_workspace(piv_plan_t plan, void* d_ws, size_t bytes);
 
 /* Optional device slot mask uint8 [max_batch]: when bound, every kernel of

@@ -41,6 +41,9 @@ struct Plan {
   size_t ws_bytes = 0;
   int ws_pairs = 0;   // pairs the bound workspace can hold
   const uint8_t* slot_mask = nullptr;
+  // the pyramid margins of the bound workspace have been zeroed (they are
+  // written once, at the first predict after binding)
+  mutable bool margins_clean = false;
 };
 
 // Image view of one frame batch.

@@ -139,7 +139,7 @@ piv_status piv_plan(const piv_params* pp, piv_plan_t* out) {
     // node grid may overhang the image by < step; block offset (block-step)/2;
     // word-granular loads read up to 8 bytes past the search span
     int m = p.step + (block - p.step) / 2 + cand + v.R + 8;
-    v.margin = (m + 3) & ~3;
+    v.margin = (m + 15) & ~15;   // 16 px: every level's core starts 16-byte aligned
     v.pitch = (int)((size_t)((v.W + 2 * v.margin) * es + 63) & ~size_t(63));
     v.rows = v.H + 2 * v.margin;
   }
@@ -181,6 +181,7 @@ piv_status piv_plan_bind_workspace(piv_plan_t plan, void* d_ws, size_t bytes) {
   P->ws = static_cast<uint8_t*>(d_ws);
   P->ws_bytes = d_ws ? bytes : 0;
   P->ws_pairs = d_ws ? (int)(bytes / P->per_pair) : 0;
+  P->margins_clean = false;
   if (d_ws && P->ws_pairs == 0) {
     P->ws = nullptr;
     return fail(PIV_ENOWORKSPACE, "workspace of %zu bytes holds no pair (need %zu)", bytes, P->per_pair);

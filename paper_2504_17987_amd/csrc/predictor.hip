@@ -16,37 +16,100 @@ namespace piv {
 namespace {
 
 // ---------------------------------------------------------------------------
-// Padded copy of level 0: one thread per 4-byte word of the padded image;
-// words outside the image core are zero.
+// Zero margins of one padded level (both frames, every pair the workspace
+// holds): every 4-byte word of a padded row that lies wholly outside the
+// image core.  The copy kernels below write the core only (plus the zero
+// tail of a ragged last word), so this runs once per bound workspace.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_pad_copy(const uint8_t* __restrict__ A, const uint8_t* __restrict__ B,
-                                                  int64_t spitch, int64_t sstride, int rowbytes, int H,
-                                                  uint8_t* ws, int64_t offA, int64_t offB, int dpitch,
-                                                  int drows, int mbytes, int mrows, int64_t dstride,
-                                                  const uint8_t* mask) {
+__global__ __launch_bounds__(256) void k_clear_margins(uint8_t* ws, int64_t stride, int64_t offA, int64_t offB,
+                                                       int pitch, int rows, int mbytes, int cbytes, int mrows,
+                                                       int H) {
+  const int pair = blockIdx.z >> 1, frame = blockIdx.z & 1;
+  const int nw = pitch / 4;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = (int)(idx / nw);
+  const int w = (int)(idx - (int64_t)y * nw);
+  if (y >= rows) return;
+  const int xb = 4 * w;
+  const int core_end = (mbytes + cbytes + 3) & ~3;   // end of the last (maybe ragged) core word
+  const bool core_row = y >= mrows && y < mrows + H;
+  if (core_row && xb + 4 > mbytes && xb < core_end) return;
+  uint8_t* row = ws + (int64_t)pair * stride + (frame ? offB : offA) + (int64_t)y * pitch;
+  *reinterpret_cast<uint32_t*>(row + xb) = 0u;
+}
+
+// ---------------------------------------------------------------------------
+// Level 0 core copy fused with level 1: one thread per pair of image rows
+// (2k, 2k+1) and 16-byte column chunk.  It copies both rows into the padded
+// level-0 buffer and writes the 2x2 means of the chunk into level 1:
+// out(y,x) = floor((in(2y,2x) + in(2y,2x+1) + in(2y+1,2x) + in(2y+1,2x+1) + 2) / 4),
+// zero outside the level-1 image.  Rows and columns past the image read as
+// zero (the level's margin).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_pad_pyr(const uint8_t* __restrict__ A, const uint8_t* __restrict__ B,
+                                                 int64_t spitch, int64_t sstride, int W, int H, uint8_t* ws,
+                                                 int64_t stride, int64_t offA0, int64_t offB0, int pitch0,
+                                                 int m0, int64_t offA1, int64_t offB1, int pitch1, int m1,
+                                                 int W1, int H1, int do_l1, const uint8_t* mask) {
+  constexpr int ES = (int)sizeof(T);
   const int pair = blockIdx.z >> 1, frame = blockIdx.z & 1;
   if (slot_off(mask, pair)) return;
-  const int nq = dpitch / 16;                     // 16-byte chunks per padded row
+  const int rowbytes = W * ES;
+  const int nq = (rowbytes + 15) / 16;
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  const int y = idx / nq;                         // padded row
-  const int q = idx - y * nq;
-  if (y >= drows) return;
-  const int sy = y - mrows;
-  uint4 v = make_uint4(0u, 0u, 0u, 0u);
-  if (sy >= 0 && sy < H) {
-    const uint8_t* row = (frame ? B : A) + (int64_t)pair * sstride + (int64_t)sy * spitch;
-    const int xb = q * 16 - mbytes;                // byte offset in the source row
-    const int xa = xb & ~3, sh = xb & 3;
-    uint32_t w[5];
+  const int k = idx / nq, q = idx - (idx / nq) * nq;
+  if (k >= (H + 1) / 2) return;
+  const uint8_t* src = (frame ? B : A) + (int64_t)pair * sstride;
+  uint32_t w[2][4];
+  // whole chunks of rows inside the image, from 16-byte aligned addresses,
+  // take one 16-byte read; the ragged right end and a missing last row are
+  // read word by word with zero fill
+  const bool whole = 16 * q + 16 <= rowbytes && ((reinterpret_cast<uintptr_t>(src) | spitch) & 15) == 0;
 #pragma unroll
-    for (int i = 0; i < 5; ++i) w[i] = masked_word(row, rowbytes, xa + 4 * i);
-    v.x = __builtin_amdgcn_alignbyte(w[1], w[0], sh);
-    v.y = __builtin_amdgcn_alignbyte(w[2], w[1], sh);
-    v.z = __builtin_amdgcn_alignbyte(w[3], w[2], sh);
-    v.w = __builtin_amdgcn_alignbyte(w[4], w[3], sh);
+  for (int r = 0; r < 2; ++r) {
+    const int y = 2 * k + r;
+    const uint8_t* row = src + (int64_t)min(y, H - 1) * spitch;
+    if (whole && y < H) {
+      const uint4 v = *reinterpret_cast<const uint4*>(row + 16 * q);
+      w[r][0] = v.x; w[r][1] = v.y; w[r][2] = v.z; w[r][3] = v.w;
+    } else {
+      const uint32_t ok = y < H ? 0xffffffffu : 0u;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) w[r][i] = masked_word(row, rowbytes, 16 * q + 4 * i) & ok;
+    }
   }
-  uint8_t* out = ws + (int64_t)pair * dstride + (frame ? offB : offA) + (int64_t)y * dpitch;
-  reinterpret_cast<uint4*>(out)[q] = v;
+  uint8_t* base = ws + (int64_t)pair * stride;
+  const int x0 = m0 * ES + 16 * q;   // byte offset of the chunk in a padded level-0 row (16-aligned)
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+    uint8_t* row = base + (frame ? offB0 : offA0) + (int64_t)(2 * k + r + m0) * pitch0;
+    if (x0 + 16 <= pitch0) *reinterpret_cast<uint4*>(row + x0) = make_uint4(w[r][0], w[r][1], w[r][2], w[r][3]);
+  }
+  if (!do_l1) return;
+  // the chunk's 16 / ES pixels of each row -> 8 / ES level-1 pixels
+  constexpr int NP = 16 / ES, NO = NP / 2;
+  uint32_t s[NO];
+#pragma unroll
+  for (int j = 0; j < NO; ++j) {
+    uint32_t acc = 2u;
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int px = 2 * j + h;                  // pixel in the chunk
+        const int bit = (px * ES * 8) & 31, wd = (px * ES) / 4;
+        acc += (w[r][wd] >> bit) & (ES == 1 ? 0xffu : 0xffffu);
+      }
+    const int x1 = q * NO + j;
+    s[j] = (k < H1 && x1 < W1) ? (acc >> 2) : 0u;
+  }
+  uint32_t o[2] = {0u, 0u};
+#pragma unroll
+  for (int j = 0; j < NO; ++j) o[(j * ES) / 4] |= s[j] << ((j * ES * 8) & 31);
+  uint8_t* row1 = base + (frame ? offB1 : offA1) + (int64_t)(k + m1) * pitch1;
+  const int x1b = m1 * ES + 8 * q;   // 8-byte aligned
+  if (x1b + 8 <= pitch1) *reinterpret_cast<uint2*>(row1 + x1b) = make_uint2(o[0], o[1]);
 }
 
 // ---------------------------------------------------------------------------
@@ -504,16 +567,36 @@ bool sad_supported(int block_words) {
 
 hipError_t launch_pyramid(const Plan& P, const void* A, const void* B, int64_t pitch, int n,
                           hipStream_t s) {
+  if (!P.margins_clean) {
+    // every level's margins, for every pair the workspace holds
+    for (int l = 0; l < P.L; ++l) {
+      const Level& v = P.lv[l];
+      const int64_t words = (int64_t)(v.pitch / 4) * v.rows;
+      dim3 grid((unsigned)((words + 255) / 256), 1, 2 * P.ws_pairs);
+      hipLaunchKernelGGL(k_clear_margins, grid, dim3(256), 0, s, P.ws, (int64_t)P.per_pair, (int64_t)v.off_a,
+                         (int64_t)v.off_b, v.pitch, v.rows, v.margin * P.es, v.W * P.es, v.margin, v.H);
+      if (hipError_t e = hipGetLastError()) return e;
+    }
+    P.margins_clean = true;
+  }
   const Level& v0 = P.lv[0];
   {
-    // one thread per 16-byte chunk of the padded image, rows x chunks flattened
-    dim3 grid(((v0.pitch / 16) * v0.rows + 255) / 256, 1, 2 * n);
-    hipLaunchKernelGGL(k_pad_copy, grid, dim3(256), 0, s, (const uint8_t*)A, (const uint8_t*)B, pitch,
-                       pitch * P.p.height, v0.W * P.es, v0.H, P.ws, (int64_t)v0.off_a, (int64_t)v0.off_b,
-                       v0.pitch, v0.rows, v0.margin * P.es, v0.margin, (int64_t)P.per_pair, P.slot_mask);
+    const Level& v1 = P.lv[P.L > 1 ? 1 : 0];
+    const int nq = (v0.W * P.es + 15) / 16;
+    dim3 grid((nq * ((v0.H + 1) / 2) + 255) / 256, 1, 2 * n);
+    if (P.es == 1)
+      hipLaunchKernelGGL(k_pad_pyr<uint8_t>, grid, dim3(256), 0, s, (const uint8_t*)A, (const uint8_t*)B, pitch,
+                         pitch * P.p.height, v0.W, v0.H, P.ws, (int64_t)P.per_pair, (int64_t)v0.off_a,
+                         (int64_t)v0.off_b, v0.pitch, v0.margin, (int64_t)v1.off_a, (int64_t)v1.off_b, v1.pitch,
+                         v1.margin, v1.W, v1.H, P.L > 1 ? 1 : 0, P.slot_mask);
+    else
+      hipLaunchKernelGGL(k_pad_pyr<uint16_t>, grid, dim3(256), 0, s, (const uint8_t*)A, (const uint8_t*)B, pitch,
+                         pitch * P.p.height, v0.W, v0.H, P.ws, (int64_t)P.per_pair, (int64_t)v0.off_a,
+                         (int64_t)v0.off_b, v0.pitch, v0.margin, (int64_t)v1.off_a, (int64_t)v1.off_b, v1.pitch,
+                         v1.margin, v1.W, v1.H, P.L > 1 ? 1 : 0, P.slot_mask);
     if (hipError_t e = hipGetLastError()) return e;
   }
-  for (int l = 1; l < P.L; ++l) {
+  for (int l = 2; l < P.L; ++l) {
     const Level& u = P.lv[l - 1];
     const Level& v = P.lv[l];
     const int dcols = v.pitch / P.es;

@@ -160,4 +160,4 @@ def test_padded_pyramid_holds_every_sad_read(L, kw):
         if l > 0:
             u = lv[l - 1]
             assert 2 * v["H"] - 1 < u["H"] + u["margin"] and 2 * v["W"] - 1 < u["W"] + u["margin"]
-        assert v["pitch"] % 64 == 0 and M % 4 == 0
+        assert v["pitch"] % 64 == 0 and M % 16 == 0
