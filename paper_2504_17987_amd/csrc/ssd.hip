@@ -215,6 +215,260 @@ __global__ __launch_bounds__(256) void k_ssd_backward(SsdArgs a, int TN) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Tiled forms for win = 2 step (the plans' geometry).  A workgroup owns a
+// TN x TN tile (of windows forward, of nodes backward).  The nodes covering
+// the tile's pixel region are cached in LDS with per-row / per-column
+// interpolation tables; samples of A and B are read from global memory (L1
+// serves the bilinear neighbours), which keeps LDS small and occupancy high
+// enough to hide the read latency.
+// ---------------------------------------------------------------------------
+template <int STEP, int TN>
+struct SsdTile {
+  static constexpr int H2 = STEP / 2;                 // (win - step) / 2
+  static constexpr int RW = (TN + 1) * STEP;          // max region side (px)
+  static constexpr int NNC = RW / STEP + 3;           // cached node rows / columns
+  static constexpr int NG = RW / STEP + 2;            // cached window rows / columns
+};
+
+// The cached nodes and tables of a region [ylo, ylo+RH) x [xlo, xlo+RW_).
+template <int STEP, int TN>
+struct SsdShared {
+  using C = SsdTile<STEP, TN>;
+  float node[2][C::NNC][C::NNC];
+  int rb[C::RW], cb[C::RW];       // base node (cache index)
+  float rf[C::RW], cf[C::RW];     // fraction towards base + 1
+};
+
+// Loads the node cache and the interpolation tables of the region rows and
+// columns (base node as a cache index, fraction towards base + 1).
+template <int STEP, int TN>
+__device__ __forceinline__ void ssd_prepare(const SsdArgs& a, const float* U, int ylo, int xlo, int RH, int RWc,
+                                            SsdShared<STEP, TN>& sh, int& nly, int& nlx) {
+  using C = SsdTile<STEP, TN>;
+  const int t = threadIdx.x;
+  const float cen = 0.5f * (float)(STEP - 1);
+  nly = max(0, (int)floorf(((float)ylo - cen) / STEP));
+  nlx = max(0, (int)floorf(((float)xlo - cen) / STEP));
+  const int np = a.nx * a.ny;
+  for (int i = t; i < C::NNC * C::NNC; i += 256) {
+    const int r = i / C::NNC, q = i - (i / C::NNC) * C::NNC;
+    const int ny_ = min(nly + r, a.ny - 1), nx_ = min(nlx + q, a.nx - 1);
+    sh.node[0][r][q] = U[ny_ * a.nx + nx_];
+    sh.node[1][r][q] = U[np + ny_ * a.nx + nx_];
+  }
+  for (int i = t; i < RH + RWc; i += 256) {
+    const bool row = i < RH;
+    const int pp = row ? ylo + i : xlo + (i - RH);
+    const int n = row ? a.ny : a.nx;
+    int bb;
+    float ff;
+    node_coord((float)pp, n, STEP, bb, ff);
+    if (row) { sh.rb[i] = bb - nly; sh.rf[i] = ff; }
+    else { sh.cb[i - RH] = bb - nlx; sh.cf[i - RH] = ff; }
+  }
+  __syncthreads();
+}
+
+// residual r = B'(p) - A(p) at region pixel (i, j) = (y - ylo, x - xlo), and
+// the floor-cell gradient of the sample
+template <int STEP, int TN>
+__device__ __forceinline__ void ssd_residual(const SsdArgs& a, const float* A, const float* B,
+                                             const SsdShared<STEP, TN>& sh, int ylo, int xlo, int i, int j,
+                                             float& r, float& gx, float& gy) {
+  const int rb = sh.rb[i], cb = sh.cb[j];
+  const float fy = sh.rf[i], fx = sh.cf[j];
+  const float u = (1.0f - fy) * ((1.0f - fx) * sh.node[0][rb][cb] + fx * sh.node[0][rb][cb + 1]) +
+                  fy * ((1.0f - fx) * sh.node[0][rb + 1][cb] + fx * sh.node[0][rb + 1][cb + 1]);
+  const float v = (1.0f - fy) * ((1.0f - fx) * sh.node[1][rb][cb] + fx * sh.node[1][rb][cb + 1]) +
+                  fy * ((1.0f - fx) * sh.node[1][rb + 1][cb] + fx * sh.node[1][rb + 1][cb + 1]);
+  const int x = xlo + j, y = ylo + i;
+  const float qx = (float)x + u, qy = (float)y + v;
+  const float x0 = floorf(qx), y0 = floorf(qy);
+  const float ex = qx - x0, ey = qy - y0;
+  const int ix = (int)x0, iy = (int)y0;
+  const float p00 = ldA(B, a.W, a.H, iy, ix), p01 = ldA(B, a.W, a.H, iy, ix + 1);
+  const float p10 = ldA(B, a.W, a.H, iy + 1, ix), p11 = ldA(B, a.W, a.H, iy + 1, ix + 1);
+  const float bs = (1.0f - ey) * ((1.0f - ex) * p00 + ex * p01) + ey * ((1.0f - ex) * p10 + ex * p11);
+  r = bs - ldA(A, a.W, a.H, y, x);
+  gx = (1.0f - ey) * (p01 - p00) + ey * (p11 - p10);
+  gy = (1.0f - ex) * (p10 - p00) + ex * (p11 - p01);
+}
+
+// Forward, TN x TN windows per workgroup: squared residuals of the tile's
+// pixel region in LDS, then 4 threads per window sum its block.
+template <int STEP, int TN>
+__global__ __launch_bounds__(256) void k_ssd_forward_t(SsdArgs a) {
+  using C = SsdTile<STEP, TN>;
+  constexpr int WIN = 2 * STEP, RWF = (TN - 1) * STEP + WIN;
+  static_assert(RWF <= C::RW, "forward region");
+  __shared__ SsdShared<STEP, TN> sh;
+  __shared__ float s_r2[RWF * RWF];
+  const WgIdx wg = xcd_order();
+  const int pair = wg.z;
+  if (slot_off(a.mask, pair)) return;
+  const int t = threadIdx.x;
+  const int np = a.nx * a.ny;
+  const int64_t img = (int64_t)a.W * a.H;
+  const float* A = a.A + pair * img;
+  const float* B = a.B + pair * img;
+  const float* U = a.U + (int64_t)pair * 2 * np;
+  const int ta = wg.y * TN, tb = wg.x * TN;
+  const int ylo = ta * STEP - C::H2, xlo = tb * STEP - C::H2;
+  int nly, nlx;
+  ssd_prepare<STEP, TN>(a, U, ylo, xlo, RWF, RWF, sh, nly, nlx);
+  for (int idx = t; idx < RWF * RWF; idx += 256) {
+    const int i = idx / RWF, j = idx - (idx / RWF) * RWF;
+    float r, gx, gy;
+    ssd_residual<STEP, TN>(a, A, B, sh, ylo, xlo, i, j, r, gx, gy);
+    s_r2[idx] = r * r;
+  }
+  __syncthreads();
+  const int w = t >> 2, p = t & 3;
+  const int wi = w / TN, wj = w - (w / TN) * TN;
+  float s = 0.0f;
+  if (w < TN * TN) {
+    for (int i = p; i < WIN; i += 4) {
+      const float* row = s_r2 + (wi * STEP + i) * RWF + wj * STEP;
+#pragma unroll
+      for (int j = 0; j < WIN; ++j) s += row[j];
+    }
+  }
+  s += __shfl_xor(s, 1);
+  s += __shfl_xor(s, 2);
+  if (w < TN * TN && p == 0) {
+    const int aa = ta + wi, bb = tb + wj;
+    if (aa < a.ny && bb < a.nx) a.loss[(int64_t)pair * np + aa * a.nx + bb] = s;
+  }
+}
+
+// Backward, TN x TN nodes per workgroup.  Every pixel of the nodes' support
+// region contributes to the two node columns and two node rows of its
+// bilinear cell (weights 1-f and f, squared for the diagonal), so the
+// adjoint separates: pass 1 sums each (pixel row, STEP-pixel chunk) into
+// left/right column partials of the four terms 2 m r gx, 2 m r gy,
+// 2 m gx^2, 2 m gy^2; pass 2 sums a node's partials over its rows with the
+// row weights.  Chunks of STEP pixels starting at the region edge share one
+// base node column (the region starts on a cell boundary), and m (the sum
+// of the upstream gradients of the windows holding the pixel) is constant
+// along a chunk.
+template <int STEP, int TN>
+__global__ __launch_bounds__(256) void k_ssd_backward_t(SsdArgs a) {
+  using C = SsdTile<STEP, TN>;
+  constexpr int NCH = C::RW / STEP;                    // chunks per region row
+  __shared__ SsdShared<STEP, TN> sh;
+  __shared__ float s_part[C::RW][NCH][8];              // [row][chunk][term*2 + side]
+  __shared__ float s_g[C::NG][C::NG];                  // upstream window gradients
+  __shared__ int s_chb[NCH];                           // base node column of a chunk
+  const WgIdx wg = xcd_order();
+  const int pair = wg.z;
+  if (slot_off(a.mask, pair)) return;
+  const int t = threadIdx.x;
+  const int np = a.nx * a.ny;
+  const int64_t img = (int64_t)a.W * a.H;
+  const float* A = a.A + pair * img;
+  const float* B = a.B + pair * img;
+  const float* U = a.U + (int64_t)pair * 2 * np;
+  const float* G = a.g + (int64_t)pair * np;
+  const int ta = wg.y * TN, tb = wg.x * TN;
+  constexpr int h = C::H2;
+  const int lo_all = -h, hi_x = a.nx * STEP + h - 1, hi_y = a.ny * STEP + h - 1;
+  const int ylo = ta == 0 ? lo_all : (ta - 1) * STEP + STEP / 2;
+  const int xlo = tb == 0 ? lo_all : (tb - 1) * STEP + STEP / 2;
+  const int tae = min(ta + TN, a.ny) - 1, tbe = min(tb + TN, a.nx) - 1;
+  const int yhi = tae == a.ny - 1 ? hi_y : (tae + 1) * STEP + (STEP - 1) / 2;
+  const int xhi = tbe == a.nx - 1 ? hi_x : (tbe + 1) * STEP + (STEP - 1) / 2;
+  const int RH = yhi - ylo + 1, RWc = xhi - xlo + 1;
+  // upstream gradients of the windows that can hold a region pixel:
+  // window rows i with i STEP - h <= y <= i STEP - h + 2 STEP - 1
+  const int gi0 = max((ylo + h) / STEP - 1, 0), gj0 = max((xlo + h) / STEP - 1, 0);
+  for (int i = t; i < C::NG * C::NG; i += 256) {
+    const int r = i / C::NG, q = i - (i / C::NG) * C::NG;
+    const int gi = gi0 + r, gj = gj0 + q;
+    s_g[r][q] = (gi < a.ny && gj < a.nx) ? G[gi * a.nx + gj] : 0.0f;
+  }
+  int nly, nlx;
+  ssd_prepare<STEP, TN>(a, U, ylo, xlo, RH, RWc, sh, nly, nlx);
+  if (t < NCH) s_chb[t] = t * STEP < RWc ? sh.cb[t * STEP] : -100;
+  const int nchunks = (RWc + STEP - 1) / STEP;
+  for (int item = t; item < RH * nchunks; item += 256) {
+    const int i = item / nchunks, c = item - (item / nchunks) * nchunks;
+    const int y = ylo + i;
+    // windows holding row y: rows a0..a1; columns from the chunk
+    const int a0 = max(fdiv(y + h - STEP, STEP), 0), a1 = min(fdiv(y + h, STEP), a.ny - 1);
+    const int x0c = xlo + c * STEP;
+    const int b0 = max(fdiv(x0c + h - STEP, STEP), 0), b1 = min(fdiv(x0c + h, STEP), a.nx - 1);
+    float m = 0.0f;
+    for (int ii = a0; ii <= a1; ++ii)
+      for (int jj = b0; jj <= b1; ++jj) m += s_g[ii - gi0][jj - gj0];
+    float acc[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) acc[k] = 0.0f;
+    if (m != 0.0f) {
+#pragma unroll
+      for (int e = 0; e < STEP; ++e) {
+        const int j = c * STEP + e;
+        if (j < RWc) {
+          float r, gx, gy;
+          ssd_residual<STEP, TN>(a, A, B, sh, ylo, xlo, i, j, r, gx, gy);
+          const float f = sh.cf[j], wl = a.nx > 1 ? 1.0f - f : 1.0f, wr = a.nx > 1 ? f : 0.0f;
+          const float t0 = 2.0f * m * r * gx, t1 = 2.0f * m * r * gy;
+          const float t2 = 2.0f * m * gx * gx, t3 = 2.0f * m * gy * gy;
+          acc[0] += wl * t0; acc[1] += wr * t0;
+          acc[2] += wl * t1; acc[3] += wr * t1;
+          acc[4] += wl * wl * t2; acc[5] += wr * wr * t2;
+          acc[6] += wl * wl * t3; acc[7] += wr * wr * t3;
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) s_part[i][c][k] = acc[k];
+  }
+  __syncthreads();
+  // pass 2: thread = (node, term); a node collects the left partials of the
+  // chunks based on its column and the right partials of the chunks based
+  // on the column before, weighted by its row weight
+  const int nd = t >> 2, term = t & 3;
+  const int na = ta + nd / TN, nb = tb + nd % TN;
+  if (nd < TN * TN && na < a.ny && nb < a.nx) {
+    const int cbn = nb - nlx;                          // node column in cache indices
+    const int rbn = na - nly;
+    const bool sq = term >= 2;
+    // base rows and chunk bases do not decrease along the region: the rows
+    // and chunks that touch the node are contiguous runs
+    int rf = RH, rl = -1, cf0 = nchunks, cl = -1;
+    for (int i = 0; i < RH; ++i) {
+      const int rb = sh.rb[i];
+      if (rb == rbn || (a.ny > 1 && rb + 1 == rbn)) { rf = min(rf, i); rl = i; }
+    }
+    for (int c = 0; c < nchunks; ++c) {
+      const int base = s_chb[c];
+      if (base == cbn || (a.nx > 1 && base + 1 == cbn)) { cf0 = min(cf0, c); cl = c; }
+    }
+    float s = 0.0f;
+    for (int i = rf; i <= rl; ++i) {
+      const int rb = sh.rb[i];
+      const float f = sh.rf[i];
+      float wy = 0.0f;
+      if (rb == rbn) wy += a.ny > 1 ? 1.0f - f : 1.0f;
+      if (a.ny > 1 && rb + 1 == rbn) wy += f;
+      float rowsum = 0.0f;
+      for (int c = cf0; c <= cl; ++c) {
+        const int base = s_chb[c];
+        if (base == cbn) rowsum += s_part[i][c][2 * term];
+        if (base + 1 == cbn) rowsum += s_part[i][c][2 * term + 1];
+      }
+      s += (sq ? wy * wy : wy) * rowsum;
+    }
+    const int idx = na * a.nx + nb;
+    if (term < 2) {
+      a.gU[(int64_t)pair * 2 * np + term * np + idx] = s;
+    } else if (a.D) {
+      a.D[(int64_t)pair * 2 * np + (term - 2) * np + idx] = s;
+    }
+  }
+}
+
 SsdArgs make_args(const Plan& P, const float* A, const float* B, const float* U) {
   SsdArgs a;
   a.A = A;
@@ -241,6 +495,11 @@ hipError_t launch_ssd_forward(const Plan& P, const float* A, const float* B, con
   SsdArgs a = make_args(P, A, B, U);
   a.loss = loss;
   // tile: at most 8 x 8 windows with a pixel region of at most 96 x 96
+  if (a.step == 8 && a.win == 16) {
+    dim3 grid((a.nx + 7) / 8, (a.ny + 7) / 8, n);
+    hipLaunchKernelGGL((k_ssd_forward_t<8, 8>), grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+  }
   int TN = max(1, min(8, (96 - a.win) / a.step + 1));
   int RW = (TN - 1) * a.step + a.win;
   size_t lds = sizeof(float) * (size_t)RW * RW;
@@ -255,6 +514,11 @@ hipError_t launch_ssd_backward(const Plan& P, const float* A, const float* B, co
   a.g = g;
   a.gU = gU;
   a.D = D;
+  if (a.step == 8 && a.win == 16) {
+    dim3 grid((a.nx + 7) / 8, (a.ny + 7) / 8, n);
+    hipLaunchKernelGGL((k_ssd_backward_t<8, 8>), grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+  }
   // 16 threads per node -> 16 nodes per workgroup; support region of a
   // 4 x 4 node tile spans (TN+1) step + h px plus edge extension
   const int TN = 4;
