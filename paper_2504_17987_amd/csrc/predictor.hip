@@ -310,6 +310,109 @@ __global__ __launch_bounds__(256) void k_sad_q(SadArgs g) {
 }
 
 // ---------------------------------------------------------------------------
+// SAD block search with a lane per candidate row, for any element size: a
+// group of G = 2R+1 lanes per node, lane q owning dy = cand_y - R + q and
+// all G candidate columns.  The node's A block is staged in LDS; per block
+// row, a lane reads its B row once, realigns it to the leftmost candidate,
+// and feeds every candidate column from the same registers (an A row word
+// is read once per row, not once per candidate).
+// ---------------------------------------------------------------------------
+template <int ES, int NW, int KMAX>
+__global__ __launch_bounds__(256) void k_sad_r(SadArgs g) {
+  constexpr int BLK = 4 * NW / ES;
+  constexpr int SPAN = (KMAX - 1) * ES;           // bytes from the first to the last candidate
+  constexpr int RWR = NW + (SPAN + 3) / 4;        // realigned words a row needs
+  extern __shared__ uint32_t s_ablk[];            // [npw][BLK][NW]
+  __shared__ unsigned long long s_key[256];
+
+  const WgIdx wg = xcd_order();
+  const int pair = wg.z;
+  if (slot_off(g.mask, pair)) return;
+  const int G = 2 * g.R + 1;
+  const int npw = g.npw;
+  const int t = threadIdx.x;
+  const int j = t / G, q = t - j * G;
+  const int a = wg.y;
+  const int b0 = wg.x * npw;
+  const int b = b0 + j;
+  const bool active = j < npw && b < g.nx;
+  const int off = (g.step - BLK) / 2;
+  const int oy = a * g.step + off;
+  const uint8_t* Ab = g.A + (int64_t)pair * g.stride;
+  const uint8_t* Bb = g.B + (int64_t)pair * g.stride;
+
+  const int nblk = min(npw, g.nx - b0);
+  for (int idx = t; idx < nblk * BLK * NW; idx += 256) {
+    int jj = idx / (BLK * NW), r = (idx / NW) % BLK, w = idx % NW;
+    const uint8_t* row = Ab + (int64_t)(oy + r) * g.pitch;
+    s_ablk[idx] = word_at(row, ((b0 + jj) * g.step + off) * ES + 4 * w);
+  }
+
+  int cx = 0, cy = 0;
+  if (g.parent && active) {
+    const int32_t* par = g.parent + (int64_t)pair * g.pstride;
+    int pa = min(a >> 1, g.pny - 1), pb = min(b >> 1, g.pnx - 1);
+    cx = 2 * parent_value(g, par, 0, pa, pb);
+    cy = 2 * parent_value(g, par, 1, pa, pb);
+  }
+  __syncthreads();
+
+  unsigned long long best = ~0ull;
+  if (active) {
+    const int xs = (b * g.step + off + cx - g.R) * ES;   // byte of candidate column 0
+    const int xa = xs & ~3, sh = xs & 3;
+    const int by = oy + cy - g.R + q;
+    uint32_t acc[KMAX];
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) acc[k] = 0u;
+    const uint32_t* ablk = s_ablk + j * BLK * NW;
+#pragma unroll 2
+    for (int ar = 0; ar < BLK; ++ar) {
+      const uint32_t* row = reinterpret_cast<const uint32_t*>(Bb + (int64_t)(by + ar) * g.pitch + xa);
+      uint32_t w[RWR + 1];
+#pragma unroll
+      for (int i = 0; i <= RWR; ++i) w[i] = row[i];
+      uint32_t rw[RWR];
+#pragma unroll
+      for (int i = 0; i < RWR; ++i) rw[i] = __builtin_amdgcn_alignbyte(w[i + 1], w[i], sh);
+      uint32_t aw[NW];
+#pragma unroll
+      for (int i = 0; i < NW; ++i) aw[i] = ablk[ar * NW + i];
+#pragma unroll
+      for (int k = 0; k < KMAX; ++k) {
+        if (k < G) {
+          const int kb = k * ES, kw = kb >> 2, ks = kb & 3;
+          uint32_t s = acc[k];
+#pragma unroll
+          for (int i = 0; i < NW; ++i) {
+            const uint32_t bw = ks ? __builtin_amdgcn_alignbyte(rw[kw + i + 1], rw[kw + i], ks) : rw[kw + i];
+            s = sad_word<ES>(aw[i], bw, s);
+          }
+          acc[k] = s;
+        }
+      }
+    }
+    const int dy = cy - g.R + q;
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+      if (k < G) {
+        unsigned long long key = sad_key(acc[k], dy, cx - g.R + k);
+        best = key < best ? key : best;
+      }
+    }
+  }
+  s_key[t] = best;
+  __syncthreads();
+  if (active && q == 0) {
+    unsigned long long m = s_key[t];
+    for (int k = 1; k < G; ++k) m = s_key[t + k] < m ? s_key[t + k] : m;
+    int32_t* out = g.out + (int64_t)pair * g.ostride;
+    out[a * g.nx + b] = (int)(m & 0xff) - 128;
+    out[g.nx * g.ny + a * g.nx + b] = (int)((m >> 8) & 0xff) - 128;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // SAD block search, general form: a group of G = 2R+1 lanes per node, lane k
 // owning the candidate column dx = cand_x - R + k; npw nodes of one node row
 // per workgroup.  The node's A block is staged in LDS as packed words; every
@@ -673,6 +776,15 @@ hipError_t launch_sad_level(const Plan& P, int l, const void*, const void*, int6
   g.npw = npw;
   dim3 grid((v.nx + npw - 1) / npw, v.ny, n);
   size_t lds = sizeof(uint32_t) * (size_t)npw * P.block * NW;
+  if (P.es == 2 && G <= 17) {
+    // a lane per candidate row (u16 blocks of 8..32 px)
+#define PIV_SAD_R(NW_, K_) \
+  if (NW == NW_ && G <= K_) { hipLaunchKernelGGL((k_sad_r<2, NW_, K_>), grid, dim3(256), lds, s, g); return hipGetLastError(); }
+#define PIV_SAD_R_NW(NW_) PIV_SAD_R(NW_, 5) PIV_SAD_R(NW_, 9) PIV_SAD_R(NW_, 13) PIV_SAD_R(NW_, 17)
+    PIV_SAD_R_NW(4) PIV_SAD_R_NW(6) PIV_SAD_R_NW(8) PIV_SAD_R_NW(12) PIV_SAD_R_NW(16)
+#undef PIV_SAD_R_NW
+#undef PIV_SAD_R
+  }
   return P.es == 1 ? sad_dispatch<1>(NW, G, grid, lds, s, g) : sad_dispatch<2>(NW, G, grid, lds, s, g);
 }
 

@@ -68,6 +68,7 @@ class GraphRunner:
             b *= 2
         self.buckets.append(slots)
         self.graphs: Dict[int, object] = {}
+        self._mask_state: Optional[Tuple[int, int]] = None   # (active, upto) last written
 
     @property
     def graph(self):
@@ -83,6 +84,7 @@ class GraphRunner:
     def capture(self) -> None:
         torch = self.torch
         self.plan.bind_slot_mask(self.mask)
+        self._mask_state = None
         self.stream.wait_stream(torch.cuda.current_stream())
         for n in self.buckets:
             A, B = self.A[:n], self.B[:n]
@@ -99,12 +101,17 @@ class GraphRunner:
 
     def set_active(self, n: int, upto: Optional[int] = None) -> None:
         """Slots [0, n) run, slots [n, upto) are skipped (small fill kernels
-        on the runner's stream; no memset node)."""
+        on the runner's stream; no memset node).  Skipped when the mask
+        already reads so."""
         upto = self.slots if upto is None else upto
+        st = self._mask_state
+        if st is not None and st[0] == n and (n >= upto or st[1] >= upto):
+            return
         with self.torch.cuda.stream(self.stream):
             self.mask[:n].fill_(1)
             if n < upto:
                 self.mask[n:upto].fill_(0)
+        self._mask_state = (n, upto)
 
     def replay(self, n: Optional[int] = None) -> None:
         """Replay the graph of the smallest bucket holding n slots (all slots

@@ -116,6 +116,8 @@ PLANS = [
     dict(width=96, height=40, win=24, step=8, block=16, levels=2, radius_coarse=16, radius_fine=16),
     dict(width=512, height=512, levels=6, radius_coarse=3, radius_fine=1),
     dict(width=64, height=64, win=8, step=8, block=8, levels=1, radius_coarse=0),
+    dict(width=640, height=480, dtype=2, bit_depth=16, win=16, step=8, levels=3, radius_coarse=8, radius_fine=1),
+    dict(width=512, height=512, dtype=2, bit_depth=12, win=32, step=16, levels=2, radius_coarse=4, radius_fine=2),
 ]
 
 
@@ -144,6 +146,12 @@ def test_padded_pyramid_holds_every_sad_read(L, kw):
             # RW + 1 words with RW = NW + (2R+3)//4 + 1
             start = ((v["nx"] - 1) * step + off + cand - R) * es
             span = 4 * (NW + (2 * R + 3) // 4 + 2)
+        elif es == 2 and 2 * R + 1 <= 17:
+            # u16, a lane per candidate row: from the floor word of the
+            # leftmost shift, RWR + 1 words, RWR = NW + ceil((KMAX-1) es / 4)
+            kmax = next(k for k in (5, 9, 13, 17) if k >= 2 * R + 1)
+            start = ((v["nx"] - 1) * step + off + cand - R) * es
+            span = 4 * (NW + ((kmax - 1) * es + 3) // 4 + 1)
         elif es == 1 and NW <= 4 and 2 * R + 1 <= 32:
             # a lane per candidate row (quad SAD): from the floor word of the
             # leftmost shift, RW + 1 words with RW = NW + ceil((2R+1)/4)
