@@ -379,8 +379,11 @@ struct TileCfg {
   static constexpr int XBUF = 3 * NC * CSTR;              // P, S, Q of one band, all cells
   static constexpr int RES_FLOATS = 2 * XBUF;             // two band buffers
   // room for the raw source tile of B behind the A and B' tiles: what the
-  // result arrays leave free, at least 16 KiB
-  static constexpr int RAW_WORDS = RES_FLOATS - IN_FLOATS > 4096 ? RES_FLOATS - IN_FLOATS : 4096;
+  // result arrays leave free, else what fits a 71 KiB union (two
+  // workgroups per CU with the small arrays), at least 16 KiB
+  static constexpr int UNION_CAP = 71 * 1024 / 4;
+  static constexpr int RAW_FIT = UNION_CAP - IN_FLOATS > 4096 ? UNION_CAP - IN_FLOATS : 4096;
+  static constexpr int RAW_WORDS = RES_FLOATS - IN_FLOATS > RAW_FIT ? RES_FLOATS - IN_FLOATS : RAW_FIT;
   static constexpr int UNION = IN_FLOATS + RAW_WORDS > RES_FLOATS ? IN_FLOATS + RAW_WORDS : RES_FLOATS;
   static constexpr int NWIN = TW * TH;
   static_assert(NSY % SYG == 0, "shift rows must split evenly");
@@ -1006,8 +1009,8 @@ template <typename T>
 hipError_t launch_tiled_t(const CorrArgs& g, int n, hipStream_t s) {
   if (g.step == 8 && g.R == 4) return launch_tiled<T, 8, 4, 3, 8, 8, 256>(g, n, s);
   if (g.step == 8 && g.R == 1) return launch_tiled<T, 8, 1, 1, 8, 8, 256>(g, n, s);
-  if (g.step == 12 && g.R == 4) return launch_tiled<T, 12, 4, 3, 6, 5, 128>(g, n, s);
-  if (g.step == 12 && g.R == 1) return launch_tiled<T, 12, 1, 1, 6, 5, 128>(g, n, s);
+  if (g.step == 12 && g.R == 4) return launch_tiled<T, 12, 4, 3, 5, 5, 128>(g, n, s);
+  if (g.step == 12 && g.R == 1) return launch_tiled<T, 12, 1, 1, 5, 5, 128>(g, n, s);
   return hipErrorInvalidValue;
 }
 
