@@ -2,10 +2,12 @@
 // library, not in the paper): forward loss per window and its adjoint with
 // respect to the node displacement field, with the Gauss-Newton diagonal.
 //
-// Both kernels work on tiles staged through LDS.  The backward kernel
-// forms each pixel's terms 2 m r dB'/du and 2 m (dB'/du)^2 once per tile
-// and lets every node gather its own weighted terms: no atomics, so the
-// result is bitwise reproducible.
+// The tiled forms (win = 2 step) cache the nodes of a tile in LDS; the
+// backward forms each pixel's terms 2 m r dB'/du and 2 m (dB'/du)^2 once per
+// tile, splits them into left/right node-column partials per pixel row and
+// lets every node sum its partials over its rows.  The general forms gather
+// per node with per-pixel weights.  No atomics anywhere, so the results are
+// bitwise reproducible.
 #include "dev_common.h"
 #include "piv_internal.h"
 
