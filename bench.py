@@ -13,7 +13,8 @@ measured with HIP events on its stream, the FP64 CPU oracle timed on a
 bounded sample of the same workload, and the other forms of the path:
 HIP-graph batches of 8, continuous batching of a served mix of sizes
 against the plain per-pair FIFO form on the same arrival trace, a stream
-of 4K u16 pairs in graph batches of 8, and the differentiable SSD.
+of 4K u16 pairs in graph batches of 8, the differentiable SSD, and the
+largest image the paper runs (8192 x 4096).
 """
 from __future__ import annotations
 
@@ -235,6 +236,28 @@ def stream_cfg3(torch, api, synth, log_fn, npairs=64, distinct=4):
             "mvec_per_s": round(pps * 320 * 180 / 1e6, 2)}
 
 
+def largest(torch, api, synth, kw, log_fn, n=4, reps=10):
+    """The largest image the paper runs (8192 x 4096 u8, 33.6 MP), batches of
+    4 pairs through the whole path; the frames tile a rendered 1 MP pair."""
+    A1, B1, _ = synth.cfg2_pair(2600)
+    A = torch.from_numpy(np.tile(A1, (4, 8))).cuda().expand(n, -1, -1).contiguous()
+    B = torch.from_numpy(np.tile(B1, (4, 8))).cuda().expand(n, -1, -1).contiguous()
+    P = api.Plan(8192, 4096, max_batch=n, **kw)
+    out = P.run(A, B)
+    torch.cuda.synchronize()
+    e0, e1 = events(torch, 2)
+    e0.record()
+    for _ in range(reps):
+        P.run(A, B, out)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    pps = n / (ms / 1e3)
+    log_fn(f"8192x4096: {pps:.0f} pairs/s ({ms:.2f} ms per batch of {n})")
+    return {"pairs_per_s": round(pps, 1), "ms_per_batch": round(ms, 3), "batch": n,
+            "mvec_per_s": round(pps * 1024 * 512 / 1e6, 1)}
+
+
 def ssd_cfg4(torch, api, synth, log_fn, n=64, distinct=8):
     """64 pairs of 512x512 f32, forward + backward of the windowed SSD."""
     prs = [synth.cfg4_pair(k) for k in range(distinct)]
@@ -368,6 +391,7 @@ def main():
         forms["served_cfg5"] = served(torch, api, synth, kw, args, lg)
         forms["stream_cfg3"] = stream_cfg3(torch, api, synth, lg)
         forms["ssd_cfg4"] = ssd_cfg4(torch, api, synth, lg)
+        forms["largest_8192x4096"] = largest(torch, api, synth, kw, lg)
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -8,7 +8,9 @@ exactly as bench.py runs them) through one piv_run.  Against the FP64 oracle:
   predictor: displacement within 0.01 px, coefficient within 2e-5, flags
   exact, unless the oracle's plane shows a near-tie;
 * validation and vorticity on the whole grid, from the GPU's correction;
-* all eight copies of a pair give bitwise identical results.
+* all eight copies of a pair give bitwise identical results;
+* the largest image the paper runs, 8192 x 4096, one pair, checked the same
+  way.
 """
 import numpy as np
 import pytest
@@ -114,3 +116,43 @@ def test_fullsize_validation_and_vorticity(fullsize):
         assert bad.sum() <= 2
         om = oracle.vorticity(g["disp"][i].astype(np.float64), 8)
         assert np.abs(g["omega"][i] - om).max() <= TOL_REL * np.abs(om).max(), i
+
+
+def test_largest_image_8192x4096():
+    """The largest image the paper runs (Sec. 4.1: 8192 x 4096, 33.6 MP), one
+    pair through piv_run: predictor bit-exact on every node, correction at
+    sampled nodes, validation and vorticity on the whole grid.  The frames
+    tile one rendered 1 MP pair 8 x 4 times."""
+    from paper_2504_17987_amd import api
+    A1, B1, _ = synth.cfg2_pair(2600)
+    A, B = np.tile(A1, (4, 8)), np.tile(B1, (4, 8))
+    H, W = A.shape
+    P = api.Plan(W, H, max_batch=1, **KW)
+    say(f"[largest] {W}x{H}")
+    out = P.run(torch.from_numpy(A[None]).cuda(), torch.from_numpy(B[None]).cuda())
+    disp = torch.empty_like(out["disp"])
+    peak = torch.empty_like(out["peak"])
+    flags = torch.empty_like(out["flags"])
+    P.correct(torch.from_numpy(A[None]).cuda(), torch.from_numpy(B[None]).cuda(), out["pred"], disp, peak, flags)
+    torch.cuda.synchronize()
+    g = {k: v.cpu().numpy()[0] for k, v in out.items()}
+    c = dict(disp=disp.cpu().numpy()[0], peak=peak.cpu().numpy()[0], flags=flags.cpu().numpy()[0])
+    po = oracle.predict(A, B, 8, 16, 3, 6, 2).astype(np.float64)
+    po, _ = oracle.validate(po, None)
+    assert np.array_equal(g["pred"], po.astype(np.float32))
+    ny, nx = po.shape[1:]
+    Ad, Bd = A.astype(np.float64), B.astype(np.float64)
+    rng = np.random.default_rng(2601)
+    ties = 0
+    for a, b in _sample_nodes(rng, ny, nx, 40):
+        du, dv, pk, fl = oracle.correct_node(Ad, Bd, 16, 8, 4, g["pred"].astype(np.float64), a, b)
+        d = max(abs(c["disp"][0, a, b] - du), abs(c["disp"][1, a, b] - dv))
+        if not (d <= TOL_DISP_PX and abs(c["peak"][a, b] - pk) <= TOL_RHO and c["flags"][a, b] == fl):
+            assert corr_gap(Ad, Bd, 16, 8, 4, 0, g["pred"].astype(np.float64), a, b) < NEAR_TIE_RHO, (a, b)
+            ties += 1
+    assert ties <= 2
+    vo, flo = oracle.validate(c["disp"].astype(np.float64), c["flags"].copy())
+    bad = (np.abs(g["disp"] - vo).max(axis=0) > 1e-5) | (g["flags"] != flo)
+    assert bad.sum() <= 4
+    om = oracle.vorticity(g["disp"].astype(np.float64), 8)
+    assert np.abs(g["omega"] - om).max() <= TOL_REL * np.abs(om).max()
