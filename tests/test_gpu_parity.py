@@ -42,6 +42,9 @@ PRED_CASES = {
                       dict(win=16, step=8, levels=2, radius_coarse=4, radius_fine=1, median=False)),
     "block24_step8": (lambda: small_vortex_pair(seed=12)[:2],
                       dict(win=16, step=8, block=24, levels=3, radius_coarse=3, radius_fine=2)),
+    # image rows not a multiple of 4 and a ragged last 32-byte chunk
+    "step6_204x138": (lambda: small_vortex_pair(204, 138, seed=13)[:2],
+                      dict(win=12, step=6, levels=3, radius_coarse=5, radius_fine=2)),
 }
 
 
