@@ -310,6 +310,100 @@ __global__ __launch_bounds__(256) void k_sad_q(SadArgs g) {
 }
 
 // ---------------------------------------------------------------------------
+// SAD block search, one node per lane, A rows streamed (any element size,
+// small R): the lane keeps the last G = 2R+1 rows of its A block in a ring of
+// registers and streams the rows of B once each; a B row, realigned to the
+// leftmost candidate, feeds every candidate column and every candidate row
+// whose A row is in the ring.  Neighbouring lanes are neighbouring nodes, so
+// a wave's row reads are contiguous.
+// ---------------------------------------------------------------------------
+template <int ES, int NW, int R>
+__global__ __launch_bounds__(256) void k_sad_stream(SadArgs g) {
+  constexpr int G = 2 * R + 1;
+  constexpr int BLK = 4 * NW / ES;
+  constexpr int RWS = NW + (2 * R * ES + 3) / 4;   // realigned words covering every candidate column
+  const WgIdx wg = xcd_order();
+  const int pair = wg.y;
+  if (slot_off(g.mask, pair)) return;
+  const int node = wg.x * blockDim.x + threadIdx.x;
+  if (node >= g.nx * g.ny) return;
+  const int a = node / g.nx, b = node - a * g.nx;
+  const int off = (g.step - BLK) / 2;
+  const int oy = a * g.step + off, ox = b * g.step + off;
+  const uint8_t* Ab = g.A + (int64_t)pair * g.stride;
+  const uint8_t* Bb = g.B + (int64_t)pair * g.stride;
+  int cx = 0, cy = 0;
+  if (g.parent) {
+    const int32_t* par = g.parent + (int64_t)pair * g.pstride;
+    int pa = min(a >> 1, g.pny - 1), pb = min(b >> 1, g.pnx - 1);
+    cx = 2 * parent_value(g, par, 0, pa, pb);
+    cy = 2 * parent_value(g, par, 1, pa, pb);
+  }
+  uint32_t acc[G][G];   // [candidate row q][candidate column k]
+#pragma unroll
+  for (int q = 0; q < G; ++q)
+#pragma unroll
+    for (int k = 0; k < G; ++k) acc[q][k] = 0u;
+  const int y0 = oy + cy - R;
+  const int xs = (ox + cx - R) * ES, xa = xs & ~3, sh = xs & 3;
+  const int axs = ox * ES, axa = axs & ~3, ash = axs & 3;
+  uint32_t ring[G][NW];   // A row ar sits in ring[ar % G]
+  for (int rb0 = 0; rb0 < BLK + 2 * R; rb0 += G) {
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+      const int rb = rb0 + u;   // rb % G == u
+      if (rb < BLK + 2 * R) {
+        if (rb < BLK) {
+          const uint32_t* row = reinterpret_cast<const uint32_t*>(Ab + (int64_t)(oy + rb) * g.pitch + axa);
+          uint32_t w[NW + 1];
+#pragma unroll
+          for (int i = 0; i <= NW; ++i) w[i] = row[i];
+#pragma unroll
+          for (int i = 0; i < NW; ++i) ring[u][i] = __builtin_amdgcn_alignbyte(w[i + 1], w[i], ash);
+        }
+        const uint32_t* row = reinterpret_cast<const uint32_t*>(Bb + (int64_t)(y0 + rb) * g.pitch + xa);
+        uint32_t w[RWS + 1];
+#pragma unroll
+        for (int i = 0; i <= RWS; ++i) w[i] = row[i];
+        uint32_t rw[RWS];
+#pragma unroll
+        for (int i = 0; i < RWS; ++i) rw[i] = __builtin_amdgcn_alignbyte(w[i + 1], w[i], sh);
+#pragma unroll
+        for (int k = 0; k < G; ++k) {
+          const int kb = k * ES, kw = kb >> 2, ks = kb & 3;
+          uint32_t bw[NW];
+#pragma unroll
+          for (int i = 0; i < NW; ++i) bw[i] = ks ? __builtin_amdgcn_alignbyte(rw[kw + i + 1], rw[kw + i], ks) : rw[kw + i];
+#pragma unroll
+          for (int q = 0; q < G; ++q) {
+            const int ar = rb - q;
+            if (ar >= 0 && ar < BLK) {
+              const int slot = (u - q + G) % G;   // ar % G
+              uint32_t s = acc[q][k];
+#pragma unroll
+              for (int i = 0; i < NW; ++i) s = sad_word<ES>(ring[slot][i], bw[i], s);
+              acc[q][k] = s;
+            }
+          }
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+  unsigned long long best = ~0ull;
+#pragma unroll
+  for (int q = 0; q < G; ++q)
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+      unsigned long long key = sad_key(acc[q][k], cy - R + q, cx - R + k);
+      best = key < best ? key : best;
+    }
+  int32_t* out = g.out + (int64_t)pair * g.ostride;
+  out[a * g.nx + b] = (int)(best & 0xff) - 128;
+  out[g.nx * g.ny + a * g.nx + b] = (int)((best >> 8) & 0xff) - 128;
+}
+
+// ---------------------------------------------------------------------------
 // SAD block search with a lane per candidate row, for any element size: a
 // group of G = 2R+1 lanes per node, lane q owning dy = cand_y - R + q and
 // all G candidate columns.  The node's A block is staged in LDS; per block
@@ -749,6 +843,14 @@ hipError_t launch_sad_level(const Plan& P, int l, const void*, const void*, int6
   g.npw = 0;
   const int G = 2 * g.R + 1;
   const int NW = P.block * P.es / 4;
+  if (P.es == 2 && g.R >= 1 && g.R <= 2 && (NW == 6 || NW == 8 || NW == 12)) {
+    dim3 grid((v.nx * v.ny + 255) / 256, n);
+#define PIV_SAD_STREAM(NW_, R_) \
+  if (NW == NW_ && g.R == R_) { hipLaunchKernelGGL((k_sad_stream<2, NW_, R_>), grid, dim3(256), 0, s, g); return hipGetLastError(); }
+    PIV_SAD_STREAM(12, 2) PIV_SAD_STREAM(12, 1) PIV_SAD_STREAM(8, 2) PIV_SAD_STREAM(8, 1)
+    PIV_SAD_STREAM(6, 2) PIV_SAD_STREAM(6, 1)
+#undef PIV_SAD_STREAM
+  }
   if (P.es == 1 && g.R <= 2 && (NW == 2 || NW == 3 || NW == 4)) {
     dim3 grid((v.nx * v.ny + 255) / 256, n);
 #define PIV_SAD_LANE(NW_, R_) \

@@ -146,6 +146,11 @@ def test_padded_pyramid_holds_every_sad_read(L, kw):
             # RW + 1 words with RW = NW + (2R+3)//4 + 1
             start = ((v["nx"] - 1) * step + off + cand - R) * es
             span = 4 * (NW + (2 * R + 3) // 4 + 2)
+        elif es == 2 and 1 <= R <= 2 and NW in (6, 8, 12):
+            # u16, one node per lane with streamed A rows: from the floor word
+            # of the leftmost shift, NW + ceil(2R es / 4) + 1 words
+            start = ((v["nx"] - 1) * step + off + cand - R) * es
+            span = 4 * (NW + (2 * R * es + 3) // 4 + 1)
         elif es == 2 and 2 * R + 1 <= 17:
             # u16, a lane per candidate row: from the floor word of the
             # leftmost shift, RWR + 1 words, RWR = NW + ceil((KMAX-1) es / 4)
