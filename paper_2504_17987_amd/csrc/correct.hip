@@ -998,6 +998,447 @@ __global__ __launch_bounds__(NT) void k_correct_tiled(CorrArgs g) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Band per wave (win = 2 step, frames deformed by the whole predictor): a
+// workgroup owns TW x TH windows whose (TW+1)(TH+1) <= 64 cells map one to a
+// lane, and wave g correlates every cell with shift band g (SYG rows of
+// shifts).  Window sums are pair sums of lanes, the right-hand cell by DPP
+// and the cell below by a lane permute, so that after the products the only
+// LDS traffic is one coefficient per window and shift.  The A cell stays in
+// registers as packed pixels.  Small LDS and register footprints give four
+// workgroups per compute unit.
+// ---------------------------------------------------------------------------
+template <int STEP, int R, int SYG, int TW, int TH>
+struct BandCfg {
+  static constexpr int CW = TW + 1, CH = TH + 1, NC = CW * CH;
+  static constexpr int NSY = 2 * R + 1, NS = NSY * NSY, NG = NSY / SYG;
+  static constexpr int AW = CW * STEP, AH = CH * STEP;
+  static constexpr int BW = AW + 2 * R, BH = AH + 2 * R;
+  static constexpr int BP = (BW + 3) / 4 * 4 + 4;   // B' row pitch (floats)
+  static constexpr int NNX = BW / STEP + 4, NNY = BH / STEP + 3;
+  static constexpr int NWIN = TW * TH;
+  // union after the B' tile: raw source box + interpolation tables while the
+  // tile is deformed, then coefficients [window][shift] and the per-band
+  // peaks [band][window] (value, key << 8 | flat count)
+  static constexpr int TAB_WORDS = 2 * (BH + BW);
+  static constexpr int RES_WORDS = NWIN * NS + 2 * NG * NWIN;
+  static constexpr int RAW_WORDS = 3888;
+  static constexpr int UNION = RAW_WORDS + TAB_WORDS > RES_WORDS ? RAW_WORDS + TAB_WORDS : RES_WORDS;
+  static_assert(NC <= 64, "a cell per lane");
+  static_assert(NSY % SYG == 0, "shift rows must split evenly");
+  static_assert(STEP % 2 == 0 && STEP > 4, "50% overlap; a group of four pixels spans two node columns");
+};
+
+template <typename T, int STEP, int R, int SYG, int TW, int TH>
+__global__ __launch_bounds__(64 * ((2 * R + 1) / SYG)) __attribute__((amdgpu_waves_per_eu(3)))
+void k_correct_bands(CorrArgs g) {
+  using C = BandCfg<STEP, R, SYG, TW, TH>;
+  constexpr int NT = 64 * C::NG;
+  constexpr int ES = (int)sizeof(T);
+  constexpr int NWR = STEP * ES / 4;   // words per cell row
+  static_assert(((STEP / 2) * ES) % 4 == 0 && (STEP * ES) % 4 == 0, "cell rows are whole aligned words");
+  __shared__ __align__(16) float sB[C::BH * C::BP];
+  __shared__ __align__(16) float s_un[C::UNION];
+  __shared__ float s_node[2][C::NNY][C::NNX];
+
+  const WgIdx wg = xcd_order();
+  const int pair = wg.z;
+  if (slot_off(g.mask, pair)) return;
+  const int t = threadIdx.x, lane = t & 63;
+  const int band = __builtin_amdgcn_readfirstlane(t >> 6);
+  const int a0 = wg.y * TH, b0 = wg.x * TW;
+  const int y0 = a0 * STEP - STEP / 2, x0 = b0 * STEP - STEP / 2;   // A tile origin
+  const int yb = y0 - R, xb = x0 - R;                              // B' tile origin
+  const uint8_t* Ai = g.A + (int64_t)pair * g.stride;
+  const uint8_t* Bi = g.B + (int64_t)pair * g.stride;
+  const int np = g.nx * g.ny;
+  const float* Pn = g.pred ? g.pred + (int64_t)pair * 2 * np : nullptr;
+  const bool cell_ok = lane < C::NC;
+  const int ci = cell_ok ? lane / C::CW : 0, cj = cell_ok ? lane - (lane / C::CW) * C::CW : 0;
+
+  // predictor nodes covering the B' tile: every wave reads all of them and
+  // takes their range itself (no barrier before the raw box is requested)
+  const float cen = 0.5f * (float)(STEP - 1);
+  const int nlo_y = max(0, (int)floorf(((float)yb - cen) / STEP));
+  const int nlo_x = max(0, (int)floorf(((float)xb - cen) / STEP));
+  constexpr int NNODE = C::NNY * C::NNX, NL = (NNODE + 63) / 64;
+  float nu[NL], nv[NL];
+  if (Pn) {
+#pragma unroll
+    for (int i = 0; i < NL; ++i) {
+      const int idx = min(lane + 64 * i, NNODE - 1);
+      const int r = idx / C::NNX, q = idx - (idx / C::NNX) * C::NNX;
+      const int o = min(nlo_y + r, g.ny - 1) * g.nx + min(nlo_x + q, g.nx - 1);
+      nu[i] = Pn[o];
+      nv[i] = Pn[np + o];
+    }
+  }
+  // the A cell of this lane as packed pixels (zero outside the image)
+  uint32_t aw[STEP][NWR];
+  {
+    const int rowbytes = g.W * ES;
+    const int xa0 = (x0 + cj * STEP) * ES;
+#pragma unroll
+    for (int py = 0; py < STEP; ++py) {
+      const int y = y0 + ci * STEP + py;
+      const uint32_t ok = (cell_ok && (unsigned)y < (unsigned)g.H) ? 0xffffffffu : 0u;
+      const uint8_t* row = Ai + (int64_t)min(max(y, 0), g.H - 1) * g.pitch;
+#pragma unroll
+      for (int k = 0; k < NWR; ++k) aw[py][k] = masked_word(row, rowbytes, xa0 + 4 * k) & ok;
+    }
+  }
+  float umin = 0.0f, umax = 0.0f, vmin = 0.0f, vmax = 0.0f, bad = 0.0f;
+  if (Pn) {
+    umin = vmin = 3.0e38f;
+    umax = vmax = -3.0e38f;
+#pragma unroll
+    for (int i = 0; i < NL; ++i) {
+      umin = fminf(umin, nu[i]);
+      umax = fmaxf(umax, nu[i]);
+      vmin = fminf(vmin, nv[i]);
+      vmax = fmaxf(vmax, nv[i]);
+      if (!(fabsf(nu[i]) < 1.0e6f && fabsf(nv[i]) < 1.0e6f)) bad = 1.0f;   // also NaN
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      bad = fmaxf(bad, __shfl_xor(bad, o));
+      umin = fminf(umin, __shfl_xor(umin, o));
+      umax = fmaxf(umax, __shfl_xor(umax, o));
+      vmin = fminf(vmin, __shfl_xor(vmin, o));
+      vmax = fmaxf(vmax, __shfl_xor(vmax, o));
+    }
+    if (band == 0) {
+#pragma unroll
+      for (int i = 0; i < NL; ++i) {
+        const int idx = lane + 64 * i;
+        if (idx < NNODE) {
+          const int r = idx / C::NNX, q = idx - (idx / C::NNX) * C::NNX;
+          s_node[0][r][q] = nu[i];
+          s_node[1][r][q] = nv[i];
+        }
+      }
+    }
+  }
+
+  // raw source box of B for the deformation, when it fits
+  const int ix0 = (int)floorf((float)xb + umin) - 1;
+  const int ix1 = (int)floorf((float)(xb + C::BW - 1) + umax) + 2;
+  const int iy0 = (int)floorf((float)yb + vmin) - 1;
+  const int iy1 = (int)floorf((float)(yb + C::BH - 1) + vmax) + 2;
+  const int xw0 = (ix0 * ES) >> 2;
+  const int nwords = ((ix1 * ES + ES - 1) >> 2) - xw0 + 1;
+  const int nrows = iy1 - iy0 + 1;
+  // (a displacement range that is not finite or wider than a window takes
+  // the unstaged path, whose reads are checked one by one)
+  const bool sane = bad == 0.0f && (umax - umin) < 64.0f && (vmax - vmin) < 64.0f;
+  const bool staged = sane && nwords <= NT && nwords * nrows <= C::RAW_WORDS;
+  uint32_t* sraw = reinterpret_cast<uint32_t*>(s_un);
+  int* s_rb = reinterpret_cast<int*>(s_un + C::RAW_WORDS);   // per B' row: base node, fraction
+  float* s_rf = s_un + C::RAW_WORDS + C::BH;
+  int* s_cb = reinterpret_cast<int*>(s_un + C::RAW_WORDS + 2 * C::BH);   // per B' column
+  float* s_cf = s_un + C::RAW_WORDS + 2 * C::BH + C::BW;
+  if (staged) {
+    // thread -> (word column, first row); U reads in flight per thread
+    const int rowbytes = g.W * ES;
+    const int rstep = NT / nwords;
+    const int r0 = t / nwords, w = t - r0 * nwords;
+    constexpr int U = 8;
+    if (r0 < rstep) {
+      for (int rb = r0; rb < nrows; rb += U * rstep) {
+        uint32_t val[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int y = iy0 + rb + u * rstep;
+          const uint32_t ok = (unsigned)y < (unsigned)g.H ? 0xffffffffu : 0u;
+          val[u] = masked_word(Bi + (int64_t)min(max(y, 0), g.H - 1) * g.pitch, rowbytes, 4 * (xw0 + w)) & ok;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+          if (rb + u * rstep < nrows) sraw[(rb + u * rstep) * nwords + w] = val[u];
+      }
+    }
+  }
+  // interpolation tables of the B' tile (the same arithmetic as interp_u)
+  for (int i = t; i < C::BH + C::BW; i += NT) {
+    const bool row = i < C::BH;
+    const int p = row ? yb + i : xb + (i - C::BH);
+    const int n = row ? g.ny : g.nx;
+    float tt = fminf(fmaxf(((float)p - cen) / (float)STEP, 0.0f), (float)(n - 1));
+    int bb = min((int)tt, max(n - 2, 0));
+    float ff = tt - (float)bb;
+    if (row) { s_rb[i] = bb - nlo_y; s_rf[i] = ff; }
+    else { s_cb[i - C::BH] = bb - nlo_x; s_cf[i - C::BH] = ff; }
+  }
+  // the tile offset K: the rounded mean of the A tile (every wave holds all
+  // of its cells and reduces them in the same order)
+  int isum = 0;
+#pragma unroll
+  for (int py = 0; py < STEP; ++py)
+#pragma unroll
+    for (int k = 0; k < NWR; ++k) {
+      if constexpr (ES == 1) isum = (int)__builtin_amdgcn_sad_u8(aw[py][k], 0u, (uint32_t)isum);
+      else isum += (int)(aw[py][k] & 0xffffu) + (int)(aw[py][k] >> 16);
+    }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) isum += __shfl_xor(isum, o);
+  const float K = rintf((float)isum / (float)(C::AH * C::AW));
+  __syncthreads();
+
+  // deformed B' tile, in groups of four pixels of one row
+  if (staged) {
+    constexpr int BQ = (C::BW + 3) / 4;
+    constexpr bool kUniformCols = (STEP + R) % 4 == 0;
+    const uint8_t* rawb = reinterpret_cast<const uint8_t*>(sraw);
+    const int rowb = 4 * nwords, xoff = 4 * xw0;
+    auto rawv = [&](const uint8_t* p) -> float { return (float)*reinterpret_cast<const T*>(p); };
+    const float fxlo = (float)ix0, fxhi = (float)(ix1 - 1), fylo = (float)iy0, fyhi = (float)(iy1 - 1);
+    const int rbase = iy0 * rowb + xoff;
+    for (int idx = t; idx < C::BH * BQ; idx += NT) {
+      const int r = idx / BQ, q = 4 * (idx - (idx / BQ) * BQ);
+      float uu[4] = {0.0f, 0.0f, 0.0f, 0.0f}, vv[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+      if (Pn) {
+        const int rb = s_rb[r];
+        const float fy = s_rf[r];
+        const int cb0 = s_cb[q];
+        if constexpr (kUniformCols) {
+          const float u0 = s_node[0][rb][cb0] + fy * (s_node[0][rb + 1][cb0] - s_node[0][rb][cb0]);
+          const float u1 = s_node[0][rb][cb0 + 1] + fy * (s_node[0][rb + 1][cb0 + 1] - s_node[0][rb][cb0 + 1]);
+          const float v0 = s_node[1][rb][cb0] + fy * (s_node[1][rb + 1][cb0] - s_node[1][rb][cb0]);
+          const float v1 = s_node[1][rb][cb0 + 1] + fy * (s_node[1][rb + 1][cb0 + 1] - s_node[1][rb][cb0 + 1]);
+          const float du = u1 - u0, dv = v1 - v0;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const float fx = s_cf[min(q + e, C::BW - 1)];
+            uu[e] = u0 + fx * du;
+            vv[e] = v0 + fx * dv;
+          }
+        } else {
+          float Vu[3], Vv[3];
+#pragma unroll
+          for (int j = 0; j < 3; ++j) {
+            Vu[j] = s_node[0][rb][cb0 + j] + fy * (s_node[0][rb + 1][cb0 + j] - s_node[0][rb][cb0 + j]);
+            Vv[j] = s_node[1][rb][cb0 + j] + fy * (s_node[1][rb + 1][cb0 + j] - s_node[1][rb][cb0 + j]);
+          }
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int qq = min(q + e, C::BW - 1);
+            const bool nxt = s_cb[qq] != cb0;
+            const float fx = s_cf[qq];
+            const float ul = nxt ? Vu[1] : Vu[0], ur = nxt ? Vu[2] : Vu[1];
+            const float vl = nxt ? Vv[1] : Vv[0], vr = nxt ? Vv[2] : Vv[1];
+            uu[e] = ul + fx * (ur - ul);
+            vv[e] = vl + fx * (vr - vl);
+          }
+        }
+      }
+      const float yr = (float)(yb + r), xq = (float)(xb + q);
+      float out[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const float qx = (xq + (float)e) + uu[e], qy = yr + vv[e];
+        const float fx0 = floorf(qx), fy0 = floorf(qy);
+        const float fx = qx - fx0, fy = qy - fy0;
+        const int ix = (int)__builtin_amdgcn_fmed3f(fx0, fxlo, fxhi);
+        const int iy = (int)__builtin_amdgcn_fmed3f(fy0, fylo, fyhi);
+        const uint8_t* p0 = rawb + (iy * rowb + ix * ES) - rbase;
+        const float p00 = rawv(p0), p01 = rawv(p0 + ES), p10 = rawv(p0 + rowb), p11 = rawv(p0 + rowb + ES);
+        const float top = p00 + fx * (p01 - p00), bot = p10 + fx * (p11 - p10);
+        out[e] = (top + fy * (bot - top)) - K;
+      }
+      *reinterpret_cast<float4*>(sB + r * C::BP + q) = make_float4(out[0], out[1], out[2], out[3]);
+    }
+  } else {
+    for (int idx = t; idx < C::BH * C::BW; idx += NT) {
+      const int r = idx / C::BW, q = idx - (idx / C::BW) * C::BW;
+      const int y = yb + r, x = xb + q;
+      float v;
+      if (Pn) {
+        const int rb = s_rb[r], cb = s_cb[q];
+        const float fy = s_rf[r], fx = s_cf[q];
+        const float u = (1.0f - fy) * ((1.0f - fx) * s_node[0][rb][cb] + fx * s_node[0][rb][cb + 1]) +
+                        fy * ((1.0f - fx) * s_node[0][rb + 1][cb] + fx * s_node[0][rb + 1][cb + 1]);
+        const float w = (1.0f - fy) * ((1.0f - fx) * s_node[1][rb][cb] + fx * s_node[1][rb][cb + 1]) +
+                        fy * ((1.0f - fx) * s_node[1][rb + 1][cb] + fx * s_node[1][rb + 1][cb + 1]);
+        v = bilin<T>(Bi, g.pitch, g.W, g.H, x + u, y + w);
+      } else {
+        v = pixf<T>(Bi, g.pitch, g.W, g.H, y, x);
+      }
+      sB[r * C::BP + q] = v - K;
+    }
+  }
+  __syncthreads();
+
+  // ---- this lane's cell against the wave's shift band: P = sum (A-K)(B'-K),
+  // S = sum (B'-K), Q = sum (B'-K)^2, and the cell's own sum (A-K), (A-K)^2
+  constexpr int BRW = STEP + 2 * R;   // B' columns one cell row needs
+  float Pacc[SYG][C::NSY], Sacc[SYG][C::NSY], Qacc[SYG][C::NSY];
+  float sa = 0.0f, saa = 0.0f;
+  {
+#pragma unroll
+    for (int k = 0; k < SYG; ++k)
+#pragma unroll
+      for (int j = 0; j < C::NSY; ++j) Pacc[k][j] = 0.0f;
+    float cs[BRW], cq[BRW];
+#pragma unroll
+    for (int x = 0; x < BRW; ++x) cs[x] = cq[x] = 0.0f;
+    const float* bbase = sB + (ci * STEP + band * SYG) * C::BP + cj * STEP;
+    // stream the B' rows of the band once each; B' row rb meets A row
+    // rb - k for shift row k, so the last SYG A rows are kept (converted)
+    float ar[SYG][STEP];
+#pragma unroll
+    for (int rb = 0; rb < STEP + SYG - 1; ++rb) {
+      float brow[BRW];
+#pragma unroll
+      for (int x = 0; x < BRW; ++x) brow[x] = bbase[rb * C::BP + x];
+      if (rb < STEP) {
+        float* an = ar[rb % SYG];
+#pragma unroll
+        for (int x = 0; x < STEP; ++x) {
+          const uint32_t wd = aw[rb][(x * ES) >> 2];
+          const uint32_t px = ES == 1 ? (wd >> (8 * (x & 3))) & 0xffu : (wd >> (16 * (x & 1))) & 0xffffu;
+          an[x] = (float)px - K;
+          sa += an[x];
+          saa += an[x] * an[x];
+        }
+#pragma unroll
+        for (int x = 0; x < BRW; ++x) {
+          cs[x] += brow[x];
+          cq[x] += brow[x] * brow[x];
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < SYG; ++k) {
+        const int py = rb - k;
+        if (py >= 0 && py < STEP) {
+          const float* ap = ar[py % SYG];
+#pragma unroll
+          for (int j = 0; j < C::NSY; ++j) {
+            float s = Pacc[k][j];
+#pragma unroll
+            for (int x = 0; x < STEP; ++x) s += ap[x] * brow[x + j];
+            Pacc[k][j] = s;
+          }
+        }
+      }
+    }
+    // column sums of the band's first row, slid down for the other rows;
+    // box sums over STEP columns for every shift column
+#pragma unroll
+    for (int k = 0; k < SYG; ++k) {
+      if (k > 0) {
+        const float* rin = bbase + (STEP + k - 1) * C::BP;
+        const float* rout = bbase + (k - 1) * C::BP;
+#pragma unroll
+        for (int x = 0; x < BRW; ++x) {
+          const float vi = rin[x], vo = rout[x];
+          cs[x] += vi - vo;
+          cq[x] += vi * vi - vo * vo;
+        }
+      }
+      float s = 0.0f, q = 0.0f;
+#pragma unroll
+      for (int x = 0; x < STEP; ++x) {
+        s += cs[x];
+        q += cq[x];
+      }
+      Sacc[k][0] = s;
+      Qacc[k][0] = q;
+#pragma unroll
+      for (int j = 1; j < C::NSY; ++j) {
+        s += cs[j + STEP - 1] - cs[j - 1];
+        q += cq[j + STEP - 1] - cq[j - 1];
+        Sacc[k][j] = s;
+        Qacc[k][j] = q;
+      }
+    }
+  }
+  // ---- window sums: (cell + right-hand neighbour) by DPP wave_shl:1, then
+  // + the same pair one cell row down (lane + CW) by a lane permute.  Only
+  // lanes of a window's top-left cell keep meaningful sums.
+  auto quad = [&](float x) {
+    const float h = x + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x130, 0xF, 0xF, false));
+    return h + __int_as_float(__builtin_amdgcn_ds_bpermute((lane + C::CW) << 2, __float_as_int(h)));
+  };
+  sa = quad(sa);
+  saa = quad(saa);
+#pragma unroll
+  for (int k = 0; k < SYG; ++k)
+#pragma unroll
+    for (int j = 0; j < C::NSY; ++j) {
+      Pacc[k][j] = quad(Pacc[k][j]);
+      Sacc[k][j] = quad(Sacc[k][j]);
+      Qacc[k][j] = quad(Qacc[k][j]);
+    }
+  // ---- Pearson coefficient per shift, the band's peak by the tie key
+  const bool wact = cell_ok && ci < TH && cj < TW;
+  const int w = ci * TW + cj;
+  float* const rhoW = s_un;                      // [window][shift]
+  float* const s_best = s_un + C::NWIN * C::NS;  // [band][window]
+  int* const s_pk = reinterpret_cast<int*>(s_best + C::NG * C::NWIN);
+  {
+    const float n = (float)(4 * STEP * STEP);
+    const float mA = sa / n;
+    const float varA = saa - sa * mA;
+    const bool flatA = !(varA > kFlatRel * saa);
+    float best = -2.0f;
+    int bkey = 1 << 20, nflat = 0;
+#pragma unroll
+    for (int k = 0; k < SYG; ++k)
+#pragma unroll
+      for (int j = 0; j < C::NSY; ++j) {
+        const int sy = band * SYG + k - R, sx = j - R;
+        const float num = Pacc[k][j] - mA * Sacc[k][j];
+        const float varB = Qacc[k][j] - Sacc[k][j] * Sacc[k][j] / n;
+        const bool flat = flatA || !(varB > kFlatRel * Qacc[k][j]);
+        const float r = flat ? 0.0f : num * rsqrtf(varA * varB);
+        if (!g.fixed || sx == 0 || sy == 0) {
+          nflat += flat;
+          const int key = tie_key(sy, sx);
+          if (!g.fixed && better(r, key, best, bkey)) {
+            best = r;
+            bkey = key;
+          }
+        }
+        if (wact) rhoW[w * C::NS + (band * SYG + k) * C::NSY + j] = r;
+      }
+    if (wact) {
+      s_best[band * C::NWIN + w] = best;
+      s_pk[band * C::NWIN + w] = (bkey << 8) | nflat;
+    }
+  }
+  __syncthreads();
+  // ---- peak over the bands, fit, composition with the predictor's window mean
+  if (t < C::NWIN) {
+    const int wi = t / TW, wj = t - (t / TW) * TW;
+    const int a = a0 + wi, b = b0 + wj;
+    if (a < g.ny && b < g.nx) {
+      float best = -2.0f;
+      int bkey = 1 << 20, nflat = 0;
+#pragma unroll
+      for (int q = 0; q < C::NG; ++q) {
+        const float bq = s_best[q * C::NWIN + t];
+        const int pk = s_pk[q * C::NWIN + t];
+        nflat += pk & 255;
+        if (better(bq, pk >> 8, best, bkey)) {
+          best = bq;
+          bkey = pk >> 8;
+        }
+      }
+      int sy = 0, sx = 0;
+      if (!g.fixed) {
+        sx = (bkey & 63) - 32;
+        sy = ((bkey >> 6) & 63) - 32;
+      }
+      const float* rr = rhoW + t * C::NS;
+      auto rhof = [&](int y, int x) { return rr[(y + R) * C::NSY + x + R]; };
+      auto node = [&](int c, int y, int x) { return s_node[c][y - nlo_y][x - nlo_x]; };
+      float pu = 0.0f, pv = 0.0f;
+      if (Pn) window_mean_half_overlap(a, b, g.nx, g.ny, node, pu, pv);
+      finish_vector(g, pair, a, b, sy, sx, nflat == (g.fixed ? 5 : C::NS), pu, pv, rhof);
+    }
+  }
+}
+
 template <typename T, int STEP, int R, int SYG, int TW, int TH, int NT>
 hipError_t launch_tiled(const CorrArgs& g, int n, hipStream_t s) {
   dim3 grid((g.nx + TW - 1) / TW, (g.ny + TH - 1) / TH, n);
@@ -1005,8 +1446,17 @@ hipError_t launch_tiled(const CorrArgs& g, int n, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <typename T, int STEP, int R, int SYG, int TW, int TH>
+hipError_t launch_bands(const CorrArgs& g, int n, hipStream_t s) {
+  dim3 grid((g.nx + TW - 1) / TW, (g.ny + TH - 1) / TH, n);
+  hipLaunchKernelGGL((k_correct_bands<T, STEP, R, SYG, TW, TH>), grid, dim3(64 * ((2 * R + 1) / SYG)), 0, s, g);
+  return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_tiled_t(const CorrArgs& g, int n, hipStream_t s) {
+  if (!g.central && g.step == 8 && g.R == 4) return launch_bands<T, 8, 4, 3, 8, 6>(g, n, s);
+  if (!g.central && g.step == 8 && g.R == 1) return launch_bands<T, 8, 1, 1, 8, 6>(g, n, s);
   if (g.step == 8 && g.R == 4) return launch_tiled<T, 8, 4, 3, 8, 8, 256>(g, n, s);
   if (g.step == 8 && g.R == 1) return launch_tiled<T, 8, 1, 1, 8, 8, 256>(g, n, s);
   if (g.step == 12 && g.R == 4) return launch_tiled<T, 12, 4, 3, 5, 5, 128>(g, n, s);
