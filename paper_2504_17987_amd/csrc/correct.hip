@@ -1019,8 +1019,9 @@ struct BandCfg {
   static constexpr int NWIN = TW * TH;
   // union after the B' tile: raw source box + interpolation tables while the
   // tile is deformed, then coefficients [window][shift] and the per-band
-  // peaks [band][window] (value, key << 8 | flat count)
-  static constexpr int TAB_WORDS = 2 * (BH + BW);
+  // peaks [band][window] (value, key << 1 | all shifts flat)
+  static constexpr int BW4 = (BW + 3) / 4 * 4;            // B' columns written (whole groups)
+  static constexpr int TAB_WORDS = 2 * (BH + BW4);
   static constexpr int RES_WORDS = NWIN * NS + 2 * NG * NWIN;
   static constexpr int RAW_WORDS = 3888;
   static constexpr int UNION = RAW_WORDS + TAB_WORDS > RES_WORDS ? RAW_WORDS + TAB_WORDS : RES_WORDS;
@@ -1078,13 +1079,24 @@ void k_correct_bands(CorrArgs g) {
   {
     const int rowbytes = g.W * ES;
     const int xa0 = (x0 + cj * STEP) * ES;
+    if (y0 >= 0 && y0 + C::AH <= g.H && x0 >= 0 && (x0 + C::AW) * ES <= rowbytes) {
+      // the whole A tile lies inside the image
+      const uint32_t ok = cell_ok ? 0xffffffffu : 0u;
+      const uint8_t* row = Ai + (int64_t)(y0 + ci * STEP) * g.pitch + xa0;
 #pragma unroll
-    for (int py = 0; py < STEP; ++py) {
-      const int y = y0 + ci * STEP + py;
-      const uint32_t ok = (cell_ok && (unsigned)y < (unsigned)g.H) ? 0xffffffffu : 0u;
-      const uint8_t* row = Ai + (int64_t)min(max(y, 0), g.H - 1) * g.pitch;
+      for (int py = 0; py < STEP; ++py)
 #pragma unroll
-      for (int k = 0; k < NWR; ++k) aw[py][k] = masked_word(row, rowbytes, xa0 + 4 * k) & ok;
+        for (int k = 0; k < NWR; ++k)
+          aw[py][k] = *reinterpret_cast<const uint32_t*>(row + (int64_t)py * g.pitch + 4 * k) & ok;
+    } else {
+#pragma unroll
+      for (int py = 0; py < STEP; ++py) {
+        const int y = y0 + ci * STEP + py;
+        const uint32_t ok = (cell_ok && (unsigned)y < (unsigned)g.H) ? 0xffffffffu : 0u;
+        const uint8_t* row = Ai + (int64_t)min(max(y, 0), g.H - 1) * g.pitch;
+#pragma unroll
+        for (int k = 0; k < NWR; ++k) aw[py][k] = masked_word(row, rowbytes, xa0 + 4 * k) & ok;
+      }
     }
   }
   float umin = 0.0f, umax = 0.0f, vmin = 0.0f, vmax = 0.0f, bad = 0.0f;
@@ -1099,14 +1111,11 @@ void k_correct_bands(CorrArgs g) {
       vmax = fmaxf(vmax, nv[i]);
       if (!(fabsf(nu[i]) < 1.0e6f && fabsf(nv[i]) < 1.0e6f)) bad = 1.0f;   // also NaN
     }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-      bad = fmaxf(bad, __shfl_xor(bad, o));
-      umin = fminf(umin, __shfl_xor(umin, o));
-      umax = fmaxf(umax, __shfl_xor(umax, o));
-      vmin = fminf(vmin, __shfl_xor(vmin, o));
-      vmax = fmaxf(vmax, __shfl_xor(vmax, o));
-    }
+    bad = wave_max(bad);
+    umin = wave_min(umin);
+    umax = wave_max(umax);
+    vmin = wave_min(vmin);
+    vmax = wave_max(vmax);
     if (band == 0) {
 #pragma unroll
       for (int i = 0; i < NL; ++i) {
@@ -1136,21 +1145,32 @@ void k_correct_bands(CorrArgs g) {
   int* s_rb = reinterpret_cast<int*>(s_un + C::RAW_WORDS);   // per B' row: base node, fraction
   float* s_rf = s_un + C::RAW_WORDS + C::BH;
   int* s_cb = reinterpret_cast<int*>(s_un + C::RAW_WORDS + 2 * C::BH);   // per B' column
-  float* s_cf = s_un + C::RAW_WORDS + 2 * C::BH + C::BW;
+  float* s_cf = s_un + C::RAW_WORDS + 2 * C::BH + C::BW4;
   if (staged) {
     // thread -> (word column, first row); U reads in flight per thread
     const int rowbytes = g.W * ES;
     const int rstep = NT / nwords;
     const int r0 = t / nwords, w = t - r0 * nwords;
     constexpr int U = 8;
+    const bool inside = iy0 >= 0 && iy0 + nrows <= g.H && xw0 >= 0 && 4 * (xw0 + nwords) <= rowbytes;
     if (r0 < rstep) {
       for (int rb = r0; rb < nrows; rb += U * rstep) {
         uint32_t val[U];
+        if (inside) {
+          // the box lies inside the image: rows past the box read its last row
+          const uint8_t* col = Bi + 4 * (xw0 + w);
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int y = iy0 + rb + u * rstep;
-          const uint32_t ok = (unsigned)y < (unsigned)g.H ? 0xffffffffu : 0u;
-          val[u] = masked_word(Bi + (int64_t)min(max(y, 0), g.H - 1) * g.pitch, rowbytes, 4 * (xw0 + w)) & ok;
+          for (int u = 0; u < U; ++u) {
+            const int y = iy0 + min(rb + u * rstep, nrows - 1);
+            val[u] = *reinterpret_cast<const uint32_t*>(col + (int64_t)y * g.pitch);
+          }
+        } else {
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const int y = iy0 + rb + u * rstep;
+            const uint32_t ok = (unsigned)y < (unsigned)g.H ? 0xffffffffu : 0u;
+            val[u] = masked_word(Bi + (int64_t)min(max(y, 0), g.H - 1) * g.pitch, rowbytes, 4 * (xw0 + w)) & ok;
+          }
         }
 #pragma unroll
         for (int u = 0; u < U; ++u)
@@ -1159,7 +1179,8 @@ void k_correct_bands(CorrArgs g) {
     }
   }
   // interpolation tables of the B' tile (the same arithmetic as interp_u)
-  for (int i = t; i < C::BH + C::BW; i += NT) {
+  // (columns past BW pad the last group: written to B', never correlated)
+  for (int i = t; i < C::BH + C::BW4; i += NT) {
     const bool row = i < C::BH;
     const int p = row ? yb + i : xb + (i - C::BH);
     const int n = row ? g.ny : g.nx;
@@ -1179,8 +1200,7 @@ void k_correct_bands(CorrArgs g) {
       if constexpr (ES == 1) isum = (int)__builtin_amdgcn_sad_u8(aw[py][k], 0u, (uint32_t)isum);
       else isum += (int)(aw[py][k] & 0xffffu) + (int)(aw[py][k] >> 16);
     }
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) isum += __shfl_xor(isum, o);
+  isum = wave_sum(isum);
   const float K = rintf((float)isum / (float)(C::AH * C::AW));
   __syncthreads();
 
@@ -1192,7 +1212,6 @@ void k_correct_bands(CorrArgs g) {
     const int rowb = 4 * nwords, xoff = 4 * xw0;
     auto rawv = [&](const uint8_t* p) -> float { return (float)*reinterpret_cast<const T*>(p); };
     const float fxlo = (float)ix0, fxhi = (float)(ix1 - 1), fylo = (float)iy0, fyhi = (float)(iy1 - 1);
-    const int rbase = iy0 * rowb + xoff;
     for (int idx = t; idx < C::BH * BQ; idx += NT) {
       const int r = idx / BQ, q = 4 * (idx - (idx / BQ) * BQ);
       float uu[4] = {0.0f, 0.0f, 0.0f, 0.0f}, vv[4] = {0.0f, 0.0f, 0.0f, 0.0f};
@@ -1208,7 +1227,7 @@ void k_correct_bands(CorrArgs g) {
           const float du = u1 - u0, dv = v1 - v0;
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
-            const float fx = s_cf[min(q + e, C::BW - 1)];
+            const float fx = s_cf[q + e];
             uu[e] = u0 + fx * du;
             vv[e] = v0 + fx * dv;
           }
@@ -1221,9 +1240,8 @@ void k_correct_bands(CorrArgs g) {
           }
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
-            const int qq = min(q + e, C::BW - 1);
-            const bool nxt = s_cb[qq] != cb0;
-            const float fx = s_cf[qq];
+            const bool nxt = s_cb[q + e] != cb0;
+            const float fx = s_cf[q + e];
             const float ul = nxt ? Vu[1] : Vu[0], ur = nxt ? Vu[2] : Vu[1];
             const float vl = nxt ? Vv[1] : Vv[0], vr = nxt ? Vv[2] : Vv[1];
             uu[e] = ul + fx * (ur - ul);
@@ -1238,9 +1256,10 @@ void k_correct_bands(CorrArgs g) {
         const float qx = (xq + (float)e) + uu[e], qy = yr + vv[e];
         const float fx0 = floorf(qx), fy0 = floorf(qy);
         const float fx = qx - fx0, fy = qy - fy0;
+        // offsets relative to the box are small and non-negative: 24-bit products
         const int ix = (int)__builtin_amdgcn_fmed3f(fx0, fxlo, fxhi);
         const int iy = (int)__builtin_amdgcn_fmed3f(fy0, fylo, fyhi);
-        const uint8_t* p0 = rawb + (iy * rowb + ix * ES) - rbase;
+        const uint8_t* p0 = rawb + (__umul24((unsigned)(iy - iy0), (unsigned)rowb) + (unsigned)(ix * ES - xoff));
         const float p00 = rawv(p0), p01 = rawv(p0 + ES), p10 = rawv(p0 + rowb), p11 = rawv(p0 + rowb + ES);
         const float top = p00 + fx * (p01 - p00), bot = p10 + fx * (p11 - p10);
         out[e] = (top + fy * (bot - top)) - K;
@@ -1273,6 +1292,20 @@ void k_correct_bands(CorrArgs g) {
   constexpr int BRW = STEP + 2 * R;   // B' columns one cell row needs
   float Pacc[SYG][C::NSY], Sacc[SYG][C::NSY], Qacc[SYG][C::NSY];
   float sa = 0.0f, saa = 0.0f;
+  if constexpr (ES == 1) {
+    // the cell's sums of (A-K) and (A-K)^2 from exact integer sums of A, A^2
+    uint32_t s1 = 0u, s2 = 0u;
+#pragma unroll
+    for (int py = 0; py < STEP; ++py)
+#pragma unroll
+      for (int k = 0; k < NWR; ++k) {
+        s1 = __builtin_amdgcn_sad_u8(aw[py][k], 0u, s1);
+        s2 = __builtin_amdgcn_udot4(aw[py][k], aw[py][k], s2, false);
+      }
+    const int Ki = (int)K;
+    sa = (float)((int)s1 - STEP * STEP * Ki);
+    saa = (float)((int)s2 - 2 * Ki * (int)s1 + STEP * STEP * Ki * Ki);
+  }
   {
 #pragma unroll
     for (int k = 0; k < SYG; ++k)
@@ -1297,8 +1330,10 @@ void k_correct_bands(CorrArgs g) {
           const uint32_t wd = aw[rb][(x * ES) >> 2];
           const uint32_t px = ES == 1 ? (wd >> (8 * (x & 3))) & 0xffu : (wd >> (16 * (x & 1))) & 0xffffu;
           an[x] = (float)px - K;
-          sa += an[x];
-          saa += an[x] * an[x];
+          if constexpr (ES != 1) {
+            sa += an[x];
+            saa += an[x] * an[x];
+          }
         }
 #pragma unroll
         for (int x = 0; x < BRW; ++x) {
@@ -1380,8 +1415,9 @@ void k_correct_bands(CorrArgs g) {
     const float mA = sa / n;
     const float varA = saa - sa * mA;
     const bool flatA = !(varA > kFlatRel * saa);
-    float best = -2.0f;
-    int bkey = 1 << 20, nflat = 0;
+    // coefficients first (no control flow), then the band's peak
+    float rv[SYG][C::NSY];
+    bool allflat = true;   // every used shift of the band is flat
 #pragma unroll
     for (int k = 0; k < SYG; ++k)
 #pragma unroll
@@ -1390,20 +1426,35 @@ void k_correct_bands(CorrArgs g) {
         const float num = Pacc[k][j] - mA * Sacc[k][j];
         const float varB = Qacc[k][j] - Sacc[k][j] * Sacc[k][j] / n;
         const bool flat = flatA || !(varB > kFlatRel * Qacc[k][j]);
-        const float r = flat ? 0.0f : num * rsqrtf(varA * varB);
-        if (!g.fixed || sx == 0 || sy == 0) {
-          nflat += flat;
-          const int key = tie_key(sy, sx);
-          if (!g.fixed && better(r, key, best, bkey)) {
-            best = r;
-            bkey = key;
-          }
-        }
-        if (wact) rhoW[w * C::NS + (band * SYG + k) * C::NSY + j] = r;
+        // (varA varB > 0 unless flat; the flat value replaces the quotient)
+        const float r = num * __builtin_amdgcn_rsqf(varA * varB);
+        rv[k][j] = flat ? 0.0f : r;
+        const bool used = !g.fixed || sx == 0 || sy == 0;
+        if (used) allflat = allflat && flat;
       }
+    // the band's peak: the largest coefficient, then the smallest tie key
+    // among the shifts that reach it
+    float best = -2.0f;
+    int bkey = 1 << 20;
+    if (!g.fixed) {
+#pragma unroll
+      for (int k = 0; k < SYG; ++k)
+#pragma unroll
+        for (int j = 0; j < C::NSY; ++j) best = fmaxf(best, rv[k][j]);
+#pragma unroll
+      for (int k = 0; k < SYG; ++k)
+#pragma unroll
+        for (int j = 0; j < C::NSY; ++j)
+          bkey = rv[k][j] == best ? min(bkey, tie_key(band * SYG + k - R, j - R)) : bkey;
+    }
     if (wact) {
+      float* d = rhoW + w * C::NS + band * SYG * C::NSY;
+#pragma unroll
+      for (int k = 0; k < SYG; ++k)
+#pragma unroll
+        for (int j = 0; j < C::NSY; ++j) d[k * C::NSY + j] = rv[k][j];
       s_best[band * C::NWIN + w] = best;
-      s_pk[band * C::NWIN + w] = (bkey << 8) | nflat;
+      s_pk[band * C::NWIN + w] = (bkey << 1) | (allflat ? 1 : 0);
     }
   }
   __syncthreads();
@@ -1413,15 +1464,16 @@ void k_correct_bands(CorrArgs g) {
     const int a = a0 + wi, b = b0 + wj;
     if (a < g.ny && b < g.nx) {
       float best = -2.0f;
-      int bkey = 1 << 20, nflat = 0;
+      int bkey = 1 << 20;
+      bool allflat = true;
 #pragma unroll
       for (int q = 0; q < C::NG; ++q) {
         const float bq = s_best[q * C::NWIN + t];
         const int pk = s_pk[q * C::NWIN + t];
-        nflat += pk & 255;
-        if (better(bq, pk >> 8, best, bkey)) {
+        allflat = allflat && (pk & 1);
+        if (better(bq, pk >> 1, best, bkey)) {
           best = bq;
-          bkey = pk >> 8;
+          bkey = pk >> 1;
         }
       }
       int sy = 0, sx = 0;
@@ -1434,7 +1486,7 @@ void k_correct_bands(CorrArgs g) {
       auto node = [&](int c, int y, int x) { return s_node[c][y - nlo_y][x - nlo_x]; };
       float pu = 0.0f, pv = 0.0f;
       if (Pn) window_mean_half_overlap(a, b, g.nx, g.ny, node, pu, pv);
-      finish_vector(g, pair, a, b, sy, sx, nflat == (g.fixed ? 5 : C::NS), pu, pv, rhof);
+      finish_vector(g, pair, a, b, sy, sx, allflat, pu, pv, rhof);
     }
   }
 }

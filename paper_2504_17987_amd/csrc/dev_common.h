@@ -47,6 +47,48 @@ __device__ __forceinline__ WgIdx xcd_order() {
   return w;
 }
 
+// Whole-wave reductions by DPP (all 64 lanes active), returned wave-uniform:
+// pairs and quads by quad permutes, rows of 16 by the half-row and row
+// mirrors, then row 15 -> row 1, row 31 -> rows 2 and 3; lane 63 ends
+// with the reduction of every lane.  For min and max a lane whose row is
+// masked keeps its own value (harmless: the operations are idempotent); for
+// the sum it takes 0.
+#define PIV_DPP_I(v, ctrl, rmask, old) __builtin_amdgcn_update_dpp((old), (v), (ctrl), (rmask), 0xF, false)
+#define PIV_WAVE_REDUCE_F(x, OP)                                                        \
+  do {                                                                                 \
+    int xi_ = __float_as_int(x);                                                       \
+    x = OP(x, __int_as_float(PIV_DPP_I(xi_, 0xB1, 0xF, xi_)));                         \
+    xi_ = __float_as_int(x);                                                           \
+    x = OP(x, __int_as_float(PIV_DPP_I(xi_, 0x4E, 0xF, xi_)));                         \
+    xi_ = __float_as_int(x);                                                           \
+    x = OP(x, __int_as_float(PIV_DPP_I(xi_, 0x141, 0xF, xi_)));                        \
+    xi_ = __float_as_int(x);                                                           \
+    x = OP(x, __int_as_float(PIV_DPP_I(xi_, 0x140, 0xF, xi_)));                        \
+    xi_ = __float_as_int(x);                                                           \
+    x = OP(x, __int_as_float(PIV_DPP_I(xi_, 0x142, 0xA, xi_)));                        \
+    xi_ = __float_as_int(x);                                                           \
+    x = OP(x, __int_as_float(PIV_DPP_I(xi_, 0x143, 0xC, xi_)));                        \
+    x = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));              \
+  } while (0)
+
+__device__ __forceinline__ float wave_min(float x) {
+  PIV_WAVE_REDUCE_F(x, fminf);
+  return x;
+}
+__device__ __forceinline__ float wave_max(float x) {
+  PIV_WAVE_REDUCE_F(x, fmaxf);
+  return x;
+}
+__device__ __forceinline__ int wave_sum(int x) {
+  x += PIV_DPP_I(x, 0xB1, 0xF, 0);
+  x += PIV_DPP_I(x, 0x4E, 0xF, 0);
+  x += PIV_DPP_I(x, 0x141, 0xF, 0);
+  x += PIV_DPP_I(x, 0x140, 0xF, 0);
+  x += PIV_DPP_I(x, 0x142, 0xA, 0);
+  x += PIV_DPP_I(x, 0x143, 0xC, 0);
+  return __builtin_amdgcn_readlane(x, 63);
+}
+
 // Pixel value as float with zero outside the image.
 template <typename T>
 __device__ __forceinline__ float pixf(const uint8_t* img, int64_t pitch, int W, int H, int y, int x) {
