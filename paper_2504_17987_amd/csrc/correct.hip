@@ -1069,25 +1069,29 @@ void k_correct_bands(CorrArgs g) {
     for (int i = 0; i < NL; ++i) {
       const int idx = min(lane + 64 * i, NNODE - 1);
       const int r = idx / C::NNX, q = idx - (idx / C::NNX) * C::NNX;
-      const int o = min(nlo_y + r, g.ny - 1) * g.nx + min(nlo_x + q, g.nx - 1);
-      nu[i] = Pn[o];
-      nv[i] = Pn[np + o];
+      const int o = __umul24(min(nlo_y + r, g.ny - 1), g.nx) + min(nlo_x + q, g.nx - 1);
+      nu[i] = Pn[(unsigned)o];
+      nv[i] = Pn[(unsigned)(np + o)];
     }
   }
   // the A cell of this lane as packed pixels (zero outside the image)
+  // a frame whose bytes fit 31 bits (pitch below 2^24) is addressed by 32-bit
+  // offsets from its base, with 24-bit products
+  const bool off32 = g.pitch < (1 << 24) && g.pitch * (int64_t)g.H <= 0x7fffffff;
+  const unsigned pitch32 = (unsigned)g.pitch;
   uint32_t aw[STEP][NWR];
   {
     const int rowbytes = g.W * ES;
     const int xa0 = (x0 + cj * STEP) * ES;
-    if (y0 >= 0 && y0 + C::AH <= g.H && x0 >= 0 && (x0 + C::AW) * ES <= rowbytes) {
+    if (off32 && y0 >= 0 && y0 + C::AH <= g.H && x0 >= 0 && (x0 + C::AW) * ES <= rowbytes) {
       // the whole A tile lies inside the image
       const uint32_t ok = cell_ok ? 0xffffffffu : 0u;
-      const uint8_t* row = Ai + (int64_t)(y0 + ci * STEP) * g.pitch + xa0;
+      const unsigned o0 = __umul24((unsigned)(y0 + ci * STEP), pitch32) + (unsigned)xa0;
 #pragma unroll
       for (int py = 0; py < STEP; ++py)
 #pragma unroll
         for (int k = 0; k < NWR; ++k)
-          aw[py][k] = *reinterpret_cast<const uint32_t*>(row + (int64_t)py * g.pitch + 4 * k) & ok;
+          aw[py][k] = *reinterpret_cast<const uint32_t*>(Ai + (size_t)(o0 + py * pitch32 + 4 * k)) & ok;
     } else {
 #pragma unroll
       for (int py = 0; py < STEP; ++py) {
@@ -1099,23 +1103,30 @@ void k_correct_bands(CorrArgs g) {
       }
     }
   }
-  float umin = 0.0f, umax = 0.0f, vmin = 0.0f, vmax = 0.0f, bad = 0.0f;
+  // range of the nodes as integer floors: the raw box only needs floor(u)
+  // and floor(v) (the tile origin is an integer).  A node that is not finite
+  // or not below 100 px marks the tile (range 255), which sends it to the
+  // checked path.
+  int flu = 0, fhu = 0, flv = 0, fhv = 0;
   if (Pn) {
-    umin = vmin = 3.0e38f;
-    umax = vmax = -3.0e38f;
+    float lu = nu[0], hu = nu[0], lv = nv[0], hv = nv[0];
+    bool ok = true;
 #pragma unroll
     for (int i = 0; i < NL; ++i) {
-      umin = fminf(umin, nu[i]);
-      umax = fmaxf(umax, nu[i]);
-      vmin = fminf(vmin, nv[i]);
-      vmax = fmaxf(vmax, nv[i]);
-      if (!(fabsf(nu[i]) < 1.0e6f && fabsf(nv[i]) < 1.0e6f)) bad = 1.0f;   // also NaN
+      lu = fminf(lu, nu[i]);
+      hu = fmaxf(hu, nu[i]);
+      lv = fminf(lv, nv[i]);
+      hv = fmaxf(hv, nv[i]);
+      ok = ok && fabsf(nu[i]) < 100.0f && fabsf(nv[i]) < 100.0f;   // false for NaN
     }
-    bad = wave_max(bad);
-    umin = wave_min(umin);
-    umax = wave_max(umax);
-    vmin = wave_min(vmin);
-    vmax = wave_max(vmax);
+    // encoded so that one max-reduction per bound serves: 127 - floor(lo), floor(hi) + 128
+    const int el_u = ok ? 127 - (int)floorf(lu) : 255, eh_u = ok ? (int)floorf(hu) + 128 : 255;
+    const int el_v = ok ? 127 - (int)floorf(lv) : 255, eh_v = ok ? (int)floorf(hv) + 128 : 255;
+    const int ru = wave_max_i((el_u << 16) | eh_u), rv = wave_max_i((el_v << 16) | eh_v);
+    flu = 127 - (ru >> 16);
+    fhu = (ru & 0xffff) - 128;
+    flv = 127 - (rv >> 16);
+    fhv = (rv & 0xffff) - 128;
     if (band == 0) {
 #pragma unroll
       for (int i = 0; i < NL; ++i) {
@@ -1130,16 +1141,16 @@ void k_correct_bands(CorrArgs g) {
   }
 
   // raw source box of B for the deformation, when it fits
-  const int ix0 = (int)floorf((float)xb + umin) - 1;
-  const int ix1 = (int)floorf((float)(xb + C::BW - 1) + umax) + 2;
-  const int iy0 = (int)floorf((float)yb + vmin) - 1;
-  const int iy1 = (int)floorf((float)(yb + C::BH - 1) + vmax) + 2;
+  const int ix0 = xb + flu - 1;
+  const int ix1 = xb + C::BW - 1 + fhu + 2;
+  const int iy0 = yb + flv - 1;
+  const int iy1 = yb + C::BH - 1 + fhv + 2;
   const int xw0 = (ix0 * ES) >> 2;
   const int nwords = ((ix1 * ES + ES - 1) >> 2) - xw0 + 1;
   const int nrows = iy1 - iy0 + 1;
-  // (a displacement range that is not finite or wider than a window takes
-  // the unstaged path, whose reads are checked one by one)
-  const bool sane = bad == 0.0f && (umax - umin) < 64.0f && (vmax - vmin) < 64.0f;
+  // (a displacement range that is marked or wider than a window takes the
+  // unstaged path, whose reads are checked one by one)
+  const bool sane = fhu - flu < 64 && fhv - flv < 64;
   const bool staged = sane && nwords <= NT && nwords * nrows <= C::RAW_WORDS;
   uint32_t* sraw = reinterpret_cast<uint32_t*>(s_un);
   int* s_rb = reinterpret_cast<int*>(s_un + C::RAW_WORDS);   // per B' row: base node, fraction
@@ -1152,29 +1163,29 @@ void k_correct_bands(CorrArgs g) {
     const int rstep = NT / nwords;
     const int r0 = t / nwords, w = t - r0 * nwords;
     constexpr int U = 8;
-    const bool inside = iy0 >= 0 && iy0 + nrows <= g.H && xw0 >= 0 && 4 * (xw0 + nwords) <= rowbytes;
+    const bool inside = off32 && iy0 >= 0 && iy0 + nrows <= g.H && xw0 >= 0 && 4 * (xw0 + nwords) <= rowbytes;
     if (r0 < rstep) {
+      // slots past the box take its last row again (the same word is
+      // written twice with the same value), so the stores need no branch
       for (int rb = r0; rb < nrows; rb += U * rstep) {
         uint32_t val[U];
         if (inside) {
-          // the box lies inside the image: rows past the box read its last row
-          const uint8_t* col = Bi + 4 * (xw0 + w);
+          const unsigned col = 4u * (unsigned)(xw0 + w);
 #pragma unroll
           for (int u = 0; u < U; ++u) {
-            const int y = iy0 + min(rb + u * rstep, nrows - 1);
-            val[u] = *reinterpret_cast<const uint32_t*>(col + (int64_t)y * g.pitch);
+            const unsigned y = (unsigned)(iy0 + min(rb + u * rstep, nrows - 1));
+            val[u] = *reinterpret_cast<const uint32_t*>(Bi + (size_t)(__umul24(y, pitch32) + col));
           }
         } else {
 #pragma unroll
           for (int u = 0; u < U; ++u) {
-            const int y = iy0 + rb + u * rstep;
+            const int y = iy0 + min(rb + u * rstep, nrows - 1);
             const uint32_t ok = (unsigned)y < (unsigned)g.H ? 0xffffffffu : 0u;
             val[u] = masked_word(Bi + (int64_t)min(max(y, 0), g.H - 1) * g.pitch, rowbytes, 4 * (xw0 + w)) & ok;
           }
         }
 #pragma unroll
-        for (int u = 0; u < U; ++u)
-          if (rb + u * rstep < nrows) sraw[(rb + u * rstep) * nwords + w] = val[u];
+        for (int u = 0; u < U; ++u) sraw[min(rb + u * rstep, nrows - 1) * nwords + w] = val[u];
       }
     }
   }
@@ -1201,7 +1212,7 @@ void k_correct_bands(CorrArgs g) {
       else isum += (int)(aw[py][k] & 0xffffu) + (int)(aw[py][k] >> 16);
     }
   isum = wave_sum(isum);
-  const float K = rintf((float)isum / (float)(C::AH * C::AW));
+  const float K = (float)((isum + C::AH * C::AW / 2) / (C::AH * C::AW));   // (isum >= 0)
   __syncthreads();
 
   // deformed B' tile, in groups of four pixels of one row
@@ -1211,7 +1222,11 @@ void k_correct_bands(CorrArgs g) {
     const uint8_t* rawb = reinterpret_cast<const uint8_t*>(sraw);
     const int rowb = 4 * nwords, xoff = 4 * xw0;
     auto rawv = [&](const uint8_t* p) -> float { return (float)*reinterpret_cast<const T*>(p); };
-    const float fxlo = (float)ix0, fxhi = (float)(ix1 - 1), fylo = (float)iy0, fyhi = (float)(iy1 - 1);
+    // coordinates relative to the box: every real pixel lands at >= 1 (the
+    // box has a one-pixel margin), so truncation is the floor; the clamps
+    // only keep the padding columns of a ragged last group inside the box
+    const int ixhi = ix1 - 1 - ix0, iyhi = iy1 - 1 - iy0;
+    const int xadd = ix0 * ES - xoff;   // byte offset of box column 0 in a staged row
     for (int idx = t; idx < C::BH * BQ; idx += NT) {
       const int r = idx / BQ, q = 4 * (idx - (idx / BQ) * BQ);
       float uu[4] = {0.0f, 0.0f, 0.0f, 0.0f}, vv[4] = {0.0f, 0.0f, 0.0f, 0.0f};
@@ -1249,17 +1264,15 @@ void k_correct_bands(CorrArgs g) {
           }
         }
       }
-      const float yr = (float)(yb + r), xq = (float)(xb + q);
+      const float yr = (float)(yb + r - iy0), xq = (float)(xb + q - ix0);
       float out[4];
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const float qx = (xq + (float)e) + uu[e], qy = yr + vv[e];
-        const float fx0 = floorf(qx), fy0 = floorf(qy);
-        const float fx = qx - fx0, fy = qy - fy0;
-        // offsets relative to the box are small and non-negative: 24-bit products
-        const int ix = (int)__builtin_amdgcn_fmed3f(fx0, fxlo, fxhi);
-        const int iy = (int)__builtin_amdgcn_fmed3f(fy0, fylo, fyhi);
-        const uint8_t* p0 = rawb + (__umul24((unsigned)(iy - iy0), (unsigned)rowb) + (unsigned)(ix * ES - xoff));
+        const float fx = __builtin_amdgcn_fractf(qx), fy = __builtin_amdgcn_fractf(qy);
+        // (as unsigned, a negative index would clamp to the top as well)
+        const unsigned ix = min((unsigned)(int)qx, (unsigned)ixhi), iy = min((unsigned)(int)qy, (unsigned)iyhi);
+        const uint8_t* p0 = rawb + (__umul24(iy, (unsigned)rowb) + (ix * ES + xadd));
         const float p00 = rawv(p0), p01 = rawv(p0 + ES), p10 = rawv(p0 + rowb), p11 = rawv(p0 + rowb + ES);
         const float top = p00 + fx * (p01 - p00), bot = p10 + fx * (p11 - p10);
         out[e] = (top + fy * (bot - top)) - K;

@@ -79,6 +79,15 @@ __device__ __forceinline__ float wave_max(float x) {
   PIV_WAVE_REDUCE_F(x, fmaxf);
   return x;
 }
+__device__ __forceinline__ int wave_max_i(int x) {
+  x = max(x, PIV_DPP_I(x, 0xB1, 0xF, x));
+  x = max(x, PIV_DPP_I(x, 0x4E, 0xF, x));
+  x = max(x, PIV_DPP_I(x, 0x141, 0xF, x));
+  x = max(x, PIV_DPP_I(x, 0x140, 0xF, x));
+  x = max(x, PIV_DPP_I(x, 0x142, 0xA, x));
+  x = max(x, PIV_DPP_I(x, 0x143, 0xC, x));
+  return __builtin_amdgcn_readlane(x, 63);
+}
 __device__ __forceinline__ int wave_sum(int x) {
   x += PIV_DPP_I(x, 0xB1, 0xF, 0);
   x += PIV_DPP_I(x, 0x4E, 0xF, 0);
