@@ -124,6 +124,13 @@ __device__ __forceinline__ void cswap(V& a, V& b) {
   a = lo;
   b = hi;
 }
+// floats by min/max (two instructions; the values sorted here are finite)
+template <>
+__device__ __forceinline__ void cswap<float>(float& a, float& b) {
+  const float lo = fminf(a, b), hi = fmaxf(a, b);
+  a = lo;
+  b = hi;
+}
 
 // Sort the first 8 of N >= 8 values ascending (Batcher's odd-even merge
 // network, 19 exchanges).
@@ -173,6 +180,7 @@ constexpr int kSlotI = 0x7fffffff;
 // two middle values.
 __device__ __forceinline__ float median8_f(float (&v)[8], int k) {
   sort8<8, float>(v);
+  if (k == 8) return 0.5f * (v[3] + v[4]);   // every slot real (the usual case)
   if (k & 1) return pick<8>(v, k >> 1);
   return 0.5f * (pick<8>(v, (k >> 1) - 1) + pick<8>(v, k >> 1));
 }
@@ -180,6 +188,7 @@ __device__ __forceinline__ float median8_f(float (&v)[8], int k) {
 // Lower median of the k (>= 1) real values among 9 slots.
 __device__ __forceinline__ int median9_low_i(int (&v)[9], int k) {
   sort9(v);
+  if (k == 9) return v[4];   // every slot real (the usual case)
   return pick<9>(v, (k - 1) >> 1);
 }
 

@@ -212,13 +212,17 @@ __device__ __forceinline__ unsigned long long sad_key(uint32_t sad, int dy, int 
 // and every candidate column, four at a time with v_qsad_pk_u16_u8 (four
 // 16-bit SADs of one A word against four byte offsets of an 8-byte B span).
 // The node's A block is staged in LDS; each lane streams its BLK rows of B.
+// Without a parent (the coarsest level) every node of a workgroup searches
+// the same rows, so with STAGE the band of B they cover (one span of words
+// per row, the nodes step/4 words apart) is staged in LDS too, instead of
+// each lane reading its own row from global memory.
 // Winner as in the other forms: the minimum packed key over the node's lanes.
 // ---------------------------------------------------------------------------
-template <int NW, int NGRP>
+template <int NW, int NGRP, bool STAGE>
 __global__ __launch_bounds__(256) void k_sad_q(SadArgs g) {
   constexpr int BLK = 4 * NW, RW = NW + NGRP;
   static_assert(BLK * BLK * 255 <= 65535, "16-bit SAD fields");
-  extern __shared__ uint32_t s_ablk[];        // [npw][BLK][NW]
+  extern __shared__ uint32_t s_ablk[];        // [npw][BLK][NW], then (STAGE) [G + BLK - 1][nwb]
   __shared__ unsigned long long s_key[256];
 
   const WgIdx wg = xcd_order();
@@ -243,6 +247,19 @@ __global__ __launch_bounds__(256) void k_sad_q(SadArgs g) {
     const uint8_t* row = Ab + (int64_t)(oy + r) * g.pitch;
     s_ablk[idx] = word_at(row, (b0 + jj) * g.step + off + 4 * w);
   }
+  // (STAGE) the B band: rows oy - R .. oy - R + G + BLK - 2, words from the
+  // first node's aligned start; node j's span starts j step/4 words in
+  const int nwb = (npw - 1) * (g.step >> 2) + RW + 1;   // words per staged row
+  uint32_t* s_b = s_ablk + npw * BLK * NW;
+  if constexpr (STAGE) {
+    const int x0 = (b0 * g.step + off - g.R) & ~3;
+    const int nw = (nblk - 1) * (g.step >> 2) + RW + 1;   // words the active nodes read
+    const int nr = G + BLK - 1;
+    for (int idx = t; idx < nr * nw; idx += 256) {
+      const int r = idx / nw, w = idx - r * nw;
+      s_b[r * nwb + w] = *reinterpret_cast<const uint32_t*>(Bb + (int64_t)(oy - g.R + r) * g.pitch + x0 + 4 * w);
+    }
+  }
 
   int cx = 0, cy = 0;
   if (g.parent && active) {
@@ -264,7 +281,8 @@ __global__ __launch_bounds__(256) void k_sad_q(SadArgs g) {
     const uint32_t* ablk = s_ablk + j * BLK * NW;
 #pragma unroll 4
     for (int ar = 0; ar < BLK; ++ar) {
-      const uint32_t* row = reinterpret_cast<const uint32_t*>(Bb + (int64_t)(by + ar) * g.pitch + xa);
+      const uint32_t* row = STAGE ? s_b + (q + ar) * nwb + j * (g.step >> 2)
+                                  : reinterpret_cast<const uint32_t*>(Bb + (int64_t)(by + ar) * g.pitch + xa);
       uint32_t w[RW + 1];
 #pragma unroll
       for (int i = 0; i <= RW; ++i) w[i] = row[i];
@@ -867,8 +885,17 @@ hipError_t launch_sad_level(const Plan& P, int l, const void*, const void*, int6
     dim3 grid((v.nx + npw - 1) / npw, v.ny, n);
     size_t lds = sizeof(uint32_t) * (size_t)npw * P.block * NW;
     const int ngrp = (G + 3) / 4;
+    // the coarsest level stages its common band of B when the nodes' spans
+    // stay word-aligned relative to each other and the band fits
+    const size_t band = sizeof(uint32_t) * (size_t)(G + P.block - 1) *
+                        (size_t)((npw - 1) * (P.p.step / 4) + NW + ngrp + 1);
+    const bool stage = !g.parent && P.p.step % 4 == 0 && lds + band <= 60 * 1024;
+    if (stage) lds += band;
 #define PIV_SAD_Q(NW_, NG_) \
-  if (NW == NW_ && ngrp == NG_) { hipLaunchKernelGGL((k_sad_q<NW_, NG_>), grid, dim3(256), lds, s, g); return hipGetLastError(); }
+  if (NW == NW_ && ngrp == NG_) { \
+    if (stage) hipLaunchKernelGGL((k_sad_q<NW_, NG_, true>), grid, dim3(256), lds, s, g); \
+    else hipLaunchKernelGGL((k_sad_q<NW_, NG_, false>), grid, dim3(256), lds, s, g); \
+    return hipGetLastError(); }
 #define PIV_SAD_Q_NW(NW_) PIV_SAD_Q(NW_, 1) PIV_SAD_Q(NW_, 2) PIV_SAD_Q(NW_, 3) PIV_SAD_Q(NW_, 4) \
   PIV_SAD_Q(NW_, 5) PIV_SAD_Q(NW_, 6) PIV_SAD_Q(NW_, 7) PIV_SAD_Q(NW_, 8)
     PIV_SAD_Q_NW(1) PIV_SAD_Q_NW(2) PIV_SAD_Q_NW(3) PIV_SAD_Q_NW(4)
