@@ -1119,14 +1119,15 @@ void k_correct_bands(CorrArgs g) {
       hv = fmaxf(hv, nv[i]);
       ok = ok && fabsf(nu[i]) < 100.0f && fabsf(nv[i]) < 100.0f;   // false for NaN
     }
-    // encoded so that one max-reduction per bound serves: 127 - floor(lo), floor(hi) + 128
-    const int el_u = ok ? 127 - (int)floorf(lu) : 255, eh_u = ok ? (int)floorf(hu) + 128 : 255;
-    const int el_v = ok ? 127 - (int)floorf(lv) : 255, eh_v = ok ? (int)floorf(hv) + 128 : 255;
-    const int ru = wave_max_i((el_u << 16) | eh_u), rv = wave_max_i((el_v << 16) | eh_v);
-    flu = 127 - (ru >> 16);
-    fhu = (ru & 0xffff) - 128;
-    flv = 127 - (rv >> 16);
-    fhv = (rv & 0xffff) - 128;
+    // encoded so that a max serves every bound: 127 - floor(lo) and
+    // floor(hi) + 128, two 16-bit fields per word, each reduced on its own
+    const uint32_t el_u = ok ? 127 - (int)floorf(lu) : 255, eh_u = ok ? (int)floorf(hu) + 128 : 255;
+    const uint32_t el_v = ok ? 127 - (int)floorf(lv) : 255, eh_v = ok ? (int)floorf(hv) + 128 : 255;
+    const uint32_t ru = wave_max_pk16((el_u << 16) | eh_u), rv = wave_max_pk16((el_v << 16) | eh_v);
+    flu = 127 - (int)(ru >> 16);
+    fhu = (int)(ru & 0xffffu) - 128;
+    flv = 127 - (int)(rv >> 16);
+    fhv = (int)(rv & 0xffffu) - 128;
     if (band == 0) {
 #pragma unroll
       for (int i = 0; i < NL; ++i) {

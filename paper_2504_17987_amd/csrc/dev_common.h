@@ -79,14 +79,27 @@ __device__ __forceinline__ float wave_max(float x) {
   PIV_WAVE_REDUCE_F(x, fmaxf);
   return x;
 }
-__device__ __forceinline__ int wave_max_i(int x) {
-  x = max(x, PIV_DPP_I(x, 0xB1, 0xF, x));
-  x = max(x, PIV_DPP_I(x, 0x4E, 0xF, x));
-  x = max(x, PIV_DPP_I(x, 0x141, 0xF, x));
-  x = max(x, PIV_DPP_I(x, 0x140, 0xF, x));
-  x = max(x, PIV_DPP_I(x, 0x142, 0xA, x));
-  x = max(x, PIV_DPP_I(x, 0x143, 0xC, x));
-  return __builtin_amdgcn_readlane(x, 63);
+// Two 16-bit unsigned fields per word, each reduced to its own maximum
+// (v_pk_max_u16: a per-field max, not a 32-bit one).
+typedef unsigned short piv_u16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t pk_max_u16(uint32_t a, uint32_t b) {
+  return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(piv_u16x2, a),
+                                                                __builtin_bit_cast(piv_u16x2, b)));
+}
+__device__ __forceinline__ uint32_t wave_max_pk16(uint32_t x) {
+  int xi = (int)x;
+  x = pk_max_u16(x, (uint32_t)PIV_DPP_I(xi, 0xB1, 0xF, xi));
+  xi = (int)x;
+  x = pk_max_u16(x, (uint32_t)PIV_DPP_I(xi, 0x4E, 0xF, xi));
+  xi = (int)x;
+  x = pk_max_u16(x, (uint32_t)PIV_DPP_I(xi, 0x141, 0xF, xi));
+  xi = (int)x;
+  x = pk_max_u16(x, (uint32_t)PIV_DPP_I(xi, 0x140, 0xF, xi));
+  xi = (int)x;
+  x = pk_max_u16(x, (uint32_t)PIV_DPP_I(xi, 0x142, 0xA, xi));
+  xi = (int)x;
+  x = pk_max_u16(x, (uint32_t)PIV_DPP_I(xi, 0x143, 0xC, xi));
+  return (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
 }
 __device__ __forceinline__ int wave_sum(int x) {
   x += PIV_DPP_I(x, 0xB1, 0xF, 0);

@@ -44,21 +44,63 @@ def uod_r0(field, flags, a, b, eps=0.1):
     return worst
 
 
+def near_flat(Ao, Bo, win, step, r, mode, pred, a, b, warped=None):
+    """True when a window of the node's search (A, or B' at any shift) is
+    flat enough that the kernels' FP32 rule may call it flat while the
+    oracle's exact-zero rule does not: the kernels take a variance below
+    1e-6 of the second moment about the tile offset K as zero, and that
+    moment is at most var + n L^2 for any K in [0, L], L the largest
+    intensity of the frames."""
+    if warped is None:
+        warped = (oracle.warp_image(Ao, 0, mode, pred, step), oracle.warp_image(Bo, 1, mode, pred, step))
+    Aw, Bw = warped
+    H, W = Aw.shape
+    n = float(win * win)
+    L = float(max(Ao.max(), Bo.max()))
+    h = (win - step) // 2
+    y0, x0 = a * step - h, b * step - h
+
+    def var(I, y, x):
+        w = np.zeros((win, win))
+        ys, xs = max(y, 0), max(x, 0)
+        ye, xe = min(y + win, H), min(x + win, W)
+        if ye > ys and xe > xs:
+            w[ys - y:ye - y, xs - x:xe - x] = I[ys:ye, xs:xe]
+        return (w * w).sum() - w.sum() ** 2 / n
+
+    lim = 1e-6 * n * L * L
+    if var(Aw, y0, x0) < lim:
+        return True
+    return any(var(Bw, y0 + sy, x0 + sx) < lim for sy in range(-r, r + 1) for sx in range(-r, r + 1))
+
+
 def compare_correct(Ag, Bg, Ao, Bo, win, step, r, pred, disp_g, peak_g, flags_g, disp_o, peak_o,
                     flags_o, mode=0, fixed=False, max_ties=None):
     """Element-wise comparison of a correction result with the oracle's.
-    Where they differ, the oracle's correlation plane must show a near-tie.
-    Returns the number of near-tie exemptions."""
+    Where they differ, the oracle's correlation plane must show a near-tie,
+    or one of the node's windows must be near-flat (the FP32 flatness rule
+    and the oracle's exact zero may then disagree; every such node is checked
+    on its own, so they are not capped).  Returns the number of near-tie
+    exemptions (capped by max_ties)."""
     d = np.abs(disp_g - disp_o).max(axis=0)
     bad = (d > TOL_DISP_PX) | (np.abs(peak_g - peak_o) > TOL_RHO) | (flags_g != flags_o)
-    ties = 0
+    ties = flat = 0
+    warped = None
     for a, b in zip(*np.nonzero(bad)):
         R = 1 if fixed else r
         gap = corr_gap(Ao, Bo, win, step, R, mode, pred, int(a), int(b))
+        if gap >= NEAR_TIE_RHO:
+            if warped is None:
+                warped = (oracle.warp_image(Ao, 0, mode, pred, step), oracle.warp_image(Bo, 1, mode, pred, step))
+            if near_flat(Ao, Bo, win, step, R, mode, pred, int(a), int(b), warped):
+                flat += 1
+                continue
         assert gap < NEAR_TIE_RHO, (
             f"node ({a},{b}): gpu {disp_g[:, a, b]} rho {peak_g[a, b]} fl {flags_g[a, b]} vs "
             f"oracle {disp_o[:, a, b]} rho {peak_o[a, b]} fl {flags_o[a, b]}, top-2 gap {gap}")
         ties += 1
+    if flat:
+        say(f"  near-flat exemptions: {flat}")
     if max_ties is not None:
         assert ties <= max_ties, f"{ties} near-tie exemptions"
     return ties

@@ -45,6 +45,9 @@ PRED_CASES = {
     # image rows not a multiple of 4 and a ragged last 32-byte chunk
     "step6_204x138": (lambda: small_vortex_pair(204, 138, seed=13)[:2],
                       dict(win=12, step=6, levels=3, radius_coarse=5, radius_fine=2)),
+    # a fine level searched by the lane-per-row kernel (radius above 2, with a parent)
+    "fine_r3_L2": (lambda: small_vortex_pair(seed=14)[:2],
+                   dict(win=16, step=8, levels=2, radius_coarse=4, radius_fine=3)),
 }
 
 
@@ -97,6 +100,13 @@ CORR_CASES = {
     "generic_u8_win24_8": ("vortex", dict(win=24, step=8, radius=4, block=16), True),
     "tiled_u16_12_r4": ("u16", dict(dtype="u16", win=24, step=12, radius=4), True),
     "tiled_u8_ragged": ("ragged", dict(win=16, step=8, radius=4, radius_coarse=5), True),
+    "tiled_u16_8_r4": ("u16", dict(dtype="u16", win=16, step=8, radius=4), True),
+    "tiled_u16_8_fixed": ("u16", dict(dtype="u16", win=16, step=8, radius=4, peak="fixed"), True),
+    "tiled_u8_8_nopred": ("vortex_small", dict(win=16, step=8, radius=4), False),
+    # displacements of 16 px: a tile's predictor range decides the staged box
+    "tiled_u8_vortex16_r1": ("vortex16", dict(win=16, step=8, radius=1), True),
+    "tiled_u8_vortex16_fixed": ("vortex16", dict(win=16, step=8, radius=4, peak="fixed"), True),
+    "tiled_u8_vortex16_r4": ("vortex16", dict(win=16, step=8, radius=4), True),
 }
 
 
@@ -105,6 +115,8 @@ def _images(kind):
         return small_vortex_pair()[:2]
     if kind == "vortex_small":
         return small_vortex_pair(peak=0.8, seed=5)[:2]
+    if kind == "vortex16":
+        return small_vortex_pair(peak=16.0, seed=9)[:2]
     if kind == "ragged":
         return small_vortex_pair(200, 136, seed=3)[:2]
     if kind == "cfg1":
@@ -142,6 +154,50 @@ def test_correct_parity(case):
                            pred, disp.cpu().numpy()[0], peak.cpu().numpy()[0], flags.cpu().numpy()[0],
                            disp_o, peak_o, flags_o, mode=mode, fixed=fixed, max_ties=2)
     say(f"  near-tie exemptions: {ties}")
+
+
+STRETCH = 0.6
+
+
+def _stretch(x, y):
+    x = np.asarray(x, dtype=np.float64)
+    return STRETCH * (x - 128.0), np.zeros_like(x)
+
+
+def _stretch_pred():
+    # the pair renders particles at midpoint -/+ u/2, so in the frame of A the
+    # correspondence is s / (1 - s/2) (x - 128)
+    X, _ = synth.node_centres(256, 192, 8)
+    u = STRETCH / (1.0 - STRETCH / 2.0) * (X - 128.0)
+    return np.stack([u, np.zeros_like(u)]).astype(np.float32).astype(np.float64)
+
+
+# predictors far from zero or steep across a tile: the deformation then reads
+# the frame with checked loads instead of a staged box
+WILD_CASES = {
+    # |d| >= 100 px at every node
+    "far_uniform": (synth.Uniform(104.3, -2.6),
+                    lambda: np.round(synth.truth(synth.Uniform(104.3, -2.6), 256, 192, 8))),
+    # the predictor spans more than 64 px across every tile
+    "steep_stretch": (_stretch, _stretch_pred),
+}
+
+
+@pytest.mark.parametrize("case", list(WILD_CASES))
+def test_correct_parity_wild_predictor(case):
+    say(f"[correct] {case}")
+    flow, make_pred = WILD_CASES[case]
+    A, B = synth.make_pair(256, 192, flow, 0.04, noise=2.0, seed=31, margin=240)
+    kw = dict(win=16, step=8, radius=4)
+    pred = make_pred()
+    P = api().Plan(256, 192, max_batch=1, **kw)
+    disp_o, peak_o, flags_o = oracle.correct(A, B, 16, 8, 4, pred, 0, 0)
+    Ad, Bd = dev(A[None]), dev(B[None])
+    disp, peak, flags = P.correct(Ad, Bd, dev(pred[None].astype(np.float32)))
+    ties = compare_correct(Ad, Bd, A.astype(float), B.astype(float), 16, 8, 4, pred, disp.cpu().numpy()[0],
+                           peak.cpu().numpy()[0], flags.cpu().numpy()[0], disp_o, peak_o, flags_o,
+                           max_ties=2)
+    say(f"  near-tie exemptions: {ties}, flat windows {int((flags_o & 1).sum())}")
 
 
 def test_correct_impl_selection():
