@@ -102,7 +102,7 @@ def cpu_baseline(A, B, log_fn):
                       "512-row strip (8192 of 16384 windows) scaled x2"}
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_correct_tiled_cfg2_b64_traffic.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_correct_bands_cfg2_b64_traffic.txt")
 CORR_SRC = os.path.join(ROOT, "paper_2504_17987_amd", "csrc", "correct.hip")
 
 
@@ -423,7 +423,7 @@ def main():
         "hbm_roofline": {"achieved_gbs": round(path_gbs, 1), "peak_gbs": HBM_PEAK_GBS,
                          "frac": round(path_gbs / HBM_PEAK_GBS, 5),
                          "bytes_per_pair": alg["path_bytes"]},
-        "roofline": {"kernel": "k_correct_tiled (deformation + correlation + fit)", "bound": "alu",
+        "roofline": {"kernel": "k_correct_bands (deformation + correlation + fit)", "bound": "alu",
                      "achieved": round(corr_tflops, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(corr_tflops / FP32_PEAK_TFLOPS, 5), "traffic": measured_traffic(),
                      "ms_per_launch": round(corr_ms, 4), "flop_per_pair": alg["corr_flop"],

@@ -6,7 +6,8 @@ exactly as bench.py runs them) through one piv_run.  Against the FP64 oracle:
 * the correction at sampled nodes (edges, corners and random interior nodes),
   called again with the same kernel and launch configuration on the run's own
   predictor: displacement within 0.01 px, coefficient within 2e-5, flags
-  exact, unless the oracle's plane shows a near-tie;
+  exact, unless the oracle's plane shows a near-tie; and at every node of two
+  of the pairs;
 * validation and vorticity on the whole grid, from the GPU's correction;
 * all eight copies of a pair give bitwise identical results;
 * the largest image the paper runs, 8192 x 4096, one pair, checked the same
@@ -17,7 +18,8 @@ import pytest
 import torch
 
 import oracle
-from _helpers import NEAR_TIE_RHO, NEAR_TIE_UOD, TOL_DISP_PX, TOL_REL, TOL_RHO, corr_gap, say, uod_r0
+from _helpers import (NEAR_TIE_RHO, NEAR_TIE_UOD, TOL_DISP_PX, TOL_REL, TOL_RHO, compare_correct, corr_gap, say,
+                      uod_r0)
 from paper_2504_17987_amd import synth
 
 pytestmark = [pytest.mark.gpu,
@@ -99,6 +101,20 @@ def test_fullsize_correction_sampled(fullsize):
                 worst = max(worst, d)
     say(f"  max |d disp| {worst:.2e} px, near-tie exemptions {ties}")
     assert ties <= 2
+
+
+def test_fullsize_correction_full_grid(fullsize):
+    """Every node of two of the distinct pairs (all 256 tiles of each, edges
+    included) against the oracle's full correction on the run's predictor."""
+    pairs, g, c = fullsize
+    for i in (0, 5):
+        A, B, _ = pairs[i]
+        pred = g["pred"][i].astype(np.float64)
+        disp_o, peak_o, flags_o = oracle.correct(A, B, 16, 8, 4, pred)
+        ties = compare_correct(None, None, A.astype(np.float64), B.astype(np.float64), 16, 8, 4, pred,
+                               c["disp"][i], c["peak"][i], c["flags"][i], disp_o, peak_o, flags_o, max_ties=4)
+        d = np.abs(c["disp"][i] - disp_o).max()
+        say(f"  pair {i}: max |d disp| {d:.2e} px over {pred.shape[1] * pred.shape[2]} nodes, near-ties {ties}")
 
 
 def test_fullsize_validation_and_vorticity(fullsize):
