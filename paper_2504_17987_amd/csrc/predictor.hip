@@ -165,6 +165,7 @@ struct SadArgs {
   int64_t ostride;        // int32 elements per pair
   const uint8_t* mask;
   int npw;                // nodes per workgroup (k_sad)
+  int margin;             // level margin (px): A - margin (pitch + bytes per px) is padded row 0
 };
 
 template <int ES>
@@ -658,18 +659,25 @@ __global__ __launch_bounds__(256) void k_sad_lane(SadArgs g) {
   const int y0 = oy + cy - R, xs = ox + cx - R;
   const int xa = xs & ~3, sh = xs & 3;
   const int axa = ox & ~3, ash = ox & 3;
+  // 32-bit offsets from padded row 0 (non-negative; the launcher checks that
+  // a padded level fits 31 bits), so a row costs one add of a uniform step
+  const unsigned pitch32 = (unsigned)g.pitch;
+  const uint8_t* Ap = Ab - ((int64_t)g.margin * g.pitch + g.margin);
+  const uint8_t* Bp = Bb - ((int64_t)g.margin * g.pitch + g.margin);
+  const unsigned aoff = __umul24((unsigned)(oy + g.margin), pitch32) + (unsigned)(axa + g.margin);
+  const unsigned boff = __umul24((unsigned)(y0 + g.margin), pitch32) + (unsigned)(xa + g.margin);
   uint32_t av[BLK][NW];
 #pragma unroll
   for (int rb = 0; rb < BLK + 2 * R; ++rb) {
     if (rb < BLK) {
-      const uint32_t* row = reinterpret_cast<const uint32_t*>(Ab + (int64_t)(oy + rb) * g.pitch + axa);
+      const uint32_t* row = reinterpret_cast<const uint32_t*>(Ap + (size_t)(aoff + rb * pitch32));
       uint32_t w[NW + 1];
 #pragma unroll
       for (int i = 0; i <= NW; ++i) w[i] = row[i];
 #pragma unroll
       for (int i = 0; i < NW; ++i) av[rb][i] = __builtin_amdgcn_alignbyte(w[i + 1], w[i], ash);
     }
-    const uint32_t* row = reinterpret_cast<const uint32_t*>(Bb + (int64_t)(y0 + rb) * g.pitch + xa);
+    const uint32_t* row = reinterpret_cast<const uint32_t*>(Bp + (size_t)(boff + rb * pitch32));
     uint32_t w[RW + 1];
 #pragma unroll
     for (int i = 0; i <= RW; ++i) w[i] = row[i];
@@ -859,6 +867,7 @@ hipError_t launch_sad_level(const Plan& P, int l, const void*, const void*, int6
   g.ostride = (int64_t)(P.per_pair / sizeof(int32_t));
   g.mask = P.slot_mask;
   g.npw = 0;
+  g.margin = v.margin;
   const int G = 2 * g.R + 1;
   const int NW = P.block * P.es / 4;
   if (P.es == 2 && g.R >= 1 && g.R <= 2 && (NW == 6 || NW == 8 || NW == 12)) {
@@ -869,7 +878,8 @@ hipError_t launch_sad_level(const Plan& P, int l, const void*, const void*, int6
     PIV_SAD_STREAM(6, 2) PIV_SAD_STREAM(6, 1)
 #undef PIV_SAD_STREAM
   }
-  if (P.es == 1 && g.R <= 2 && (NW == 2 || NW == 3 || NW == 4)) {
+  const bool off31 = (size_t)v.rows * v.pitch < (1u << 31) && v.pitch < (1 << 24);
+  if (P.es == 1 && g.R <= 2 && (NW == 2 || NW == 3 || NW == 4) && off31) {
     dim3 grid((v.nx * v.ny + 255) / 256, n);
 #define PIV_SAD_LANE(NW_, R_) \
   if (NW == NW_ && g.R == R_) { hipLaunchKernelGGL((k_sad_lane<NW_, R_>), grid, dim3(256), 0, s, g); return hipGetLastError(); }
