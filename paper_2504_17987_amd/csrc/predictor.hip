@@ -151,6 +151,13 @@ __global__ __launch_bounds__(256) void k_pyr_down(uint8_t* ws, int64_t stride, i
 // ---------------------------------------------------------------------------
 // Shared by the SAD kernels
 // ---------------------------------------------------------------------------
+// N consecutive 4-byte words at a 4-byte-aligned address, read together
+// (wide loads: one instruction per up to four words)
+template <int N>
+struct __attribute__((aligned(4))) Words {
+  uint32_t w[N];
+};
+
 struct SadArgs {
   const uint8_t* A;   // padded level image, pair 0, at the core origin (0, 0)
   const uint8_t* B;
@@ -670,20 +677,14 @@ __global__ __launch_bounds__(256) void k_sad_lane(SadArgs g) {
 #pragma unroll
   for (int rb = 0; rb < BLK + 2 * R; ++rb) {
     if (rb < BLK) {
-      const uint32_t* row = reinterpret_cast<const uint32_t*>(Ap + (size_t)(aoff + rb * pitch32));
-      uint32_t w[NW + 1];
+      const Words<NW + 1> w = *reinterpret_cast<const Words<NW + 1>*>(Ap + (size_t)(aoff + rb * pitch32));
 #pragma unroll
-      for (int i = 0; i <= NW; ++i) w[i] = row[i];
-#pragma unroll
-      for (int i = 0; i < NW; ++i) av[rb][i] = __builtin_amdgcn_alignbyte(w[i + 1], w[i], ash);
+      for (int i = 0; i < NW; ++i) av[rb][i] = __builtin_amdgcn_alignbyte(w.w[i + 1], w.w[i], ash);
     }
-    const uint32_t* row = reinterpret_cast<const uint32_t*>(Bp + (size_t)(boff + rb * pitch32));
-    uint32_t w[RW + 1];
-#pragma unroll
-    for (int i = 0; i <= RW; ++i) w[i] = row[i];
+    const Words<RW + 1> w = *reinterpret_cast<const Words<RW + 1>*>(Bp + (size_t)(boff + rb * pitch32));
     uint32_t rw[RW];
 #pragma unroll
-    for (int i = 0; i < RW; ++i) rw[i] = __builtin_amdgcn_alignbyte(w[i + 1], w[i], sh);
+    for (int i = 0; i < RW; ++i) rw[i] = __builtin_amdgcn_alignbyte(w.w[i + 1], w.w[i], sh);
 #pragma unroll
     for (int k = 0; k < G; ++k) {
       uint32_t bw[NW];
