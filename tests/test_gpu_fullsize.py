@@ -11,7 +11,9 @@ exactly as bench.py runs them) through one piv_run.  Against the FP64 oracle:
 * validation and vorticity on the whole grid, from the GPU's correction;
 * all eight copies of a pair give bitwise identical results;
 * the largest image the paper runs, 8192 x 4096, one pair, checked the same
-  way.
+  way;
+* the 4K u16 stream form (3840 x 2160, 12-bit, 24/12 windows) as the bench
+  runs it: a captured HIP graph over 8 slots, two distinct rendered pairs.
 """
 import numpy as np
 import pytest
@@ -172,3 +174,52 @@ def test_largest_image_8192x4096():
     assert bad.sum() <= 4
     om = oracle.vorticity(g["disp"].astype(np.float64), 8)
     assert np.abs(g["omega"] - om).max() <= TOL_REL * np.abs(om).max()
+
+
+def test_cfg3_4k_u16_graph_slots():
+    """The 4K u16 stream configuration through the bench's graph runner
+    (8 slots, one replay): predictor bit-exact on every node, correction on
+    sampled nodes (re-run eagerly on the replay's predictor), validation and
+    vorticity on the whole grid, and slots holding the same pair identical."""
+    from paper_2504_17987_amd import api
+    from paper_2504_17987_amd.serve import GraphRunner
+    kw3 = dict(dtype="u16", win=24, step=12, radius=4, levels=3, radius_coarse=6, radius_fine=2)
+    say("[cfg3] rendering 2 distinct 3840x2160 u16 pairs")
+    prs = [synth.cfg3_pair(k)[:2] for k in (0, 1)]
+    run = GraphRunner(api.Plan(3840, 2160, max_batch=8, **kw3), 8)
+    run.capture()
+    for i in range(8):
+        run.A[i].copy_(torch.from_numpy(prs[i % 2][0].view(np.int16)).view(torch.uint16))
+        run.B[i].copy_(torch.from_numpy(prs[i % 2][1].view(np.int16)).view(torch.uint16))
+    say("[cfg3] graph replay, 8 slots")
+    run.replay(8)
+    torch.cuda.synchronize()
+    g = {k: v.cpu().numpy() for k, v in run.out.items()}
+    for k in range(2, 8):
+        for name in ("pred", "disp", "flags", "omega"):
+            assert np.array_equal(g[name][k], g[name][k % 2]), (name, k)
+    P = run.plan
+    for i in range(2):
+        A, B = prs[i]
+        po = oracle.predict(A, B, 12, 24, 3, 6, 2).astype(np.float64)
+        po, _ = oracle.validate(po, None)
+        assert np.array_equal(g["pred"][i], po.astype(np.float32)), i
+        disp, peak, flags = P.correct(run.A[i:i + 1], run.B[i:i + 1], run.out["pred"][i:i + 1])
+        c = dict(disp=disp.cpu().numpy()[0], peak=peak.cpu().numpy()[0], flags=flags.cpu().numpy()[0])
+        Ad, Bd = A.astype(np.float64), B.astype(np.float64)
+        ny, nx = po.shape[1:]
+        rng = np.random.default_rng(3000 + i)
+        ties = 0
+        for a, b in _sample_nodes(rng, ny, nx, 40):
+            du, dv, pk, fl = oracle.correct_node(Ad, Bd, 24, 12, 4, po, a, b)
+            d = max(abs(c["disp"][0, a, b] - du), abs(c["disp"][1, a, b] - dv))
+            if not (d <= TOL_DISP_PX and abs(c["peak"][a, b] - pk) <= TOL_RHO and c["flags"][a, b] == fl):
+                assert corr_gap(Ad, Bd, 24, 12, 4, 0, po, a, b) < NEAR_TIE_RHO, (i, a, b)
+                ties += 1
+        assert ties <= 2
+        vo, flo = oracle.validate(c["disp"].astype(np.float64), c["flags"].copy())
+        bad = (np.abs(g["disp"][i] - vo).max(axis=0) > 1e-5) | (g["flags"][i] != flo)
+        assert bad.sum() <= 4
+        om = oracle.vorticity(g["disp"][i].astype(np.float64), 12)
+        assert np.abs(g["omega"][i] - om).max() <= TOL_REL * np.abs(om).max()
+        say(f"  pair {i}: predictor bit-exact, {ny * nx} vectors, near-ties {ties}")
