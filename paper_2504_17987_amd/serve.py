@@ -330,10 +330,13 @@ class GpuExecutor(Executor):
     ``pairs[stream]`` holds each admitted stream's device-resident pairs
     (A, B tensors of shape [k, H, W]); a launch copies the requested pairs
     into a free runner's slots (device-to-device, on the runner's stream),
-    sets the active-slot mask and replays the runner's graph."""
+    sets the active-slot mask and replays the runner's graph.  A batch of
+    one pair (what light load produces) skips the copies and the graph: the
+    runner's plan runs that pair eagerly from its own buffers into slot 0
+    (same kernels, same workspace, same stream)."""
 
     def __init__(self, runners: Dict[str, List[GraphRunner]], pairs: Dict[int, Tuple[object, object]],
-                 keep_results: bool = False):
+                 keep_results: bool = False, eager_single: bool = True):
         import torch
         self.torch = torch
         self.runners = runners
@@ -342,17 +345,28 @@ class GpuExecutor(Executor):
         self.live: Dict[int, Tuple[str, GraphRunner, object, List[Request]]] = {}
         self.n = 0
         self.keep = keep_results
+        self.eager_single = eager_single
         self.results: Dict[int, Dict[str, object]] = {}
+        self.slot0 = {id(r): {k: v[0:1] for k, v in r.out.items()} for rs in runners.values() for r in rs}
 
     def launch(self, cls, reqs, now):
         torch = self.torch
         run = self.free[cls].pop()
-        with torch.cuda.stream(run.stream):
-            for i, r in enumerate(reqs):
-                a, b = self.pairs[r.stream]
-                run.A[i].copy_(a[r.item], non_blocking=True)
-                run.B[i].copy_(b[r.item], non_blocking=True)
-        run.replay(len(reqs))
+        if len(reqs) == 1 and self.eager_single:
+            r = reqs[0]
+            a, b = self.pairs[r.stream]
+            run.stream.wait_stream(torch.cuda.current_stream())
+            # (the plan's slot mask is the runner's; slot 0 is active under
+            # every mask set_active writes, and the mask starts all ones)
+            with torch.cuda.stream(run.stream):
+                run.plan.run(a[r.item:r.item + 1], b[r.item:r.item + 1], self.slot0[id(run)])
+        else:
+            with torch.cuda.stream(run.stream):
+                for i, r in enumerate(reqs):
+                    a, b = self.pairs[r.stream]
+                    run.A[i].copy_(a[r.item], non_blocking=True)
+                    run.B[i].copy_(b[r.item], non_blocking=True)
+            run.replay(len(reqs))
         ev = torch.cuda.Event()
         ev.record(run.stream)
         self.n += 1
@@ -376,7 +390,8 @@ class GpuExecutor(Executor):
 
 def make_gpu_server(classes: Dict[str, Tuple[int, int, int]], pairs: Dict[int, Tuple[object, object]],
                     stream_class: Dict[int, str], budget: int, plan_kw: Optional[dict] = None,
-                    inflight: int = 2, max_wait: float = 2e-3, keep_results: bool = False):
+                    inflight: int = 2, max_wait: float = 2e-3, keep_results: bool = False,
+                    eager_single: bool = True):
     """Build runners (``inflight`` per class, each with its own plan,
     workspace, HIP stream and captured graph), the executor and the
     scheduler, and admit the streams in order.  classes: name -> (W, H,
@@ -399,7 +414,7 @@ def make_gpu_server(classes: Dict[str, Tuple[int, int, int]], pairs: Dict[int, T
                 per_stream = a.numel() * a.element_size() + b.numel() * b.element_size()
                 break
         specs.append(ClassSpec(name, W, H, cap, rs[0].resident_bytes(), per_stream))
-    ex = GpuExecutor(runners, pairs, keep_results=keep_results)
+    ex = GpuExecutor(runners, pairs, keep_results=keep_results, eager_single=eager_single)
     sched = Scheduler(specs, ex, budget, max_wait=max_wait, inflight=inflight)
     for s, c in stream_class.items():
         sched.admit(s, c)

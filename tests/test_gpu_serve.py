@@ -86,17 +86,22 @@ def test_u16_stream_through_graph():
             assert torch.equal(run.out["disp"][i], e["disp"][0]) and torch.equal(run.out["flags"][i], e["flags"][0])
 
 
-def test_served_results_equal_pair_alone():
+@pytest.mark.parametrize("eager_single", [True, False])
+def test_served_results_equal_pair_alone(eager_single):
+    """Every served result equals the pair run alone, bitwise; with lone
+    requests run eagerly from their own buffers, and with every batch going
+    through slot copies and a graph replay."""
     from paper_2504_17987_amd import api
     from paper_2504_17987_amd.serve import latency_stats, make_gpu_server, poisson_trace, serve_trace
-    say("[serve] invariance")
+    say(f"[serve] invariance, eager single {eager_single}")
     sizes = {"s": (128, 128, 8), "m": (256, 256, 4), "l": (512, 512, 2)}
     stream_class = {s: "sml"[s % 3] for s in range(6)}
     pairs = {}
     for s, c in stream_class.items():
         W, H, _ = sizes[c]
         pairs[s] = pairs_u8(W, H, 4, 1000 + 10 * s)
-    sched, ex = make_gpu_server(sizes, pairs, stream_class, budget=8 << 30, keep_results=True)
+    sched, ex = make_gpu_server(sizes, pairs, stream_class, budget=8 << 30, keep_results=True,
+                                eager_single=eager_single)
     trace = poisson_trace(list(stream_class.items()), 400.0, 0.25, 4, seed=7)
     serve_trace(sched, trace, time.perf_counter, poll=0, deadline=60.0)
     torch.cuda.synchronize()
