@@ -115,37 +115,51 @@ __global__ __launch_bounds__(256) void k_pad_pyr(const uint8_t* __restrict__ A, 
 // ---------------------------------------------------------------------------
 // Pyramid level from the padded level below:
 // out(y,x) = floor((in(2y,2x) + in(2y,2x+1) + in(2y+1,2x) + in(2y+1,2x+1) + 2) / 4)
-// with zero outside the input (its margin); the output margin is written as
-// zero.  One thread per pixel of the padded output.
+// with zero outside the input (its margin).  The core only: the margins
+// were zeroed once with the workspace.
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(256) void k_pyr_down(uint8_t* ws, int64_t stride, int64_t sA, int64_t sB,
                                                   int spitch, int smargin, int64_t dA, int64_t dB, int dpitch,
                                                   int dmargin, int dW, int dH, const uint8_t* mask) {
+  // one thread: 8 outputs of one row of the level's core from two 16-pixel
+  // source rows (aligned 16-byte reads: every level's core starts 16-byte
+  // aligned); past the image (a ragged last chunk, inside the margin) it
+  // writes 0.
   const int pair = blockIdx.z >> 1, frame = blockIdx.z & 1;
   if (slot_off(mask, pair)) return;
-  const int Y = blockIdx.y * blockDim.y + threadIdx.y;      // padded output row
-  const int X = 4 * (blockIdx.x * blockDim.x + threadIdx.x);  // first of 4 padded output columns
-  const int dcols = dpitch / (int)sizeof(T);
-  if (Y >= dH + 2 * dmargin || X >= dcols) return;
+  const int nch = (dW + 7) / 8;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = idx / nch, c = idx - (idx / nch) * nch;
+  if (y >= dH) return;
   uint8_t* base = ws + (int64_t)pair * stride;
-  const int y = Y - dmargin, x = X - dmargin;   // x is a multiple of 4 (margins are)
-  T v[4] = {0, 0, 0, 0};
-  if (y >= 0 && y < dH && x + 3 >= 0 && x < dW) {
-    // the 8 source pixels 2x .. 2x+7 of rows 2y, 2y+1 lie inside the
-    // source's padded extent (past its image they read its zero margin)
-    const uint8_t* src = base + (frame ? sB : sA) + (int64_t)smargin * spitch + (int64_t)smargin * sizeof(T);
-    const T* r0 = reinterpret_cast<const T*>(src + (int64_t)(2 * y) * spitch) + 2 * x;
-    const T* r1 = reinterpret_cast<const T*>(src + (int64_t)(2 * y + 1) * spitch) + 2 * x;
+  const uint8_t* src = base + (frame ? sB : sA) + (int64_t)smargin * spitch + (int64_t)smargin * sizeof(T);
+  constexpr int NV = 16 * (int)sizeof(T) / 16;   // 16-byte vectors per 16 source pixels
+  const uint4* r0 = reinterpret_cast<const uint4*>(src + (int64_t)(2 * y) * spitch) + NV * c;
+  const uint4* r1 = reinterpret_cast<const uint4*>(src + (int64_t)(2 * y + 1) * spitch) + NV * c;
+  T a0[16], a1[16];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      uint32_t s = (uint32_t)r0[2 * i] + r0[2 * i + 1] + r1[2 * i] + r1[2 * i + 1];
-      v[i] = (x + i >= 0 && x + i < dW) ? (T)((s + 2u) >> 2) : (T)0;
-    }
+  for (int v = 0; v < NV; ++v) {
+    const uint4 w0 = r0[v], w1 = r1[v];
+    __builtin_memcpy(a0 + v * (16 / (int)sizeof(T)), &w0, 16);
+    __builtin_memcpy(a1 + v * (16 / (int)sizeof(T)), &w1, 16);
   }
-  T* out = reinterpret_cast<T*>(base + (frame ? dB : dA) + (int64_t)Y * dpitch) + X;
+  T o[8];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) out[i] = v[i];
+  for (int i = 0; i < 8; ++i) {
+    const uint32_t sum = (uint32_t)a0[2 * i] + a0[2 * i + 1] + a1[2 * i] + a1[2 * i + 1];
+    o[i] = (8 * c + i < dW) ? (T)((sum + 2u) >> 2) : (T)0;
+  }
+  T* out = reinterpret_cast<T*>(base + (frame ? dB : dA) + (int64_t)(dmargin + y) * dpitch) + dmargin + 8 * c;
+  if constexpr (sizeof(T) == 1) {
+    uint2 w;
+    __builtin_memcpy(&w, o, 8);
+    *reinterpret_cast<uint2*>(out) = w;
+  } else {
+    uint4 w;
+    __builtin_memcpy(&w, o, 16);
+    *reinterpret_cast<uint4*>(out) = w;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -823,9 +837,9 @@ hipError_t launch_pyramid(const Plan& P, const void* A, const void* B, int64_t p
   for (int l = 2; l < P.L; ++l) {
     const Level& u = P.lv[l - 1];
     const Level& v = P.lv[l];
-    const int dcols = v.pitch / P.es;
-    dim3 blk(64, 4);
-    dim3 grid((dcols / 4 + 63) / 64, (v.rows + 3) / 4, 2 * n);
+    const int nch = (v.W + 7) / 8;
+    dim3 blk(256);
+    dim3 grid((unsigned)((nch * v.H + 255) / 256), 1, 2 * n);
     if (P.es == 1)
       hipLaunchKernelGGL(k_pyr_down<uint8_t>, grid, blk, 0, s, P.ws, (int64_t)P.per_pair, (int64_t)u.off_a,
                          (int64_t)u.off_b, u.pitch, u.margin, (int64_t)v.off_a, (int64_t)v.off_b, v.pitch,
