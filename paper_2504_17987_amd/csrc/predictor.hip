@@ -297,7 +297,12 @@ __global__ __launch_bounds__(256) void k_sad_q(SadArgs g) {
     const int xs = b * g.step + off + cx - g.R;
     const int xa = xs & ~3, sh = xs & 3;
     const int by = oy + cy - g.R + q;
+    // the last group of four candidate columns holds REM real ones; with one
+    // or two, plain v_sad_u8 (full rate) replaces the quarter-rate quad SAD
+    const int REM = G - 4 * (NGRP - 1);
+    const bool tail_sad = REM <= 2;
     unsigned long long acc[NGRP];
+    uint32_t tacc[2] = {0u, 0u};
 #pragma unroll
     for (int m = 0; m < NGRP; ++m) acc[m] = 0ull;
     const uint32_t* ablk = s_ablk + j * BLK * NW;
@@ -316,6 +321,16 @@ __global__ __launch_bounds__(256) void k_sad_q(SadArgs g) {
       for (int i = 0; i < NW; ++i) aw[i] = ablk[ar * NW + i];
 #pragma unroll
       for (int m = 0; m < NGRP; ++m) {
+        if (m == NGRP - 1 && tail_sad) {
+          // columns 4m and 4m+1: words i+m and (realigned by one byte) i+m..i+m+1
+#pragma unroll
+          for (int i = 0; i < NW; ++i) {
+            tacc[0] = __builtin_amdgcn_sad_u8(aw[i], rw[i + m], tacc[0]);
+            if (REM == 2)
+              tacc[1] = __builtin_amdgcn_sad_u8(aw[i], __builtin_amdgcn_alignbyte(rw[i + m + 1], rw[i + m], 1), tacc[1]);
+          }
+          continue;
+        }
         unsigned long long s = acc[m];
 #pragma unroll
         for (int i = 0; i < NW; ++i) {
@@ -332,7 +347,7 @@ __global__ __launch_bounds__(256) void k_sad_q(SadArgs g) {
       for (int jj = 0; jj < 4; ++jj) {
         const int k = 4 * m + jj;
         if (k < G) {
-          const uint32_t sad = (uint32_t)(acc[m] >> (16 * jj)) & 0xffffu;
+          const uint32_t sad = (m == NGRP - 1 && tail_sad) ? tacc[jj & 1] : (uint32_t)(acc[m] >> (16 * jj)) & 0xffffu;
           unsigned long long key = sad_key(sad, dy, cx - g.R + k);
           best = key < best ? key : best;
         }
