@@ -35,6 +35,7 @@ struct CorrArgs {
   int fixed;               // fixed-centre 5-point stencil
   const float* pred;       // [n][2][ny][nx] or null
   float* disp;
+  int64_t dstride;         // floats per pair of disp
   float* peak;             // nullable
   uint8_t* flags;
   const uint8_t* mask;
@@ -176,7 +177,7 @@ __device__ __forceinline__ void finish_vector(const CorrArgs& g, int pair, int a
     ey = fminf(fmaxf(ey, -1.0f), 1.0f);
   }
   const int np = g.nx * g.ny, i = a * g.nx + b;
-  float* D = g.disp + (int64_t)pair * 2 * np;
+  float* D = g.disp + (int64_t)pair * g.dstride;
   D[i] = pu + (float)sx + ex;
   D[np + i] = pv + (float)sy + ey;
   if (g.peak) g.peak[(int64_t)pair * np + i] = c0;
@@ -1541,7 +1542,8 @@ int correct_impl(const Plan& P) {
 }
 
 hipError_t launch_correct(const Plan& P, const void* A, const void* B, int64_t pitch, int n,
-                          const float* pred, float* disp, float* peak, uint8_t* flags, hipStream_t s) {
+                          const float* pred, float* disp, float* peak, uint8_t* flags, hipStream_t s,
+                          int64_t disp_stride) {
   CorrArgs g;
   g.A = (const uint8_t*)A;
   g.B = (const uint8_t*)B;
@@ -1558,6 +1560,7 @@ hipError_t launch_correct(const Plan& P, const void* A, const void* B, int64_t p
   g.central = P.p.warp == PIV_WARP_CENTRAL;
   g.pred = pred;
   g.disp = disp;
+  g.dstride = disp_stride ? disp_stride : 2 * (int64_t)P.nx * P.ny;
   g.peak = peak;
   g.flags = flags;
   g.mask = P.slot_mask;

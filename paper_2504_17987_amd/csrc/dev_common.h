@@ -137,10 +137,15 @@ __device__ __forceinline__ void cswap(V& a, V& b) {
   a = lo;
   b = hi;
 }
-// floats by min/max (two instructions; the values sorted here are finite)
+// Minimum and maximum of finite floats: IEEE minimum/maximum, one
+// instruction each, with no quieting of the operands first.
+__device__ __forceinline__ float fmin_fin(float a, float b) { return __builtin_elementwise_minimum(a, b); }
+__device__ __forceinline__ float fmax_fin(float a, float b) { return __builtin_elementwise_maximum(a, b); }
+
+// floats (finite here) by minimum/maximum
 template <>
 __device__ __forceinline__ void cswap<float>(float& a, float& b) {
-  const float lo = fminf(a, b), hi = fmaxf(a, b);
+  const float lo = fmin_fin(a, b), hi = fmax_fin(a, b);
   a = lo;
   b = hi;
 }
@@ -198,10 +203,28 @@ __device__ __forceinline__ float median8_f(float (&v)[8], int k) {
   return 0.5f * (pick<8>(v, (k >> 1) - 1) + pick<8>(v, k >> 1));
 }
 
+__device__ __forceinline__ int med3i(int a, int b, int c) { return max(min(a, b), min(max(a, b), c)); }
+
+// Median of nine values: order each group of three (slots 0-2, 3-5, 6-8);
+// the median is the median of the largest group minimum, the median of the
+// group medians and the smallest group maximum.  A min/max network, so by
+// the 0-1 principle it is exact for any input, ties included.
+__device__ __forceinline__ int median9_groups(const int (&v)[9]) {
+  int lo[3], md[3], hi[3];
+#pragma unroll
+  for (int g = 0; g < 3; ++g) {
+    const int a = v[3 * g], b = v[3 * g + 1], c = v[3 * g + 2];
+    lo[g] = min(min(a, b), c);
+    md[g] = med3i(a, b, c);
+    hi[g] = max(max(a, b), c);
+  }
+  return med3i(max(max(lo[0], lo[1]), lo[2]), med3i(md[0], md[1], md[2]), min(min(hi[0], hi[1]), hi[2]));
+}
+
 // Lower median of the k (>= 1) real values among 9 slots.
 __device__ __forceinline__ int median9_low_i(int (&v)[9], int k) {
+  if (k == 9) return median9_groups(v);   // every slot real (the usual case)
   sort9(v);
-  if (k == 9) return v[4];   // every slot real (the usual case)
   return pick<9>(v, (k - 1) >> 1);
 }
 

@@ -35,7 +35,8 @@ struct Plan {
   int block;          // predictor block (resolved)
   int L;
   Level lv[kMaxLevels];
-  size_t off_mask;    // per-pair offset of the validation mask uint8 [ny][nx]
+  size_t off_raw;     // per-pair offset of a float [2][ny][nx] field: the detection-pass
+                      // input of validation
   size_t per_pair;    // workspace bytes per pair
   uint8_t* ws = nullptr;
   size_t ws_bytes = 0;
@@ -59,10 +60,16 @@ hipError_t launch_pyramid(const Plan& P, const void* A, const void* B, int64_t p
 hipError_t launch_sad_level(const Plan& P, int l, const void* A, const void* B, int64_t pitch,
                             int n, hipStream_t s);
 hipError_t launch_pred_out(const Plan& P, int n, float* pred, hipStream_t s);
+// disp_stride: floats per pair of disp (0: 2 nx ny)
 hipError_t launch_correct(const Plan& P, const void* A, const void* B, int64_t pitch, int n,
                           const float* pred, float* disp, float* peak, uint8_t* flags,
-                          hipStream_t s);
+                          hipStream_t s, int64_t disp_stride = 0);
 hipError_t launch_validate(const Plan& P, float* field, uint8_t* flags, int n, hipStream_t s);
+// validation from src (pair stride in floats) into dst [n][2][ny][nx]; src != dst
+hipError_t launch_uod(const Plan& P, const float* src, int64_t sstride, float* dst, uint8_t* flags,
+                      int n, hipStream_t s);
+// level-0 predictor field (through the median) -> validated float predictor
+hipError_t launch_pred_validate(const Plan& P, int n, float* pred, hipStream_t s);
 hipError_t launch_vorticity(const Plan& P, const float* disp, float* omega, int n, hipStream_t s);
 hipError_t launch_ssd_forward(const Plan& P, const float* A, const float* B, const float* U, int n,
                               float* loss, hipStream_t s);

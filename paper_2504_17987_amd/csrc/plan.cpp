@@ -154,8 +154,8 @@ piv_status piv_plan(const piv_params* pp, piv_plan_t* out) {
     v.off_d = off;
     off = align256(off + sizeof(int32_t) * 2 * (size_t)v.nx * v.ny);
   }
-  P->off_mask = off;
-  off = align256(off + (size_t)P->nx * P->ny);
+  P->off_raw = off;
+  off = align256(off + sizeof(float) * 2 * (size_t)P->nx * P->ny);
   P->per_pair = off;
   *out = reinterpret_cast<piv_plan_t>(P);
   g_err[0] = 0;
@@ -250,11 +250,23 @@ piv_status piv_run(piv_plan_t plan, const void* A, const void* B, int64_t pitch,
   if (piv_status s = check_images(P, A, B, pitch, n)) return s;
   if (!pred || !disp || !flags || !omega) return fail(PIV_EINVAL, "pred, disp, flags, omega must not be NULL");
   if (piv_status s = need_ws(P, n)) return s;
-  if (piv_status s = piv_predict(plan, A, B, pitch, n, pred, stream)) return s;
-  if (piv_status s = piv_validate(plan, pred, nullptr, n, stream)) return s;
-  if (piv_status s = piv_correct(plan, A, B, pitch, n, pred, disp, peak, flags, stream)) return s;
-  if (piv_status s = piv_validate(plan, disp, flags, n, stream)) return s;
-  return piv_vorticity(plan, disp, omega, n, stream);
+  if (n == 0) return PIV_OK;
+  // the same steps as predict, validate, correct, validate, vorticity; the
+  // predictor's output step and its validation are one kernel, and the
+  // correction writes the detection-pass field to the workspace, from which
+  // validation writes disp
+  if (P.p.dtype == PIV_F32) return fail(PIV_EUNSUPPORTED, "the predictor takes U8/U16 frames");
+  if (piv_status s = dev(piv::launch_pyramid(P, A, B, pitch, n, stream), "pyramid")) return s;
+  for (int l = P.L - 1; l >= 0; --l)
+    if (piv_status s = dev(piv::launch_sad_level(P, l, A, B, pitch, n, stream), "sad_search")) return s;
+  if (piv_status s = dev(piv::launch_pred_validate(P, n, pred, stream), "pred_validate")) return s;
+  float* raw = reinterpret_cast<float*>(P.ws + P.off_raw);
+  const int64_t rstride = (int64_t)(P.per_pair / sizeof(float));
+  if (piv_status s = dev(piv::launch_correct(P, A, B, pitch, n, pred, raw, peak, flags, stream, rstride),
+                         "correct"))
+    return s;
+  if (piv_status s = dev(piv::launch_uod(P, raw, rstride, disp, flags, n, stream), "validate")) return s;
+  return dev(piv::launch_vorticity(P, disp, omega, n, stream), "vorticity");
 }
 
 piv_status piv_ssd_forward(piv_plan_t plan, const float* A, const float* B, const float* U, int32_t n,

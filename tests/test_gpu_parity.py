@@ -235,6 +235,61 @@ def test_validate_parity():
     assert np.abs(f2.cpu().numpy()[0] - g2).max() < 1e-5
 
 
+def test_validate_parity_tiles():
+    """Several pairs on a grid of several ragged 32 x 8 tiles, with outlier
+    clusters across tile edges and FLAT/BORDER flags, against the oracle."""
+    say("[validate] tiles")
+    rng = np.random.default_rng(73)
+    n, ny, nx = 3, 29, 70
+    f = rng.normal(0, 0.4, (n, 2, ny, nx))
+    for p in range(n):
+        for (y, x) in [(7, 31), (8, 32), (15, 63), (16, 64), (0, 0), (28, 69), (23, 31), (24, 32)]:
+            f[p, :, max(0, y - 1):y + 2, max(0, x - 1):x + 2] += rng.normal(0, 6, (2, 1, 1))
+        k = 200
+        f[p, :, rng.integers(0, ny, k), rng.integers(0, nx, k)] += rng.normal(0, 5, (k, 2))
+    f = f.astype(np.float32).astype(np.float64)
+    flags = ((rng.random((n, ny, nx)) < 0.05) * 2 + (rng.random((n, ny, nx)) < 0.03) * 1).astype(np.uint8)
+    P = api().Plan(nx * 8, ny * 8, win=16, step=8, max_batch=n)
+    fg = dev(f.astype(np.float32))
+    flg = dev(flags)
+    P.validate(fg, flg)
+    total_bad = 0
+    for p in range(n):
+        go, flo = oracle.validate(f[p], flags[p])
+        g, fl = fg.cpu().numpy()[p], flg.cpu().numpy()[p]
+        bad = (np.abs(g - go).max(axis=0) > 1e-5) | (fl != flo)
+        for a, b in zip(*np.nonzero(bad)):
+            near = [abs(uod_r0(f[p], flags[p], y, x) - 2.0) for y in range(a - 1, a + 2)
+                    for x in range(b - 1, b + 2) if 0 <= y < ny and 0 <= x < nx]
+            assert min(near) < NEAR_TIE_UOD, f"pair {p} ({a},{b})"
+        total_bad += int(bad.sum())
+    assert total_bad <= 6
+
+
+@pytest.mark.parametrize("dtype", ["u8", "u16"])
+def test_run_equals_separate_steps(dtype):
+    """piv_run (predictor output and its validation in one kernel; the
+    correction written to the workspace and validated from there) gives the
+    same bits as predict, validate, correct, validate, vorticity called one
+    by one."""
+    say(f"[run] separate steps {dtype}")
+    pairs = [small_vortex_pair(seed=s)[:2] for s in (41, 42)]
+    A = np.stack([p[0] for p in pairs])
+    B = np.stack([p[1] for p in pairs])
+    if dtype == "u16":
+        A, B = A.astype(np.uint16) * 181, B.astype(np.uint16) * 181
+    P = api().Plan(256, 192, max_batch=2, win=16, step=8, dtype=dtype)
+    Ag, Bg = dev(A), dev(B)
+    out = P.run(Ag, Bg)
+    pred = P.predict(Ag, Bg)
+    P.validate(pred, None)
+    disp, peak, flags = P.correct(Ag, Bg, pred)
+    P.validate(disp, flags)
+    omega = P.vorticity(disp)
+    for k, v in (("pred", pred), ("disp", disp), ("peak", peak), ("flags", flags), ("omega", omega)):
+        assert torch.equal(out[k], v), k
+
+
 def test_vorticity_parity():
     say("[vorticity]")
     lo = synth.cfg2_flow()
