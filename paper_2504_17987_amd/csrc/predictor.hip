@@ -665,9 +665,15 @@ __global__ __launch_bounds__(256) void k_sad(SadArgs g) {
 // static.  A row r is loaded just before B row r first needs it and dies
 // after B row r + 2R; each B row is realigned to the search origin once and
 // every shift dx is a further static alignbyte of the realigned words.
+// AAL: every block column starts on a 4-byte boundary (step and block offset
+// multiples of 4), so A rows are read as aligned words.  The winner is the
+// least 31-bit key (SAD, |dx|+|dy|, candidate row, candidate column): within
+// a node the row and column indices order dy and dx, and a block of at most
+// 16x16 u8 pixels keeps the SAD below 2^16.
 // ---------------------------------------------------------------------------
-template <int NW, int R>
+template <int NW, int R, bool AAL>
 __global__ __launch_bounds__(256) void k_sad_lane(SadArgs g) {
+  static_assert(NW <= 4 && 2 * R + 1 <= 8, "the 31-bit key holds a SAD of 16x16 u8 pixels and 3-bit indices");
   constexpr int BLK = 4 * NW, G = 2 * R + 1;
   constexpr int RW = NW + (2 * R + 3) / 4 + 1;   // realigned words covering BLK + 2R bytes
   const WgIdx wg = xcd_order();
@@ -706,9 +712,15 @@ __global__ __launch_bounds__(256) void k_sad_lane(SadArgs g) {
 #pragma unroll
   for (int rb = 0; rb < BLK + 2 * R; ++rb) {
     if (rb < BLK) {
-      const Words<NW + 1> w = *reinterpret_cast<const Words<NW + 1>*>(Ap + (size_t)(aoff + rb * pitch32));
+      if constexpr (AAL) {
+        const Words<NW> w = *reinterpret_cast<const Words<NW>*>(Ap + (size_t)(aoff + rb * pitch32));
 #pragma unroll
-      for (int i = 0; i < NW; ++i) av[rb][i] = __builtin_amdgcn_alignbyte(w.w[i + 1], w.w[i], ash);
+        for (int i = 0; i < NW; ++i) av[rb][i] = w.w[i];
+      } else {
+        const Words<NW + 1> w = *reinterpret_cast<const Words<NW + 1>*>(Ap + (size_t)(aoff + rb * pitch32));
+#pragma unroll
+        for (int i = 0; i < NW; ++i) av[rb][i] = __builtin_amdgcn_alignbyte(w.w[i + 1], w.w[i], ash);
+      }
     }
     const Words<RW + 1> w = *reinterpret_cast<const Words<RW + 1>*>(Bp + (size_t)(boff + rb * pitch32));
     uint32_t rw[RW];
@@ -735,17 +747,21 @@ __global__ __launch_bounds__(256) void k_sad_lane(SadArgs g) {
     }
     __builtin_amdgcn_sched_barrier(0);
   }
-  unsigned long long best = ~0ull;
+  // key = SAD << 15 | (|dx| + |dy|) << 6 | q << 3 | k
+  uint32_t kx[G], ky[G];
+#pragma unroll
+  for (int k = 0; k < G; ++k) {
+    kx[k] = ((uint32_t)abs(cx - R + k) << 6) | (uint32_t)k;
+    ky[k] = ((uint32_t)abs(cy - R + k) << 6) | ((uint32_t)k << 3);
+  }
+  uint32_t best = ~0u;
 #pragma unroll
   for (int q = 0; q < G; ++q)
 #pragma unroll
-    for (int k = 0; k < G; ++k) {
-      unsigned long long key = sad_key(acc[q][k], cy - R + q, cx - R + k);
-      best = key < best ? key : best;
-    }
+    for (int k = 0; k < G; ++k) best = min(best, (acc[q][k] << 15) | (kx[k] + ky[q]));
   int32_t* out = g.out + (int64_t)pair * g.ostride;
-  out[a * g.nx + b] = (int)(best & 0xff) - 128;
-  out[g.nx * g.ny + a * g.nx + b] = (int)((best >> 8) & 0xff) - 128;
+  out[a * g.nx + b] = cx - R + (int)(best & 7u);
+  out[g.nx * g.ny + a * g.nx + b] = cy - R + (int)((best >> 3) & 7u);
 }
 
 // final level-0 field -> float predictor, through the 3x3 median when enabled
@@ -911,8 +927,13 @@ hipError_t launch_sad_level(const Plan& P, int l, const void*, const void*, int6
   const bool off31 = (size_t)v.rows * v.pitch < (1u << 31) && v.pitch < (1 << 24);
   if (P.es == 1 && g.R <= 2 && (NW == 2 || NW == 3 || NW == 4) && off31) {
     dim3 grid((v.nx * v.ny + 255) / 256, n);
-#define PIV_SAD_LANE(NW_, R_) \
-  if (NW == NW_ && g.R == R_) { hipLaunchKernelGGL((k_sad_lane<NW_, R_>), grid, dim3(256), 0, s, g); return hipGetLastError(); }
+    const bool aal = P.p.step % 4 == 0 && ((P.p.step - P.block) / 2) % 4 == 0;
+#define PIV_SAD_LANE(NW_, R_)                                                                \
+  if (NW == NW_ && g.R == R_) {                                                             \
+    if (aal) hipLaunchKernelGGL((k_sad_lane<NW_, R_, true>), grid, dim3(256), 0, s, g);   \
+    else hipLaunchKernelGGL((k_sad_lane<NW_, R_, false>), grid, dim3(256), 0, s, g);      \
+    return hipGetLastError();                                                               \
+  }
     PIV_SAD_LANE(4, 2) PIV_SAD_LANE(4, 1) PIV_SAD_LANE(4, 0)
     PIV_SAD_LANE(3, 2) PIV_SAD_LANE(3, 1) PIV_SAD_LANE(3, 0)
     PIV_SAD_LANE(2, 2) PIV_SAD_LANE(2, 1) PIV_SAD_LANE(2, 0)
