@@ -51,7 +51,7 @@ __global__ __launch_bounds__(256) void k_pad_pyr(const uint8_t* __restrict__ A, 
                                                  int64_t spitch, int64_t sstride, int W, int H, uint8_t* ws,
                                                  int64_t stride, int64_t offA0, int64_t offB0, int pitch0,
                                                  int m0, int64_t offA1, int64_t offB1, int pitch1, int m1,
-                                                 int W1, int H1, int do_l1, const uint8_t* mask) {
+                                                 int W1, int H1, int do_l1, int lframe, const uint8_t* mask) {
   constexpr int ES = (int)sizeof(T);
   const int pair = blockIdx.z >> 1, frame = blockIdx.z & 1;
   if (slot_off(mask, pair)) return;
@@ -81,10 +81,15 @@ __global__ __launch_bounds__(256) void k_pad_pyr(const uint8_t* __restrict__ A, 
   }
   uint8_t* base = ws + (int64_t)pair * stride;
   const int x0 = m0 * ES + 16 * q;   // byte offset of the chunk in a padded level-0 row (16-aligned)
+  // lframe > 0: level 0 is read in place except near its edges, so only the
+  // chunks and rows within lframe px of an edge are copied
+  const bool col_edge = lframe == 0 || 16 * q < lframe * ES || 16 * q + 16 > (W - lframe) * ES;
 #pragma unroll
   for (int r = 0; r < 2; ++r) {
-    uint8_t* row = base + (frame ? offB0 : offA0) + (int64_t)(2 * k + r + m0) * pitch0;
-    if (x0 + 16 <= pitch0) *reinterpret_cast<uint4*>(row + x0) = make_uint4(w[r][0], w[r][1], w[r][2], w[r][3]);
+    const int y = 2 * k + r;
+    const bool edge = col_edge || y < lframe || y >= H - lframe;
+    uint8_t* row = base + (frame ? offB0 : offA0) + (int64_t)(y + m0) * pitch0;
+    if (edge && x0 + 16 <= pitch0) *reinterpret_cast<uint4*>(row + x0) = make_uint4(w[r][0], w[r][1], w[r][2], w[r][3]);
   }
   if (!do_l1) return;
   // the chunk's 16 / ES pixels of each row -> 8 / ES level-1 pixels
@@ -187,7 +192,22 @@ struct SadArgs {
   const uint8_t* mask;
   int npw;                // nodes per workgroup (k_sad)
   int margin;             // level margin (px): A - margin (pitch + bytes per px) is padded row 0
+  // level 0 read in place (k_sad_lane): an A block or B span wholly inside
+  // the image reads the caller's frames (pair 0 at srcA/srcB); one that
+  // crosses the image edge reads the padded copy, of which only a frame of
+  // kFrame px along the edges is written
+  const uint8_t* srcA;
+  const uint8_t* srcB;
+  int64_t spitch, sstride;
+  int W, H;               // level size (px)
+  int direct;
 };
+
+// Depth of the written frame of the level-0 copy when level 0 is read in
+// place: a span that crosses the image edge has all of its in-image pixels
+// within its own extent of that edge (at most 2R + 16 rows and 4 (RW + 1) <= 28
+// columns for the one-node-per-lane kernel).
+constexpr int kFrame = 32;
 
 template <int ES>
 __device__ __forceinline__ uint32_t sad_word(uint32_t a, uint32_t b, uint32_t c) {
@@ -702,27 +722,41 @@ __global__ __launch_bounds__(256) void k_sad_lane(SadArgs g) {
   const int xa = xs & ~3, sh = xs & 3;
   const int axa = ox & ~3, ash = ox & 3;
   // 32-bit offsets from padded row 0 (non-negative; the launcher checks that
-  // a padded level fits 31 bits), so a row costs one add of a uniform step
-  const unsigned pitch32 = (unsigned)g.pitch;
-  const uint8_t* Ap = Ab - ((int64_t)g.margin * g.pitch + g.margin);
-  const uint8_t* Bp = Bb - ((int64_t)g.margin * g.pitch + g.margin);
-  const unsigned aoff = __umul24((unsigned)(oy + g.margin), pitch32) + (unsigned)(axa + g.margin);
-  const unsigned boff = __umul24((unsigned)(y0 + g.margin), pitch32) + (unsigned)(xa + g.margin);
+  // a padded level fits 31 bits), or from row 0 of the caller's frame for a
+  // span wholly inside the image (the launcher checks that a frame fits too)
+  const unsigned pitch32 = (unsigned)g.pitch, spitch32 = (unsigned)g.spitch;
+  const bool ain = g.direct && oy >= 0 && oy + BLK <= g.H && axa >= 0 && axa + 4 * (AAL ? NW : NW + 1) <= g.W;
+  const bool bin = g.direct && y0 >= 0 && y0 + BLK + 2 * R <= g.H && xa >= 0 && xa + 4 * (RW + 1) <= g.W;
+  // (two uniform bases, a per-lane choice between loads, so that addresses
+  // stay a uniform base plus a 32-bit lane offset)
+  const uint8_t* Apad = Ab - ((int64_t)g.margin * g.pitch + g.margin);
+  const uint8_t* Bpad = Bb - ((int64_t)g.margin * g.pitch + g.margin);
+  const uint8_t* Asrc = g.srcA + (int64_t)pair * g.sstride;
+  const uint8_t* Bsrc = g.srcB + (int64_t)pair * g.sstride;
+  const unsigned pa = ain ? spitch32 : pitch32, pb = bin ? spitch32 : pitch32;
+  const int am = ain ? 0 : g.margin, bm = bin ? 0 : g.margin;
+  const unsigned aoff = __umul24((unsigned)(oy + am), pa) + (unsigned)(axa + am);
+  const unsigned boff = __umul24((unsigned)(y0 + bm), pb) + (unsigned)(xa + bm);
   uint32_t av[BLK][NW];
 #pragma unroll
   for (int rb = 0; rb < BLK + 2 * R; ++rb) {
     if (rb < BLK) {
+      const unsigned o = aoff + rb * pa;
       if constexpr (AAL) {
-        const Words<NW> w = *reinterpret_cast<const Words<NW>*>(Ap + (size_t)(aoff + rb * pitch32));
+        const Words<NW> w = ain ? *reinterpret_cast<const Words<NW>*>(Asrc + (size_t)o)
+                                : *reinterpret_cast<const Words<NW>*>(Apad + (size_t)o);
 #pragma unroll
         for (int i = 0; i < NW; ++i) av[rb][i] = w.w[i];
       } else {
-        const Words<NW + 1> w = *reinterpret_cast<const Words<NW + 1>*>(Ap + (size_t)(aoff + rb * pitch32));
+        const Words<NW + 1> w = ain ? *reinterpret_cast<const Words<NW + 1>*>(Asrc + (size_t)o)
+                                    : *reinterpret_cast<const Words<NW + 1>*>(Apad + (size_t)o);
 #pragma unroll
         for (int i = 0; i < NW; ++i) av[rb][i] = __builtin_amdgcn_alignbyte(w.w[i + 1], w.w[i], ash);
       }
     }
-    const Words<RW + 1> w = *reinterpret_cast<const Words<RW + 1>*>(Bp + (size_t)(boff + rb * pitch32));
+    const unsigned ob = boff + rb * pb;
+    const Words<RW + 1> w = bin ? *reinterpret_cast<const Words<RW + 1>*>(Bsrc + (size_t)ob)
+                                : *reinterpret_cast<const Words<RW + 1>*>(Bpad + (size_t)ob);
     uint32_t rw[RW];
 #pragma unroll
     for (int i = 0; i < RW; ++i) rw[i] = __builtin_amdgcn_alignbyte(w.w[i + 1], w.w[i], sh);
@@ -834,6 +868,17 @@ bool sad_supported(int block_words) {
          block_words == 14 || block_words == 16;
 }
 
+// Level 0 is searched by the one-node-per-lane kernel reading the caller's
+// frames in place (see SadArgs): u8, radius <= 2, 8-16 px blocks, and
+// 32-bit offsets into both the padded copy and one caller frame.
+static bool level0_in_place(const Plan& P, int64_t pitch) {
+  const Level& v = P.lv[0];
+  const int NW = P.block * P.es / 4;
+  const bool off31 = (size_t)v.rows * v.pitch < (1u << 31) && v.pitch < (1 << 24);
+  return P.es == 1 && v.R <= 2 && (NW == 2 || NW == 3 || NW == 4) && off31 && pitch < (1 << 24) &&
+         (int64_t)P.p.height * pitch < (int64_t(1) << 31);
+}
+
 hipError_t launch_pyramid(const Plan& P, const void* A, const void* B, int64_t pitch, int n,
                           hipStream_t s) {
   if (!P.margins_clean) {
@@ -853,16 +898,17 @@ hipError_t launch_pyramid(const Plan& P, const void* A, const void* B, int64_t p
     const Level& v1 = P.lv[P.L > 1 ? 1 : 0];
     const int nq = (v0.W * P.es + 15) / 16;
     dim3 grid((nq * ((v0.H + 1) / 2) + 255) / 256, 1, 2 * n);
+    const int lframe = level0_in_place(P, pitch) ? kFrame : 0;
     if (P.es == 1)
       hipLaunchKernelGGL(k_pad_pyr<uint8_t>, grid, dim3(256), 0, s, (const uint8_t*)A, (const uint8_t*)B, pitch,
                          pitch * P.p.height, v0.W, v0.H, P.ws, (int64_t)P.per_pair, (int64_t)v0.off_a,
                          (int64_t)v0.off_b, v0.pitch, v0.margin, (int64_t)v1.off_a, (int64_t)v1.off_b, v1.pitch,
-                         v1.margin, v1.W, v1.H, P.L > 1 ? 1 : 0, P.slot_mask);
+                         v1.margin, v1.W, v1.H, P.L > 1 ? 1 : 0, lframe, P.slot_mask);
     else
       hipLaunchKernelGGL(k_pad_pyr<uint16_t>, grid, dim3(256), 0, s, (const uint8_t*)A, (const uint8_t*)B, pitch,
                          pitch * P.p.height, v0.W, v0.H, P.ws, (int64_t)P.per_pair, (int64_t)v0.off_a,
                          (int64_t)v0.off_b, v0.pitch, v0.margin, (int64_t)v1.off_a, (int64_t)v1.off_b, v1.pitch,
-                         v1.margin, v1.W, v1.H, P.L > 1 ? 1 : 0, P.slot_mask);
+                         v1.margin, v1.W, v1.H, P.L > 1 ? 1 : 0, lframe, P.slot_mask);
     if (hipError_t e = hipGetLastError()) return e;
   }
   for (int l = 2; l < P.L; ++l) {
@@ -884,9 +930,17 @@ hipError_t launch_pyramid(const Plan& P, const void* A, const void* B, int64_t p
   return hipSuccess;
 }
 
-hipError_t launch_sad_level(const Plan& P, int l, const void*, const void*, int64_t, int n, hipStream_t s) {
+hipError_t launch_sad_level(const Plan& P, int l, const void* A, const void* B, int64_t pitch, int n,
+                            hipStream_t s) {
   const Level& v = P.lv[l];
   SadArgs g;
+  g.direct = l == 0 && level0_in_place(P, pitch) ? 1 : 0;
+  g.srcA = (const uint8_t*)A;
+  g.srcB = (const uint8_t*)B;
+  g.spitch = pitch;
+  g.sstride = pitch * P.p.height;
+  g.W = v.W;
+  g.H = v.H;
   const size_t origin = (size_t)v.margin * v.pitch + (size_t)v.margin * P.es;
   g.A = P.ws + v.off_a + origin;
   g.B = P.ws + v.off_b + origin;
