@@ -39,82 +39,104 @@ __global__ __launch_bounds__(256) void k_clear_margins(uint8_t* ws, int64_t stri
 }
 
 // ---------------------------------------------------------------------------
-// Level 0 core copy fused with level 1: one thread per pair of image rows
-// (2k, 2k+1) and 16-byte column chunk.  It copies both rows into the padded
-// level-0 buffer and writes the 2x2 means of the chunk into level 1:
-// out(y,x) = floor((in(2y,2x) + in(2y,2x+1) + in(2y+1,2x) + in(2y+1,2x+1) + 2) / 4),
-// zero outside the level-1 image.  Rows and columns past the image read as
-// zero (the level's margin).
+// Level 0 core copy fused with levels 1 and 2.  Every level is
+// out(y,x) = floor((in(2y,2x) + in(2y,2x+1) + in(2y+1,2x) + in(2y+1,2x+1) + 2) / 4)
+// of the level below, zero outside its image.  One thread per 16-byte column
+// chunk and pair of image rows (2k, 2k+1), or with L2 per four image rows:
+// it copies the rows into the padded level-0 buffer and writes the chunk's
+// level-1 means (and, with L2, the means of those, level 2).  Rows and
+// columns past the image read as zero (the level's margin).
 // ---------------------------------------------------------------------------
-template <typename T>
+struct PyrDst {
+  int64_t offA, offB;   // per-pair offsets of the level's padded buffers
+  int pitch, m, W, H;   // bytes per row, margin (px), level size (px)
+};
+
+template <typename T, bool L2>
 __global__ __launch_bounds__(256) void k_pad_pyr(const uint8_t* __restrict__ A, const uint8_t* __restrict__ B,
                                                  int64_t spitch, int64_t sstride, int W, int H, uint8_t* ws,
-                                                 int64_t stride, int64_t offA0, int64_t offB0, int pitch0,
-                                                 int m0, int64_t offA1, int64_t offB1, int pitch1, int m1,
-                                                 int W1, int H1, int do_l1, int lframe, const uint8_t* mask) {
+                                                 int64_t stride, PyrDst d0, PyrDst d1, PyrDst d2, int do_l1,
+                                                 int lframe, const uint8_t* mask) {
   constexpr int ES = (int)sizeof(T);
+  constexpr int NP = 16 / ES, NO = NP / 2;   // pixels of a chunk, level-1 pixels they give
+  constexpr int NR = L2 ? 2 : 1;             // row pairs per thread
   const int pair = blockIdx.z >> 1, frame = blockIdx.z & 1;
   if (slot_off(mask, pair)) return;
   const int rowbytes = W * ES;
   const int nq = (rowbytes + 15) / 16;
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  const int k = idx / nq, q = idx - (idx / nq) * nq;
-  if (k >= (H + 1) / 2) return;
+  const int kk = idx / nq, q = idx - (idx / nq) * nq;
+  if (kk >= (H + 2 * NR - 1) / (2 * NR)) return;
   const uint8_t* src = (frame ? B : A) + (int64_t)pair * sstride;
-  uint32_t w[2][4];
+  uint8_t* base = ws + (int64_t)pair * stride;
   // whole chunks of rows inside the image, from 16-byte aligned addresses,
-  // take one 16-byte read; the ragged right end and a missing last row are
+  // take one 16-byte read; the ragged right end and missing last rows are
   // read word by word with zero fill
   const bool whole = 16 * q + 16 <= rowbytes && ((reinterpret_cast<uintptr_t>(src) | spitch) & 15) == 0;
-#pragma unroll
-  for (int r = 0; r < 2; ++r) {
-    const int y = 2 * k + r;
-    const uint8_t* row = src + (int64_t)min(y, H - 1) * spitch;
-    if (whole && y < H) {
-      const uint4 v = *reinterpret_cast<const uint4*>(row + 16 * q);
-      w[r][0] = v.x; w[r][1] = v.y; w[r][2] = v.z; w[r][3] = v.w;
-    } else {
-      const uint32_t ok = y < H ? 0xffffffffu : 0u;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) w[r][i] = masked_word(row, rowbytes, 16 * q + 4 * i) & ok;
-    }
-  }
-  uint8_t* base = ws + (int64_t)pair * stride;
-  const int x0 = m0 * ES + 16 * q;   // byte offset of the chunk in a padded level-0 row (16-aligned)
+  const int x0 = d0.m * ES + 16 * q;   // byte offset of the chunk in a padded level-0 row (16-aligned)
   // lframe > 0: level 0 is read in place except near its edges, so only the
   // chunks and rows within lframe px of an edge are copied
   const bool col_edge = lframe == 0 || 16 * q < lframe * ES || 16 * q + 16 > (W - lframe) * ES;
+  uint32_t s[NR][NO];   // level-1 pixels of the chunk, per row pair
 #pragma unroll
-  for (int r = 0; r < 2; ++r) {
-    const int y = 2 * k + r;
-    const bool edge = col_edge || y < lframe || y >= H - lframe;
-    uint8_t* row = base + (frame ? offB0 : offA0) + (int64_t)(y + m0) * pitch0;
-    if (edge && x0 + 16 <= pitch0) *reinterpret_cast<uint4*>(row + x0) = make_uint4(w[r][0], w[r][1], w[r][2], w[r][3]);
-  }
-  if (!do_l1) return;
-  // the chunk's 16 / ES pixels of each row -> 8 / ES level-1 pixels
-  constexpr int NP = 16 / ES, NO = NP / 2;
-  uint32_t s[NO];
+  for (int h2 = 0; h2 < NR; ++h2) {
+    const int k = NR * kk + h2;   // level-1 row
+    uint32_t w[2][4];
 #pragma unroll
-  for (int j = 0; j < NO; ++j) {
-    uint32_t acc = 2u;
+    for (int r = 0; r < 2; ++r) {
+      const int y = 2 * k + r;
+      const uint8_t* row = src + (int64_t)min(y, H - 1) * spitch;
+      if (whole && y < H) {
+        const uint4 v = *reinterpret_cast<const uint4*>(row + 16 * q);
+        w[r][0] = v.x; w[r][1] = v.y; w[r][2] = v.z; w[r][3] = v.w;
+      } else {
+        const uint32_t ok = y < H ? 0xffffffffu : 0u;
 #pragma unroll
-    for (int r = 0; r < 2; ++r)
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int px = 2 * j + h;                  // pixel in the chunk
-        const int bit = (px * ES * 8) & 31, wd = (px * ES) / 4;
-        acc += (w[r][wd] >> bit) & (ES == 1 ? 0xffu : 0xffffu);
+        for (int i = 0; i < 4; ++i) w[r][i] = masked_word(row, rowbytes, 16 * q + 4 * i) & ok;
       }
-    const int x1 = q * NO + j;
-    s[j] = (k < H1 && x1 < W1) ? (acc >> 2) : 0u;
-  }
-  uint32_t o[2] = {0u, 0u};
+    }
 #pragma unroll
-  for (int j = 0; j < NO; ++j) o[(j * ES) / 4] |= s[j] << ((j * ES * 8) & 31);
-  uint8_t* row1 = base + (frame ? offB1 : offA1) + (int64_t)(k + m1) * pitch1;
-  const int x1b = m1 * ES + 8 * q;   // 8-byte aligned
-  if (x1b + 8 <= pitch1) *reinterpret_cast<uint2*>(row1 + x1b) = make_uint2(o[0], o[1]);
+    for (int r = 0; r < 2; ++r) {
+      const int y = 2 * k + r;
+      const bool edge = col_edge || y < lframe || y >= H - lframe;
+      uint8_t* row = base + (frame ? d0.offB : d0.offA) + (int64_t)(y + d0.m) * d0.pitch;
+      if (edge && x0 + 16 <= d0.pitch) *reinterpret_cast<uint4*>(row + x0) = make_uint4(w[r][0], w[r][1], w[r][2], w[r][3]);
+    }
+    if (!do_l1) return;
+#pragma unroll
+    for (int j = 0; j < NO; ++j) {
+      uint32_t acc = 2u;
+#pragma unroll
+      for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int px = 2 * j + h;                  // pixel in the chunk
+          const int bit = (px * ES * 8) & 31, wd = (px * ES) / 4;
+          acc += (w[r][wd] >> bit) & (ES == 1 ? 0xffu : 0xffffu);
+        }
+      const int x1 = q * NO + j;
+      s[h2][j] = (k < d1.H && x1 < d1.W) ? (acc >> 2) : 0u;
+    }
+    uint32_t o[2] = {0u, 0u};
+#pragma unroll
+    for (int j = 0; j < NO; ++j) o[(j * ES) / 4] |= s[h2][j] << ((j * ES * 8) & 31);
+    uint8_t* row1 = base + (frame ? d1.offB : d1.offA) + (int64_t)(k + d1.m) * d1.pitch;
+    const int x1b = d1.m * ES + 8 * q;   // 8-byte aligned
+    if (x1b + 8 <= d1.pitch) *reinterpret_cast<uint2*>(row1 + x1b) = make_uint2(o[0], o[1]);
+  }
+  if constexpr (L2) {
+    // the chunk's level-1 2 x NO block -> NO / 2 level-2 pixels (4 bytes)
+    uint32_t o = 0u;
+#pragma unroll
+    for (int j = 0; j < NO / 2; ++j) {
+      const uint32_t acc = s[0][2 * j] + s[0][2 * j + 1] + s[1][2 * j] + s[1][2 * j + 1] + 2u;
+      const int x2 = q * (NO / 2) + j;
+      o |= ((kk < d2.H && x2 < d2.W) ? (acc >> 2) : 0u) << (j * ES * 8);
+    }
+    uint8_t* row2 = base + (frame ? d2.offB : d2.offA) + (int64_t)(kk + d2.m) * d2.pitch;
+    const int x2b = d2.m * ES + 4 * q;   // 4-byte aligned
+    if (x2b + 4 <= d2.pitch) *reinterpret_cast<uint32_t*>(row2 + x2b) = o;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -894,24 +916,39 @@ hipError_t launch_pyramid(const Plan& P, const void* A, const void* B, int64_t p
     P.margins_clean = true;
   }
   const Level& v0 = P.lv[0];
+  const bool l2 = P.L > 2;   // levels 1 and 2 from one read of the frames
   {
-    const Level& v1 = P.lv[P.L > 1 ? 1 : 0];
+    auto dst = [&](const Level& v) {
+      PyrDst d;
+      d.offA = (int64_t)v.off_a;
+      d.offB = (int64_t)v.off_b;
+      d.pitch = v.pitch;
+      d.m = v.margin;
+      d.W = v.W;
+      d.H = v.H;
+      return d;
+    };
+    const PyrDst d0 = dst(v0), d1 = dst(P.lv[P.L > 1 ? 1 : 0]), d2 = dst(P.lv[l2 ? 2 : 0]);
     const int nq = (v0.W * P.es + 15) / 16;
-    dim3 grid((nq * ((v0.H + 1) / 2) + 255) / 256, 1, 2 * n);
+    const int rows = l2 ? (v0.H + 3) / 4 : (v0.H + 1) / 2;
+    dim3 grid((nq * rows + 255) / 256, 1, 2 * n);
     const int lframe = level0_in_place(P, pitch) ? kFrame : 0;
-    if (P.es == 1)
-      hipLaunchKernelGGL(k_pad_pyr<uint8_t>, grid, dim3(256), 0, s, (const uint8_t*)A, (const uint8_t*)B, pitch,
-                         pitch * P.p.height, v0.W, v0.H, P.ws, (int64_t)P.per_pair, (int64_t)v0.off_a,
-                         (int64_t)v0.off_b, v0.pitch, v0.margin, (int64_t)v1.off_a, (int64_t)v1.off_b, v1.pitch,
-                         v1.margin, v1.W, v1.H, P.L > 1 ? 1 : 0, lframe, P.slot_mask);
-    else
-      hipLaunchKernelGGL(k_pad_pyr<uint16_t>, grid, dim3(256), 0, s, (const uint8_t*)A, (const uint8_t*)B, pitch,
-                         pitch * P.p.height, v0.W, v0.H, P.ws, (int64_t)P.per_pair, (int64_t)v0.off_a,
-                         (int64_t)v0.off_b, v0.pitch, v0.margin, (int64_t)v1.off_a, (int64_t)v1.off_b, v1.pitch,
-                         v1.margin, v1.W, v1.H, P.L > 1 ? 1 : 0, lframe, P.slot_mask);
+    const int do_l1 = P.L > 1 ? 1 : 0;
+#define PIV_PAD_PYR(T_, L2_)                                                                           \
+  hipLaunchKernelGGL((k_pad_pyr<T_, L2_>), grid, dim3(256), 0, s, (const uint8_t*)A, (const uint8_t*)B, \
+                     pitch, pitch * P.p.height, v0.W, v0.H, P.ws, (int64_t)P.per_pair, d0, d1, d2, do_l1,  \
+                     lframe, P.slot_mask)
+    if (P.es == 1) {
+      if (l2) PIV_PAD_PYR(uint8_t, true);
+      else PIV_PAD_PYR(uint8_t, false);
+    } else {
+      if (l2) PIV_PAD_PYR(uint16_t, true);
+      else PIV_PAD_PYR(uint16_t, false);
+    }
+#undef PIV_PAD_PYR
     if (hipError_t e = hipGetLastError()) return e;
   }
-  for (int l = 2; l < P.L; ++l) {
+  for (int l = l2 ? 3 : 2; l < P.L; ++l) {
     const Level& u = P.lv[l - 1];
     const Level& v = P.lv[l];
     const int nch = (v.W + 7) / 8;
