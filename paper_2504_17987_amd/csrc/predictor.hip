@@ -407,6 +407,142 @@ __global__ __launch_bounds__(256) void k_sad_q(SadArgs g) {
 }
 
 // ---------------------------------------------------------------------------
+// Coarsest-level SAD search with cell-shared sums (u8, block = 2 step,
+// step 8).  Without a parent every node searches the same (2R+1)^2 shifts,
+// and a node's 16x16 block is four 8x8 cells that it shares with its
+// neighbours, so the SAD of a block is the sum of four cell SADs for the same
+// shift: each pixel difference is taken once instead of four times.
+// Lane = cell of a 9x7 tile (8x6 nodes per wave, four independent waves per
+// workgroup); the lane keeps its A cell in registers and streams the B rows
+// once per pass of DYG shift rows, four shift columns per quad SAD (16-bit
+// fields: a cell is at most 64 x 255).  Cell sums become block sums with a
+// DPP add of the right-hand cell (lane + 1) and a lane permute of the cell
+// below (lane + 9); four cells stay below 2^16, so the packed fields add
+// without carries.  Winner: the least (SAD, |dx|+|dy|, dy, dx).
+// ---------------------------------------------------------------------------
+template <int R, int DYG>
+__global__ __launch_bounds__(256) void k_sad_cells(SadArgs g) {
+  constexpr int G = 2 * R + 1, NGRP = (G + 3) / 4, REM = G - 4 * (NGRP - 1);
+  constexpr bool TAIL = REM <= 2;           // last group by full-rate v_sad_u8
+  constexpr int NQ = TAIL ? NGRP - 1 : NGRP;  // groups by quad SAD
+  constexpr int CWD = 2, RW = CWD + NGRP;     // cell words, realigned B words
+  constexpr int CW = 9, CH = 7, NPASS = (G + DYG - 1) / DYG;
+  static_assert(G <= 15, "4-bit shift indices in the key");
+  const int lane = threadIdx.x & 63;
+  const int pair = blockIdx.z;
+  if (slot_off(g.mask, pair)) return;
+  const int ntx = (g.nx + CW - 2) / (CW - 1), nty = (g.ny + CH - 2) / (CH - 1);
+  const int tile = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (tile >= ntx * nty) return;   // a whole wave (no barriers below)
+  const int ty = tile / ntx, tx = tile - ty * ntx;
+  const int lr = lane / CW, lc = lane - lr * CW;
+  // cells beyond the last node's read the last needed cell (results unused)
+  const int ci = min(ty * (CH - 1) + lr, g.ny), cj = min(tx * (CW - 1) + lc, g.nx);
+  const int y = ci * 8 - 4, x = cj * 8 - 4;
+  // 32-bit offsets from padded row 0 (the launcher checks that a padded
+  // level fits 31 bits): a row costs one add of a uniform step
+  const unsigned pitch32 = (unsigned)g.pitch;
+  const uint8_t* Ap = g.A + (int64_t)pair * g.stride - ((int64_t)g.margin * g.pitch + g.margin);
+  const uint8_t* Bp = g.B + (int64_t)pair * g.stride - ((int64_t)g.margin * g.pitch + g.margin);
+  const unsigned aoff = __umul24((unsigned)(y + g.margin), pitch32) + (unsigned)(x + g.margin);
+  uint32_t aw[8][CWD];
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    const Words<CWD> v = *reinterpret_cast<const Words<CWD>*>(Ap + (size_t)(aoff + r * pitch32));
+    aw[r][0] = v.w[0];
+    aw[r][1] = v.w[1];
+  }
+  const int xa = (x - R) & ~3, sh = (x - R) & 3;
+  const unsigned boff = __umul24((unsigned)(y - R + g.margin), pitch32) + (unsigned)(xa + g.margin);
+  const int node_a = ty * (CH - 1) + lr, node_b = tx * (CW - 1) + lc;
+  const bool node = lr < CH - 1 && lc < CW - 1 && node_a < g.ny && node_b < g.nx;
+  uint32_t best = ~0u;
+#pragma unroll
+  for (int ps = 0; ps < NPASS; ++ps) {
+    const int k0 = ps * DYG;                 // first shift row of the pass
+    const int nk = min(DYG, G - k0);         // shift rows in the pass
+    unsigned long long acc[DYG][NQ > 0 ? NQ : 1];
+    uint32_t tacc[DYG][2];
+#pragma unroll
+    for (int k = 0; k < DYG; ++k) {
+#pragma unroll
+      for (int m = 0; m < (NQ > 0 ? NQ : 1); ++m) acc[k][m] = 0ull;
+      tacc[k][0] = tacc[k][1] = 0u;
+    }
+#pragma unroll
+    for (int rb = 0; rb < 8 + DYG - 1; ++rb) {
+      if (rb >= 8 + nk - 1) continue;
+      // B row y + (k0 - R) + rb: it meets A row rb - k for shift row k0 + k
+      const Words<RW + 1> wv =
+          *reinterpret_cast<const Words<RW + 1>*>(Bp + (size_t)(boff + (unsigned)(k0 + rb) * pitch32));
+      uint32_t rw[RW];
+#pragma unroll
+      for (int i = 0; i < RW; ++i) rw[i] = __builtin_amdgcn_alignbyte(wv.w[i + 1], wv.w[i], sh);
+#pragma unroll
+      for (int k = 0; k < DYG; ++k) {
+        const int r = rb - k;
+        if (r < 0 || r >= 8 || k0 + k >= G) continue;
+#pragma unroll
+        for (int i = 0; i < CWD; ++i) {
+#pragma unroll
+          for (int m = 0; m < NQ; ++m) {
+            const unsigned long long src = ((unsigned long long)rw[i + m + 1] << 32) | rw[i + m];
+            acc[k][m] = __builtin_amdgcn_qsad_pk_u16_u8(src, aw[r][i], acc[k][m]);
+          }
+          if constexpr (TAIL) {
+            tacc[k][0] = __builtin_amdgcn_sad_u8(aw[r][i], rw[i + NQ], tacc[k][0]);
+            if constexpr (REM == 2)
+              tacc[k][1] = __builtin_amdgcn_sad_u8(aw[r][i], __builtin_amdgcn_alignbyte(rw[i + NQ + 1], rw[i + NQ], 1),
+                                                   tacc[k][1]);
+          }
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    // block sums: + right cell (DPP wave_shl:1), then + the cell row below
+    auto quad = [&](uint32_t v) {
+      const uint32_t h = v + (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x130, 0xF, 0xF, false);
+      return h + (uint32_t)__builtin_amdgcn_ds_bpermute((lane + CW) << 2, (int)h);
+    };
+#pragma unroll
+    for (int k = 0; k < DYG; ++k) {
+      if (k0 + k >= G) continue;
+      const int dy = k0 + k - R;
+      const uint32_t kdy = ((uint32_t)abs(dy) << 8) | ((uint32_t)(dy + R) << 4);
+#pragma unroll
+      for (int m = 0; m < NQ; ++m) {
+        const uint32_t lo = quad((uint32_t)acc[k][m]), hi = quad((uint32_t)(acc[k][m] >> 32));
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+          const int c = 4 * m + f;
+          if (c >= G) continue;
+          const uint32_t sad = ((f < 2 ? lo : hi) >> (16 * (f & 1))) & 0xffffu;
+          const int dx = c - R;
+          best = min(best, (sad << 12) | (kdy + ((uint32_t)abs(dx) << 8)) | (uint32_t)(dx + R));
+        }
+      }
+      if constexpr (TAIL) {
+#pragma unroll
+        for (int f = 0; f < REM; ++f) {
+          const int c = 4 * NQ + f, dx = c - R;
+          const uint32_t sad = quad(tacc[k][f]);
+          best = min(best, (sad << 12) | (kdy + ((uint32_t)abs(dx) << 8)) | (uint32_t)(dx + R));
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);   // one shift row's permutes in flight at a time
+    }
+    // the next pass's row reads stay behind this pass's sums, so that one
+    // pass of accumulators is live at a time
+    asm volatile("" : "+v"(best)::"memory");
+  }
+  if (node) {
+    int32_t* out = g.out + (int64_t)pair * g.ostride;
+    out[node_a * g.nx + node_b] = (int)(best & 15u) - R;
+    out[g.nx * g.ny + node_a * g.nx + node_b] = (int)((best >> 4) & 15u) - R;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // SAD block search, one node per lane, A rows streamed (any element size,
 // small R): the lane keeps the last G = 2R+1 rows of its A block in a ring of
 // registers and streams the rows of B once each; a B row, realigned to the
@@ -1029,6 +1165,20 @@ hipError_t launch_sad_level(const Plan& P, int l, const void* A, const void* B, 
     PIV_SAD_LANE(3, 2) PIV_SAD_LANE(3, 1) PIV_SAD_LANE(3, 0)
     PIV_SAD_LANE(2, 2) PIV_SAD_LANE(2, 1) PIV_SAD_LANE(2, 0)
 #undef PIV_SAD_LANE
+  }
+  // coarsest level, u8, 16x16 blocks at step 8: cell-shared sums
+  if (!g.parent && P.es == 1 && P.p.step == 8 && P.block == 16 && g.R >= 3 && g.R <= 7 &&
+      (size_t)v.rows * v.pitch < (1u << 31) && v.pitch < (1 << 24)) {
+    const int tiles = ((v.nx + 7) / 8) * ((v.ny + 5) / 6);
+    dim3 grid((tiles + 3) / 4, 1, n);
+    switch (g.R) {
+      case 3: hipLaunchKernelGGL((k_sad_cells<3, 7>), grid, dim3(256), 0, s, g); break;
+      case 4: hipLaunchKernelGGL((k_sad_cells<4, 5>), grid, dim3(256), 0, s, g); break;
+      case 5: hipLaunchKernelGGL((k_sad_cells<5, 6>), grid, dim3(256), 0, s, g); break;
+      case 6: hipLaunchKernelGGL((k_sad_cells<6, 7>), grid, dim3(256), 0, s, g); break;
+      default: hipLaunchKernelGGL((k_sad_cells<7, 5>), grid, dim3(256), 0, s, g); break;
+    }
+    return hipGetLastError();
   }
   // nodes per workgroup: G lanes each, A blocks within 64 KiB of LDS
   const int npw = min(256 / G, 65536 / (P.block * NW * 4));
