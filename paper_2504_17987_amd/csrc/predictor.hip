@@ -264,6 +264,40 @@ __device__ __forceinline__ int parent_value(const SadArgs& g, const int32_t* par
   return median9_low_i(v, k);
 }
 
+// Both components of the candidate centre at once (twice the parent's
+// result, through its 3x3 median when enabled): the 18 reads go to clamped,
+// always valid addresses and are all in flight before the first is used.
+__device__ __forceinline__ void parent_centre(const SadArgs& g, const int32_t* par, int pa, int pb, int& cx,
+                                              int& cy) {
+  const int np = g.pnx * g.pny;
+  if (!g.median) {
+    cx = 2 * par[pa * g.pnx + pb];
+    cy = 2 * par[np + pa * g.pnx + pb];
+    return;
+  }
+  int vx[9], vy[9];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const int o = min(max(pa + i - 1, 0), g.pny - 1) * g.pnx + min(max(pb + j - 1, 0), g.pnx - 1);
+      vx[i * 3 + j] = par[o];
+      vy[i * 3 + j] = par[np + o];
+    }
+  int k = 0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const int y = pa + i - 1, x = pb + j - 1;
+      const bool in = y >= 0 && x >= 0 && y < g.pny && x < g.pnx;
+      if (!in) vx[i * 3 + j] = vy[i * 3 + j] = kSlotI;
+      k += in;
+    }
+  cx = 2 * median9_low_i(vx, k);
+  cy = 2 * median9_low_i(vy, k);
+}
+
 __device__ __forceinline__ unsigned long long sad_key(uint32_t sad, int dy, int dx) {
   const unsigned l1 = (unsigned)(abs(dx) + abs(dy));
   return ((unsigned long long)sad << 25) | ((unsigned long long)l1 << 16) |
@@ -573,7 +607,8 @@ __global__ __launch_bounds__(256) void k_sad_cells_fine(SadArgs g) {
   // candidate centre: twice the parent's result (through its median)
   const int32_t* par = g.parent + (int64_t)pair * g.pstride;
   const int ppa = min(pa, g.pny - 1), ppb = min(pb, g.pnx - 1);
-  const int cx = 2 * parent_value(g, par, 0, ppa, ppb), cy = 2 * parent_value(g, par, 1, ppa, ppb);
+  int cx, cy;
+  parent_centre(g, par, ppa, ppb, cx, cy);
   // cells past the last node read the last needed cell (results unused)
   const int ci = min(2 * pa + u, g.ny), cj = min(2 * pb + v, g.nx);
   const int y = ci * 8 - 4, x = cj * 8 - 4;
