@@ -643,7 +643,7 @@ __global__ __launch_bounds__(256) void k_sad_cells_fine(SadArgs g) {
     tacc[k][0] = tacc[k][1] = 0u;
   }
   // B rows y0 .. y0 + 7 + 2R, read PF rows ahead of their use
-  constexpr int NROWS = 8 + G - 1, PF = 3;
+  constexpr int NROWS = 8 + G - 1, PF = 5;
   auto brow = [&](int rb) {
     const unsigned o = boff + rb * pb32;
     return bin ? *reinterpret_cast<const Words<RW + 1>*>(Bsrc + (size_t)o)
