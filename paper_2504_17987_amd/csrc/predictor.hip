@@ -595,11 +595,13 @@ __global__ __launch_bounds__(256) void k_sad_cells_fine(SadArgs g) {
   constexpr int CWD = 2, RW = CWD + NGRP, PPW = 7;   // parents per wave
   static_assert(G <= 5, "one pass of shift rows");
   const int lane = threadIdx.x & 63;
-  const int pair = blockIdx.z;
+  // consecutive tiles (neighbouring parents, overlapping B rows) on one XCD
+  const WgIdx wg = xcd_order();
+  const int pair = wg.z;
   if (slot_off(g.mask, pair)) return;
   const int pnx = (g.nx + 1) / 2, pny = (g.ny + 1) / 2;
   const int ntx = (pnx + PPW - 1) / PPW;
-  const int tile = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int tile = wg.x * 4 + (threadIdx.x >> 6);
   if (tile >= ntx * pny) return;   // a whole wave (no barriers below)
   const int pa = tile / ntx, grp = min(lane / 9, PPW - 1);
   const int pb = min((tile - pa * ntx) * PPW + grp, pnx - 1);
