@@ -1229,6 +1229,7 @@ void k_correct_bands(CorrArgs g) {
     // only keep the padding columns of a ragged last group inside the box
     const int ixhi = ix1 - 1 - ix0, iyhi = iy1 - 1 - iy0;
     const int xadd = ix0 * ES - xoff;   // byte offset of box column 0 in a staged row
+    const uint8_t* rawx = rawb + xadd;  // (folded into the base: one multiply-add per pixel)
     for (int idx = t; idx < C::BH * BQ; idx += NT) {
       const int r = idx / BQ, q = 4 * (idx - (idx / BQ) * BQ);
       float uu[4] = {0.0f, 0.0f, 0.0f, 0.0f}, vv[4] = {0.0f, 0.0f, 0.0f, 0.0f};
@@ -1274,7 +1275,7 @@ void k_correct_bands(CorrArgs g) {
         const float fx = __builtin_amdgcn_fractf(qx), fy = __builtin_amdgcn_fractf(qy);
         // (as unsigned, a negative index would clamp to the top as well)
         const unsigned ix = min((unsigned)(int)qx, (unsigned)ixhi), iy = min((unsigned)(int)qy, (unsigned)iyhi);
-        const uint8_t* p0 = rawb + (__umul24(iy, (unsigned)rowb) + (ix * ES + xadd));
+        const uint8_t* p0 = rawx + (__umul24(iy, (unsigned)rowb) + ix * ES);
         const float p00 = rawv(p0), p01 = rawv(p0 + ES), p10 = rawv(p0 + rowb), p11 = rawv(p0 + rowb + ES);
         const float top = p00 + fx * (p01 - p00), bot = p10 + fx * (p11 - p10);
         out[e] = (top + fy * (bot - top)) - K;
