@@ -48,6 +48,10 @@ PRED_CASES = {
     # a fine level searched by the lane-per-row kernel (radius above 2, with a parent)
     "fine_r3_L2": (lambda: small_vortex_pair(seed=14)[:2],
                    dict(win=16, step=8, levels=2, radius_coarse=4, radius_fine=3)),
+    # 12 px blocks at step 8: the staged quad-SAD coarse level and the
+    # one-node-per-lane fine level with unaligned block columns
+    "block12_step8": (lambda: small_vortex_pair(seed=15)[:2],
+                      dict(win=12, step=8, levels=2, radius_coarse=4, radius_fine=2)),
 }
 
 
