@@ -729,6 +729,165 @@ __global__ __launch_bounds__(256) void k_sad_cells_fine(SadArgs g) {
 }
 
 // ---------------------------------------------------------------------------
+// The same cell-shared search with a column of three cells per lane: lane =
+// (parent, cell column), 21 parents per wave.  The lane streams the 24 A rows
+// and 24 + 2R B rows of its column once (A rows in a ring of 2R + 1), keeps
+// the SADs of its three cells, and forms its two children's sums as (cell +
+// the cell below, a register add) + the same pair of the right-hand column
+// (DPP lane + 1).  The parent's centre, the addressing and the winner search
+// are paid once per three cells instead of once per cell.
+// ---------------------------------------------------------------------------
+template <int R>
+__global__ __launch_bounds__(256) void k_sad_cols(SadArgs g) {
+  constexpr int G = 2 * R + 1, NGRP = (G + 3) / 4, REM = G - 4 * (NGRP - 1);
+  constexpr bool TAIL = REM <= 2;
+  constexpr int NQ = TAIL ? NGRP - 1 : NGRP;
+  constexpr int CWD = 2, RW = CWD + NGRP, PPW = 21;   // parents per wave
+  constexpr int NA = 24, NB = NA + G - 1;             // A and B rows of the column
+  static_assert(G <= 5, "one pass of shift rows");
+  const int lane = threadIdx.x & 63;
+  const WgIdx wg = xcd_order();
+  const int pair = wg.z;
+  if (slot_off(g.mask, pair)) return;
+  const int pnx = (g.nx + 1) / 2, pny = (g.ny + 1) / 2;
+  const int ntx = (pnx + PPW - 1) / PPW;
+  const int tile = wg.x * 4 + (threadIdx.x >> 6);
+  if (tile >= ntx * pny) return;   // a whole wave (no barriers below)
+  const int pa = tile / ntx, tx = tile - pa * ntx;
+  const int grp = min(lane / 3, PPW - 1), v = lane - 3 * (lane / 3);
+  const int pb = min(tx * PPW + grp, pnx - 1);
+  const int32_t* par = g.parent + (int64_t)pair * g.pstride;
+  int cx, cy;
+  parent_centre(g, par, min(pa, g.pny - 1), min(pb, g.pnx - 1), cx, cy);
+  // the column's cells 2pa .. 2pa + 2 (clamped cells past the last node are
+  // read but unused)
+  const int cj = min(2 * pb + v, g.nx);
+  const int y = min(2 * pa, g.ny - 1) * 8 - 4, x = cj * 8 - 4;
+  const int y0 = y + cy - R, xs = x + cx - R;
+  const int xa = xs & ~3, sh = xs & 3;
+  const unsigned pitch32 = (unsigned)g.pitch, spitch32 = (unsigned)g.spitch;
+  const bool ain = g.direct && y >= 0 && y + NA <= g.H && x >= 0 && x + 8 <= g.W;
+  const bool bin = g.direct && y0 >= 0 && y0 + NB <= g.H && xa >= 0 && xa + 4 * (RW + 1) <= g.W;
+  const uint8_t* Apad = g.A + (int64_t)pair * g.stride - ((int64_t)g.margin * g.pitch + g.margin);
+  const uint8_t* Bpad = g.B + (int64_t)pair * g.stride - ((int64_t)g.margin * g.pitch + g.margin);
+  const uint8_t* Asrc = g.srcA + (int64_t)pair * g.sstride;
+  const uint8_t* Bsrc = g.srcB + (int64_t)pair * g.sstride;
+  const unsigned pa32 = ain ? spitch32 : pitch32, pb32 = bin ? spitch32 : pitch32;
+  const int am = ain ? 0 : g.margin, bm = bin ? 0 : g.margin;
+  const unsigned aoff = __umul24((unsigned)(y + am), pa32) + (unsigned)(x + am);
+  const unsigned boff = __umul24((unsigned)(y0 + bm), pb32) + (unsigned)(xa + bm);
+  auto arow = [&](int r) {
+    const unsigned o = aoff + r * pa32;
+    return ain ? *reinterpret_cast<const Words<CWD>*>(Asrc + (size_t)o)
+               : *reinterpret_cast<const Words<CWD>*>(Apad + (size_t)o);
+  };
+  auto brow = [&](int rb) {
+    const unsigned o = boff + rb * pb32;
+    return bin ? *reinterpret_cast<const Words<RW + 1>*>(Bsrc + (size_t)o)
+               : *reinterpret_cast<const Words<RW + 1>*>(Bpad + (size_t)o);
+  };
+  unsigned long long acc[3][G][NQ > 0 ? NQ : 1];
+  uint32_t tacc[3][G][2];
+#pragma unroll
+  for (int u = 0; u < 3; ++u)
+#pragma unroll
+    for (int q = 0; q < G; ++q) {
+#pragma unroll
+      for (int m = 0; m < (NQ > 0 ? NQ : 1); ++m) acc[u][q][m] = 0ull;
+      tacc[u][q][0] = tacc[u][q][1] = 0u;
+    }
+  constexpr int PF = 4;   // B and A rows read PF rows ahead of their use
+  Words<RW + 1> bring[PF];
+  Words<CWD> aring[G + PF];
+#pragma unroll
+  for (int i = 0; i < PF; ++i) {
+    bring[i] = brow(i);
+    aring[i] = arow(i);
+  }
+#pragma unroll
+  for (int rb = 0; rb < NB; ++rb) {
+    // B row y0 + rb meets A row rb - q (cell (rb - q) / 8) for shift row q
+    const Words<RW + 1> wv = bring[rb % PF];
+    if (rb + PF < NB) bring[rb % PF] = brow(rb + PF);
+    if (rb + PF < NA) aring[(rb + PF) % (G + PF)] = arow(rb + PF);
+    uint32_t rw[RW];
+#pragma unroll
+    for (int i = 0; i < RW; ++i) rw[i] = __builtin_amdgcn_alignbyte(wv.w[i + 1], wv.w[i], sh);
+#pragma unroll
+    for (int q = 0; q < G; ++q) {
+      const int r = rb - q;
+      if (r < 0 || r >= NA) continue;
+      const int u = r / 8;
+      const Words<CWD> aw = aring[r % (G + PF)];
+#pragma unroll
+      for (int i = 0; i < CWD; ++i) {
+#pragma unroll
+        for (int m = 0; m < NQ; ++m) {
+          const unsigned long long src = ((unsigned long long)rw[i + m + 1] << 32) | rw[i + m];
+          acc[u][q][m] = __builtin_amdgcn_qsad_pk_u16_u8(src, aw.w[i], acc[u][q][m]);
+        }
+        if constexpr (TAIL) {
+          tacc[u][q][0] = __builtin_amdgcn_sad_u8(aw.w[i], rw[i + NQ], tacc[u][q][0]);
+          if constexpr (REM == 2)
+            tacc[u][q][1] = __builtin_amdgcn_sad_u8(aw.w[i], __builtin_amdgcn_alignbyte(rw[i + NQ + 1], rw[i + NQ], 1),
+                                                    tacc[u][q][1]);
+        }
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  // children (2pa + uc, 2pb + v) for uc = 0, 1 on lanes with v < 2:
+  // (cell uc + cell uc + 1) of this column + the same of the next column
+  auto pair_sum = [&](uint32_t val) {
+    return val + (uint32_t)__builtin_amdgcn_update_dpp(0, (int)val, 0x130, 0xF, 0xF, false);
+  };
+  uint32_t kx[G], ky[G];
+#pragma unroll
+  for (int k = 0; k < G; ++k) {
+    kx[k] = ((uint32_t)abs(cx - R + k) << 6) | (uint32_t)k;
+    ky[k] = ((uint32_t)abs(cy - R + k) << 6) | ((uint32_t)k << 3);
+  }
+  uint32_t best[2] = {~0u, ~0u};
+#pragma unroll
+  for (int uc = 0; uc < 2; ++uc) {
+#pragma unroll
+    for (int q = 0; q < G; ++q) {
+#pragma unroll
+      for (int m = 0; m < NQ; ++m) {
+        const unsigned long long t2 = acc[uc][q][m] + acc[uc + 1][q][m];   // fields stay below 2^15
+        const uint32_t lo = pair_sum((uint32_t)t2), hi = pair_sum((uint32_t)(t2 >> 32));
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+          const int c = 4 * m + f;
+          if (c >= G) continue;
+          const uint32_t sad = ((f < 2 ? lo : hi) >> (16 * (f & 1))) & 0xffffu;
+          best[uc] = min(best[uc], (sad << 15) | (kx[c] + ky[q]));
+        }
+      }
+      if constexpr (TAIL) {
+#pragma unroll
+        for (int f = 0; f < REM; ++f) {
+          const int c = 4 * NQ + f;
+          best[uc] = min(best[uc], (pair_sum(tacc[uc][q][f] + tacc[uc + 1][q][f]) << 15) | (kx[c] + ky[q]));
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+  const int b = 2 * pb + v;
+  const bool col = lane < 3 * PPW && v < 2 && tx * PPW + lane / 3 < pnx && b < g.nx;
+  int32_t* out = g.out + (int64_t)pair * g.ostride;
+#pragma unroll
+  for (int uc = 0; uc < 2; ++uc) {
+    const int a = 2 * pa + uc;
+    if (col && a < g.ny) {
+      out[a * g.nx + b] = cx - R + (int)(best[uc] & 7u);
+      out[g.nx * g.ny + a * g.nx + b] = cy - R + (int)((best[uc] >> 3) & 7u);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // SAD block search, one node per lane, A rows streamed (any element size,
 // small R): the lane keeps the last G = 2R+1 rows of its A block in a ring of
 // registers and streams the rows of B once each; a B row, realigned to the
@@ -1342,8 +1501,12 @@ hipError_t launch_sad_level(const Plan& P, int l, const void* A, const void* B, 
       (size_t)v.rows * v.pitch < (1u << 31) && v.pitch < (1 << 24)) {
     const int tiles = (((v.nx + 1) / 2 + 6) / 7) * ((v.ny + 1) / 2);
     dim3 grid((tiles + 3) / 4, 1, n);
-    if (g.R == 2) hipLaunchKernelGGL((k_sad_cells_fine<2>), grid, dim3(256), 0, s, g);
-    else hipLaunchKernelGGL((k_sad_cells_fine<1>), grid, dim3(256), 0, s, g);
+    if (g.R == 2) {
+      const int tiles3 = (((v.nx + 1) / 2 + 20) / 21) * ((v.ny + 1) / 2);
+      hipLaunchKernelGGL((k_sad_cols<2>), dim3((tiles3 + 3) / 4, 1, n), dim3(256), 0, s, g);
+    } else {
+      hipLaunchKernelGGL((k_sad_cells_fine<1>), grid, dim3(256), 0, s, g);
+    }
     return hipGetLastError();
   }
   const bool off31 = (size_t)v.rows * v.pitch < (1u << 31) && v.pitch < (1 << 24);

@@ -235,6 +235,20 @@ def test_level0_in_place_reads_stay_in_written_bytes(L, kw):
                     for cx in (cs if cj in (0, 1, v["nx"] - 1, v["nx"]) else (-cand, 0, cand)):
                         xs = x + cx - R
                         check(y + cy - R, 8 + 2 * R, xs & ~3, 4 * (rwc + 1))
+    if step == 8 and blk == 16 and len(lv) > 1 and R == 2:
+        # the column form: three stacked cells per lane (24 A rows, 24 + 2R
+        # B rows) from cell row 2 pa
+        rwc = 2 + (2 * R + 4) // 4
+        for pa in range((v["ny"] + 1) // 2):
+            y = 2 * pa * 8 - 4
+            for cj in range(v["nx"] + 1):
+                check(y, 24, cj * 8 - 4, 8)
+            for cy in cs:
+                for cj in range(v["nx"] + 1):
+                    x = cj * 8 - 4
+                    for cx in (cs if cj in (0, 1, v["nx"] - 1, v["nx"]) else (-cand, 0, cand)):
+                        xs = x + cx - R
+                        check(y + cy - R, 24 + 2 * R, xs & ~3, 4 * (rwc + 1))
     for a in range(v["ny"]):
         oy = a * step + off
         for b in range(v["nx"]):
