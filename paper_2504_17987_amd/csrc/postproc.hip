@@ -21,7 +21,7 @@ constexpr uint8_t kInvalid = PIV_F_FLAT | PIV_F_BORDER;
 // ring (the replacement of a tile vector needs the outcome of its
 // neighbours), and writes the validated tile to a field other than its
 // source, so that no workgroup reads what another one writes.
-constexpr int TW = 32, TH = 16;             // tile; one thread per vector
+constexpr int TW = 64, TH = 16;             // tile; one thread per vector
 constexpr int NT = TW * TH;
 constexpr int E1W = TW + 2, E1H = TH + 2;   // detection region: tile + 1 ring
 constexpr int E2W = TW + 4, E2H = TH + 4;   // staged field: tile + 2 rings
