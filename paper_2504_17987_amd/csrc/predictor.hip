@@ -580,162 +580,16 @@ __global__ __launch_bounds__(256) void k_sad_cells(SadArgs g) {
 // Finer-level SAD search with cell-shared sums (u8, block = 2 step, step 8,
 // R <= 2).  The four children of a parent search the same shifts (around
 // twice the parent's result), and their 16x16 blocks are the 2x2 windows of
-// a 3x3 group of 8x8 cells: 9 cell SADs per shift instead of 16.  Lane =
-// cell of a parent's group (7 parents along a row per wave); the lane keeps
-// its A cell in registers and streams the 8 + 2R rows of B once, four shift
-// columns per quad SAD.  A child's sums: its cell + the right-hand cell (DPP
-// lane + 1) + the pair below (lane permute, lane + 3).  Level 0 reads in
-// place as in k_sad_lane.  Winner: the least 31-bit key as in k_sad_lane.
-// ---------------------------------------------------------------------------
-template <int R>
-__global__ __launch_bounds__(256) void k_sad_cells_fine(SadArgs g) {
-  constexpr int G = 2 * R + 1, NGRP = (G + 3) / 4, REM = G - 4 * (NGRP - 1);
-  constexpr bool TAIL = REM <= 2;
-  constexpr int NQ = TAIL ? NGRP - 1 : NGRP;
-  constexpr int CWD = 2, RW = CWD + NGRP, PPW = 7;   // parents per wave
-  static_assert(G <= 5, "one pass of shift rows");
-  const int lane = threadIdx.x & 63;
-  // consecutive tiles (neighbouring parents, overlapping B rows) on one XCD
-  const WgIdx wg = xcd_order();
-  const int pair = wg.z;
-  if (slot_off(g.mask, pair)) return;
-  const int pnx = (g.nx + 1) / 2, pny = (g.ny + 1) / 2;
-  const int ntx = (pnx + PPW - 1) / PPW;
-  const int tile = wg.x * 4 + (threadIdx.x >> 6);
-  if (tile >= ntx * pny) return;   // a whole wave (no barriers below)
-  const int pa = tile / ntx, grp = min(lane / 9, PPW - 1);
-  const int pb = min((tile - pa * ntx) * PPW + grp, pnx - 1);
-  const int u = (lane - 9 * (lane / 9)) / 3, v = (lane - 9 * (lane / 9)) % 3;
-  // candidate centre: twice the parent's result (through its median)
-  const int32_t* par = g.parent + (int64_t)pair * g.pstride;
-  const int ppa = min(pa, g.pny - 1), ppb = min(pb, g.pnx - 1);
-  int cx, cy;
-  parent_centre(g, par, ppa, ppb, cx, cy);
-  // cells past the last node read the last needed cell (results unused)
-  const int ci = min(2 * pa + u, g.ny), cj = min(2 * pb + v, g.nx);
-  const int y = ci * 8 - 4, x = cj * 8 - 4;
-  const int y0 = y + cy - R, xs = x + cx - R;
-  const int xa = xs & ~3, sh = xs & 3;
-  const unsigned pitch32 = (unsigned)g.pitch, spitch32 = (unsigned)g.spitch;
-  const bool ain = g.direct && y >= 0 && y + 8 <= g.H && x >= 0 && x + 8 <= g.W;
-  const bool bin = g.direct && y0 >= 0 && y0 + 8 + 2 * R <= g.H && xa >= 0 && xa + 4 * (RW + 1) <= g.W;
-  const uint8_t* Apad = g.A + (int64_t)pair * g.stride - ((int64_t)g.margin * g.pitch + g.margin);
-  const uint8_t* Bpad = g.B + (int64_t)pair * g.stride - ((int64_t)g.margin * g.pitch + g.margin);
-  const uint8_t* Asrc = g.srcA + (int64_t)pair * g.sstride;
-  const uint8_t* Bsrc = g.srcB + (int64_t)pair * g.sstride;
-  const unsigned pa32 = ain ? spitch32 : pitch32, pb32 = bin ? spitch32 : pitch32;
-  const int am = ain ? 0 : g.margin, bm = bin ? 0 : g.margin;
-  const unsigned aoff = __umul24((unsigned)(y + am), pa32) + (unsigned)(x + am);
-  const unsigned boff = __umul24((unsigned)(y0 + bm), pb32) + (unsigned)(xa + bm);
-  uint32_t aw[8][CWD];
-#pragma unroll
-  for (int r = 0; r < 8; ++r) {
-    const unsigned o = aoff + r * pa32;
-    const Words<CWD> w = ain ? *reinterpret_cast<const Words<CWD>*>(Asrc + (size_t)o)
-                             : *reinterpret_cast<const Words<CWD>*>(Apad + (size_t)o);
-    aw[r][0] = w.w[0];
-    aw[r][1] = w.w[1];
-  }
-  unsigned long long acc[G][NQ > 0 ? NQ : 1];
-  uint32_t tacc[G][2];
-#pragma unroll
-  for (int k = 0; k < G; ++k) {
-#pragma unroll
-    for (int m = 0; m < (NQ > 0 ? NQ : 1); ++m) acc[k][m] = 0ull;
-    tacc[k][0] = tacc[k][1] = 0u;
-  }
-  // B rows y0 .. y0 + 7 + 2R, read PF rows ahead of their use
-  constexpr int NROWS = 8 + G - 1, PF = 5;
-  auto brow = [&](int rb) {
-    const unsigned o = boff + rb * pb32;
-    return bin ? *reinterpret_cast<const Words<RW + 1>*>(Bsrc + (size_t)o)
-               : *reinterpret_cast<const Words<RW + 1>*>(Bpad + (size_t)o);
-  };
-  Words<RW + 1> ring[PF];
-#pragma unroll
-  for (int i = 0; i < PF; ++i) ring[i] = brow(i);
-#pragma unroll
-  for (int rb = 0; rb < NROWS; ++rb) {
-    // B row y0 + rb meets A row rb - q for shift row q
-    const Words<RW + 1> wv = ring[rb % PF];
-    if (rb + PF < NROWS) ring[rb % PF] = brow(rb + PF);
-    uint32_t rw[RW];
-#pragma unroll
-    for (int i = 0; i < RW; ++i) rw[i] = __builtin_amdgcn_alignbyte(wv.w[i + 1], wv.w[i], sh);
-#pragma unroll
-    for (int q = 0; q < G; ++q) {
-      const int r = rb - q;
-      if (r < 0 || r >= 8) continue;
-#pragma unroll
-      for (int i = 0; i < CWD; ++i) {
-#pragma unroll
-        for (int m = 0; m < NQ; ++m) {
-          const unsigned long long src = ((unsigned long long)rw[i + m + 1] << 32) | rw[i + m];
-          acc[q][m] = __builtin_amdgcn_qsad_pk_u16_u8(src, aw[r][i], acc[q][m]);
-        }
-        if constexpr (TAIL) {
-          tacc[q][0] = __builtin_amdgcn_sad_u8(aw[r][i], rw[i + NQ], tacc[q][0]);
-          if constexpr (REM == 2)
-            tacc[q][1] = __builtin_amdgcn_sad_u8(aw[r][i], __builtin_amdgcn_alignbyte(rw[i + NQ + 1], rw[i + NQ], 1),
-                                                 tacc[q][1]);
-        }
-      }
-    }
-    __builtin_amdgcn_sched_barrier(0);
-  }
-  // block sums of the child whose top-left cell is this lane's
-  auto quad = [&](uint32_t val) {
-    const uint32_t h = val + (uint32_t)__builtin_amdgcn_update_dpp(0, (int)val, 0x130, 0xF, 0xF, false);
-    return h + (uint32_t)__builtin_amdgcn_ds_bpermute((lane + 3) << 2, (int)h);
-  };
-  // key = SAD << 15 | (|dx| + |dy|) << 6 | q << 3 | k
-  uint32_t kx[G], ky[G];
-#pragma unroll
-  for (int k = 0; k < G; ++k) {
-    kx[k] = ((uint32_t)abs(cx - R + k) << 6) | (uint32_t)k;
-    ky[k] = ((uint32_t)abs(cy - R + k) << 6) | ((uint32_t)k << 3);
-  }
-  uint32_t best = ~0u;
-#pragma unroll
-  for (int q = 0; q < G; ++q) {
-#pragma unroll
-    for (int m = 0; m < NQ; ++m) {
-      const uint32_t lo = quad((uint32_t)acc[q][m]), hi = quad((uint32_t)(acc[q][m] >> 32));
-#pragma unroll
-      for (int f = 0; f < 4; ++f) {
-        const int c = 4 * m + f;
-        if (c >= G) continue;
-        const uint32_t sad = ((f < 2 ? lo : hi) >> (16 * (f & 1))) & 0xffffu;
-        best = min(best, (sad << 15) | (kx[c] + ky[q]));
-      }
-    }
-    if constexpr (TAIL) {
-#pragma unroll
-      for (int f = 0; f < REM; ++f) {
-        const int c = 4 * NQ + f;
-        best = min(best, (quad(tacc[q][f]) << 15) | (kx[c] + ky[q]));
-      }
-    }
-    __builtin_amdgcn_sched_barrier(0);
-  }
-  const int a = 2 * pa + u, b = 2 * pb + v;
-  const bool child = lane < 9 * PPW && u < 2 && v < 2 && (tile - pa * ntx) * PPW + lane / 9 < pnx &&
-                     a < g.ny && b < g.nx;
-  if (child) {
-    int32_t* out = g.out + (int64_t)pair * g.ostride;
-    out[a * g.nx + b] = cx - R + (int)(best & 7u);
-    out[g.nx * g.ny + a * g.nx + b] = cy - R + (int)((best >> 3) & 7u);
-  }
-}
-
-// ---------------------------------------------------------------------------
-// The same cell-shared search with a column of three cells per lane: lane =
-// (parent, cell column), 21 parents per wave.  The lane streams the 24 A rows
-// and 24 + 2R B rows of its column once (A rows in a ring of 2R + 1), keeps
-// the SADs of its three cells, and forms its two children's sums as (cell +
-// the cell below, a register add) + the same pair of the right-hand column
-// (DPP lane + 1).  The parent's centre, the addressing and the winner search
-// are paid once per three cells instead of once per cell.
+// a 3x3 group of 8x8 cells: 9 cell SADs per shift instead of 16, four shift
+// columns per quad SAD (16-bit fields: a cell is at most 64 x 255, four
+// cells stay below 2^16).  Lane = (parent, cell column), 21 parents per
+// wave: the lane streams the 24 A rows and 24 + 2R B rows of its column once
+// (A rows in a ring, both read ahead), keeps the SADs of its three cells, and
+// forms its two children's sums as (cell + the cell below, a register add) +
+// the same pair of the right-hand column (DPP lane + 1).  The parent's
+// centre, the addressing and the winner search are paid once per three
+// cells.  Level 0 reads in place as in k_sad_lane.  Winner: the least 31-bit
+// key as in k_sad_lane.
 // ---------------------------------------------------------------------------
 template <int R>
 __global__ __launch_bounds__(256) void k_sad_cols(SadArgs g) {
@@ -1499,14 +1353,10 @@ hipError_t launch_sad_level(const Plan& P, int l, const void* A, const void* B, 
   // finer levels, u8, 16x16 blocks at step 8, R <= 2: cell-shared sums per parent
   if (g.parent && P.es == 1 && P.p.step == 8 && P.block == 16 && g.R >= 1 && g.R <= 2 &&
       (size_t)v.rows * v.pitch < (1u << 31) && v.pitch < (1 << 24)) {
-    const int tiles = (((v.nx + 1) / 2 + 6) / 7) * ((v.ny + 1) / 2);
-    dim3 grid((tiles + 3) / 4, 1, n);
-    if (g.R == 2) {
-      const int tiles3 = (((v.nx + 1) / 2 + 20) / 21) * ((v.ny + 1) / 2);
-      hipLaunchKernelGGL((k_sad_cols<2>), dim3((tiles3 + 3) / 4, 1, n), dim3(256), 0, s, g);
-    } else {
-      hipLaunchKernelGGL((k_sad_cells_fine<1>), grid, dim3(256), 0, s, g);
-    }
+    const int tiles3 = (((v.nx + 1) / 2 + 20) / 21) * ((v.ny + 1) / 2);
+    const dim3 grid3((tiles3 + 3) / 4, 1, n);
+    if (g.R == 2) hipLaunchKernelGGL((k_sad_cols<2>), grid3, dim3(256), 0, s, g);
+    else hipLaunchKernelGGL((k_sad_cols<1>), grid3, dim3(256), 0, s, g);
     return hipGetLastError();
   }
   const bool off31 = (size_t)v.rows * v.pitch < (1u << 31) && v.pitch < (1 << 24);

@@ -221,23 +221,8 @@ def test_level0_in_place_reads_stay_in_written_bytes(L, kw):
 
     cs = range(-cand, cand + 1, 2)
     if step == 8 and blk == 16 and len(lv) > 1:
-        # the cell-shared form: 8x8 A cells at the cell grid, B spans of the
-        # cell plus 2R rows and RW + 1 = 2 + ceil((2R+1)/4) + 1 words
-        rwc = 2 + (2 * R + 4) // 4
-        for ci in range(v["ny"] + 1):
-            y = ci * 8 - 4
-            for cj in range(v["nx"] + 1):
-                x = cj * 8 - 4
-                check(y, 8, x, 8)
-            for cy in cs:
-                for cj in range(v["nx"] + 1):
-                    x = cj * 8 - 4
-                    for cx in (cs if cj in (0, 1, v["nx"] - 1, v["nx"]) else (-cand, 0, cand)):
-                        xs = x + cx - R
-                        check(y + cy - R, 8 + 2 * R, xs & ~3, 4 * (rwc + 1))
-    if step == 8 and blk == 16 and len(lv) > 1 and R == 2:
-        # the column form: three stacked cells per lane (24 A rows, 24 + 2R
-        # B rows) from cell row 2 pa
+        # the cell-shared form: a column of three stacked 8x8 cells per lane
+        # (24 A rows, 24 + 2R B rows) from cell row 2 pa
         rwc = 2 + (2 * R + 4) // 4
         for pa in range((v["ny"] + 1) // 2):
             y = 2 * pa * 8 - 4
