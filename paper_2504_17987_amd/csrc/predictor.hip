@@ -214,7 +214,7 @@ struct SadArgs {
   const uint8_t* mask;
   int npw;                // nodes per workgroup (k_sad)
   int margin;             // level margin (px): A - margin (pitch + bytes per px) is padded row 0
-  // level 0 read in place (k_sad_lane): an A block or B span wholly inside
+  // level 0 read in place (k_sad_lane, k_sad_cols): an A block or B span wholly inside
   // the image reads the caller's frames (pair 0 at srcA/srcB); one that
   // crosses the image edge reads the padded copy, of which only a frame of
   // kFrame px along the edges is written
@@ -227,8 +227,8 @@ struct SadArgs {
 
 // Depth of the written frame of the level-0 copy when level 0 is read in
 // place: a span that crosses the image edge has all of its in-image pixels
-// within its own extent of that edge (at most 2R + 16 rows and 4 (RW + 1) <= 28
-// columns for the one-node-per-lane kernel).
+// within its own extent of that edge (at most 2R + 24 <= 28 rows and 4 (RW + 1)
+// <= 28 columns for the one-node-per-lane and the cell-column kernels).
 constexpr int kFrame = 32;
 
 template <int ES>
@@ -1225,9 +1225,9 @@ bool sad_supported(int block_words) {
          block_words == 14 || block_words == 16;
 }
 
-// Level 0 is searched by the one-node-per-lane kernel reading the caller's
-// frames in place (see SadArgs): u8, radius <= 2, 8-16 px blocks, and
-// 32-bit offsets into both the padded copy and one caller frame.
+// Level 0 is searched reading the caller's frames in place (see SadArgs) by
+// the one-node-per-lane or the cell-column kernel: u8, radius <= 2, 8-16 px
+// blocks, and 32-bit offsets into both the padded copy and one caller frame.
 static bool level0_in_place(const Plan& P, int64_t pitch) {
   const Level& v = P.lv[0];
   const int NW = P.block * P.es / 4;
