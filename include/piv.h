@@ -114,8 +114,9 @@ piv_status piv_plan(const piv_params* p, piv_plan_t* out);
 piv_status piv_plan_grid(piv_plan_t plan, int32_t* nx, int32_t* ny);
 
 /* Bytes of device workspace needed for `batch` pairs: predictor pyramids,
- * per-level integer fields and the validation mask.  Exact, so that callers
- * can admit work against an HBM budget. */
+ * per-level integer fields and one float field [2][ny][nx] (the input of
+ * validation).  Exact, so that callers can admit work against an HBM
+ * budget. */
 size_t piv_plan_workspace_bytes(piv_plan_t plan, int32_t batch);
 
 /* Bind caller-owned device workspace (e.g. a torch tensor) to the plan.
@@ -175,8 +176,11 @@ piv_status piv_vorticity(piv_plan_t plan, const float* disp, float* omega, int32
                          hipStream_t stream);
 
 /* The whole plain path in one call: predict, validate the predictor,
- * correct, validate, vorticity.  pred (scratch for the predictor, also an
- * output), disp, flags and omega are required; peak is nullable. */
+ * correct, validate, vorticity, with the same results as those calls made
+ * one by one.  pred (scratch for the predictor, also an output), disp, flags
+ * and omega are required; peak is nullable.  Needs a bound workspace.  With
+ * u8 frames and a level-0 search radius <= 2, level 0 of the predictor reads
+ * A and B in place (only a 32 px frame along the edges is copied). */
 piv_status piv_run(piv_plan_t plan, const void* A, const void* B, int64_t pitch_bytes, int32_t n,
                    float* pred, float* disp, float* peak, uint8_t* flags, float* omega,
                    hipStream_t stream);
