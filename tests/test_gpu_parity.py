@@ -386,6 +386,28 @@ def test_batch_invariance_and_determinism():
             assert torch.equal(one[k][0], full[k][i]), (i, k)
 
 
+def test_padded_rows_equal_packed_rows():
+    """Frames whose rows are longer than the image (pitch = width + 68 bytes)
+    give the same bits as packed frames: the pyramid copy, the in-place
+    level-0 search and the correlation all address rows by the pitch."""
+    say("[run] padded rows")
+    pairs = [small_vortex_pair(seed=s)[:2] for s in (51, 52)]
+    A = np.stack([p[0] for p in pairs])
+    B = np.stack([p[1] for p in pairs])
+    n, H, W = A.shape
+    P = api().Plan(W, H, max_batch=2, win=16, step=8)
+    ref = P.run(dev(A), dev(B))
+    Aw = torch.zeros((n, H, W + 68), dtype=torch.uint8, device="cuda")
+    Bw = torch.zeros_like(Aw)
+    Aw[:, :, :W] = dev(A)
+    Bw[:, :, :W] = dev(B)
+    Aw[:, :, W:] = 255   # bytes past the image row must not be read as image
+    Bw[:, :, W:] = 255
+    out = P.run(Aw[:, :, :W], Bw[:, :, :W])
+    for k in ("pred", "disp", "flags", "omega"):
+        assert torch.equal(out[k], ref[k]), k
+
+
 def test_slot_mask_skips_pairs():
     say("[run] slot mask")
     pairs = [small_vortex_pair(seed=s)[:2] for s in (31, 32)]
