@@ -81,6 +81,20 @@ def test_predict_u16_bitexact():
     assert np.array_equal(pred, ref.astype(np.float32))
 
 
+@pytest.mark.parametrize("W,H,step,win", [(200, 136, 8, 16), (204, 204, 12, 24)])
+def test_predict_u16_ragged_bitexact(W, H, step, win):
+    """u16 frames with ragged pyramid edges (204 px rows are not a whole
+    number of 16-byte chunks; 204 rows give odd level-2 heights): levels 1
+    and 2 come from one pass over the frames."""
+    say(f"[predict] u16 ragged {W}x{H} step {step}")
+    A, B, _ = synth.cfg3_pair(1, W=W, H=H)
+    P = api().Plan(W, H, dtype="u16", win=win, step=step, levels=3, radius_coarse=5, radius_fine=2)
+    pred = P.predict(dev(A[None].view(np.int16)).view(torch.uint16),
+                     dev(B[None].view(np.int16)).view(torch.uint16)).cpu().numpy()[0]
+    ref = oracle.predict(A, B, step, win, 3, 5, 2)
+    assert np.array_equal(pred, ref.astype(np.float32))
+
+
 def test_predict_equal_frames_is_zero():
     say("[predict] A = B")
     A, _, _ = small_vortex_pair()
