@@ -179,8 +179,9 @@ piv_status piv_vorticity(piv_plan_t plan, const float* disp, float* omega, int32
  * correct, validate, vorticity, with the same results as those calls made
  * one by one.  pred (scratch for the predictor, also an output), disp, flags
  * and omega are required; peak is nullable.  Needs a bound workspace.  With
- * u8 frames and a level-0 search radius <= 2, level 0 of the predictor reads
- * A and B in place (only a 32 px frame along the edges is copied). */
+ * a level-0 search radius <= 2 (u8, or u16 with 12-24 px blocks), level 0 of
+ * the predictor (here and in piv_predict) reads A and B in place (only a 32 px frame along the edges
+ * is copied). */
 piv_status piv_run(piv_plan_t plan, const void* A, const void* B, int64_t pitch_bytes, int32_t n,
                    float* pred, float* disp, float* peak, uint8_t* flags, float* omega,
                    hipStream_t stream);

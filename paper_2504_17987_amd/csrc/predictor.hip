@@ -214,7 +214,7 @@ struct SadArgs {
   const uint8_t* mask;
   int npw;                // nodes per workgroup (k_sad)
   int margin;             // level margin (px): A - margin (pitch + bytes per px) is padded row 0
-  // level 0 read in place (k_sad_lane, k_sad_cols): an A block or B span wholly inside
+  // level 0 read in place (k_sad_lane, k_sad_cols, k_sad_stream): an A block or B span wholly inside
   // the image reads the caller's frames (pair 0 at srcA/srcB); one that
   // crosses the image edge reads the padded copy, of which only a frame of
   // kFrame px along the edges is written
@@ -227,8 +227,8 @@ struct SadArgs {
 
 // Depth of the written frame of the level-0 copy when level 0 is read in
 // place: a span that crosses the image edge has all of its in-image pixels
-// within its own extent of that edge (at most 2R + 24 <= 28 rows and 4 (RW + 1)
-// <= 28 columns for the one-node-per-lane and the cell-column kernels).
+// within its own extent of that edge (at most 2R + 24 <= 28 rows and 28
+// columns for the u8 kernels, 30 columns for the streamed u16 kernel).
 constexpr int kFrame = 32;
 
 template <int ES>
@@ -762,8 +762,6 @@ __global__ __launch_bounds__(256) void k_sad_stream(SadArgs g) {
   const int a = node / g.nx, b = node - a * g.nx;
   const int off = (g.step - BLK) / 2;
   const int oy = a * g.step + off, ox = b * g.step + off;
-  const uint8_t* Ab = g.A + (int64_t)pair * g.stride;
-  const uint8_t* Bb = g.B + (int64_t)pair * g.stride;
   int cx = 0, cy = 0;
   if (g.parent) {
     const int32_t* par = g.parent + (int64_t)pair * g.pstride;
@@ -779,6 +777,14 @@ __global__ __launch_bounds__(256) void k_sad_stream(SadArgs g) {
   const int y0 = oy + cy - R;
   const int xs = (ox + cx - R) * ES, xa = xs & ~3, sh = xs & 3;
   const int axs = ox * ES, axa = axs & ~3, ash = axs & 3;
+  // level 0 read in place: a span wholly inside the image reads the caller's
+  // frame (the same coordinates, its own pitch), others the padded copy
+  const int rowbytes = g.W * ES;
+  const bool ain = g.direct && oy >= 0 && oy + BLK <= g.H && axa >= 0 && axa + 4 * (NW + 1) <= rowbytes;
+  const bool bin = g.direct && y0 >= 0 && y0 + BLK + 2 * R <= g.H && xa >= 0 && xa + 4 * (RWS + 1) <= rowbytes;
+  const uint8_t* Ab = ain ? g.srcA + (int64_t)pair * g.sstride : g.A + (int64_t)pair * g.stride;
+  const uint8_t* Bb = bin ? g.srcB + (int64_t)pair * g.sstride : g.B + (int64_t)pair * g.stride;
+  const int64_t apitch = ain ? g.spitch : g.pitch, bpitch = bin ? g.spitch : g.pitch;
   uint32_t ring[G][NW];   // A row ar sits in ring[ar % G]
   for (int rb0 = 0; rb0 < BLK + 2 * R; rb0 += G) {
 #pragma unroll
@@ -786,14 +792,14 @@ __global__ __launch_bounds__(256) void k_sad_stream(SadArgs g) {
       const int rb = rb0 + u;   // rb % G == u
       if (rb < BLK + 2 * R) {
         if (rb < BLK) {
-          const uint32_t* row = reinterpret_cast<const uint32_t*>(Ab + (int64_t)(oy + rb) * g.pitch + axa);
+          const uint32_t* row = reinterpret_cast<const uint32_t*>(Ab + (int64_t)(oy + rb) * apitch + axa);
           uint32_t w[NW + 1];
 #pragma unroll
           for (int i = 0; i <= NW; ++i) w[i] = row[i];
 #pragma unroll
           for (int i = 0; i < NW; ++i) ring[u][i] = __builtin_amdgcn_alignbyte(w[i + 1], w[i], ash);
         }
-        const uint32_t* row = reinterpret_cast<const uint32_t*>(Bb + (int64_t)(y0 + rb) * g.pitch + xa);
+        const uint32_t* row = reinterpret_cast<const uint32_t*>(Bb + (int64_t)(y0 + rb) * bpitch + xa);
         uint32_t w[RWS + 1];
 #pragma unroll
         for (int i = 0; i <= RWS; ++i) w[i] = row[i];
@@ -1226,11 +1232,14 @@ bool sad_supported(int block_words) {
 }
 
 // Level 0 is searched reading the caller's frames in place (see SadArgs) by
-// the one-node-per-lane or the cell-column kernel: u8, radius <= 2, 8-16 px
-// blocks, and 32-bit offsets into both the padded copy and one caller frame.
+// the one-node-per-lane or the cell-column kernel (u8, radius <= 2, 8-16 px
+// blocks, 32-bit offsets into both the padded copy and one caller frame) or
+// by the streamed u16 kernel (radius 1-2, 12-24 px blocks).
 static bool level0_in_place(const Plan& P, int64_t pitch) {
   const Level& v = P.lv[0];
   const int NW = P.block * P.es / 4;
+  if (P.es == 2)   // the streamed u16 kernel (64-bit row addresses)
+    return v.R >= 1 && v.R <= 2 && (NW == 6 || NW == 8 || NW == 12);
   const bool off31 = (size_t)v.rows * v.pitch < (1u << 31) && v.pitch < (1 << 24);
   return P.es == 1 && v.R <= 2 && (NW == 2 || NW == 3 || NW == 4) && off31 && pitch < (1 << 24) &&
          (int64_t)P.p.height * pitch < (int64_t(1) << 31);

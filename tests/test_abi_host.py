@@ -181,19 +181,22 @@ FRAME = 32   # px of the level-0 copy written along each edge when level 0 is re
 
 @pytest.mark.parametrize("kw", [dict(), dict(width=200, height=136, levels=3, radius_coarse=5),
                                 dict(width=204, height=138, win=12, step=6, levels=3, radius_coarse=5),
-                                dict(width=256, height=192, levels=2, radius_coarse=4, radius_fine=1)])
+                                dict(width=256, height=192, levels=2, radius_coarse=4, radius_fine=1),
+                                dict(width=384, height=216, dtype=2, bit_depth=12, win=24, step=12, levels=3),
+                                dict(width=200, height=136, dtype=2, bit_depth=12, levels=3, radius_coarse=5)])
 def test_level0_in_place_reads_stay_in_written_bytes(L, kw):
-    """When level 0 is searched in place (u8, one node per lane), an A block
-    or B span wholly inside the image reads the caller's frame and any other
-    reads the padded copy, of which only FRAME px along the edges (plus the
-    zero margins) are written.  For every node and every candidate centre the
-    level can see, a padded read must touch only margin or frame bytes."""
+    """When level 0 is searched in place (u8 one node per lane or cell
+    columns, u16 streamed), an A block or B span wholly inside the image
+    reads the caller's frame and any other reads the padded copy, of which
+    only FRAME px along the edges (plus the zero margins) are written.  For
+    every node and every candidate centre the level can see, a padded read
+    must touch only margin or frame bytes (columns in bytes below)."""
     import numpy as np
     lv = _levels(L, **kw)
     v = lv[0]
     es, step, blk, R, W, H = v["es"], v["step"], v["block"], v["R"], v["W"], v["H"]
     NW = blk * es // 4
-    assert es == 1 and R <= 2 and NW in (2, 3, 4)
+    assert (es == 1 and R <= 2 and NW in (2, 3, 4)) or (es == 2 and 1 <= R <= 2 and NW in (6, 8, 12))
     maxd = 0
     for u in lv[:0:-1]:
         maxd = (0 if maxd == 0 and u is lv[-1] else 2 * maxd) + u["R"]
@@ -201,25 +204,41 @@ def test_level0_in_place_reads_stay_in_written_bytes(L, kw):
     RW = NW + (2 * R + 3) // 4 + 1
     off = (step - blk) // 2
     aal = step % 4 == 0 and off % 4 == 0
-    written_col = np.zeros(W, bool)
-    for q in range((W + 15) // 16):
-        if 16 * q < FRAME or 16 * q + 16 > W - FRAME:
+    WB = W * es   # row bytes
+    written_col = np.zeros(WB, bool)
+    for q in range((WB + 15) // 16):
+        if 16 * q < FRAME * es or 16 * q + 16 > (W - FRAME) * es:
             written_col[16 * q:16 * q + 16] = True
     written_row = np.zeros(H, bool)
     written_row[:FRAME] = True
     written_row[max(H - FRAME, 0):] = True
 
     def check(r0, nr, c0, nc):
-        inside = r0 >= 0 and r0 + nr <= H and c0 >= 0 and c0 + nc <= W
+        inside = r0 >= 0 and r0 + nr <= H and c0 >= 0 and c0 + nc <= WB
         if inside:
             return
         rows = np.arange(max(r0, 0), min(r0 + nr, H))
-        cols = np.arange(max(c0, 0), min(c0 + nc, W))
+        cols = np.arange(max(c0, 0), min(c0 + nc, WB))
         if len(rows) and len(cols):
             ok = written_row[rows][:, None] | written_col[cols][None, :]
             assert ok.all(), (r0, nr, c0, nc)
 
     cs = range(-cand, cand + 1, 2)
+    if es == 2:
+        # the streamed u16 kernel: A rows from the floor word of the block,
+        # NW + 1 words; B rows from the floor word of the leftmost shift,
+        # NW + ceil(2R es / 4) + 1 words
+        rws = NW + (2 * R * es + 3) // 4
+        for a in range(v["ny"]):
+            oy = a * step + off
+            for b in range(v["nx"]):
+                check(oy, blk, ((b * step + off) * es) & ~3, 4 * (NW + 1))
+            for cy in cs:
+                for b in range(v["nx"]):
+                    for cx in (cs if b in (0, 1, v["nx"] - 2, v["nx"] - 1) else (-cand, 0, cand)):
+                        xs = (b * step + off + cx - R) * es
+                        check(oy + cy - R, blk + 2 * R, xs & ~3, 4 * (rws + 1))
+        return
     if step == 8 and blk == 16 and len(lv) > 1:
         # the cell-shared form: a column of three stacked 8x8 cells per lane
         # (24 A rows, 24 + 2R B rows) from cell row 2 pa
