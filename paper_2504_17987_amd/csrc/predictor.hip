@@ -577,6 +577,96 @@ __global__ __launch_bounds__(256) void k_sad_cells(SadArgs g) {
 }
 
 // ---------------------------------------------------------------------------
+// Coarsest-level SAD search with cell-shared sums for u16 frames (block =
+// 2 step, step 12): as k_sad_cells (every node searches the same shifts, a
+// block is four 12x12 cells it shares with its neighbours, block sums by DPP
+// and lane permute), with v_sad_u16 on realigned words (an odd shift column
+// is a 2-byte realignment).  The lane streams its cell's A rows through a
+// ring and the B rows once per pass of DYG shift rows.
+// ---------------------------------------------------------------------------
+template <int R, int DYG>
+__global__ __launch_bounds__(256) void k_sad_cells16(SadArgs g) {
+  constexpr int G = 2 * R + 1, CWD = 6, RW = CWD + R;   // cell words, realigned B words
+  constexpr int CW = 9, CH = 7, NPASS = (G + DYG - 1) / DYG;
+  const int lane = threadIdx.x & 63;
+  const int pair = blockIdx.z;
+  if (slot_off(g.mask, pair)) return;
+  const int ntx = (g.nx + CW - 2) / (CW - 1), nty = (g.ny + CH - 2) / (CH - 1);
+  const int tile = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (tile >= ntx * nty) return;   // a whole wave (no barriers below)
+  const int ty = tile / ntx, tx = tile - ty * ntx;
+  const int lr = lane / CW, lc = lane - lr * CW;
+  // cells beyond the last node's read the last needed cell (results unused)
+  const int ci = min(ty * (CH - 1) + lr, g.ny), cj = min(tx * (CW - 1) + lc, g.nx);
+  const int y = ci * 12 - 6, x = cj * 12 - 6;
+  const uint8_t* Ab = g.A + (int64_t)pair * g.stride + (int64_t)y * g.pitch + 2 * x;   // 4-byte aligned
+  const int xs = 2 * (x - R), sh = xs & 3;
+  const uint8_t* Bb = g.B + (int64_t)pair * g.stride + (int64_t)(y - R) * g.pitch + (xs & ~3);
+  const int node_a = ty * (CH - 1) + lr, node_b = tx * (CW - 1) + lc;
+  const bool node = lr < CH - 1 && lc < CW - 1 && node_a < g.ny && node_b < g.nx;
+  auto quad = [&](uint32_t v) {
+    const uint32_t h = v + (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x130, 0xF, 0xF, false);
+    return h + (uint32_t)__builtin_amdgcn_ds_bpermute((lane + CW) << 2, (int)h);
+  };
+  unsigned long long best = ~0ull;
+#pragma unroll
+  for (int ps = 0; ps < NPASS; ++ps) {
+    const int k0 = ps * DYG;             // first shift row of the pass
+    const int nk = min(DYG, G - k0);     // shift rows in the pass
+    uint32_t acc[DYG][G];
+#pragma unroll
+    for (int k = 0; k < DYG; ++k)
+#pragma unroll
+      for (int c = 0; c < G; ++c) acc[k][c] = 0u;
+    Words<CWD> aring[DYG];   // A row r sits in aring[r % DYG]
+#pragma unroll
+    for (int rb = 0; rb < 12 + DYG - 1; ++rb) {
+      if (rb >= 12 + nk - 1) continue;
+      if (rb < 12) aring[rb % DYG] = *reinterpret_cast<const Words<CWD>*>(Ab + (int64_t)rb * g.pitch);
+      // B row y - R + k0 + rb meets A row rb - k for shift row k0 + k
+      const Words<RW + 1> wv = *reinterpret_cast<const Words<RW + 1>*>(Bb + (int64_t)(k0 + rb) * g.pitch);
+      uint32_t rw[RW];
+#pragma unroll
+      for (int i = 0; i < RW; ++i) rw[i] = __builtin_amdgcn_alignbyte(wv.w[i + 1], wv.w[i], sh);
+#pragma unroll
+      for (int c = 0; c < G; ++c) {
+        uint32_t bw[CWD];
+#pragma unroll
+        for (int i = 0; i < CWD; ++i)
+          bw[i] = (c & 1) ? __builtin_amdgcn_alignbyte(rw[c / 2 + i + 1], rw[c / 2 + i], 2) : rw[c / 2 + i];
+#pragma unroll
+        for (int k = 0; k < DYG; ++k) {
+          const int r = rb - k;
+          if (k >= nk || r < 0 || r >= 12) continue;
+          uint32_t sacc = acc[k][c];
+#pragma unroll
+          for (int i = 0; i < CWD; ++i) sacc = __builtin_amdgcn_sad_u16(aring[r % DYG].w[i], bw[i], sacc);
+          acc[k][c] = sacc;
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int k = 0; k < DYG; ++k) {
+      if (k >= nk) continue;
+      const int dy = k0 + k - R;
+#pragma unroll
+      for (int c = 0; c < G; ++c) {
+        const unsigned long long key = sad_key(quad(acc[k][c]), dy, c - R);
+        best = key < best ? key : best;
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    asm volatile("" : "+v"(best)::"memory");
+  }
+  if (node) {
+    int32_t* out = g.out + (int64_t)pair * g.ostride;
+    out[node_a * g.nx + node_b] = (int)(best & 0xff) - 128;
+    out[g.nx * g.ny + node_a * g.nx + node_b] = (int)((best >> 8) & 0xff) - 128;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Finer-level SAD search with cell-shared sums (u8, block = 2 step, step 8,
 // R <= 2).  The four children of a parent search the same shifts (around
 // twice the parent's result), and their 16x16 blocks are the 2x2 windows of
@@ -1382,6 +1472,19 @@ hipError_t launch_sad_level(const Plan& P, int l, const void* A, const void* B, 
     PIV_SAD_LANE(3, 2) PIV_SAD_LANE(3, 1) PIV_SAD_LANE(3, 0)
     PIV_SAD_LANE(2, 2) PIV_SAD_LANE(2, 1) PIV_SAD_LANE(2, 0)
 #undef PIV_SAD_LANE
+  }
+  // coarsest level, u16, 24x24 blocks at step 12: cell-shared sums
+  if (!g.parent && P.es == 2 && P.p.step == 12 && P.block == 24 && g.R >= 3 && g.R <= 7) {
+    const int tiles = ((v.nx + 7) / 8) * ((v.ny + 5) / 6);
+    dim3 grid((tiles + 3) / 4, 1, n);
+    switch (g.R) {
+      case 3: hipLaunchKernelGGL((k_sad_cells16<3, 4>), grid, dim3(256), 0, s, g); break;
+      case 4: hipLaunchKernelGGL((k_sad_cells16<4, 4>), grid, dim3(256), 0, s, g); break;
+      case 5: hipLaunchKernelGGL((k_sad_cells16<5, 3>), grid, dim3(256), 0, s, g); break;
+      case 6: hipLaunchKernelGGL((k_sad_cells16<6, 3>), grid, dim3(256), 0, s, g); break;
+      default: hipLaunchKernelGGL((k_sad_cells16<7, 3>), grid, dim3(256), 0, s, g); break;
+    }
+    return hipGetLastError();
   }
   // coarsest level, u8, 16x16 blocks at step 8: cell-shared sums
   if (!g.parent && P.es == 1 && P.p.step == 8 && P.block == 16 && g.R >= 3 && g.R <= 7 &&
