@@ -667,6 +667,101 @@ __global__ __launch_bounds__(256) void k_sad_cells16(SadArgs g) {
 }
 
 // ---------------------------------------------------------------------------
+// Finer-level SAD search with cell-shared sums for u16 frames (block =
+// 2 step, step 12, R <= 2): the four children of a parent share a 3x3 group
+// of 12x12 cells (9 cell SADs per shift instead of 16).  Lane = cell of a
+// parent's group (7 parents per wave); the lane streams its 12 A rows
+// through a ring of 2R + 1 and the 12 + 2R B rows once, v_sad_u16 on
+// realigned words (an odd shift column is a 2-byte realignment).  A child's
+// sums: its cell + the right-hand cell (DPP lane + 1) + the pair below (lane
+// permute, lane + 3).  Level 0 reads in place as in k_sad_stream.  Winner:
+// the least (SAD, |dx|+|dy|, dy, dx).
+// ---------------------------------------------------------------------------
+template <int R>
+__global__ __launch_bounds__(256) void k_sad_cells16_fine(SadArgs g) {
+  constexpr int G = 2 * R + 1, CWD = 6, RW = CWD + R, PPW = 7;
+  const int lane = threadIdx.x & 63;
+  const WgIdx wg = xcd_order();
+  const int pair = wg.z;
+  if (slot_off(g.mask, pair)) return;
+  const int pnx = (g.nx + 1) / 2, pny = (g.ny + 1) / 2;
+  const int ntx = (pnx + PPW - 1) / PPW;
+  const int tile = wg.x * 4 + (threadIdx.x >> 6);
+  if (tile >= ntx * pny) return;   // a whole wave (no barriers below)
+  const int pa = tile / ntx, tx = tile - pa * ntx;
+  const int grp = min(lane / 9, PPW - 1), cell = lane - 9 * (lane / 9);
+  const int u = cell / 3, v = cell - 3 * (cell / 3);
+  const int pb = min(tx * PPW + grp, pnx - 1);
+  const int32_t* par = g.parent + (int64_t)pair * g.pstride;
+  int cx, cy;
+  parent_centre(g, par, min(pa, g.pny - 1), min(pb, g.pnx - 1), cx, cy);
+  // cells past the last node's read the last needed cell (results unused)
+  const int ci = min(2 * pa + u, g.ny), cj = min(2 * pb + v, g.nx);
+  const int y = ci * 12 - 6, x = cj * 12 - 6;
+  const int y0 = y + cy - R, xs = 2 * (x + cx - R), xa = xs & ~3, sh = xs & 3;
+  const int rowbytes = 2 * g.W;
+  const bool ain = g.direct && y >= 0 && y + 12 <= g.H && x >= 0 && 2 * x + 4 * CWD <= rowbytes;
+  const bool bin = g.direct && y0 >= 0 && y0 + 12 + 2 * R <= g.H && xa >= 0 && xa + 4 * (RW + 1) <= rowbytes;
+  const uint8_t* Ab = ain ? g.srcA + (int64_t)pair * g.sstride : g.A + (int64_t)pair * g.stride;
+  const uint8_t* Bb = bin ? g.srcB + (int64_t)pair * g.sstride : g.B + (int64_t)pair * g.stride;
+  const int64_t apitch = ain ? g.spitch : g.pitch, bpitch = bin ? g.spitch : g.pitch;
+  Ab += (int64_t)y * apitch + 2 * x;   // 4-byte aligned
+  Bb += (int64_t)y0 * bpitch + xa;
+  uint32_t acc[G][G];   // [shift row][shift column]
+#pragma unroll
+  for (int q = 0; q < G; ++q)
+#pragma unroll
+    for (int c = 0; c < G; ++c) acc[q][c] = 0u;
+  Words<CWD> aring[G];   // A row r sits in aring[r % G]
+#pragma unroll
+  for (int rb = 0; rb < 12 + 2 * R; ++rb) {
+    if (rb < 12) aring[rb % G] = *reinterpret_cast<const Words<CWD>*>(Ab + (int64_t)rb * apitch);
+    // B row y0 + rb meets A row rb - q for shift row q
+    const Words<RW + 1> wv = *reinterpret_cast<const Words<RW + 1>*>(Bb + (int64_t)rb * bpitch);
+    uint32_t rw[RW];
+#pragma unroll
+    for (int i = 0; i < RW; ++i) rw[i] = __builtin_amdgcn_alignbyte(wv.w[i + 1], wv.w[i], sh);
+#pragma unroll
+    for (int c = 0; c < G; ++c) {
+      uint32_t bw[CWD];
+#pragma unroll
+      for (int i = 0; i < CWD; ++i)
+        bw[i] = (c & 1) ? __builtin_amdgcn_alignbyte(rw[c / 2 + i + 1], rw[c / 2 + i], 2) : rw[c / 2 + i];
+#pragma unroll
+      for (int q = 0; q < G; ++q) {
+        const int r = rb - q;
+        if (r < 0 || r >= 12) continue;
+        uint32_t sacc = acc[q][c];
+#pragma unroll
+        for (int i = 0; i < CWD; ++i) sacc = __builtin_amdgcn_sad_u16(aring[r % G].w[i], bw[i], sacc);
+        acc[q][c] = sacc;
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  auto quad = [&](uint32_t val) {
+    const uint32_t h = val + (uint32_t)__builtin_amdgcn_update_dpp(0, (int)val, 0x130, 0xF, 0xF, false);
+    return h + (uint32_t)__builtin_amdgcn_ds_bpermute((lane + 3) << 2, (int)h);
+  };
+  unsigned long long best = ~0ull;
+#pragma unroll
+  for (int q = 0; q < G; ++q) {
+#pragma unroll
+    for (int c = 0; c < G; ++c) {
+      const unsigned long long key = sad_key(quad(acc[q][c]), cy - R + q, cx - R + c);
+      best = key < best ? key : best;
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  const int a = 2 * pa + u, b = 2 * pb + v;
+  if (lane < 9 * PPW && u < 2 && v < 2 && tx * PPW + lane / 9 < pnx && a < g.ny && b < g.nx) {
+    int32_t* out = g.out + (int64_t)pair * g.ostride;
+    out[a * g.nx + b] = (int)(best & 0xff) - 128;
+    out[g.nx * g.ny + a * g.nx + b] = (int)((best >> 8) & 0xff) - 128;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Finer-level SAD search with cell-shared sums (u8, block = 2 step, step 8,
 // R <= 2).  The four children of a parent search the same shifts (around
 // twice the parent's result), and their 16x16 blocks are the 2x2 windows of
@@ -1441,6 +1536,14 @@ hipError_t launch_sad_level(const Plan& P, int l, const void* A, const void* B, 
   g.margin = v.margin;
   const int G = 2 * g.R + 1;
   const int NW = P.block * P.es / 4;
+  // finer levels, u16, 24x24 blocks at step 12, R <= 2: cell-shared sums per parent
+  if (g.parent && P.es == 2 && P.p.step == 12 && P.block == 24 && g.R >= 1 && g.R <= 2) {
+    const int tiles = (((v.nx + 1) / 2 + 6) / 7) * ((v.ny + 1) / 2);
+    const dim3 grid((tiles + 3) / 4, 1, n);
+    if (g.R == 2) hipLaunchKernelGGL((k_sad_cells16_fine<2>), grid, dim3(256), 0, s, g);
+    else hipLaunchKernelGGL((k_sad_cells16_fine<1>), grid, dim3(256), 0, s, g);
+    return hipGetLastError();
+  }
   if (P.es == 2 && g.R >= 1 && g.R <= 2 && (NW == 6 || NW == 8 || NW == 12)) {
     dim3 grid((v.nx * v.ny + 255) / 256, n);
 #define PIV_SAD_STREAM(NW_, R_) \

@@ -224,6 +224,20 @@ def test_level0_in_place_reads_stay_in_written_bytes(L, kw):
             assert ok.all(), (r0, nr, c0, nc)
 
     cs = range(-cand, cand + 1, 2)
+    if es == 2 and step == 12 and blk == 24 and len(lv) > 1:
+        # the u16 cell-shared form: 12x12 cells (24-byte A rows), B spans of
+        # the cell plus 2R rows and CWD + R + 1 = 7 + R words
+        for ci in range(v["ny"] + 1):
+            y = ci * 12 - 6
+            for cj in range(v["nx"] + 1):
+                check(y, 12, (cj * 12 - 6) * 2, 24)
+            for cy in cs:
+                for cj in range(v["nx"] + 1):
+                    x = cj * 12 - 6
+                    for cx in (cs if cj in (0, 1, v["nx"] - 1, v["nx"]) else (-cand, 0, cand)):
+                        xs = (x + cx - R) * 2
+                        check(y + cy - R, 12 + 2 * R, xs & ~3, 4 * (7 + R))
+        return
     if es == 2:
         # the streamed u16 kernel: A rows from the floor word of the block,
         # NW + 1 words; B rows from the floor word of the leftmost shift,
