@@ -214,7 +214,7 @@ struct SadArgs {
   const uint8_t* mask;
   int npw;                // nodes per workgroup (k_sad)
   int margin;             // level margin (px): A - margin (pitch + bytes per px) is padded row 0
-  // level 0 read in place (k_sad_lane, k_sad_cols, k_sad_stream): an A block or B span wholly inside
+  // level 0 read in place (k_sad_lane, k_sad_cols, k_sad_stream, k_sad_cells16_fine): an A block or B span wholly inside
   // the image reads the caller's frames (pair 0 at srcA/srcB); one that
   // crosses the image edge reads the padded copy, of which only a frame of
   // kFrame px along the edges is written
@@ -1419,7 +1419,7 @@ bool sad_supported(int block_words) {
 // Level 0 is searched reading the caller's frames in place (see SadArgs) by
 // the one-node-per-lane or the cell-column kernel (u8, radius <= 2, 8-16 px
 // blocks, 32-bit offsets into both the padded copy and one caller frame) or
-// by the streamed u16 kernel (radius 1-2, 12-24 px blocks).
+// by the streamed or cell-shared u16 kernel (radius 1-2, 12-24 px blocks).
 static bool level0_in_place(const Plan& P, int64_t pitch) {
   const Level& v = P.lv[0];
   const int NW = P.block * P.es / 4;
