@@ -5,6 +5,10 @@ correct -> validate -> vorticity) over one batch of synthetic 1 MP u8 pairs
 resident in HBM (1024 x 1024, 0.04 ppp, Lamb-Oseen vortex with 20 px peak
 displacement and 10% particle dropout; 16 x 16 windows at step 8 -> 128 x 128
 vectors; +-4 px correction search; 3-level predictor with radii 6/2).
+Pairs are independent, so by default two batches are in flight, each on
+its own HIP stream with its own plan and buffers (step k on stream k mod 2):
+the memory-bound stages of one batch then run beside the ALU-bound
+correlation of the other.  The one-stream rate is reported beside it.
 
 Prints ONE JSON line with pairs/s (value), Mvectors/s, p50/p99 latency of
 the batched step and of a single pair, the HBM-roofline fraction of the
@@ -41,6 +45,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--batch", type=int, default=64)
     ap.add_argument("--distinct", type=int, default=8, help="distinct rendered pairs in the batch")
+    ap.add_argument("--streams", type=int, default=2,
+                    help="batches in flight: each HIP stream has its own plan and buffers, step k runs on "
+                         "stream k mod S")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-latency", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the graph/serving/stream/SSD forms")
@@ -314,10 +321,22 @@ def main():
         B[i].copy_(torch.from_numpy(pairs[i % nd][1]))
     plan = api.Plan(W, H, max_batch=nb, **kw)
     nx, ny = plan.nx, plan.ny
-    out = dict(pred=torch.empty((nb, 2, ny, nx), device=dev), disp=torch.empty((nb, 2, ny, nx), device=dev),
-               peak=torch.empty((nb, ny, nx), device=dev), flags=torch.empty((nb, ny, nx), dtype=torch.uint8, device=dev),
-               omega=torch.empty((nb, ny, nx), device=dev))
+
+    def outputs():
+        return dict(pred=torch.empty((nb, 2, ny, nx), device=dev), disp=torch.empty((nb, 2, ny, nx), device=dev),
+                    peak=torch.empty((nb, ny, nx), device=dev),
+                    flags=torch.empty((nb, ny, nx), dtype=torch.uint8, device=dev),
+                    omega=torch.empty((nb, ny, nx), device=dev))
+
+    out = outputs()
     stream = torch.cuda.current_stream(dev)
+    # one job per stream: independent batches of the same workload, each with
+    # its own plan (workspace), inputs and outputs
+    S = max(1, args.streams)
+    jobs = [(plan, A, B, out, stream)]
+    for _ in range(1, S):
+        jobs.append((api.Plan(W, H, max_batch=nb, **kw), A.clone(), B.clone(), outputs(),
+                     torch.cuda.Stream(dev)))
     if args.copy_probe > 0:
         src = torch.zeros(args.copy_probe << 20, dtype=torch.uint8, device=dev)
         dst = torch.empty_like(src)
@@ -326,22 +345,43 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    for _ in range(args.warmup):
-        plan.run(A, B, out)
-    torch.cuda.synchronize()
-    ev = events(torch, args.steps + 1)
-    t0 = time.perf_counter()
-    ev[0].record(stream)
-    for k in range(args.steps):
-        plan.run(A, B, out)
-        ev[k + 1].record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    step_ms = np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(args.steps)])
-    total_ms = ev[0].elapsed_time(ev[-1])
+    def timed(js):
+        """K steps, step k on job k mod len(js); returns (ms in total, per-step ms, wall s)."""
+        for _ in range(args.warmup):
+            for p, a, b, o, s in js:
+                with torch.cuda.stream(s):
+                    p.run(a, b, o)
+        torch.cuda.synchronize()
+        e0, e1 = events(torch, 2)
+        beg, end = events(torch, args.steps), events(torch, args.steps)
+        t0 = time.perf_counter()
+        e0.record(stream)
+        for _, _, _, _, s in js:
+            s.wait_stream(stream)
+        for k in range(args.steps):
+            p, a, b, o, s = js[k % len(js)]
+            beg[k].record(s)
+            with torch.cuda.stream(s):
+                p.run(a, b, o)
+            end[k].record(s)
+        for _, _, _, _, s in js:
+            stream.wait_stream(s)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        return e0.elapsed_time(e1), np.array([beg[k].elapsed_time(end[k]) for k in range(args.steps)]), wall
+
+    single = None
+    if S > 1:
+        one_ms, _, _ = timed(jobs[:1])
+        single = {"pairs_per_s": round(nb * args.steps / (one_ms / 1e3), 1),
+                  "ms_per_step": round(one_ms / args.steps, 4)}
+        log(args, f"one stream: step {one_ms / args.steps:.3f} ms, {single['pairs_per_s']:.0f} pairs/s")
+    total_ms, step_ms, wall = timed(jobs)
     ms_per_step = total_ms / args.steps
     pairs_s = nb * args.steps / (total_ms / 1e3)
-    log(args, f"step {ms_per_step:.3f} ms ({wall / args.steps * 1e3:.3f} ms wall), {pairs_s:.0f} pairs/s")
+    log(args, f"{S} streams: step {ms_per_step:.3f} ms ({wall / args.steps * 1e3:.3f} ms wall), "
+              f"{pairs_s:.0f} pairs/s")
 
     # dominant kernel: the correlation stage, timed alone with events on its stream
     pred = out["pred"].clone()
@@ -417,7 +457,9 @@ def main():
         "config": {"workload": "1024x1024 u8 particle-image pairs (0.04 ppp, Lamb-Oseen 20 px peak, "
                                "10% dropout), 16x16 windows step 8 (128x128 vectors), +-4 px search, "
                                "3-level SAD predictor (radii 6/2), full path per step",
-                   "global_batch": nb, "distinct_pairs": nd, "parallelism": "single GPU"},
+                   "global_batch": nb, "distinct_pairs": nd, "parallelism": "single GPU",
+                   "batches_in_flight": S},
+        "single_stream": single,
         "mvec_per_s": round(pairs_s * nx * ny / 1e6, 2),
         "latency": lat,
         "hbm_roofline": {"achieved_gbs": round(path_gbs, 1), "peak_gbs": HBM_PEAK_GBS,
