@@ -333,7 +333,10 @@ class GpuExecutor(Executor):
     sets the active-slot mask and replays the runner's graph.  A batch of
     one pair (what light load produces) skips the copies and the graph: the
     runner's plan runs that pair eagerly from its own buffers into slot 0
-    (same kernels, same workspace, same stream)."""
+    (same kernels, same workspace, same stream).  The pairs must be written
+    (complete on the device) before the first launch that reads them:
+    launches do not order themselves after other streams.  Each runner has
+    one completion event, reused, since it holds at most one live batch."""
 
     def __init__(self, runners: Dict[str, List[GraphRunner]], pairs: Dict[int, Tuple[object, object]],
                  keep_results: bool = False, eager_single: bool = True):
@@ -348,6 +351,7 @@ class GpuExecutor(Executor):
         self.eager_single = eager_single
         self.results: Dict[int, Dict[str, object]] = {}
         self.slot0 = {id(r): {k: v[0:1] for k, v in r.out.items()} for rs in runners.values() for r in rs}
+        self.event = {id(r): torch.cuda.Event() for rs in runners.values() for r in rs}
 
     def launch(self, cls, reqs, now):
         torch = self.torch
@@ -355,7 +359,6 @@ class GpuExecutor(Executor):
         if len(reqs) == 1 and self.eager_single:
             r = reqs[0]
             a, b = self.pairs[r.stream]
-            run.stream.wait_stream(torch.cuda.current_stream())
             # (the plan's slot mask is the runner's; slot 0 is active under
             # every mask set_active writes, and the mask starts all ones)
             with torch.cuda.stream(run.stream):
@@ -367,7 +370,7 @@ class GpuExecutor(Executor):
                     run.A[i].copy_(a[r.item], non_blocking=True)
                     run.B[i].copy_(b[r.item], non_blocking=True)
             run.replay(len(reqs))
-        ev = torch.cuda.Event()
+        ev = self.event[id(run)]
         ev.record(run.stream)
         self.n += 1
         self.live[self.n] = (cls, run, ev, reqs)
@@ -396,6 +399,7 @@ def make_gpu_server(classes: Dict[str, Tuple[int, int, int]], pairs: Dict[int, T
     workspace, HIP stream and captured graph), the executor and the
     scheduler, and admit the streams in order.  classes: name -> (W, H,
     slots).  Returns (scheduler, executor)."""
+    import torch
     from .api import Plan
     plan_kw = dict(plan_kw or {})
     runners: Dict[str, List[GraphRunner]] = {}
@@ -414,6 +418,8 @@ def make_gpu_server(classes: Dict[str, Tuple[int, int, int]], pairs: Dict[int, T
                 per_stream = a.numel() * a.element_size() + b.numel() * b.element_size()
                 break
         specs.append(ClassSpec(name, W, H, cap, rs[0].resident_bytes(), per_stream))
+    # the admitted pairs are complete before the first launch reads them
+    torch.cuda.synchronize()
     ex = GpuExecutor(runners, pairs, keep_results=keep_results, eager_single=eager_single)
     sched = Scheduler(specs, ex, budget, max_wait=max_wait, inflight=inflight)
     for s, c in stream_class.items():
