@@ -308,6 +308,43 @@ def test_run_equals_separate_steps(dtype):
         assert torch.equal(out[k], v), k
 
 
+def test_two_plans_on_two_streams_equal_alone():
+    """Two plans running the whole path at once on two HIP streams (two
+    batches in flight, as the benchmark runs them) give the same bits as
+    each batch run alone: the plans share no workspace."""
+    say("[run] two plans on two streams")
+    pairs = [small_vortex_pair(seed=s)[:2] for s in (43, 44, 45, 46)]
+    A = np.stack([p[0] for p in pairs])
+    B = np.stack([p[1] for p in pairs])
+    P1 = api().Plan(256, 192, max_batch=2, win=16, step=8)
+    P2 = api().Plan(256, 192, max_batch=2, win=16, step=8)
+    A1, B1, A2, B2 = dev(A[:2]), dev(B[:2]), dev(A[2:]), dev(B[2:])
+    ref1 = {k: v.clone() for k, v in P1.run(A1, B1).items()}
+    ref2 = {k: v.clone() for k, v in P2.run(A2, B2).items()}
+    torch.cuda.synchronize()
+    o1 = {k: torch.empty_like(v) for k, v in ref1.items()}
+    o2 = {k: torch.empty_like(v) for k, v in ref2.items()}
+    main = torch.cuda.current_stream()
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    for it in range(3):
+        for o in (o1, o2):
+            for v in o.values():
+                v.zero_()
+        s1.wait_stream(main)
+        s2.wait_stream(main)
+        for _ in range(4):
+            with torch.cuda.stream(s1):
+                P1.run(A1, B1, o1)
+            with torch.cuda.stream(s2):
+                P2.run(A2, B2, o2)
+        main.wait_stream(s1)
+        main.wait_stream(s2)
+        torch.cuda.synchronize()
+        for k in ref1:
+            assert torch.equal(o1[k], ref1[k]), (it, "first", k)
+            assert torch.equal(o2[k], ref2[k]), (it, "second", k)
+
+
 def test_vorticity_parity():
     say("[vorticity]")
     lo = synth.cfg2_flow()
