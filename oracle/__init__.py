@@ -64,6 +64,8 @@ def lib():
         L.o_vorticity.argtypes = [_D, _i, _i, _i, _D]
         L.o_ssd_forward.argtypes = [_D, _D, _D, _i, _i, _i, _i, _D]
         L.o_ssd_grad.argtypes = [_D, _D, _D, _D, _i, _i, _i, _i, _D, _Dn]
+        L.o_ssd_refine.argtypes = [_D, _D, _D, _i, _i, _i, _i, _i, _d, _d, _Dn]
+        L.o_smooth.argtypes = [_D, _D, _i, _d, _i]
         _lib = L
     return _lib
 
@@ -198,6 +200,42 @@ def ssd_grad(A, B, U, g, win, step, want_diag=True):
     return gU, D
 
 
+def ssd_refine(A, B, U0, win, step, steps=10, tau=4.0 / 9.0, lam_rel=1e-3):
+    """Refined field and the total-loss history [steps + 1] (FP64)."""
+    A, B = _img_d(A), _img_d(B)
+    U = _img_d(U0).copy()
+    H, W = A.shape
+    hist = np.zeros(steps + 1)
+    lib().o_ssd_refine(A, B, U, W, H, win, step, steps, float(tau), float(lam_rel), hist)
+    return U, hist
+
+
+def smooth(field, state, alpha, first):
+    """One frame of exponential smoothing; returns (smoothed field, new state)."""
+    f = _img_d(field).copy()
+    s = np.zeros_like(f) if state is None else _img_d(state).copy()
+    lib().o_smooth(f, s, f.size, float(alpha), int(bool(first)))
+    return f, s
+
+
+def smooth_batch(fields, states, slots, alpha):
+    """Smoothing of a batch in order: fields [n][2][ny][nx], states
+    [nstate][2][ny][nx] (updated copies returned), slot k >= 0 continues
+    state k, -1 - k starts it; slots outside [0, nstate) leave their pair
+    untouched."""
+    out = np.array(fields, dtype=np.float64, copy=True)
+    st = np.array(states, dtype=np.float64, copy=True)
+    for i, k in enumerate(slots):
+        k = int(k)
+        first = k < 0
+        if first:
+            k = -1 - k
+        if not 0 <= k < st.shape[0]:
+            continue
+        out[i], st[k] = smooth(out[i], st[k], alpha, first)
+    return out, st
+
+
 def run(A, B, *, win, step, r, levels, block=0, Rc, Rf, median=True, warp_mode=0, peak_mode=0,
         thr=2.0, eps=0.1):
     """The whole plain path: predict, validate the predictor, correct,
@@ -210,3 +248,28 @@ def run(A, B, *, win, step, r, levels, block=0, Rc, Rf, median=True, warp_mode=0
     om = vorticity(disp_v, step)
     return dict(pred=pred, disp_raw=disp, peak=peak, flags_raw=flags, disp=disp_v,
                 flags=flags_v, omega=om)
+
+
+def run_temporal(frames, *, win, step, r, levels, block=0, Rc, Rf, median=True, alpha1=0.5, alpha2=0.5,
+                 warp_mode=0, peak_mode=0, thr=2.0, eps=0.1):
+    """The path with the paper's temporal smoothing over one stream of
+    pairs [(A, B), ...] in time order: predict, validate the predictor,
+    smooth it (alpha1), correct about the smoothed predictor, validate,
+    smooth the final field (alpha2), vorticity.  alpha None skips that
+    smoothing.  Returns one dict per pair."""
+    blk = block or win
+    sp = sd = None
+    outs = []
+    for t, (A, B) in enumerate(frames):
+        pred = predict(A, B, step, blk, levels, Rc, Rf, median).astype(np.float64)
+        pred, _ = validate(pred, None, thr, eps)
+        if alpha1 is not None:
+            pred, sp = smooth(pred, sp, alpha1, t == 0)
+        disp, peak, flags = correct(A, B, win, step, r, pred, warp_mode, peak_mode)
+        disp_v, flags_v = validate(disp, flags, thr, eps)
+        if alpha2 is not None:
+            disp_v, sd = smooth(disp_v, sd, alpha2, t == 0)
+        om = vorticity(disp_v, step)
+        outs.append(dict(pred=pred, disp_raw=disp, peak=peak, flags_raw=flags, disp=disp_v, flags=flags_v,
+                         omega=om))
+    return outs

@@ -601,3 +601,60 @@ void o_ssd_grad(const double* A, const double* B, const double* U, const double*
       }
     }
 }
+
+/* Gradient refinement of U by the windowed SSD (an addition of this
+ * implementation, compared with the paper's Gaussian fit): `steps`
+ * diagonally preconditioned gradient steps on the total loss
+ * L = sum of every window's SSD (upstream gradient 1 for every window):
+ *   U <- U - tau * dL/dU / (D + lambda),  lambda = lam_rel * mean(D),
+ * D the Gauss-Newton diagonal, mean(D) over both components of the grid.
+ * A node component whose D + lambda is not positive is left unchanged.
+ * U [2][ny][nx] in/out; hist (nullable) [steps + 1] receives the total loss
+ * before each step and after the last. */
+void o_ssd_refine(const double* A, const double* B, double* U, int W, int H, int win, int step, int steps,
+                  double tau, double lam_rel, double* hist) {
+  int nx = W / step, ny = H / step;
+  size_t np = (size_t)nx * ny;
+  double* loss = (double*)malloc(sizeof(double) * np);
+  double* ones = (double*)malloc(sizeof(double) * np);
+  double* gU = (double*)malloc(sizeof(double) * 2 * np);
+  double* D = (double*)malloc(sizeof(double) * 2 * np);
+  for (size_t i = 0; i < np; ++i) ones[i] = 1.0;
+  for (int k = 0; k <= steps; ++k) {
+    if (hist) {
+      o_ssd_forward(A, B, U, W, H, win, step, loss);
+      double s = 0;
+      for (size_t i = 0; i < np; ++i) s += loss[i];
+      hist[k] = s;
+    }
+    if (k == steps) break;
+    o_ssd_grad(A, B, U, ones, W, H, win, step, gU, D);
+    double mean = 0;
+    for (size_t i = 0; i < 2 * np; ++i) mean += D[i];
+    mean /= (double)(2 * np);
+    double lam = lam_rel * mean;
+    for (size_t i = 0; i < 2 * np; ++i) {
+      double den = D[i] + lam;
+      if (den > 0) U[i] -= tau * gU[i] / den;
+    }
+  }
+  free(loss);
+  free(ones);
+  free(gU);
+  free(D);
+}
+
+/* ------------------------------------------------------------------------
+ * Temporal smoothing (Sec. 2: exponential smoothing in time of the
+ * validated predictor, constant alpha1, and of the validated final field,
+ * constant alpha2).  One frame of one stream: the first frame starts the
+ * state (s = x); later frames s = alpha x + (1 - alpha) s.  The field takes
+ * the smoothed value.  field, state [2][ny][nx] (np2 values each).
+ * ---------------------------------------------------------------------- */
+void o_smooth(double* field, double* state, int np2, double alpha, int first) {
+  for (int j = 0; j < np2; ++j) {
+    double s = first ? field[j] : alpha * field[j] + (1.0 - alpha) * state[j];
+    state[j] = s;
+    field[j] = s;
+  }
+}
