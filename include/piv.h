@@ -31,8 +31,9 @@
  *    so it may be captured into a HIP graph.  Argument errors are detected
  *    on the host before any launch (no partial work).  Faults inside a
  *    kernel surface at the caller's next synchronisation.
- *  - A plan is immutable after workspace binding; use one plan (and one
- *    workspace) per concurrently used stream.
+ *  - A plan is immutable after workspace binding (the binding call itself
+ *    prepares the workspace on the stream it is given); use one plan (and
+ *    one workspace) per concurrently used stream.
  */
 #ifndef PIV_H
 #define PIV_H
@@ -115,18 +116,22 @@ piv_status piv_plan_grid(piv_plan_t plan, int32_t* nx, int32_t* ny);
 
 /* Bytes of device workspace needed for `batch` pairs: predictor pyramids,
  * per-level integer fields and one float field [2][ny][nx] (the input of
- * validation).  Exact, so that callers can admit work against an HBM
+ * validation); PIV_F32 plans also hold the refinement's gradient, diagonal
+ * and window losses.  Exact, so that callers can admit work against an HBM
  * budget. */
 size_t piv_plan_workspace_bytes(piv_plan_t plan, int32_t batch);
 
-/* Bind caller-owned device workspace (e.g. a torch tensor) to the plan.
- * The plan remembers how many pairs it can hold; later calls with a larger
- * n fail with PIV_ENOWORKSPACE.  The memory must outlive its use.  The
- * first piv_predict after binding also zeroes the pyramid margins in the
- * whole workspace (on that call's stream) and later calls rely on them:
- * the caller must not write to bound workspace; binding again (the same
- * pointer included) repeats the zeroing. */
-piv_status piv_plan_bind_workspace(piv_plan_t plan, void* d_ws, size_t bytes);
+/* Bind caller-owned device workspace (e.g. a torch tensor) to the plan,
+ * 256-byte aligned.  The plan remembers how many pairs it can hold (at most
+ * max_batch); later calls with a larger n fail with PIV_ENOWORKSPACE.  The
+ * memory must outlive its use.  Binding enqueues, on `stream`, the zeroing
+ * of the pyramid margins of every pair the workspace holds; later calls
+ * (on any stream ordered after it) rely on them, so the caller must not
+ * write to bound workspace.  Binding again (the same pointer included)
+ * repeats the zeroing.  d_ws NULL unbinds (no device work).
+ * Errors: PIV_EINVAL (misaligned), PIV_ENOWORKSPACE (holds no pair),
+ * PIV_EDEVICE (the launch failed; the previous binding is kept). */
+piv_status piv_plan_bind_workspace(piv_plan_t plan, void* d_ws, size_t bytes, hipStream_t stream);
 
 /* Optional device slot mask uint8 [max_batch]: when bound, every kernel of
  * every call skips pair i whose mask byte is 0 (its outputs are left
@@ -136,7 +141,10 @@ piv_status piv_plan_bind_slot_mask(piv_plan_t plan, const uint8_t* d_mask);
 
 void piv_plan_destroy(piv_plan_t plan);
 
-/* Predictor: coarse-to-fine integer SAD block matching.  For each level l
+/* Predictor (Sec. 2: the coarse displacement estimate that the correlation
+ * then corrects, there from a fixed-function optical-flow engine; here
+ * block matching on the compute units): coarse-to-fine integer SAD block
+ * matching.  For each level l
  * (coarsest first) and node, the block of `block` x `block` level-l pixels
  * at the node is compared with frame B moved by every integer d in
  * cand + [-R, R]^2 (R = radius_coarse on the coarsest level around 0,
@@ -169,7 +177,8 @@ piv_status piv_correct(piv_plan_t plan, const void* A, const void* B, int64_t pi
  * workspace. */
 piv_status piv_validate(piv_plan_t plan, float* field, uint8_t* flags, int32_t n, hipStream_t stream);
 
-/* Vorticity omega = dv/dx - du/dy (1/frame) on the node grid, spacing step:
+/* Vorticity (Sec. 1 and Sec. 4: the field the paper displays and compares;
+ * its scheme is not given) omega = dv/dx - du/dy (1/frame) on the node grid, spacing step:
  * central differences inside, second-order one-sided on the edges.
  * disp [n][2][ny][nx] -> omega [n][ny][nx]. */
 piv_status piv_vorticity(piv_plan_t plan, const float* disp, float* omega, int32_t n,
@@ -185,6 +194,32 @@ piv_status piv_vorticity(piv_plan_t plan, const float* disp, float* omega, int32
 piv_status piv_run(piv_plan_t plan, const void* A, const void* B, int64_t pitch_bytes, int32_t n,
                    float* pred, float* disp, float* peak, uint8_t* flags, float* omega,
                    hipStream_t stream);
+
+/* Exponential smoothing in time (Sec. 2; alpha1 = alpha2 = 0.5 in both
+ * experiments of Sec. 3), in place on field [n][2][ny][nx] with per-stream
+ * state [nstate][2][ny][nx] (device, caller-owned).  Pairs are taken in
+ * batch order; pair i uses state slot slot[i] (device int32 [n]):
+ *   slot[i] = k >= 0:      s_k <- alpha * field_i + (1 - alpha) * s_k
+ *   slot[i] = -1 - k:      s_k <- field_i (the first frame of a stream)
+ * and field_i <- s_k.  Pairs sharing a slot (consecutive frames of one
+ * stream in one batch) chain in batch order.  A slot outside [0, nstate)
+ * leaves its pair and every state untouched.  alpha in (0, 1]; 1 = off.
+ * Errors: PIV_EINVAL (NULL pointers, nstate <= 0, alpha out of range). */
+piv_status piv_smooth(piv_plan_t plan, float* field, float* state, const int32_t* slot, int32_t nstate,
+                      float alpha, int32_t n, hipStream_t stream);
+
+/* The paper's whole pipeline with temporal smoothing (Sec. 2): predict,
+ * validate the predictor, smooth it with alpha1 and state_pred, correct
+ * about the smoothed predictor, validate, smooth the final field with
+ * alpha2 and state_disp, vorticity of the smoothed field.  slot and nstate
+ * as in piv_smooth (one slot table for both states).  state_pred or
+ * state_disp NULL skips that smoothing (its alpha is then ignored); with
+ * both NULL the results equal piv_run's.  The states make results depend
+ * on each stream's history, unlike piv_run's.  Needs a bound workspace. */
+piv_status piv_run_temporal(piv_plan_t plan, const void* A, const void* B, int64_t pitch_bytes,
+                            int32_t n, const int32_t* slot, int32_t nstate, float* state_pred,
+                            float* state_disp, float alpha1, float alpha2, float* pred, float* disp,
+                            float* peak, uint8_t* flags, float* omega, hipStream_t stream);
 
 /* Windowed SSD of the deformation (an addition, not in the paper): for
  * float32 frames A, B [n][height][width] (pitch = width) and a node field
@@ -203,10 +238,35 @@ piv_status piv_ssd_backward(piv_plan_t plan, const float* A, const float* B, con
                             const float* g_loss, int32_t n, float* g_U, float* gn_diag,
                             hipStream_t stream);
 
+/* Gradient refinement by the windowed SSD (an addition, compared with the
+ * paper's Gaussian fit): `steps` diagonally preconditioned gradient steps
+ * on the total loss L = sum of every window's SSD, in place on U
+ * [n][2][ny][nx]:
+ *   U <- U - tau * dL/dU / (D + lambda),  lambda = lam_rel * mean(D),
+ * D the Gauss-Newton diagonal (as in piv_ssd_backward with g_loss = 1) and
+ * mean(D) over both components of each pair's grid; a node component whose
+ * D + lambda is not positive is left unchanged.  hist (nullable, device
+ * float [n][steps + 1]) receives the total loss before each step and after
+ * the last.  Everything runs on the device (no host synchronisation); the
+ * gradient, diagonal and losses live in the plan's workspace, so a bound
+ * workspace is needed (PIV_F32 plan).  tau in (0, 16], lam_rel in
+ * [0, 1e6], steps in [0, 10000]. */
+piv_status piv_ssd_refine(piv_plan_t plan, const float* A, const float* B, float* U, int32_t n,
+                          int32_t steps, float tau, float lam_rel, float* hist, hipStream_t stream);
+
 const char* piv_status_string(piv_status s);
 
 /* Detail of the last failure on the calling thread (never NULL). */
 const char* piv_last_error(void);
+
+/* Diagnostics for tests and benchmarks (no device work).
+ * piv_debug_correct_impl: which correlation kernel the plan selects
+ * (0 generic per window, 1 cell-shared tiled or band), -1 for NULL.
+ * piv_debug_level: geometry of pyramid level l into out[11] (host):
+ * W, H, margin, pitch, rows, R, nx, ny, bytes per pixel, step, block;
+ * returns 0, or -1 for a bad plan, pointer or level. */
+int piv_debug_correct_impl(piv_plan_t plan);
+int piv_debug_level(piv_plan_t plan, int32_t l, int32_t* out);
 
 #ifdef __cplusplus
 }

@@ -22,8 +22,9 @@ F_FLAT, F_BORDER, F_NOCURV, F_OUTLIER, F_REPLACED, F_UNRESOLVED = 1, 2, 4, 8, 16
 EXPORTS = [
     "piv_params_default", "piv_plan", "piv_plan_grid", "piv_plan_workspace_bytes",
     "piv_plan_bind_workspace", "piv_plan_bind_slot_mask", "piv_plan_destroy", "piv_predict",
-    "piv_correct", "piv_validate", "piv_vorticity", "piv_run", "piv_ssd_forward",
-    "piv_ssd_backward", "piv_status_string", "piv_last_error",
+    "piv_correct", "piv_validate", "piv_vorticity", "piv_run", "piv_smooth", "piv_run_temporal",
+    "piv_ssd_forward", "piv_ssd_backward", "piv_ssd_refine", "piv_status_string", "piv_last_error",
+    "piv_debug_correct_impl", "piv_debug_level",
 ]
 
 
@@ -61,7 +62,7 @@ def lib() -> C.CDLL:
         L.piv_plan_grid.argtypes = [vp, C.POINTER(i32), C.POINTER(i32)]
         L.piv_plan_workspace_bytes.argtypes = [vp, i32]
         L.piv_plan_workspace_bytes.restype = C.c_size_t
-        L.piv_plan_bind_workspace.argtypes = [vp, vp, C.c_size_t]
+        L.piv_plan_bind_workspace.argtypes = [vp, vp, C.c_size_t, vp]
         L.piv_plan_bind_slot_mask.argtypes = [vp, vp]
         L.piv_plan_destroy.argtypes = [vp]
         L.piv_plan_destroy.restype = None
@@ -72,9 +73,14 @@ def lib() -> C.CDLL:
         L.piv_run.argtypes = [vp, vp, vp, i64, i32, vp, vp, vp, vp, vp, vp]
         L.piv_ssd_forward.argtypes = [vp, vp, vp, vp, i32, vp, vp]
         L.piv_ssd_backward.argtypes = [vp, vp, vp, vp, vp, i32, vp, vp, vp]
+        f32 = C.c_float
+        L.piv_smooth.argtypes = [vp, vp, vp, vp, i32, f32, i32, vp]
+        L.piv_run_temporal.argtypes = [vp, vp, vp, i64, i32, vp, i32, vp, vp, f32, f32, vp, vp, vp, vp, vp, vp]
+        L.piv_ssd_refine.argtypes = [vp, vp, vp, vp, i32, i32, f32, f32, vp, vp]
         for name in ["piv_plan", "piv_plan_grid", "piv_plan_bind_workspace", "piv_plan_bind_slot_mask",
                      "piv_predict", "piv_correct", "piv_validate", "piv_vorticity", "piv_run",
-                     "piv_ssd_forward", "piv_ssd_backward"]:
+                     "piv_smooth", "piv_run_temporal", "piv_ssd_forward", "piv_ssd_backward",
+                     "piv_ssd_refine"]:
             getattr(L, name).restype = st
         L.piv_status_string.argtypes = [st]
         L.piv_status_string.restype = C.c_char_p
@@ -82,6 +88,8 @@ def lib() -> C.CDLL:
         L.piv_last_error.restype = C.c_char_p
         L.piv_debug_correct_impl.argtypes = [vp]
         L.piv_debug_correct_impl.restype = C.c_int
+        L.piv_debug_level.argtypes = [vp, i32, C.POINTER(i32)]
+        L.piv_debug_level.restype = C.c_int
         _lib = L
     return _lib
 

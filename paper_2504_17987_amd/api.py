@@ -7,7 +7,7 @@ PyTorch provides device memory and streams.
 from __future__ import annotations
 
 import ctypes as C
-from typing import Dict, Optional
+from typing import Dict, Optional, Tuple
 
 import torch
 
@@ -31,6 +31,10 @@ class Plan:
     Parameters follow ``piv_params`` (include/piv.h); defaults are the
     paper's 16 x 16 windows at 50% step-over with UOD threshold 2 and
     regulariser 0.1 px, a +-4 px correction search and a 3-level predictor.
+
+    Every tensor argument is checked (dtype, shape, batch, device,
+    contiguity) before the C ABI is called, so a wrong tensor raises here
+    instead of letting a kernel read or write out of bounds.
     """
 
     def __init__(self, width: int, height: int, *, max_batch: int = 1, dtype: str = "u8",
@@ -60,7 +64,10 @@ class Plan:
         L.check(L.lib().piv_plan_grid(h, C.byref(nx), C.byref(ny)))
         self.nx, self.ny = nx.value, ny.value
         self.width, self.height, self.max_batch = width, height, max_batch
-        self.device = torch.device(device)
+        dev = torch.device(device)
+        if dev.type == "cuda" and dev.index is None and torch.cuda.is_available():
+            dev = torch.device("cuda", torch.cuda.current_device())
+        self.device = dev
         self.workspace = None
         self.slot_mask = None
         if workspace:
@@ -72,12 +79,24 @@ class Plan:
         return int(L.lib().piv_plan_workspace_bytes(self.handle, batch))
 
     def bind_workspace(self, ws: Optional[torch.Tensor]) -> None:
-        L.check(L.lib().piv_plan_bind_workspace(self.handle, _ptr(ws), 0 if ws is None else ws.numel()))
+        """Bind a uint8 device tensor as the plan's workspace (None unbinds).
+        The library prepares it (zeroes the pyramid margins) on the current
+        stream; this waits for that, so the plan is ready on any stream when
+        it returns (binding is set-up work, not on the hot path)."""
+        if ws is not None:
+            self._dev(ws, "workspace")
+            if ws.dtype != torch.uint8 or not ws.is_contiguous():
+                raise TypeError("workspace must be a contiguous uint8 tensor")
+        L.check(L.lib().piv_plan_bind_workspace(self.handle, _ptr(ws), 0 if ws is None else ws.numel(),
+                                                None if ws is None else _stream(self.device)))
+        if ws is not None:
+            torch.cuda.current_stream(self.device).synchronize()
         self.workspace = ws
 
     def bind_slot_mask(self, mask: Optional[torch.Tensor]) -> None:
         if mask is not None:
-            assert mask.dtype == torch.uint8 and mask.is_contiguous() and mask.numel() >= self.max_batch
+            self._tensor(mask, "slot mask", torch.uint8, (), self.max_batch)
+            self._devices(mask=mask)
         L.check(L.lib().piv_plan_bind_slot_mask(self.handle, _ptr(mask)))
         self.slot_mask = mask
 
@@ -97,17 +116,53 @@ class Plan:
             pass
 
     # -- argument checks ---------------------------------------------------
+    def _dev(self, t: torch.Tensor, name: str) -> None:
+        if t.device.type != "cuda" or (self.device.index is not None and t.device.index != self.device.index):
+            raise TypeError(f"{name} must be on the plan's device {self.device}, not {t.device}")
+
+    def _tensor(self, t, name: str, dtype, tail: Tuple[int, ...], n: int, exact: bool = False) -> None:
+        """t must be a contiguous `dtype` tensor of shape [>= n, *tail] (== n if
+        exact) on the plan's device."""
+        if not isinstance(t, torch.Tensor):
+            raise TypeError(f"{name} must be a torch tensor")
+        if t.dtype != dtype:
+            raise TypeError(f"{name} must be {dtype}, not {t.dtype}")
+        if t.dim() != len(tail) + 1 or tuple(t.shape[1:]) != tuple(tail):
+            raise ValueError(f"{name} must have shape [n, {', '.join(map(str, tail))}], not {list(t.shape)}")
+        if t.shape[0] < n or (exact and t.shape[0] != n):
+            raise ValueError(f"{name} holds {t.shape[0]} pairs, the call needs {n}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+
+    def _devices(self, **named) -> None:
+        """Checked last, after every dtype and shape check: the tensors live
+        on the plan's device."""
+        for name, t in named.items():
+            if t is not None:
+                self._dev(t, name)
+
+    def _batch(self, n: int) -> None:
+        if n > self.max_batch:
+            raise ValueError(f"batch {n} exceeds the plan's max_batch {self.max_batch}")
+
     def _images(self, A: torch.Tensor, B: torch.Tensor):
         for t in (A, B):
-            if t.dtype != self.tdtype or t.device.type != "cuda":
-                raise TypeError(f"images must be {self.tdtype} device tensors")
-            if t.dim() != 3 or t.shape[1:] != (self.height, self.width):
+            if not isinstance(t, torch.Tensor) or t.dtype != self.tdtype:
+                raise TypeError(f"images must be {self.tdtype} tensors")
+            if t.dim() != 3 or tuple(t.shape[1:]) != (self.height, self.width):
                 raise ValueError(f"images must be [n, {self.height}, {self.width}]")
             if t.stride(2) != 1 or (t.shape[0] > 1 and t.stride(0) != self.height * t.stride(1)):
                 raise ValueError("images must be [n][H][pitch] with unit column stride")
         if A.stride() != B.stride() or A.shape != B.shape:
             raise ValueError("A and B must have the same shape and strides")
+        self._batch(A.shape[0])
         return A.shape[0], A.stride(1) * self.es
+
+    def _fieldT(self, t, name, n):
+        self._tensor(t, name, torch.float32, (2, self.ny, self.nx), n)
+
+    def _vecT(self, t, name, n, dtype=torch.float32):
+        self._tensor(t, name, dtype, (self.ny, self.nx), n)
 
     def _field(self, n, like=None):
         return torch.empty((n, 2, self.ny, self.nx), dtype=torch.float32, device=self.device)
@@ -115,32 +170,64 @@ class Plan:
     def _vec(self, n, dtype=torch.float32):
         return torch.empty((n, self.ny, self.nx), dtype=dtype, device=self.device)
 
+    def _outputs(self, n, out: Dict[str, torch.Tensor]) -> None:
+        for k in ("pred", "disp", "flags", "omega"):
+            if k not in out or out[k] is None:
+                raise ValueError(f"out must hold '{k}'")
+        self._fieldT(out["pred"], "pred", n)
+        self._fieldT(out["disp"], "disp", n)
+        self._vecT(out["flags"], "flags", n, torch.uint8)
+        self._vecT(out["omega"], "omega", n)
+        if out.get("peak") is not None:
+            self._vecT(out["peak"], "peak", n)
+
+    def _out_devices(self, out) -> None:
+        self._devices(**{k: out.get(k) for k in ("pred", "disp", "peak", "flags", "omega")})
+
     # -- the path ------------------------------------------------------------
     def predict(self, A, B, pred=None):
         n, pitch = self._images(A, B)
         pred = self._field(n) if pred is None else pred
+        self._fieldT(pred, "pred", n)
+        self._devices(A=A, B=B, pred=pred)
         L.check(L.lib().piv_predict(self.handle, _ptr(A), _ptr(B), pitch, n, _ptr(pred), _stream(self.device)))
         return pred
 
     def correct(self, A, B, pred=None, disp=None, peak=None, flags=None, want_peak=True):
         n, pitch = self._images(A, B)
+        if pred is not None:
+            self._fieldT(pred, "pred", n)
         disp = self._field(n) if disp is None else disp
+        self._fieldT(disp, "disp", n)
         if peak is None and want_peak:
             peak = self._vec(n)
+        if peak is not None:
+            self._vecT(peak, "peak", n)
         flags = self._vec(n, torch.uint8) if flags is None else flags
+        self._vecT(flags, "flags", n, torch.uint8)
+        self._devices(A=A, B=B, pred=pred, disp=disp, peak=peak, flags=flags)
         L.check(L.lib().piv_correct(self.handle, _ptr(A), _ptr(B), pitch, n, _ptr(pred), _ptr(disp),
                                     _ptr(peak), _ptr(flags), _stream(self.device)))
         return disp, peak, flags
 
     def validate(self, field, flags=None):
         """In place on field [n][2][ny][nx] (and flags [n][ny][nx] if given)."""
+        self._fieldT(field, "field", 0)
         n = field.shape[0]
+        self._batch(n)
+        if flags is not None:
+            self._vecT(flags, "flags", n, torch.uint8)
+        self._devices(field=field, flags=flags)
         L.check(L.lib().piv_validate(self.handle, _ptr(field), _ptr(flags), n, _stream(self.device)))
         return field, flags
 
     def vorticity(self, disp, omega=None):
+        self._fieldT(disp, "disp", 0)
         n = disp.shape[0]
+        self._batch(n)
         omega = self._vec(n) if omega is None else omega
+        self._vecT(omega, "omega", n)
+        self._devices(disp=disp, omega=omega)
         L.check(L.lib().piv_vorticity(self.handle, _ptr(disp), _ptr(omega), n, _stream(self.device)))
         return omega
 
@@ -148,32 +235,111 @@ class Plan:
         """predict -> validate(pred) -> correct -> validate -> vorticity."""
         n, pitch = self._images(A, B)
         if out is None:
-            out = dict(pred=self._field(n), disp=self._field(n), peak=self._vec(n),
-                       flags=self._vec(n, torch.uint8), omega=self._vec(n))
+            out = self._new_outputs(n)
+        self._outputs(n, out)
+        self._devices(A=A, B=B)
+        self._out_devices(out)
         L.check(L.lib().piv_run(self.handle, _ptr(A), _ptr(B), pitch, n, _ptr(out["pred"]),
                                 _ptr(out["disp"]), _ptr(out.get("peak")), _ptr(out["flags"]),
                                 _ptr(out["omega"]), _stream(self.device)))
         return out
 
-    def ssd_forward(self, A, B, U, loss=None):
+    def _new_outputs(self, n):
+        return dict(pred=self._field(n), disp=self._field(n), peak=self._vec(n),
+                    flags=self._vec(n, torch.uint8), omega=self._vec(n))
+
+    # -- temporal smoothing ----------------------------------------------------
+    def new_state(self, nstate: int) -> torch.Tensor:
+        """Zeroed smoothing state for `nstate` streams, [nstate][2][ny][nx]."""
+        return torch.zeros((nstate, 2, self.ny, self.nx), dtype=torch.float32, device=self.device)
+
+    def _slots(self, slot, n, state):
+        self._tensor(slot, "slot", torch.int32, (), n)
+        if state is not None:
+            self._tensor(state, "state", torch.float32, (2, self.ny, self.nx), 1)
+
+    def smooth(self, field, state, slot, alpha: float = 0.5):
+        """Exponential smoothing in time, in place on field [n][2][ny][nx]
+        with state [nstate][2][ny][nx] and slot int32 [n] (k continues state
+        k, -1-k starts it)."""
+        self._fieldT(field, "field", 0)
+        n = field.shape[0]
+        self._batch(n)
+        if state is None:
+            raise ValueError("state must not be None")
+        self._slots(slot, n, state)
+        self._devices(field=field, state=state, slot=slot)
+        L.check(L.lib().piv_smooth(self.handle, _ptr(field), _ptr(state), _ptr(slot), state.shape[0],
+                                   float(alpha), n, _stream(self.device)))
+        return field
+
+    def run_temporal(self, A, B, slot, state_pred=None, state_disp=None, alpha1: float = 0.5,
+                     alpha2: float = 0.5, out: Optional[Dict[str, torch.Tensor]] = None):
+        """The path with the paper's exponential smoothing of the validated
+        predictor (alpha1, state_pred) and of the final field (alpha2,
+        state_disp); both states [nstate][2][ny][nx], slot int32 [n]."""
+        n, pitch = self._images(A, B)
+        if out is None:
+            out = self._new_outputs(n)
+        self._outputs(n, out)
+        nstate = None
+        for st in (state_pred, state_disp):
+            self._slots(slot, n, st)
+            if st is not None:
+                if nstate is not None and st.shape[0] != nstate:
+                    raise ValueError("state_pred and state_disp must hold the same number of streams")
+                nstate = st.shape[0]
+        self._devices(A=A, B=B, slot=slot, state_pred=state_pred, state_disp=state_disp)
+        self._out_devices(out)
+        L.check(L.lib().piv_run_temporal(self.handle, _ptr(A), _ptr(B), pitch, n, _ptr(slot), nstate or 1,
+                                         _ptr(state_pred), _ptr(state_disp), float(alpha1), float(alpha2),
+                                         _ptr(out["pred"]), _ptr(out["disp"]), _ptr(out.get("peak")),
+                                         _ptr(out["flags"]), _ptr(out["omega"]), _stream(self.device)))
+        return out
+
+    # -- differentiable SSD (addition) ------------------------------------------
+    def _ssd_inputs(self, A, B, U):
+        for t, nm in ((A, "A"), (B, "B")):
+            self._tensor(t, nm, torch.float32, (self.height, self.width), 0)
         n = A.shape[0]
-        self._f32(A, B, U)
+        if B.shape[0] != n:
+            raise ValueError("A and B must hold the same number of pairs")
+        self._batch(n)
+        self._fieldT(U, "U", n)
+        return n
+
+    def ssd_forward(self, A, B, U, loss=None):
+        n = self._ssd_inputs(A, B, U)
         loss = self._vec(n) if loss is None else loss
+        self._vecT(loss, "loss", n)
+        self._devices(A=A, B=B, U=U, loss=loss)
         L.check(L.lib().piv_ssd_forward(self.handle, _ptr(A), _ptr(B), _ptr(U), n, _ptr(loss),
                                         _stream(self.device)))
         return loss
 
     def ssd_backward(self, A, B, U, g_loss, g_U=None, gn_diag=None, want_diag=True):
-        n = A.shape[0]
-        self._f32(A, B, U, g_loss)
+        n = self._ssd_inputs(A, B, U)
+        self._vecT(g_loss, "g_loss", n)
         g_U = self._field(n) if g_U is None else g_U
+        self._fieldT(g_U, "g_U", n)
         if gn_diag is None and want_diag:
             gn_diag = self._field(n)
+        if gn_diag is not None:
+            self._fieldT(gn_diag, "gn_diag", n)
+        self._devices(A=A, B=B, U=U, g_loss=g_loss, g_U=g_U, gn_diag=gn_diag)
         L.check(L.lib().piv_ssd_backward(self.handle, _ptr(A), _ptr(B), _ptr(U), _ptr(g_loss), n,
                                          _ptr(g_U), _ptr(gn_diag), _stream(self.device)))
         return g_U, gn_diag
 
-    def _f32(self, *ts):
-        for t in ts:
-            if t.dtype != torch.float32 or not t.is_contiguous() or t.device.type != "cuda":
-                raise TypeError("SSD tensors must be contiguous float32 device tensors")
+    def ssd_refine(self, A, B, U, steps: int = 10, tau: float = 4.0 / 9.0, lam_rel: float = 1e-3,
+                   hist=None):
+        """`steps` preconditioned gradient steps on the total windowed SSD,
+        in place on U [n][2][ny][nx]; hist (optional) [n][steps + 1] float32
+        receives the total loss before each step and after the last."""
+        n = self._ssd_inputs(A, B, U)
+        if hist is not None:
+            self._tensor(hist, "hist", torch.float32, (steps + 1,), n)
+        self._devices(A=A, B=B, U=U, hist=hist)
+        L.check(L.lib().piv_ssd_refine(self.handle, _ptr(A), _ptr(B), _ptr(U), n, int(steps), float(tau),
+                                       float(lam_rel), _ptr(hist), _stream(self.device)))
+        return U, hist

@@ -12,7 +12,7 @@ two estimates can be compared node by node.
 """
 from __future__ import annotations
 
-from typing import List, Tuple
+from typing import Tuple
 
 import torch
 
@@ -46,24 +46,18 @@ def warp_ssd(A, B, U, plan: Plan) -> torch.Tensor:
 
 
 def refine(plan: Plan, A: torch.Tensor, B: torch.Tensor, U0: torch.Tensor, steps: int = 10,
-           lam_rel: float = 1e-3, tau: float = 4.0 / 9.0) -> Tuple[torch.Tensor, List[float]]:
+           lam_rel: float = 1e-3, tau: float = 4.0 / 9.0) -> Tuple[torch.Tensor, torch.Tensor]:
     """`steps` diagonally preconditioned gradient steps on the total windowed
-    SSD, from U0 [n][2][ny][nx]:  U <- U - tau dL/dU / (D + lambda), with D
-    the Gauss-Newton diagonal and lambda = lam_rel * mean(D) per pair.
+    SSD, from U0 [n][2][ny][nx] (left unchanged):
+    U <- U - tau dL/dU / (D + lambda), with D the Gauss-Newton diagonal and
+    lambda = lam_rel * mean(D) per pair, all on the device (piv_ssd_refine).
 
     The diagonal ignores that neighbouring nodes share pixels: when they
     err together, the step overshoots by sum(w)/sum(w^2) over a node's
     support, which is (3/2)^2 = 9/4 for bilinear hat weights; tau = 4/9
-    removes that factor.  Returns the refined field and the total loss
-    before each step and after the last."""
-    U = U0.clone().contiguous()
-    ones = torch.ones((U.shape[0], plan.ny, plan.nx), dtype=torch.float32, device=U.device)
-    history = []
-    for _ in range(steps):
-        loss = plan.ssd_forward(A, B, U)
-        history.append(float(loss.sum()))
-        gU, D = plan.ssd_backward(A, B, U, ones)
-        lam = lam_rel * D.mean(dim=(1, 2, 3), keepdim=True)
-        U = U - tau * gU / (D + lam)
-    history.append(float(plan.ssd_forward(A, B, U).sum()))
-    return U, history
+    removes that factor.  Returns the refined field and the device tensor
+    [n][steps + 1] of total losses before each step and after the last."""
+    U = U0.detach().clone().contiguous()
+    hist = torch.empty((U.shape[0], steps + 1), dtype=torch.float32, device=U.device)
+    plan.ssd_refine(A, B, U, steps=steps, tau=tau, lam_rel=lam_rel, hist=hist)
+    return U, hist

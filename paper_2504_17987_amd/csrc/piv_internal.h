@@ -37,14 +37,14 @@ struct Plan {
   Level lv[kMaxLevels];
   size_t off_raw;     // per-pair offset of a float [2][ny][nx] field: the detection-pass
                       // input of validation
+  // F32 plans only: per-pair offsets of the refinement's gradient and
+  // Gauss-Newton diagonal ([2][ny][nx] each) and window losses ([ny][nx])
+  size_t off_gu = 0, off_dd = 0, off_loss = 0;
   size_t per_pair;    // workspace bytes per pair
   uint8_t* ws = nullptr;
   size_t ws_bytes = 0;
   int ws_pairs = 0;   // pairs the bound workspace can hold
   const uint8_t* slot_mask = nullptr;
-  // the pyramid margins of the bound workspace have been zeroed (they are
-  // written once, at the first predict after binding)
-  mutable bool margins_clean = false;
 };
 
 // Image view of one frame batch.
@@ -55,6 +55,9 @@ struct Img {
 };
 
 // ---- launchers (return hipError_t of the launch) ----
+// zero every pyramid margin of `pairs` pairs of the workspace at ws (laid out
+// as the plan's); the pyramid copy kernels write the image cores only
+hipError_t launch_clear_margins(const Plan& P, uint8_t* ws, int pairs, hipStream_t s);
 hipError_t launch_pyramid(const Plan& P, const void* A, const void* B, int64_t pitch, int n,
                           hipStream_t s);
 hipError_t launch_sad_level(const Plan& P, int l, const void* A, const void* B, int64_t pitch,
@@ -73,13 +76,23 @@ hipError_t launch_pred_validate(const Plan& P, int n, float* pred, hipStream_t s
 hipError_t launch_vorticity(const Plan& P, const float* disp, float* omega, int n, hipStream_t s);
 hipError_t launch_ssd_forward(const Plan& P, const float* A, const float* B, const float* U, int n,
                               float* loss, hipStream_t s);
+// g NULL: every window's upstream gradient is 1
 hipError_t launch_ssd_backward(const Plan& P, const float* A, const float* B, const float* U,
                                const float* g, int n, float* gU, float* D, hipStream_t s);
+// one refinement update per pair from the workspace's gradient, diagonal and
+// losses: hist[pair * hstride + k] = total loss (if hist), and, when update
+// is set, U -= tau gU / (D + lam_rel mean(D))
+hipError_t launch_ssd_update(const Plan& P, float* U, int n, float tau, float lam_rel, float* hist,
+                             int hstride, int k, int update, hipStream_t s);
+// exponential smoothing in time: see piv_smooth in include/piv.h
+hipError_t launch_smooth(const Plan& P, float* field, float* state, const int32_t* slot, int nstate,
+                         float alpha, int n, hipStream_t s);
 
 // Block widths (in 4-byte words) the SAD kernel is built for.
 bool sad_supported(int block_words);
 
 // Which correlation kernel a plan uses (exposed for tests and the bench).
 int correct_impl(const Plan& P);
+
 
 }  // namespace piv

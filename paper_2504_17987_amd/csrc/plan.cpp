@@ -80,7 +80,7 @@ piv_status piv_plan(const piv_params* pp, piv_plan_t* out) {
   if (!pp) return fail(PIV_EINVAL, "params is NULL");
   const piv_params& p = *pp;
   if (p.width <= 0 || p.height <= 0) return fail(PIV_EINVAL, "image size must be positive");
-  if (p.max_batch <= 0) return fail(PIV_EINVAL, "max_batch must be positive");
+  if (p.max_batch <= 0 || p.max_batch > 16384) return fail(PIV_EINVAL, "max_batch outside [1, 16384]");
   int es = p.dtype == PIV_U8 ? 1 : p.dtype == PIV_U16 ? 2 : p.dtype == PIV_F32 ? 4 : 0;
   if (!es) return fail(PIV_EINVAL, "unknown dtype %d", (int)p.dtype);
   if (p.dtype == PIV_U16 && p.bit_depth != 12 && p.bit_depth != 16)
@@ -156,6 +156,15 @@ piv_status piv_plan(const piv_params* pp, piv_plan_t* out) {
   }
   P->off_raw = off;
   off = align256(off + sizeof(float) * 2 * (size_t)P->nx * P->ny);
+  if (p.dtype == PIV_F32) {
+    const size_t np = (size_t)P->nx * P->ny;
+    P->off_gu = off;
+    off = align256(off + sizeof(float) * 2 * np);
+    P->off_dd = off;
+    off = align256(off + sizeof(float) * 2 * np);
+    P->off_loss = off;
+    off = align256(off + sizeof(float) * np);
+  }
   P->per_pair = off;
   *out = reinterpret_cast<piv_plan_t>(P);
   g_err[0] = 0;
@@ -174,18 +183,25 @@ size_t piv_plan_workspace_bytes(piv_plan_t plan, int32_t batch) {
   return cplan(plan)->per_pair * (size_t)batch;
 }
 
-piv_status piv_plan_bind_workspace(piv_plan_t plan, void* d_ws, size_t bytes) {
+piv_status piv_plan_bind_workspace(piv_plan_t plan, void* d_ws, size_t bytes, hipStream_t stream) {
   if (!plan) return fail(PIV_EINVAL, "plan is NULL");
   Plan* P = mplan(plan);
   if (d_ws && ((uintptr_t)d_ws & 255)) return fail(PIV_EINVAL, "workspace must be 256-byte aligned");
+  const size_t cap = d_ws ? bytes / P->per_pair : 0;
+  if (d_ws && cap == 0)
+    return fail(PIV_ENOWORKSPACE, "workspace of %zu bytes holds no pair (need %zu)", bytes, P->per_pair);
+  // calls never pass more than max_batch pairs
+  const int pairs = (int)(cap < (size_t)P->p.max_batch ? cap : (size_t)P->p.max_batch);
+  if (d_ws) {
+    // the pyramid margins are zeroed here, once, so that every later call
+    // only reads the plan (and may be captured into a graph)
+    if (piv_status s = dev(piv::launch_clear_margins(*P, static_cast<uint8_t*>(d_ws), pairs, stream),
+                           "clear_margins"))
+      return s;
+  }
   P->ws = static_cast<uint8_t*>(d_ws);
   P->ws_bytes = d_ws ? bytes : 0;
-  P->ws_pairs = d_ws ? (int)(bytes / P->per_pair) : 0;
-  P->margins_clean = false;
-  if (d_ws && P->ws_pairs == 0) {
-    P->ws = nullptr;
-    return fail(PIV_ENOWORKSPACE, "workspace of %zu bytes holds no pair (need %zu)", bytes, P->per_pair);
-  }
+  P->ws_pairs = pairs;
   return PIV_OK;
 }
 
@@ -242,31 +258,97 @@ piv_status piv_vorticity(piv_plan_t plan, const float* disp, float* omega, int32
   return dev(piv::launch_vorticity(P, disp, omega, n, stream), "vorticity");
 }
 
-piv_status piv_run(piv_plan_t plan, const void* A, const void* B, int64_t pitch, int32_t n,
-                   float* pred, float* disp, float* peak, uint8_t* flags, float* omega,
-                   hipStream_t stream) {
-  if (!plan) return fail(PIV_EINVAL, "plan is NULL");
-  const Plan& P = *cplan(plan);
-  if (piv_status s = check_images(P, A, B, pitch, n)) return s;
-  if (!pred || !disp || !flags || !omega) return fail(PIV_EINVAL, "pred, disp, flags, omega must not be NULL");
-  if (piv_status s = need_ws(P, n)) return s;
-  if (n == 0) return PIV_OK;
-  // the same steps as predict, validate, correct, validate, vorticity; the
-  // predictor's output step and its validation are one kernel, and the
-  // correction writes the detection-pass field to the workspace, from which
-  // validation writes disp
-  if (P.p.dtype == PIV_F32) return fail(PIV_EUNSUPPORTED, "the predictor takes U8/U16 frames");
+namespace {
+
+// The steps of piv_run (and of piv_run_temporal with smoothing states): the
+// predictor's output step and its validation are one kernel, and the
+// correction writes the detection-pass field to the workspace, from which
+// validation writes disp.
+struct Temporal {
+  const int32_t* slot;
+  int32_t nstate;
+  float* state_pred;
+  float* state_disp;
+  float alpha1, alpha2;
+};
+
+piv_status run_path(const Plan& P, const void* A, const void* B, int64_t pitch, int32_t n, float* pred,
+                    float* disp, float* peak, uint8_t* flags, float* omega, const Temporal* tm,
+                    hipStream_t stream) {
   if (piv_status s = dev(piv::launch_pyramid(P, A, B, pitch, n, stream), "pyramid")) return s;
   for (int l = P.L - 1; l >= 0; --l)
     if (piv_status s = dev(piv::launch_sad_level(P, l, A, B, pitch, n, stream), "sad_search")) return s;
   if (piv_status s = dev(piv::launch_pred_validate(P, n, pred, stream), "pred_validate")) return s;
+  if (tm && tm->state_pred)
+    if (piv_status s = dev(piv::launch_smooth(P, pred, tm->state_pred, tm->slot, tm->nstate, tm->alpha1, n,
+                                              stream), "smooth_pred"))
+      return s;
   float* raw = reinterpret_cast<float*>(P.ws + P.off_raw);
   const int64_t rstride = (int64_t)(P.per_pair / sizeof(float));
   if (piv_status s = dev(piv::launch_correct(P, A, B, pitch, n, pred, raw, peak, flags, stream, rstride),
                          "correct"))
     return s;
   if (piv_status s = dev(piv::launch_uod(P, raw, rstride, disp, flags, n, stream), "validate")) return s;
+  if (tm && tm->state_disp)
+    if (piv_status s = dev(piv::launch_smooth(P, disp, tm->state_disp, tm->slot, tm->nstate, tm->alpha2, n,
+                                              stream), "smooth_disp"))
+      return s;
   return dev(piv::launch_vorticity(P, disp, omega, n, stream), "vorticity");
+}
+
+piv_status check_run(const Plan& P, const void* A, const void* B, int64_t pitch, int32_t n, float* pred,
+                     float* disp, uint8_t* flags, float* omega) {
+  if (piv_status s = check_images(P, A, B, pitch, n)) return s;
+  if (!pred || !disp || !flags || !omega) return fail(PIV_EINVAL, "pred, disp, flags, omega must not be NULL");
+  if (P.p.dtype == PIV_F32) return fail(PIV_EUNSUPPORTED, "the predictor takes U8/U16 frames");
+  return need_ws(P, n);
+}
+
+piv_status check_alpha(float a, const char* name) {
+  if (!(a > 0.0f && a <= 1.0f)) return fail(PIV_EINVAL, "%s=%g outside (0, 1]", name, (double)a);
+  return PIV_OK;
+}
+
+}  // namespace
+
+piv_status piv_run(piv_plan_t plan, const void* A, const void* B, int64_t pitch, int32_t n,
+                   float* pred, float* disp, float* peak, uint8_t* flags, float* omega,
+                   hipStream_t stream) {
+  if (!plan) return fail(PIV_EINVAL, "plan is NULL");
+  const Plan& P = *cplan(plan);
+  if (piv_status s = check_run(P, A, B, pitch, n, pred, disp, flags, omega)) return s;
+  if (n == 0) return PIV_OK;
+  return run_path(P, A, B, pitch, n, pred, disp, peak, flags, omega, nullptr, stream);
+}
+
+piv_status piv_smooth(piv_plan_t plan, float* field, float* state, const int32_t* slot, int32_t nstate,
+                      float alpha, int32_t n, hipStream_t stream) {
+  if (!plan) return fail(PIV_EINVAL, "plan is NULL");
+  const Plan& P = *cplan(plan);
+  if (!field || !state || !slot) return fail(PIV_EINVAL, "field, state and slot must not be NULL");
+  if (n < 0 || n > P.p.max_batch) return fail(PIV_EINVAL, "n=%d outside [0, max_batch]", n);
+  if (nstate <= 0) return fail(PIV_EINVAL, "nstate must be positive");
+  if (piv_status s = check_alpha(alpha, "alpha")) return s;
+  if (n == 0) return PIV_OK;
+  return dev(piv::launch_smooth(P, field, state, slot, nstate, alpha, n, stream), "smooth");
+}
+
+piv_status piv_run_temporal(piv_plan_t plan, const void* A, const void* B, int64_t pitch, int32_t n,
+                            const int32_t* slot, int32_t nstate, float* state_pred, float* state_disp,
+                            float alpha1, float alpha2, float* pred, float* disp, float* peak,
+                            uint8_t* flags, float* omega, hipStream_t stream) {
+  if (!plan) return fail(PIV_EINVAL, "plan is NULL");
+  const Plan& P = *cplan(plan);
+  if (piv_status s = check_run(P, A, B, pitch, n, pred, disp, flags, omega)) return s;
+  if (!slot) return fail(PIV_EINVAL, "slot must not be NULL");
+  if (nstate <= 0) return fail(PIV_EINVAL, "nstate must be positive");
+  if (state_pred)
+    if (piv_status s = check_alpha(alpha1, "alpha1")) return s;
+  if (state_disp)
+    if (piv_status s = check_alpha(alpha2, "alpha2")) return s;
+  if (n == 0) return PIV_OK;
+  const Temporal tm{slot, nstate, state_pred, state_disp, alpha1, alpha2};
+  return run_path(P, A, B, pitch, n, pred, disp, peak, flags, omega, &tm, stream);
 }
 
 piv_status piv_ssd_forward(piv_plan_t plan, const float* A, const float* B, const float* U, int32_t n,
@@ -291,6 +373,36 @@ piv_status piv_ssd_backward(piv_plan_t plan, const float* A, const float* B, con
   return dev(piv::launch_ssd_backward(P, A, B, U, g, n, gU, D, stream), "ssd_backward");
 }
 
+piv_status piv_ssd_refine(piv_plan_t plan, const float* A, const float* B, float* U, int32_t n,
+                          int32_t steps, float tau, float lam_rel, float* hist, hipStream_t stream) {
+  if (!plan) return fail(PIV_EINVAL, "plan is NULL");
+  const Plan& P = *cplan(plan);
+  if (P.p.dtype != PIV_F32) return fail(PIV_EINVAL, "SSD needs a PIV_F32 plan");
+  if (!A || !B || !U) return fail(PIV_EINVAL, "NULL pointer");
+  if (n < 0 || n > P.p.max_batch) return fail(PIV_EINVAL, "n=%d outside [0, max_batch]", n);
+  if (steps < 0 || steps > 10000) return fail(PIV_EINVAL, "steps=%d outside [0, 10000]", steps);
+  if (!(tau > 0.0f) || !(tau <= 16.0f)) return fail(PIV_EINVAL, "tau=%g outside (0, 16]", (double)tau);
+  if (!(lam_rel >= 0.0f) || !(lam_rel <= 1e6f)) return fail(PIV_EINVAL, "lam_rel=%g outside [0, 1e6]", (double)lam_rel);
+  if (piv_status s = need_ws(P, n)) return s;
+  if (n == 0) return PIV_OK;
+  // per step: window losses (for the history), gradient and Gauss-Newton
+  // diagonal of the total loss into the workspace, then the update
+  for (int k = 0; k <= steps; ++k) {
+    const bool upd = k < steps;
+    if (hist)
+      if (piv_status s = dev(piv::launch_ssd_forward(P, A, B, U, n, nullptr, stream), "ssd_forward")) return s;
+    if (upd)
+      if (piv_status s = dev(piv::launch_ssd_backward(P, A, B, U, nullptr, n, nullptr, nullptr, stream),
+                             "ssd_backward"))
+        return s;
+    if (hist || upd)
+      if (piv_status s = dev(piv::launch_ssd_update(P, U, n, tau, lam_rel, hist, steps + 1, k, upd ? 1 : 0,
+                                                    stream), "ssd_update"))
+        return s;
+  }
+  return PIV_OK;
+}
+
 const char* piv_status_string(piv_status s) {
   switch (s) {
     case PIV_OK: return "PIV_OK";
@@ -304,12 +416,12 @@ const char* piv_status_string(piv_status s) {
 
 const char* piv_last_error(void) { return g_err; }
 
-// Not part of the public header: which correlation kernel a plan selects
-// (0 = generic per-window, 1 = cell-shared tiled).  Used by tests and bench.
+// Diagnostics (declared at the end of include/piv.h): which correlation
+// kernel a plan selects (0 = generic per-window, 1 = cell-shared tiled).
 int piv_debug_correct_impl(piv_plan_t plan) { return plan ? piv::correct_impl(*cplan(plan)) : -1; }
 
-// Not part of the public header: geometry of pyramid level l, for host-side
-// checks of the kernels' read extents.  out: W, H, margin, pitch, rows, R,
+// Geometry of pyramid level l, for host-side checks of the kernels' read
+// extents.  out: W, H, margin, pitch, rows, R,
 // nx, ny, es, step, block.  Returns 0, or -1 for a bad level.
 int piv_debug_level(piv_plan_t plan, int32_t l, int32_t* out) {
   if (!plan || !out) return -1;

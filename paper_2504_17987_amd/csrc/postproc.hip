@@ -266,7 +266,41 @@ __global__ __launch_bounds__(256) void k_vorticity(const float* disp, float* ome
   omega[(int64_t)pair * np + i] = dvdx - dudy;
 }
 
+// Exponential smoothing in time (Sec. 2: constants alpha1 on the validated
+// predictor, alpha2 on the validated final field).  One thread per field
+// element walks the batch in order, so that pairs of one state slot (frames
+// of one stream) chain: slot k >= 0 continues, s_k <- alpha x + (1 - alpha)
+// s_k; slot -1 - k starts, s_k <- x; the field takes s_k.  Slots outside
+// [0, nstate) leave their pair untouched.
+__global__ __launch_bounds__(256) void k_smooth(float* field, float* state, const int32_t* slot, int nstate,
+                                                float alpha, int n, int np2, const uint8_t* smask) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= np2) return;
+  const float beta = 1.0f - alpha;
+  for (int i = 0; i < n; ++i) {
+    if (slot_off(smask, i)) continue;
+    int k = slot[i];
+    const bool first = k < 0;
+    if (first) k = -1 - k;
+    if (k >= nstate) continue;
+    float* st = state + (int64_t)k * np2 + j;
+    float* f = field + (int64_t)i * np2 + j;
+    const float x = *f;
+    const float y = first ? x : alpha * x + beta * *st;
+    *st = y;
+    *f = y;
+  }
+}
+
 }  // namespace
+
+hipError_t launch_smooth(const Plan& P, float* field, float* state, const int32_t* slot, int nstate, float alpha,
+                         int n, hipStream_t s) {
+  const int np2 = 2 * P.nx * P.ny;
+  hipLaunchKernelGGL(k_smooth, dim3((np2 + 255) / 256), dim3(256), 0, s, field, state, slot, nstate, alpha, n, np2,
+                     P.slot_mask);
+  return hipGetLastError();
+}
 
 hipError_t launch_uod(const Plan& P, const float* src, int64_t sstride, float* dst, uint8_t* flags,
                       int n, hipStream_t s) {

@@ -1430,20 +1430,27 @@ static bool level0_in_place(const Plan& P, int64_t pitch) {
          (int64_t)P.p.height * pitch < (int64_t(1) << 31);
 }
 
-hipError_t launch_pyramid(const Plan& P, const void* A, const void* B, int64_t pitch, int n,
-                          hipStream_t s) {
-  if (!P.margins_clean) {
-    // every level's margins, for every pair the workspace holds
+hipError_t launch_clear_margins(const Plan& P, uint8_t* ws, int pairs, hipStream_t s) {
+  if (P.p.dtype == PIV_F32 || pairs <= 0) return hipSuccess;   // no pyramid on F32 plans
+  // every level's margins, for every pair (grid z holds 2 frames x at most
+  // 16384 pairs per launch)
+  for (int p0 = 0; p0 < pairs; p0 += 16384) {
+    const int np = min(pairs - p0, 16384);
+    uint8_t* base = ws + (size_t)p0 * P.per_pair;
     for (int l = 0; l < P.L; ++l) {
       const Level& v = P.lv[l];
       const int64_t words = (int64_t)(v.pitch / 4) * v.rows;
-      dim3 grid((unsigned)((words + 255) / 256), 1, 2 * P.ws_pairs);
-      hipLaunchKernelGGL(k_clear_margins, grid, dim3(256), 0, s, P.ws, (int64_t)P.per_pair, (int64_t)v.off_a,
+      dim3 grid((unsigned)((words + 255) / 256), 1, 2 * np);
+      hipLaunchKernelGGL(k_clear_margins, grid, dim3(256), 0, s, base, (int64_t)P.per_pair, (int64_t)v.off_a,
                          (int64_t)v.off_b, v.pitch, v.rows, v.margin * P.es, v.W * P.es, v.margin, v.H);
       if (hipError_t e = hipGetLastError()) return e;
     }
-    P.margins_clean = true;
   }
+  return hipSuccess;
+}
+
+hipError_t launch_pyramid(const Plan& P, const void* A, const void* B, int64_t pitch, int n,
+                          hipStream_t s) {
   const Level& v0 = P.lv[0];
   const bool l2 = P.L > 2;   // levels 1 and 2 from one read of the frames
   {

@@ -20,9 +20,11 @@ struct SsdArgs {
   const float* U;
   int W, H, nx, ny, win, step;
   float* loss;
-  const float* g;
+  const float* g;       // NULL: every window's upstream gradient is 1
   float* gU;
   float* D;
+  int64_t lstride;      // floats per pair of loss
+  int64_t gstride;      // floats per pair of gU and D
   const uint8_t* mask;
 };
 
@@ -121,7 +123,7 @@ __global__ __launch_bounds__(256) void k_ssd_forward(SsdArgs a, int TN) {
   s += __shfl_xor(s, 2);
   if (w < TN * TN && p == 0) {
     int aa = ta + wi, bb = tb + wj;
-    if (aa < a.ny && bb < a.nx) a.loss[(int64_t)pair * np + aa * a.nx + bb] = s;
+    if (aa < a.ny && bb < a.nx) a.loss[(int64_t)pair * a.lstride + aa * a.nx + bb] = s;
   }
 }
 
@@ -140,7 +142,7 @@ __global__ __launch_bounds__(256) void k_ssd_backward(SsdArgs a, int TN) {
   const float* A = a.A + pair * img;
   const float* B = a.B + pair * img;
   const float* U = a.U + (int64_t)pair * 2 * np;
-  const float* G = a.g + (int64_t)pair * np;
+  const float* G = a.g ? a.g + (int64_t)pair * np : nullptr;
   const int h = (a.win - a.step) / 2;
   const int ta = blockIdx.y * TN, tb = blockIdx.x * TN;
   // pixel support of the tile's nodes (clamped interpolation extends the
@@ -164,7 +166,7 @@ __global__ __launch_bounds__(256) void k_ssd_backward(SsdArgs a, int TN) {
     int b0 = max(fdiv(x + h - a.win + a.step, a.step), 0), b1 = min(fdiv(x + h, a.step), a.nx - 1);
     float m = 0.0f;
     for (int i = a0; i <= a1; ++i)
-      for (int j = b0; j <= b1; ++j) m += G[i * a.nx + j];
+      for (int j = b0; j <= b1; ++j) m += G ? G[i * a.nx + j] : 1.0f;
     float r = 0.0f, gx = 0.0f, gy = 0.0f;
     if (m != 0.0f) residual(a, A, B, U, x, y, r, gx, gy);
     T0[idx] = 2.0f * m * r * gx;
@@ -206,11 +208,11 @@ __global__ __launch_bounds__(256) void k_ssd_backward(SsdArgs a, int TN) {
   }
   if (act && lane == 0) {
     const int i = na * a.nx + nb;
-    float* gU = a.gU + (int64_t)pair * 2 * np;
+    float* gU = a.gU + (int64_t)pair * a.gstride;
     gU[i] = s0;
     gU[np + i] = s1;
     if (a.D) {
-      float* D = a.D + (int64_t)pair * 2 * np;
+      float* D = a.D + (int64_t)pair * a.gstride;
       D[i] = s2;
       D[np + i] = s3;
     }
@@ -340,7 +342,7 @@ __global__ __launch_bounds__(256) void k_ssd_forward_t(SsdArgs a) {
   s += __shfl_xor(s, 2);
   if (w < TN * TN && p == 0) {
     const int aa = ta + wi, bb = tb + wj;
-    if (aa < a.ny && bb < a.nx) a.loss[(int64_t)pair * np + aa * a.nx + bb] = s;
+    if (aa < a.ny && bb < a.nx) a.loss[(int64_t)pair * a.lstride + aa * a.nx + bb] = s;
   }
 }
 
@@ -371,7 +373,7 @@ __global__ __launch_bounds__(256) void k_ssd_backward_t(SsdArgs a) {
   const float* A = a.A + pair * img;
   const float* B = a.B + pair * img;
   const float* U = a.U + (int64_t)pair * 2 * np;
-  const float* G = a.g + (int64_t)pair * np;
+  const float* G = a.g ? a.g + (int64_t)pair * np : nullptr;
   const int ta = wg.y * TN, tb = wg.x * TN;
   constexpr int h = C::H2;
   const int lo_all = -h, hi_x = a.nx * STEP + h - 1, hi_y = a.ny * STEP + h - 1;
@@ -387,7 +389,7 @@ __global__ __launch_bounds__(256) void k_ssd_backward_t(SsdArgs a) {
   for (int i = t; i < C::NG * C::NG; i += 256) {
     const int r = i / C::NG, q = i - (i / C::NG) * C::NG;
     const int gi = gi0 + r, gj = gj0 + q;
-    s_g[r][q] = (gi < a.ny && gj < a.nx) ? G[gi * a.nx + gj] : 0.0f;
+    s_g[r][q] = (gi < a.ny && gj < a.nx) ? (G ? G[gi * a.nx + gj] : 1.0f) : 0.0f;
   }
   int nly, nlx;
   ssd_prepare<STEP, TN>(a, U, ylo, xlo, RH, RWc, sh, nly, nlx);
@@ -464,9 +466,9 @@ __global__ __launch_bounds__(256) void k_ssd_backward_t(SsdArgs a) {
     }
     const int idx = na * a.nx + nb;
     if (term < 2) {
-      a.gU[(int64_t)pair * 2 * np + term * np + idx] = s;
+      a.gU[(int64_t)pair * a.gstride + term * np + idx] = s;
     } else if (a.D) {
-      a.D[(int64_t)pair * 2 * np + (term - 2) * np + idx] = s;
+      a.D[(int64_t)pair * a.gstride + (term - 2) * np + idx] = s;
     }
   }
 }
@@ -486,8 +488,60 @@ SsdArgs make_args(const Plan& P, const float* A, const float* B, const float* U)
   a.g = nullptr;
   a.gU = nullptr;
   a.D = nullptr;
+  a.lstride = (int64_t)P.nx * P.ny;
+  a.gstride = 2 * (int64_t)P.nx * P.ny;
   a.mask = P.slot_mask;
   return a;
+}
+
+// Refinement update, one workgroup per pair: the total window loss into the
+// history, and U <- U - tau gU / (D + lambda) with lambda = lam_rel mean(D).
+// Sums run in a fixed order (per-thread strided partials, then a fixed
+// tree), so results are bitwise reproducible.  A node component whose
+// D + lambda is not positive is left unchanged.
+constexpr int kUpdT = 256;
+
+__device__ __forceinline__ float block_sum(float x, float* red) {
+  const int t = threadIdx.x;
+  red[t] = x;
+  __syncthreads();
+#pragma unroll
+  for (int o = kUpdT / 2; o > 0; o >>= 1) {
+    if (t < o) red[t] += red[t + o];
+    __syncthreads();
+  }
+  const float r = red[0];
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(kUpdT) void k_ssd_update(float* U, const float* gU, const float* D,
+                                                      const float* loss, int64_t wstride, int np, float tau,
+                                                      float lam_rel, float* hist, int hstride, int k,
+                                                      int update, const uint8_t* mask) {
+  __shared__ float red[kUpdT];
+  const int pair = blockIdx.x;
+  if (slot_off(mask, pair)) return;
+  const int t = threadIdx.x;
+  if (hist) {
+    const float* L = loss + (int64_t)pair * wstride;
+    float s = 0.0f;
+    for (int i = t; i < np; i += kUpdT) s += L[i];
+    s = block_sum(s, red);
+    if (t == 0) hist[(int64_t)pair * hstride + k] = s;
+  }
+  if (!update) return;
+  const float* G = gU + (int64_t)pair * wstride;
+  const float* Dp = D + (int64_t)pair * wstride;
+  float* Up = U + (int64_t)pair * 2 * np;
+  float s = 0.0f;
+  for (int i = t; i < 2 * np; i += kUpdT) s += Dp[i];
+  s = block_sum(s, red);
+  const float lam = lam_rel * (s / (float)(2 * np));
+  for (int i = t; i < 2 * np; i += kUpdT) {
+    const float den = Dp[i] + lam;
+    if (den > 0.0f) Up[i] -= tau * G[i] / den;
+  }
 }
 
 }  // namespace
@@ -496,6 +550,10 @@ hipError_t launch_ssd_forward(const Plan& P, const float* A, const float* B, con
                               float* loss, hipStream_t s) {
   SsdArgs a = make_args(P, A, B, U);
   a.loss = loss;
+  if (!loss) {   // the workspace's window losses
+    a.loss = reinterpret_cast<float*>(P.ws + P.off_loss);
+    a.lstride = (int64_t)(P.per_pair / sizeof(float));
+  }
   // tile: at most 8 x 8 windows with a pixel region of at most 96 x 96
   if (a.step == 8 && a.win == 16) {
     dim3 grid((a.nx + 7) / 8, (a.ny + 7) / 8, n);
@@ -516,6 +574,11 @@ hipError_t launch_ssd_backward(const Plan& P, const float* A, const float* B, co
   a.g = g;
   a.gU = gU;
   a.D = D;
+  if (!gU) {   // the workspace's gradient and diagonal
+    a.gU = reinterpret_cast<float*>(P.ws + P.off_gu);
+    a.D = reinterpret_cast<float*>(P.ws + P.off_dd);
+    a.gstride = (int64_t)(P.per_pair / sizeof(float));
+  }
   if (a.step == 8 && a.win == 16) {
     dim3 grid((a.nx + 7) / 8, (a.ny + 7) / 8, n);
     hipLaunchKernelGGL((k_ssd_backward_t<8, 8>), grid, dim3(256), 0, s, a);
@@ -530,6 +593,16 @@ hipError_t launch_ssd_backward(const Plan& P, const float* A, const float* B, co
   if (lds > 65536) return hipErrorInvalidValue;
   dim3 grid((a.nx + TN - 1) / TN, (a.ny + TN - 1) / TN, n);
   hipLaunchKernelGGL(k_ssd_backward, grid, dim3(256), lds, s, a, TN);
+  return hipGetLastError();
+}
+
+hipError_t launch_ssd_update(const Plan& P, float* U, int n, float tau, float lam_rel, float* hist, int hstride,
+                             int k, int update, hipStream_t s) {
+  const int64_t ws_f = (int64_t)(P.per_pair / sizeof(float));
+  hipLaunchKernelGGL(k_ssd_update, dim3(n), dim3(kUpdT), 0, s, U,
+                     reinterpret_cast<const float*>(P.ws + P.off_gu), reinterpret_cast<const float*>(P.ws + P.off_dd),
+                     reinterpret_cast<const float*>(P.ws + P.off_loss), ws_f, P.nx * P.ny, tau, lam_rel, hist,
+                     hstride, k, update, P.slot_mask);
   return hipGetLastError();
 }
 

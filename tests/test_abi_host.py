@@ -65,6 +65,10 @@ def test_plan_validation(L, kw, status):
 
 
 def test_workspace_and_argument_errors(L):
+    """Argument errors come back before any launch.  Binding a workspace to
+    a U8 plan enqueues the zeroing of its margins, so the successful binds
+    here use an F32 plan (no pyramid, no device work) and a pointer that is
+    never dereferenced."""
     s, h = plan(L, max_batch=4)
     assert s == 0
     lib = L.lib()
@@ -73,20 +77,55 @@ def test_workspace_and_argument_errors(L):
     fake = C.c_void_p(1 << 20)   # never dereferenced: calls fail before any launch
     # no workspace bound
     assert lib.piv_predict(h, fake, fake, 1024, 1, fake, None) == L.PIV_ENOWORKSPACE
-    # misaligned workspace and too small workspace
-    assert lib.piv_plan_bind_workspace(h, C.c_void_p((1 << 20) + 4), per) == L.PIV_EINVAL
-    assert lib.piv_plan_bind_workspace(h, fake, per - 1) == L.PIV_ENOWORKSPACE
-    assert lib.piv_plan_bind_workspace(h, fake, 2 * per) == 0
-    assert lib.piv_predict(h, fake, fake, 1024, 3, fake, None) == L.PIV_ENOWORKSPACE
+    assert lib.piv_run(h, fake, fake, 1024, 1, fake, fake, None, fake, fake, None) == L.PIV_ENOWORKSPACE
+    # misaligned workspace and too small workspace (rejected before the margins are touched)
+    assert lib.piv_plan_bind_workspace(h, C.c_void_p((1 << 20) + 4), per, None) == L.PIV_EINVAL
+    assert lib.piv_plan_bind_workspace(h, fake, per - 1, None) == L.PIV_ENOWORKSPACE
     assert lib.piv_predict(h, fake, fake, 1024, 5, fake, None) == L.PIV_EINVAL      # n > max_batch
     assert lib.piv_correct(h, fake, fake, 1022, 1, None, fake, None, fake, None) == L.PIV_EINVAL  # pitch
     assert lib.piv_correct(h, None, fake, 1024, 1, None, fake, None, fake, None) == L.PIV_EINVAL
     assert lib.piv_correct(h, fake, fake, 1024, 1, None, None, None, fake, None) == L.PIV_EINVAL
     assert lib.piv_ssd_forward(h, fake, fake, fake, 1, fake, None) == L.PIV_EINVAL  # not an F32 plan
+    assert lib.piv_ssd_refine(h, fake, fake, fake, 1, 10, 0.5, 1e-3, None, None) == L.PIV_EINVAL
+    # smoothing: NULL state/slot, nstate, alpha out of (0, 1]
+    assert lib.piv_smooth(h, fake, None, fake, 1, 0.5, 1, None) == L.PIV_EINVAL
+    assert lib.piv_smooth(h, fake, fake, fake, 0, 0.5, 1, None) == L.PIV_EINVAL
+    assert lib.piv_smooth(h, fake, fake, fake, 1, 0.0, 1, None) == L.PIV_EINVAL
+    assert lib.piv_smooth(h, fake, fake, fake, 1, 1.5, 1, None) == L.PIV_EINVAL
+    assert lib.piv_smooth(h, fake, fake, fake, 1, 0.5, 0, None) == 0                 # n = 0: no-op
+    assert lib.piv_run_temporal(h, fake, fake, 1024, 1, None, 1, fake, fake, 0.5, 0.5, fake, fake, None,
+                                fake, fake, None) == L.PIV_ENOWORKSPACE
     assert lib.piv_status_string(3) == b"PIV_ENOWORKSPACE"
     # n = 0 is a no-op that succeeds
     assert lib.piv_vorticity(h, fake, fake, 0, None) == 0
     lib.piv_plan_destroy(h)
+    # F32 plan: binding does no device work
+    s, f = plan(L, max_batch=4, dtype=3, levels=1, width=64, height=64)
+    assert s == 0
+    perf = lib.piv_plan_workspace_bytes(f, 1)
+    assert lib.piv_ssd_refine(f, fake, fake, fake, 1, 10, 0.5, 1e-3, None, None) == L.PIV_ENOWORKSPACE
+    assert lib.piv_plan_bind_workspace(f, fake, 2 * perf, None) == 0
+    assert lib.piv_ssd_refine(f, fake, fake, fake, 3, 10, 0.5, 1e-3, None, None) == L.PIV_ENOWORKSPACE
+    assert lib.piv_ssd_refine(f, fake, fake, fake, 5, 10, 0.5, 1e-3, None, None) == L.PIV_EINVAL
+    assert lib.piv_ssd_refine(f, fake, fake, fake, 1, 10, 0.0, 1e-3, None, None) == L.PIV_EINVAL   # tau
+    assert lib.piv_ssd_refine(f, fake, fake, fake, 1, 10, 0.5, -1.0, None, None) == L.PIV_EINVAL   # lam_rel
+    assert lib.piv_ssd_refine(f, fake, fake, fake, 1, -1, 0.5, 1e-3, None, None) == L.PIV_EINVAL   # steps
+    assert lib.piv_ssd_refine(f, fake, fake, fake, 0, 10, 0.5, 1e-3, None, None) == 0              # n = 0
+    assert lib.piv_predict(f, fake, fake, 256, 1, fake, None) == L.PIV_EUNSUPPORTED
+    lib.piv_plan_destroy(f)
+
+
+def test_f32_workspace_holds_refinement_fields(L):
+    """F32 plans size their workspace for the refinement's gradient and
+    diagonal ([2][ny][nx] each) and window losses ([ny][nx]) per pair."""
+    lib = L.lib()
+    s, f = plan(L, dtype=3, levels=1, width=512, height=512)
+    s2, u = plan(L, dtype=1, levels=1, width=512, height=512)
+    assert s == 0 and s2 == 0
+    np_ = 64 * 64
+    assert lib.piv_plan_workspace_bytes(f, 1) >= 5 * 4 * np_ + 2 * 4 * np_
+    lib.piv_plan_destroy(f)
+    lib.piv_plan_destroy(u)
 
 
 def _levels(L, **kw):
