@@ -44,12 +44,16 @@ class GraphRunner:
     this runner (its workspace and slot mask are used by the captured
     kernels), with max_batch >= slots."""
 
-    def __init__(self, plan, slots: int, stream=None):
+    def __init__(self, plan, slots: int, stream=None, temporal: Optional[dict] = None):
+        """temporal (optional): dict(state_pred=, state_disp=, alpha1=,
+        alpha2=) -- the captured path is then piv_run_temporal with this
+        runner's device slot table (``set_slots``) into those states."""
         import torch
         from .api import Plan  # noqa: F401
         self.torch = torch
         self.plan = plan
         self.slots = slots
+        self.temporal = temporal
         dev = plan.device
         H, W = plan.height, plan.width
         self.A = torch.zeros((slots, H, W), dtype=plan.tdtype, device=dev)
@@ -61,6 +65,10 @@ class GraphRunner:
                         flags=torch.zeros((slots, ny, nx), dtype=torch.uint8, device=dev),
                         omega=torch.zeros((slots, ny, nx), device=dev))
         self.mask = torch.ones((slots,), dtype=torch.uint8, device=dev)
+        # smoothing state slot of each batch slot (device), written from a
+        # pinned host copy before each launch (see set_slots)
+        self.slot = torch.zeros((slots,), dtype=torch.int32, device=dev)
+        self.slot_host = torch.zeros((slots,), dtype=torch.int32, pin_memory=True) if temporal else None
         self.stream = stream if stream is not None else torch.cuda.Stream(device=dev)
         b, self.buckets = 1, []
         while b < slots:
@@ -75,8 +83,39 @@ class GraphRunner:
         return self.graphs.get(self.slots)
 
     def resident_bytes(self) -> int:
-        t = [self.A, self.B, self.mask] + list(self.out.values())
+        t = [self.A, self.B, self.mask, self.slot] + list(self.out.values())
         return sum(x.numel() * x.element_size() for x in t) + self.plan.workspace_bytes(self.slots)
+
+    @staticmethod
+    def bytes_for(plan, slots: int) -> int:
+        """resident_bytes() of a runner of `slots` slots on `plan`'s geometry,
+        computed before any device memory is allocated."""
+        es = {"u8": 1, "u16": 2, "f32": 4}[plan.dtype]
+        npx = plan.ny * plan.nx
+        per = 2 * plan.width * plan.height * es + 4 * (2 + 2 + 1 + 1) * npx + npx + 1 + 4
+        return slots * per + plan.workspace_bytes(slots)
+
+    def path(self, A, B, out, n: int) -> None:
+        """One call of the path on the first n slots (the captured call)."""
+        t = self.temporal
+        if t is None:
+            self.plan.run(A, B, out)
+        else:
+            self.plan.run_temporal(A, B, self.slot[:n], t.get("state_pred"), t.get("state_disp"),
+                                   t.get("alpha1", 0.5), t.get("alpha2", 0.5), out)
+
+    def set_slots(self, slots: Sequence[int]) -> None:
+        """Write the smoothing state slot of batch slots 0..len-1 (k continues
+        state k, -1 - k starts it), on the runner's stream.  The pinned host
+        copy is reused, which is safe because a runner holds at most one live
+        batch: the previous copy from it completed before this runner was
+        handed out again."""
+        if self.slot_host is None:
+            raise RuntimeError("runner was built without temporal smoothing")
+        k = len(slots)
+        self.slot_host[:k] = self.torch.tensor(list(slots), dtype=self.torch.int32)
+        with self.torch.cuda.stream(self.stream):
+            self.slot[:k].copy_(self.slot_host[:k], non_blocking=True)
 
     def bucket(self, n: int) -> int:
         return next(b for b in self.buckets if b >= n)
@@ -89,13 +128,18 @@ class GraphRunner:
         for n in self.buckets:
             A, B = self.A[:n], self.B[:n]
             out = {k: v[:n] for k, v in self.out.items()}
-            # warm up on the capture stream, then capture
+            # warm up on the capture stream, then capture (with smoothing on,
+            # the warm-up runs with every slot outside the state tables, so
+            # no state is touched)
+            if self.temporal is not None:
+                with torch.cuda.stream(self.stream):
+                    self.slot.fill_(-(1 << 30))
             with torch.cuda.stream(self.stream):
-                self.plan.run(A, B, out)
+                self.path(A, B, out, n)
             self.stream.synchronize()
             g = torch.cuda.CUDAGraph()
             with torch.cuda.graph(g, stream=self.stream):
-                self.plan.run(A, B, out)
+                self.path(A, B, out, n)
             self.stream.synchronize()
             self.graphs[n] = g
 
@@ -161,6 +205,13 @@ class Executor:
 
     def busy(self) -> bool: ...
 
+    def class_admitted(self, cls: str) -> None:
+        """The first stream of `cls` was admitted: build its runners."""
+
+    def class_retired(self, cls: str) -> None:
+        """The last stream of `cls` retired and none of its batches runs:
+        release its runners."""
+
 
 class Scheduler:
     """Continuous batching over size classes.
@@ -192,8 +243,10 @@ class Scheduler:
         self.queues: Dict[str, Deque[Request]] = {c: collections.deque() for c in self.classes}
         self.running: Dict[str, List[Tuple[object, List[Request]]]] = {c: [] for c in self.classes}
         self.finished: List[Request] = []
+        self.refused: List[Request] = []   # requests of streams not admitted (or retired)
         self.refused_submits = 0
         self.batches = 0
+        self._release_after: set = set()
 
     # -- admission ----------------------------------------------------------
     def _cost(self, cls: str) -> int:
@@ -206,8 +259,13 @@ class Scheduler:
     def _try_admit(self, stream: int, cls: str) -> bool:
         if self.used + self._cost(cls) <= self.budget:
             self.used += self._cost(cls)
+            first = self.class_live[cls] == 0
             self.class_live[cls] += 1
             self.admitted[stream] = cls
+            if first:
+                # the class's runners are charged to the budget now and
+                # built now, so the ledger governs real memory
+                self.ex.class_admitted(cls)
             return True
         return False
 
@@ -221,12 +279,23 @@ class Scheduler:
         return False
 
     def retire(self, stream: int) -> None:
+        """Retire an admitted stream; its queued requests are dropped (and
+        counted as refused).  The class's runners are released with its last
+        stream, once none of its batches is on the device."""
         cls = self.admitted.pop(stream, None)
         if cls is not None:
+            q = self.queues[cls]
+            keep = collections.deque(r for r in q if r.stream != stream)
+            self.refused.extend(r for r in q if r.stream == stream)
+            self.queues[cls] = keep
             self.class_live[cls] -= 1
             self.used -= self.classes[cls].stream_bytes
             if self.class_live[cls] == 0:
                 self.used -= self.inflight * self.classes[cls].slot_bytes
+                if self.running[cls]:
+                    self._release_after.add(cls)
+                else:
+                    self.ex.class_retired(cls)
         self._drain_waiting()
 
     def set_budget(self, budget: int) -> None:
@@ -246,6 +315,7 @@ class Scheduler:
     def submit(self, req: Request) -> bool:
         if self.admitted.get(req.stream) != req.cls:
             self.refused_submits += 1
+            self.refused.append(req)
             return False
         self.queues[req.cls].append(req)
         return True
@@ -266,6 +336,9 @@ class Scheduler:
                 else:
                     keep.append((h, reqs))
             self.running[cls] = keep
+            if cls in self._release_after and not keep and self.class_live[cls] == 0:
+                self._release_after.discard(cls)
+                self.ex.class_retired(cls)
         launched = 0
         idle = not self.ex.busy()
         # oldest-first across classes so that no class starves
@@ -327,6 +400,9 @@ class FakeExecutor(Executor):
 class GpuExecutor(Executor):
     """Graph replays on per-class streams; completion by HIP events.
 
+    A class's runners (``inflight`` of them, each with its own plan,
+    workspace, HIP stream and captured graphs) are built when the class's
+    first stream is admitted and released when its last stream retires.
     ``pairs[stream]`` holds each admitted stream's device-resident pairs
     (A, B tensors of shape [k, H, W]); a launch copies the requested pairs
     into a free runner's slots (device-to-device, on the runner's stream),
@@ -336,33 +412,118 @@ class GpuExecutor(Executor):
     (same kernels, same workspace, same stream).  The pairs must be written
     (complete on the device) before the first launch that reads them:
     launches do not order themselves after other streams.  Each runner has
-    one completion event, reused, since it holds at most one live batch."""
+    one completion event, reused, since it holds at most one live batch.
 
-    def __init__(self, runners: Dict[str, List[GraphRunner]], pairs: Dict[int, Tuple[object, object]],
-                 keep_results: bool = False, eager_single: bool = True):
+    With ``temporal`` (dict(alpha1=, alpha2=)) each class keeps resident
+    smoothing states for its streams and runs the paper's path with
+    exponential smoothing in time (piv_run_temporal): a stream's first
+    request starts its state, later ones continue it.  Results then depend
+    on each stream's history, so the launches of one class are ordered on
+    the device (each waits for the class's previous launch)."""
+
+    def __init__(self, classes: Dict[str, Tuple[int, int, int]], pairs: Dict[int, Tuple[object, object]],
+                 stream_class: Dict[int, str], plan_kw: Optional[dict] = None, inflight: int = 2,
+                 keep_results: bool = False, eager_single: bool = True, temporal: Optional[dict] = None):
         import torch
         self.torch = torch
-        self.runners = runners
+        self.classes = classes
         self.pairs = pairs
-        self.free = {c: list(r) for c, r in runners.items()}
+        self.stream_class = stream_class
+        self.plan_kw = dict(plan_kw or {})
+        self.inflight = inflight
+        self.runners: Dict[str, List[GraphRunner]] = {}
+        self.free: Dict[str, List[GraphRunner]] = {}
         self.live: Dict[int, Tuple[str, GraphRunner, object, List[Request]]] = {}
         self.n = 0
         self.keep = keep_results
         self.eager_single = eager_single
         self.results: Dict[int, Dict[str, object]] = {}
-        self.slot0 = {id(r): {k: v[0:1] for k, v in r.out.items()} for rs in runners.values() for r in rs}
-        self.event = {id(r): torch.cuda.Event() for rs in runners.values() for r in rs}
+        self.slot0: Dict[int, Dict[str, object]] = {}
+        self.event: Dict[int, object] = {}
+        self.temporal = temporal
+        self.state_index: Dict[int, int] = {}
+        for c in classes:
+            for k, s in enumerate(sorted(s for s, cc in stream_class.items() if cc == c)):
+                self.state_index[s] = k
+        self.started: set = set()
+        self.states: Dict[str, Dict[str, object]] = {}
+        self.last_event: Dict[str, object] = {}
+
+    def runner_bytes(self, cls: str) -> int:
+        from .api import Plan
+        W, H, cap = self.classes[cls]
+        p = Plan(W, H, max_batch=cap, workspace=False, **self.plan_kw)
+        b = GraphRunner.bytes_for(p, cap)
+        if self.temporal is not None:
+            # the class's two smoothing state tables, shared by its runners
+            # (the scheduler charges runner_bytes once per runner)
+            nst = sum(1 for c in self.stream_class.values() if c == cls)
+            b += -(-2 * 4 * nst * 2 * p.ny * p.nx // self.inflight)
+        p.close()
+        return b
+
+    def class_admitted(self, cls: str) -> None:
+        if cls in self.runners:
+            return
+        torch = self.torch
+        from .api import Plan
+        W, H, cap = self.classes[cls]
+        tm = None
+        if self.temporal is not None:
+            nst = sum(1 for c in self.stream_class.values() if c == cls)
+            probe = Plan(W, H, max_batch=cap, workspace=False, **self.plan_kw)
+            st = dict(state_pred=probe.new_state(nst), state_disp=probe.new_state(nst))
+            probe.close()
+            self.states[cls] = st
+            tm = dict(st, alpha1=self.temporal.get("alpha1", 0.5), alpha2=self.temporal.get("alpha2", 0.5))
+        rs = []
+        for _ in range(self.inflight):
+            r = GraphRunner(Plan(W, H, max_batch=cap, **self.plan_kw), cap, temporal=tm)
+            r.capture()
+            rs.append(r)
+        # the runners' buffers and graphs are complete before their first launch
+        torch.cuda.synchronize()
+        self.runners[cls] = rs
+        self.free[cls] = list(rs)
+        for r in rs:
+            self.slot0[id(r)] = {k: v[0:1] for k, v in r.out.items()}
+            self.event[id(r)] = torch.cuda.Event()
+
+    def class_retired(self, cls: str) -> None:
+        for r in self.runners.pop(cls, []):
+            self.slot0.pop(id(r), None)
+            self.event.pop(id(r), None)
+        self.free.pop(cls, None)
+        self.states.pop(cls, None)
+        self.last_event.pop(cls, None)
+        self.started = {s for s in self.started if self.stream_class.get(s) != cls}
+
+    def _slot_values(self, reqs: List[Request]) -> List[int]:
+        vals = []
+        for r in reqs:
+            k = self.state_index[r.stream]
+            if r.stream in self.started:
+                vals.append(k)
+            else:
+                vals.append(-1 - k)
+                self.started.add(r.stream)
+        return vals
 
     def launch(self, cls, reqs, now):
         torch = self.torch
         run = self.free[cls].pop()
+        if self.temporal is not None:
+            run.set_slots(self._slot_values(reqs))
+            prev = self.last_event.get(cls)
+            if prev is not None:
+                run.stream.wait_event(prev)
         if len(reqs) == 1 and self.eager_single:
             r = reqs[0]
             a, b = self.pairs[r.stream]
             # (the plan's slot mask is the runner's; slot 0 is active under
             # every mask set_active writes, and the mask starts all ones)
             with torch.cuda.stream(run.stream):
-                run.plan.run(a[r.item:r.item + 1], b[r.item:r.item + 1], self.slot0[id(run)])
+                run.path(a[r.item:r.item + 1], b[r.item:r.item + 1], self.slot0[id(run)], 1)
         else:
             with torch.cuda.stream(run.stream):
                 for i, r in enumerate(reqs):
@@ -372,6 +533,8 @@ class GpuExecutor(Executor):
             run.replay(len(reqs))
         ev = self.event[id(run)]
         ev.record(run.stream)
+        if self.temporal is not None:
+            self.last_event[cls] = ev
         self.n += 1
         self.live[self.n] = (cls, run, ev, reqs)
         return self.n
@@ -380,9 +543,15 @@ class GpuExecutor(Executor):
         cls, run, ev, reqs = self.live[h]
         if not ev.query():
             return False
+        torch = self.torch
         if self.keep:
-            for i, r in enumerate(reqs):
-                self.results[r.rid] = {k: v[i].clone() for k, v in run.out.items()}
+            # the copies run on the runner's stream, so its next launch (which
+            # rewrites the slots) is ordered after them; the caller's stream
+            # waits for them before it reads the results
+            with torch.cuda.stream(run.stream):
+                for i, r in enumerate(reqs):
+                    self.results[r.rid] = {k: v[i].clone() for k, v in run.out.items()}
+            torch.cuda.current_stream().wait_stream(run.stream)
         del self.live[h]
         self.free[cls].append(run)
         return True
@@ -394,33 +563,25 @@ class GpuExecutor(Executor):
 def make_gpu_server(classes: Dict[str, Tuple[int, int, int]], pairs: Dict[int, Tuple[object, object]],
                     stream_class: Dict[int, str], budget: int, plan_kw: Optional[dict] = None,
                     inflight: int = 2, max_wait: float = 2e-3, keep_results: bool = False,
-                    eager_single: bool = True):
-    """Build runners (``inflight`` per class, each with its own plan,
-    workspace, HIP stream and captured graph), the executor and the
-    scheduler, and admit the streams in order.  classes: name -> (W, H,
-    slots).  Returns (scheduler, executor)."""
+                    eager_single: bool = True, temporal: Optional[dict] = None):
+    """Build the executor and the scheduler and admit the streams in order;
+    a class's runners (``inflight`` per class) are built when its first
+    stream is admitted.  classes: name -> (W, H, slots).  Returns
+    (scheduler, executor)."""
     import torch
-    from .api import Plan
-    plan_kw = dict(plan_kw or {})
-    runners: Dict[str, List[GraphRunner]] = {}
+    ex = GpuExecutor(classes, pairs, stream_class, plan_kw=plan_kw, inflight=inflight,
+                     keep_results=keep_results, eager_single=eager_single, temporal=temporal)
     specs = []
     for name, (W, H, cap) in classes.items():
-        rs = []
-        for _ in range(inflight):
-            r = GraphRunner(Plan(W, H, max_batch=cap, **plan_kw), cap)
-            r.capture()
-            rs.append(r)
-        runners[name] = rs
         per_stream = 0
         for s, c in stream_class.items():
             if c == name:
                 a, b = pairs[s]
                 per_stream = a.numel() * a.element_size() + b.numel() * b.element_size()
                 break
-        specs.append(ClassSpec(name, W, H, cap, rs[0].resident_bytes(), per_stream))
+        specs.append(ClassSpec(name, W, H, cap, ex.runner_bytes(name), per_stream))
     # the admitted pairs are complete before the first launch reads them
     torch.cuda.synchronize()
-    ex = GpuExecutor(runners, pairs, keep_results=keep_results, eager_single=eager_single)
     sched = Scheduler(specs, ex, budget, max_wait=max_wait, inflight=inflight)
     for s, c in stream_class.items():
         sched.admit(s, c)
@@ -449,9 +610,12 @@ def poisson_trace(streams: Sequence[Tuple[int, str]], rate: float, duration: flo
 
 
 def serve_trace(sched: Scheduler, trace: List[Request], clock: Callable[[], float],
-                poll: float = 20e-6, deadline: float = 60.0) -> None:
+                poll: float = 20e-6, deadline: float = 60.0) -> List[Request]:
     """Feed `trace` (arrival times relative to the start) into `sched` in
-    real time and run until every request has completed."""
+    real time and run until every accepted request has completed.  Returns
+    the requests refused (their streams were not admitted); those keep a
+    NaN completion time and stay out of ``latency_stats``."""
+    n_ref = len(sched.refused)
     t0 = clock()
     i = 0
     while i < len(trace) or sched.pending():
@@ -463,6 +627,7 @@ def serve_trace(sched: Scheduler, trace: List[Request], clock: Callable[[], floa
             i += 1
         if not sched.step(now) and poll > 0:
             time.sleep(poll)
+    return sched.refused[n_ref:]
 
 
 def run_fifo(plan_for: Callable[[str], object], pairs, trace: List[Request], clock,
@@ -485,8 +650,16 @@ def run_fifo(plan_for: Callable[[str], object], pairs, trace: List[Request], clo
 
 
 def latency_stats(reqs: Sequence[Request]) -> Dict[str, float]:
+    """Latency percentiles and throughput of the completed requests (refused
+    ones, with a NaN completion time, are counted apart)."""
     import numpy as np
-    lat = np.array([r.done - r.arrival for r in reqs]) * 1e3
-    span = max(r.done for r in reqs) - min(r.arrival for r in reqs)
+    done = [r for r in reqs if not math.isnan(r.done)]
+    refused = len(reqs) - len(done)
+    if not done:
+        return {"p50_ms": math.nan, "p99_ms": math.nan, "mean_ms": math.nan, "pairs_per_s": 0.0, "n": 0,
+                "refused": refused}
+    lat = np.array([r.done - r.arrival for r in done]) * 1e3
+    span = max(r.done for r in done) - min(r.arrival for r in done)
     return {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-            "mean_ms": float(lat.mean()), "pairs_per_s": len(reqs) / span, "n": len(reqs)}
+            "mean_ms": float(lat.mean()), "pairs_per_s": len(done) / span if span > 0 else math.nan,
+            "n": len(done), "refused": refused}

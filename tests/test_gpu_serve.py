@@ -120,3 +120,37 @@ def test_served_results_equal_pair_alone(eager_single):
         assert torch.equal(got["flags"], e["flags"][0])
     say(f"  max |served - alone| = {worst:.3e} px")
     assert worst == 0.0   # no cross-pair arithmetic: bit-identical
+
+
+def test_admission_budget_refuses_a_class():
+    """An HBM budget that holds class s (its runners and streams) but not
+    class l: the l stream waits unadmitted, its requests are refused and
+    counted apart, no runner of l is built, and every served s result still
+    equals the pair run alone."""
+    from paper_2504_17987_amd import api
+    from paper_2504_17987_amd.serve import latency_stats, make_gpu_server, poisson_trace, serve_trace
+    say("[serve] admission refusal")
+    sizes = {"s": (128, 128, 4), "l": (512, 512, 2)}
+    stream_class = {0: "s", 1: "s", 2: "l"}
+    pairs = {s: pairs_u8(*sizes[c][:2], 2, 2000 + 10 * s) for s, c in stream_class.items()}
+    probe_sched, probe_ex = make_gpu_server({"s": sizes["s"]}, {0: pairs[0], 1: pairs[1]}, {0: "s", 1: "s"},
+                                            budget=0)
+    assert not probe_sched.admitted and not probe_ex.runners   # nothing admitted at budget 0
+    spec = probe_sched.classes["s"]
+    need_s = 2 * spec.stream_bytes + probe_sched.inflight * spec.slot_bytes   # two s streams and their runners
+    sched, ex = make_gpu_server(sizes, pairs, stream_class, budget=need_s, keep_results=True)
+    assert set(sched.admitted) == {0, 1} and 2 not in sched.admitted and "l" not in ex.runners
+    trace = poisson_trace(list(stream_class.items()), 300.0, 0.1, 2, seed=11)
+    refused = serve_trace(sched, trace, time.perf_counter, poll=0, deadline=60.0)
+    torch.cuda.synchronize()
+    assert refused and all(r.stream == 2 for r in refused)
+    st = latency_stats(trace)
+    say(f"  served {st['n']}, refused {st['refused']}, p99 {st['p99_ms']:.3f} ms")
+    assert st["refused"] == len(refused) and st["n"] == len(trace) - len(refused)
+    P = api.Plan(128, 128)
+    for r in trace:
+        if r.stream == 2:
+            continue
+        a, b = pairs[r.stream]
+        e = P.run(a[r.item:r.item + 1], b[r.item:r.item + 1])
+        assert torch.equal(ex.results[r.rid]["disp"], e["disp"][0])

@@ -116,3 +116,44 @@ def test_idle_class_launches_while_another_class_runs():
     trace = [Request(0, 0, "l", 0, 0.0), Request(1, 1, "s", 0, 1e-3)]
     simulate(sched, clock, trace)
     assert trace[1].start - trace[1].arrival < 2e-5
+
+
+class HookedExecutor(FakeExecutor):
+    def __init__(self, *a):
+        super().__init__(*a)
+        self.events = []
+
+    def class_admitted(self, cls):
+        self.events.append(("admit", cls))
+
+    def class_retired(self, cls):
+        self.events.append(("retire", cls))
+
+
+def test_runners_follow_admission_and_refused_requests_are_counted_apart():
+    """A class's runners are built when its first stream is admitted and
+    released when its last stream retires; requests of a refused stream are
+    listed apart and kept out of the latency statistics."""
+    from paper_2504_17987_amd.serve import latency_stats
+    clock = Clock()
+    ex = HookedExecutor(lambda cls, n: 1e-4, clock)
+    # budget: class s (2 runners + streams) fits, class l does not
+    budget = 2 * 10_000 + 2 * 1_000
+    sched = Scheduler(CLASSES, ex, budget, inflight=2)
+    assert sched.admit(0, "s") and sched.admit(1, "s")
+    assert not sched.admit(2, "l")
+    assert ex.events == [("admit", "s")]
+    trace = poisson_trace([(0, "s"), (1, "s"), (2, "l")], 500.0, 0.05, 2, seed=3)
+    simulate(sched, clock, trace)
+    refused = [r for r in trace if r.stream == 2]
+    assert refused and sched.refused == refused
+    st = latency_stats(trace)
+    assert st["refused"] == len(refused) and st["n"] == len(trace) - len(refused)
+    assert math.isfinite(st["p99_ms"])
+    sched.retire(0)
+    assert ("retire", "s") not in ex.events
+    sched.retire(1)
+    assert ex.events[-1] == ("retire", "s")
+    # the budget freed by class s admits the waiting l stream, whose runners are then built
+    sched.set_budget(budget + 160_000 * 2 + 16_000)
+    assert sched.admitted.get(2) == "l" and ex.events[-1] == ("admit", "l")
