@@ -13,11 +13,23 @@ TOL_REL = 1e-4            # vorticity and gradients, relative to max |value|
 TOL_RHO = 2e-5            # correlation coefficient at the chosen shift
 NEAR_TIE_RHO = 1e-5       # top-2 coefficient gap under which either peak is correct
 NEAR_TIE_UOD = 1e-4       # |r0 - threshold| under which either decision is correct
+MAX_TIES = 2              # near-tie exemptions allowed per compared field
+MAX_FLAT = 8              # near-flat exemptions allowed per compared field
+MAX_UOD = 2               # near-threshold validation exemptions per compared field
+
+# every exemption any parity test granted: (where, kind, count); printed in
+# the session summary by conftest.py
+EXEMPTIONS = []
 
 
 def say(*a):
     print(*a, flush=True)
     sys.stdout.flush()
+
+
+def record(where, kind, n):
+    if n:
+        EXEMPTIONS.append((where, kind, int(n)))
 
 
 def corr_gap(A, B, win, step, r, mode, pred, a, b):
@@ -75,15 +87,16 @@ def near_flat(Ao, Bo, win, step, r, mode, pred, a, b, warped=None):
 
 
 def compare_correct(Ag, Bg, Ao, Bo, win, step, r, pred, disp_g, peak_g, flags_g, disp_o, peak_o,
-                    flags_o, mode=0, fixed=False, max_ties=None):
+                    flags_o, mode=0, fixed=False, max_ties=MAX_TIES, max_flat=MAX_FLAT, where="correct"):
     """Element-wise comparison of a correction result with the oracle's.
     Where they differ, the oracle's correlation plane must show a near-tie,
     or one of the node's windows must be near-flat (the FP32 flatness rule
-    and the oracle's exact zero may then disagree; every such node is checked
-    on its own, so they are not capped).  Returns the number of near-tie
-    exemptions (capped by max_ties)."""
+    and the oracle's exact zero may then disagree).  Both kinds are counted,
+    capped, and recorded for the session summary.  Returns the boolean map
+    of exempted nodes."""
     d = np.abs(disp_g - disp_o).max(axis=0)
     bad = (d > TOL_DISP_PX) | (np.abs(peak_g - peak_o) > TOL_RHO) | (flags_g != flags_o)
+    ex = np.zeros(bad.shape, bool)
     ties = flat = 0
     warped = None
     for a, b in zip(*np.nonzero(bad)):
@@ -92,15 +105,69 @@ def compare_correct(Ag, Bg, Ao, Bo, win, step, r, pred, disp_g, peak_g, flags_g,
         if gap >= NEAR_TIE_RHO:
             if warped is None:
                 warped = (oracle.warp_image(Ao, 0, mode, pred, step), oracle.warp_image(Bo, 1, mode, pred, step))
-            if near_flat(Ao, Bo, win, step, R, mode, pred, int(a), int(b), warped):
-                flat += 1
-                continue
-        assert gap < NEAR_TIE_RHO, (
-            f"node ({a},{b}): gpu {disp_g[:, a, b]} rho {peak_g[a, b]} fl {flags_g[a, b]} vs "
-            f"oracle {disp_o[:, a, b]} rho {peak_o[a, b]} fl {flags_o[a, b]}, top-2 gap {gap}")
-        ties += 1
-    if flat:
-        say(f"  near-flat exemptions: {flat}")
-    if max_ties is not None:
-        assert ties <= max_ties, f"{ties} near-tie exemptions"
-    return ties
+            assert near_flat(Ao, Bo, win, step, R, mode, pred, int(a), int(b), warped), (
+                f"{where} node ({a},{b}): gpu {disp_g[:, a, b]} rho {peak_g[a, b]} fl {flags_g[a, b]} vs "
+                f"oracle {disp_o[:, a, b]} rho {peak_o[a, b]} fl {flags_o[a, b]}, top-2 gap {gap}, not near-flat")
+            flat += 1
+        else:
+            ties += 1
+        ex[a, b] = True
+    record(where, "near-tie", ties)
+    record(where, "near-flat", flat)
+    assert ties <= max_ties, f"{where}: {ties} near-tie exemptions (cap {max_ties})"
+    assert flat <= max_flat, f"{where}: {flat} near-flat exemptions (cap {max_flat})"
+    if ties or flat:
+        say(f"  {where}: exemptions near-tie {ties}, near-flat {flat}")
+    return ex
+
+
+def near_threshold(field, flags, a, b, thr=2.0, eps=0.1):
+    """A validation decision at (a, b) or at one of its neighbours lies within
+    NEAR_TIE_UOD of the threshold (so either outcome is correct there)."""
+    _, ny, nx = field.shape
+    return min(abs(uod_r0(field, flags, y, x, eps) - thr) for y in range(a - 1, a + 2)
+               for x in range(b - 1, b + 2) if 0 <= y < ny and 0 <= x < nx) < NEAR_TIE_UOD
+
+
+def compare_validate(field_in, flags_in, g_field, g_flags, o_field, o_flags, tol=1e-5, max_near=MAX_UOD,
+                     where="validate"):
+    """Validation of the same input field on both sides: values within tol
+    and flags exact, except where a decision near the threshold (at the
+    vector or a neighbour) explains the difference.  Counted, capped,
+    recorded.  Returns the boolean map of exempted vectors."""
+    bad = (np.abs(g_field - o_field).max(axis=0) > tol) | (g_flags != o_flags)
+    for a, b in zip(*np.nonzero(bad)):
+        assert near_threshold(field_in, flags_in, a, b), (
+            f"{where} ({a},{b}): gpu {g_field[:, a, b]} fl {g_flags[a, b]} vs oracle {o_field[:, a, b]} "
+            f"fl {o_flags[a, b]}, no decision near the threshold")
+    n = int(bad.sum())
+    record(where, "uod-near-threshold", n)
+    assert n <= max_near, f"{where}: {n} near-threshold exemptions (cap {max_near})"
+    return bad
+
+
+def dilate(m):
+    """3x3 dilation of a boolean map."""
+    out = m.copy()
+    H, W = m.shape
+    for dy in (-1, 0, 1):
+        for dx in (-1, 0, 1):
+            out[max(dy, 0):H + min(dy, 0), max(dx, 0):W + min(dx, 0)] |= \
+                m[max(-dy, 0):H + min(-dy, 0), max(-dx, 0):W + min(-dx, 0)]
+    return out
+
+
+def compare_end_to_end(g, o, raw_ex, uod_ex, where="run"):
+    """Final (validated) fields of a whole run: a vector may differ only where
+    its own raw correction or one of its 3x3 neighbours' was exempted (the
+    replacement median reads the neighbours), or where the validation
+    comparison was exempted.  Returns the number of such vectors."""
+    d = np.abs(g - o).max(axis=0)
+    bad = d > TOL_DISP_PX
+    allowed = dilate(raw_ex) | dilate(uod_ex)
+    unexplained = bad & ~allowed
+    assert not unexplained.any(), (
+        f"{where}: {int(unexplained.sum())} vectors differ by up to {d[unexplained].max():.3e} px "
+        f"without an exempted raw correction or validation decision nearby")
+    record(where, "propagated", int(bad.sum()))
+    return int(bad.sum())

@@ -20,8 +20,8 @@ import pytest
 import torch
 
 import oracle
-from _helpers import (NEAR_TIE_RHO, NEAR_TIE_UOD, TOL_DISP_PX, TOL_REL, TOL_RHO, compare_correct, corr_gap, say,
-                      uod_r0)
+from _helpers import (MAX_TIES, NEAR_TIE_RHO, TOL_DISP_PX, TOL_REL, TOL_RHO, compare_correct, compare_validate,
+                      corr_gap, record, say)
 from paper_2504_17987_amd import synth
 
 pytestmark = [pytest.mark.gpu,
@@ -102,7 +102,8 @@ def test_fullsize_correction_sampled(fullsize):
             else:
                 worst = max(worst, d)
     say(f"  max |d disp| {worst:.2e} px, near-tie exemptions {ties}")
-    assert ties <= 2
+    record("fullsize sampled correction", "near-tie", ties)
+    assert ties <= MAX_TIES
 
 
 def test_fullsize_correction_full_grid(fullsize):
@@ -113,10 +114,12 @@ def test_fullsize_correction_full_grid(fullsize):
         A, B, _ = pairs[i]
         pred = g["pred"][i].astype(np.float64)
         disp_o, peak_o, flags_o = oracle.correct(A, B, 16, 8, 4, pred)
-        ties = compare_correct(None, None, A.astype(np.float64), B.astype(np.float64), 16, 8, 4, pred,
-                               c["disp"][i], c["peak"][i], c["flags"][i], disp_o, peak_o, flags_o, max_ties=4)
-        d = np.abs(c["disp"][i] - disp_o).max()
-        say(f"  pair {i}: max |d disp| {d:.2e} px over {pred.shape[1] * pred.shape[2]} nodes, near-ties {ties}")
+        ex = compare_correct(None, None, A.astype(np.float64), B.astype(np.float64), 16, 8, 4, pred,
+                             c["disp"][i], c["peak"][i], c["flags"][i], disp_o, peak_o, flags_o,
+                             where=f"fullsize full grid, pair {i}")
+        d = np.abs(c["disp"][i] - disp_o)[:, ~ex].max()
+        say(f"  pair {i}: max |d disp| {d:.2e} px over {pred.shape[1] * pred.shape[2]} nodes, "
+            f"exempted {int(ex.sum())}")
 
 
 def test_fullsize_validation_and_vorticity(fullsize):
@@ -125,13 +128,8 @@ def test_fullsize_validation_and_vorticity(fullsize):
         f = c["disp"][i].astype(np.float64)
         fl = c["flags"][i].copy()
         vo, flo = oracle.validate(f, fl)
-        bad = (np.abs(g["disp"][i] - vo).max(axis=0) > 1e-5) | (g["flags"][i] != flo)
-        ny, nx = fl.shape
-        for a, b in zip(*np.nonzero(bad)):
-            near = [abs(uod_r0(f, c["flags"][i], y, x) - 2.0) for y in range(a - 1, a + 2)
-                    for x in range(b - 1, b + 2) if 0 <= y < ny and 0 <= x < nx]
-            assert min(near) < NEAR_TIE_UOD, (i, a, b)
-        assert bad.sum() <= 2
+        compare_validate(f, c["flags"][i], g["disp"][i], g["flags"][i], vo, flo,
+                         where=f"fullsize validation, pair {i}")
         om = oracle.vorticity(g["disp"][i].astype(np.float64), 8)
         assert np.abs(g["omega"][i] - om).max() <= TOL_REL * np.abs(om).max(), i
 
@@ -168,10 +166,11 @@ def test_largest_image_8192x4096():
         if not (d <= TOL_DISP_PX and abs(c["peak"][a, b] - pk) <= TOL_RHO and c["flags"][a, b] == fl):
             assert corr_gap(Ad, Bd, 16, 8, 4, 0, g["pred"].astype(np.float64), a, b) < NEAR_TIE_RHO, (a, b)
             ties += 1
-    assert ties <= 2
+    record("largest sampled correction", "near-tie", ties)
+    assert ties <= MAX_TIES
     vo, flo = oracle.validate(c["disp"].astype(np.float64), c["flags"].copy())
-    bad = (np.abs(g["disp"] - vo).max(axis=0) > 1e-5) | (g["flags"] != flo)
-    assert bad.sum() <= 4
+    compare_validate(c["disp"].astype(np.float64), c["flags"], g["disp"], g["flags"], vo, flo,
+                     where="largest validation")
     om = oracle.vorticity(g["disp"].astype(np.float64), 8)
     assert np.abs(g["omega"] - om).max() <= TOL_REL * np.abs(om).max()
 
@@ -216,10 +215,11 @@ def test_cfg3_4k_u16_graph_slots():
             if not (d <= TOL_DISP_PX and abs(c["peak"][a, b] - pk) <= TOL_RHO and c["flags"][a, b] == fl):
                 assert corr_gap(Ad, Bd, 24, 12, 4, 0, po, a, b) < NEAR_TIE_RHO, (i, a, b)
                 ties += 1
-        assert ties <= 2
+        record(f"cfg3 sampled correction, pair {i}", "near-tie", ties)
+        assert ties <= MAX_TIES
         vo, flo = oracle.validate(c["disp"].astype(np.float64), c["flags"].copy())
-        bad = (np.abs(g["disp"][i] - vo).max(axis=0) > 1e-5) | (g["flags"][i] != flo)
-        assert bad.sum() <= 4
+        compare_validate(c["disp"].astype(np.float64), c["flags"], g["disp"][i], g["flags"][i], vo, flo,
+                         where=f"cfg3 validation, pair {i}")
         om = oracle.vorticity(g["disp"][i].astype(np.float64), 12)
         assert np.abs(g["omega"][i] - om).max() <= TOL_REL * np.abs(om).max()
         say(f"  pair {i}: predictor bit-exact, {ny * nx} vectors, near-ties {ties}")

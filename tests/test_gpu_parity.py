@@ -8,7 +8,8 @@ import pytest
 import torch
 
 import oracle
-from _helpers import TOL_DISP_PX, TOL_REL, compare_correct, say, uod_r0, NEAR_TIE_UOD
+from _helpers import (TOL_DISP_PX, TOL_REL, compare_correct, compare_end_to_end, compare_validate, dilate,
+                      say)
 from paper_2504_17987_amd import synth
 
 pytestmark = [pytest.mark.gpu,
@@ -125,6 +126,14 @@ CORR_CASES = {
     "tiled_u8_vortex16_r1": ("vortex16", dict(win=16, step=8, radius=1), True),
     "tiled_u8_vortex16_fixed": ("vortex16", dict(win=16, step=8, radius=4, peak="fixed"), True),
     "tiled_u8_vortex16_r4": ("vortex16", dict(win=16, step=8, radius=4), True),
+    # central deformation on the generic kernel, on u16 frames, and the
+    # fixed-centre stencil with a predictor on the generic kernel
+    "generic_u8_central_r3": ("vortex", dict(win=16, step=8, radius=3, warp="central"), True),
+    "generic_u8_cfg1_central": ("cfg1", dict(win=32, step=16, radius=8, levels=1, radius_coarse=8,
+                                             warp="central"), True),
+    "tiled_u16_12_central": ("u16", dict(dtype="u16", win=24, step=12, radius=4, warp="central"), True),
+    "tiled_u16_8_central": ("u16", dict(dtype="u16", win=16, step=8, radius=4, warp="central"), True),
+    "generic_u8_fixed_pred": ("vortex", dict(win=24, step=8, radius=4, block=16, peak="fixed"), True),
 }
 
 
@@ -168,10 +177,9 @@ def test_correct_parity(case):
     pg = None if pred is None else dev(pred[None].astype(np.float32))
     disp, peak, flags = P.correct(Ad, Bd, pg)
     say(f"  impl={P.correct_impl()}")
-    ties = compare_correct(Ad, Bd, A.astype(float), B.astype(float), kw["win"], kw["step"], kw["radius"],
-                           pred, disp.cpu().numpy()[0], peak.cpu().numpy()[0], flags.cpu().numpy()[0],
-                           disp_o, peak_o, flags_o, mode=mode, fixed=fixed, max_ties=2)
-    say(f"  near-tie exemptions: {ties}")
+    compare_correct(Ad, Bd, A.astype(float), B.astype(float), kw["win"], kw["step"], kw["radius"],
+                    pred, disp.cpu().numpy()[0], peak.cpu().numpy()[0], flags.cpu().numpy()[0],
+                    disp_o, peak_o, flags_o, mode=mode, fixed=fixed, where=f"correct[{case}]")
 
 
 STRETCH = 0.6
@@ -212,10 +220,9 @@ def test_correct_parity_wild_predictor(case):
     disp_o, peak_o, flags_o = oracle.correct(A, B, 16, 8, 4, pred, 0, 0)
     Ad, Bd = dev(A[None]), dev(B[None])
     disp, peak, flags = P.correct(Ad, Bd, dev(pred[None].astype(np.float32)))
-    ties = compare_correct(Ad, Bd, A.astype(float), B.astype(float), 16, 8, 4, pred, disp.cpu().numpy()[0],
-                           peak.cpu().numpy()[0], flags.cpu().numpy()[0], disp_o, peak_o, flags_o,
-                           max_ties=2)
-    say(f"  near-tie exemptions: {ties}, flat windows {int((flags_o & 1).sum())}")
+    compare_correct(Ad, Bd, A.astype(float), B.astype(float), 16, 8, 4, pred, disp.cpu().numpy()[0],
+                    peak.cpu().numpy()[0], flags.cpu().numpy()[0], disp_o, peak_o, flags_o, where=f"wild[{case}]")
+    say(f"  flat windows {int((flags_o & 1).sum())}")
 
 
 def test_correct_impl_selection():
@@ -239,18 +246,13 @@ def test_validate_parity():
     flg = dev(flags[None])
     P.validate(fg, flg)
     g, fl = fg.cpu().numpy()[0], flg.cpu().numpy()[0]
-    bad = (np.abs(g - go).max(axis=0) > 1e-5) | (fl != flo)
-    for a, b in zip(*np.nonzero(bad)):
-        # a decision near the threshold here or at a neighbour explains it
-        near = [abs(uod_r0(f, flags, y, x) - 2.0) for y in range(a - 1, a + 2)
-                for x in range(b - 1, b + 2) if 0 <= y < ny and 0 <= x < nx]
-        assert min(near) < NEAR_TIE_UOD, f"({a},{b})"
-    assert bad.sum() <= 2
+    compare_validate(f, flags, g, fl, go, flo, where="validate[flags]")
     # predictor-style call without flags
     f2 = dev(f[None].astype(np.float32))
     P.validate(f2, None)
     g2, _ = oracle.validate(f, None)
-    assert np.abs(f2.cpu().numpy()[0] - g2).max() < 1e-5
+    z = np.zeros((ny, nx), np.uint8)
+    compare_validate(f, None, f2.cpu().numpy()[0], z, g2, z, where="validate[no flags]")
 
 
 def test_validate_parity_tiles():
@@ -271,17 +273,10 @@ def test_validate_parity_tiles():
     fg = dev(f.astype(np.float32))
     flg = dev(flags)
     P.validate(fg, flg)
-    total_bad = 0
     for p in range(n):
         go, flo = oracle.validate(f[p], flags[p])
         g, fl = fg.cpu().numpy()[p], flg.cpu().numpy()[p]
-        bad = (np.abs(g - go).max(axis=0) > 1e-5) | (fl != flo)
-        for a, b in zip(*np.nonzero(bad)):
-            near = [abs(uod_r0(f[p], flags[p], y, x) - 2.0) for y in range(a - 1, a + 2)
-                    for x in range(b - 1, b + 2) if 0 <= y < ny and 0 <= x < nx]
-            assert min(near) < NEAR_TIE_UOD, f"pair {p} ({a},{b})"
-        total_bad += int(bad.sum())
-    assert total_bad <= 6
+        compare_validate(f[p], flags[p], g, fl, go, flo, where=f"validate[tiles, pair {p}]")
 
 
 @pytest.mark.parametrize("dtype", ["u8", "u16"])
@@ -362,14 +357,36 @@ def test_vorticity_parity():
     assert np.abs(om - 0.02).max() < 1e-4 * 0.02 + 1e-6
 
 
-def _run_both(A, B, kw):
+def _run_both(A, B, kw, where):
+    """The whole path on the GPU (piv_run) and in the oracle, compared stage
+    by stage on identical inputs, every difference explained:
+    the predictor bit-exact; the raw correction (piv_correct on the run's
+    predictor, the kernel piv_run uses) against the oracle's; validation of
+    that raw field against the oracle's validation of the same field; the
+    final field against the oracle's only where a raw exemption or a
+    near-threshold decision lies in the 3x3 neighbourhood; vorticity of the
+    GPU's final field within 1e-4 of its max."""
     H, W = A.shape
     P = api().Plan(W, H, max_batch=1, **kw)
-    out = P.run(dev(A[None]), dev(B[None]))
+    Ad, Bd = dev(A[None]), dev(B[None])
+    out = P.run(Ad, Bd)
+    raw, peak, flags = P.correct(Ad, Bd, out["pred"])
     torch.cuda.synchronize()
+    g = {k: v.cpu().numpy()[0] for k, v in out.items()}
+    raw, peak, flags = raw.cpu().numpy()[0], peak.cpu().numpy()[0], flags.cpu().numpy()[0]
     o = oracle.run(A, B, win=kw["win"], step=kw["step"], r=kw["radius"], levels=kw["levels"],
                    Rc=kw["radius_coarse"], Rf=kw["radius_fine"])
-    return {k: v.cpu().numpy()[0] for k, v in out.items()}, o
+    assert np.array_equal(g["pred"], o["pred"].astype(np.float32)), f"{where}: predictor"
+    raw_ex = compare_correct(None, None, A.astype(float), B.astype(float), kw["win"], kw["step"], kw["radius"],
+                             o["pred"], raw, peak, flags, o["disp_raw"], o["peak"], o["flags_raw"],
+                             where=f"{where} raw")
+    vo, flo = oracle.validate(raw.astype(np.float64), flags.copy())
+    uod_ex = compare_validate(raw.astype(np.float64), flags, g["disp"], g["flags"], vo, flo,
+                              where=f"{where} validate")
+    compare_end_to_end(g["disp"], o["disp"], raw_ex, uod_ex, where=f"{where} end-to-end")
+    om = oracle.vorticity(g["disp"].astype(np.float64), kw["step"])
+    assert np.abs(g["omega"] - om).max() <= TOL_REL * np.abs(om).max(), f"{where}: vorticity"
+    return g, o
 
 
 def test_run_end_to_end_vortex():
@@ -377,17 +394,9 @@ def test_run_end_to_end_vortex():
     flow = synth.LambOseen.with_peak(127.5, 95.5, 60.0, 6.0)
     A, B = synth.make_pair(256, 192, flow, 0.04, noise=2.0, dropout=0.1, seed=7)
     kw = dict(win=16, step=8, radius=4, levels=3, radius_coarse=6, radius_fine=2)
-    g, o = _run_both(A, B, kw)
-    assert np.array_equal(g["pred"], o["pred"].astype(np.float32))
+    g, o = _run_both(A, B, kw, "run[vortex]")
     d = np.abs(g["disp"] - o["disp"]).max(axis=0)
-    nbad = int((d > TOL_DISP_PX).sum())
-    say(f"  max |d disp| {d.max():.2e}, mismatches {nbad}")
-    assert nbad <= 2
-    ok = d <= TOL_DISP_PX
-    ok3 = ok.copy()
-    ok3[1:-1, 1:-1] = ok[:-2, 1:-1] & ok[2:, 1:-1] & ok[1:-1, :-2] & ok[1:-1, 2:] & ok[1:-1, 1:-1]
-    om = np.abs(g["omega"] - o["omega"])[ok3]
-    assert om.max() <= TOL_REL * np.abs(o["omega"]).max() * 20   # 0.01 px -> ~2e-3 rel at worst
+    say(f"  max |d disp| {d.max():.2e}")
     # accuracy against the analytic truth (reported; loose bound)
     T = synth.truth(flow, 256, 192, 8)
     err = np.abs(g["disp"] - T)[:, 2:-2, 2:-2]
@@ -395,20 +404,34 @@ def test_run_end_to_end_vortex():
     assert np.sqrt((err ** 2).mean()) < 0.25   # the oracle itself: 0.18 px on this pair
 
 
+def test_run_end_to_end_strong_vortex():
+    """The stronger vortex (core 40 px, 8 px peak) the gentler case above
+    replaced: the same stage-by-stage comparison; accuracy against the truth
+    is reported only."""
+    say("[run] strong vortex 256x192")
+    flow = synth.LambOseen.with_peak(127.5, 95.5, 40.0, 8.0)
+    A, B = synth.make_pair(256, 192, flow, 0.04, noise=2.0, dropout=0.1, seed=7)
+    kw = dict(win=16, step=8, radius=4, levels=3, radius_coarse=6, radius_fine=2)
+    g, o = _run_both(A, B, kw, "run[strong vortex]")
+    T = synth.truth(flow, 256, 192, 8)
+    err = np.abs(g["disp"] - T)[:, 2:-2, 2:-2]
+    say(f"  vs truth: rms {np.sqrt((err ** 2).mean()):.3f} px (oracle "
+        f"{np.sqrt(((o['disp'] - T)[:, 2:-2, 2:-2] ** 2).mean()):.3f} px)")
+
+
 def test_run_end_to_end_cfg1():
     say("[run] config-1 plain path L=1")
     A, B, flow = synth.cfg1_pair(1000)
     kw = dict(win=32, step=16, radius=8, levels=1, radius_coarse=8, radius_fine=2)
-    g, o = _run_both(A, B, kw)
-    assert np.array_equal(g["pred"], o["pred"].astype(np.float32))
+    g, o = _run_both(A, B, kw, "run[cfg1]")
     d = np.abs(g["disp"] - o["disp"]).max(axis=0)
     assert (d <= TOL_DISP_PX).all(), d.max()
     # pred = NULL ("plain" correction only)
     P = api().Plan(256, 256, win=32, step=16, radius=8, levels=1, radius_coarse=8)
     disp, peak, flags = P.correct(dev(A[None]), dev(B[None]), None)
     do, po, fo = oracle.correct(A, B, 32, 16, 8, None)
-    assert np.abs(disp.cpu().numpy()[0] - do).max() <= TOL_DISP_PX
-    assert np.array_equal(flags.cpu().numpy()[0], fo)
+    compare_correct(None, None, A.astype(float), B.astype(float), 32, 16, 8, None, disp.cpu().numpy()[0],
+                    peak.cpu().numpy()[0], flags.cpu().numpy()[0], do, po, fo, where="correct[cfg1 plain]")
 
 
 def test_blank_images_are_flat():
