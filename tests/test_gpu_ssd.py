@@ -6,7 +6,7 @@ import pytest
 import torch
 
 import oracle
-from _helpers import TOL_REL, say
+from _helpers import TOL_REL, dilate, record, say
 from paper_2504_17987_amd import synth
 
 pytestmark = [pytest.mark.gpu,
@@ -104,30 +104,123 @@ def test_autograd_function_matches_backward():
     assert torch.equal(U.grad, gU)
 
 
-def test_refinement_vs_gaussian_fit():
-    """10 refinement steps from the plain-method field reduce the total SSD
-    and move the field toward the truth; both estimates are reported."""
-    from paper_2504_17987_amd import api
-    from paper_2504_17987_amd.autograd import refine
-    say("[ssd] refinement")
-    n, W, H = 4, 256, 256
+def _cfg4_batch(n, distinct):
+    """n pairs of config-4 shape cycling `distinct` renders: u8 frames (for
+    the plain method), their float32 /255 versions and the truth."""
     Au, Bu, T = [], [], []
-    for k in range(n):
-        flow = synth.smooth_random_flow(W, H, 16.0, 6.0, seed=14000 + k)
-        a, b = synth.make_pair(W, H, flow, 0.05, noise=2.0, seed=4000 + k)
+    for k in range(distinct):
+        flow = synth.smooth_random_flow(512, 512, 16.0, 6.0, seed=14000 + k)
+        a, b = synth.make_pair(512, 512, flow, 0.05, noise=2.0, seed=4000 + k)
         Au.append(a)
         Bu.append(b)
-        T.append(synth.truth(flow, W, H, 8))
-    Au, Bu, T = np.stack(Au), np.stack(Bu), np.stack(T)
-    plain = api.Plan(W, H, max_batch=n, win=16, step=8, radius=4, levels=3, radius_coarse=6, radius_fine=2)
-    out = plain.run(dev(Au), dev(Bu))
-    U0 = out["disp"]
-    P = api.Plan(W, H, max_batch=n, dtype="f32", levels=1)
+        T.append(synth.truth(flow, 512, 512, 8))
+    idx = [i % distinct for i in range(n)]
+    return (np.stack([Au[i] for i in idx]), np.stack([Bu[i] for i in idx]), np.stack([T[i] for i in idx]))
+
+
+@pytest.fixture(scope="module")
+def cfg4_refined():
+    """Config 4: 64 pairs of 512 x 512, the plain method's field (predictor,
+    Gaussian fit, validation) refined by 10 steps of piv_ssd_refine."""
+    from paper_2504_17987_amd import api
+    from paper_2504_17987_amd.autograd import refine
+    n, distinct = 64, 8
+    say("[ssd] config-4 batch: rendering")
+    Au, Bu, T = _cfg4_batch(n, distinct)
+    plain = api.Plan(512, 512, max_batch=n, win=16, step=8, radius=4, levels=3, radius_coarse=6, radius_fine=2)
+    say("[ssd] config-4 batch: plain path, then 10 refinement steps")
+    U0 = plain.run(dev(Au), dev(Bu))["disp"]
+    P = api.Plan(512, 512, max_batch=n, dtype="f32", levels=1)
     Af, Bf = dev((Au / 255.0).astype(np.float32)), dev((Bu / 255.0).astype(np.float32))
     U10, hist = refine(P, Af, Bf, U0, steps=10)
+    torch.cuda.synchronize()
+    return dict(Au=Au, Bu=Bu, T=T, U0=U0.cpu().numpy(), U10=U10.cpu().numpy(), hist=hist.cpu().numpy(),
+                P=P, Af=Af, Bf=Bf, distinct=distinct)
+
+
+def test_refine_one_step_parity(cfg4_refined):
+    """One refinement step from identical inputs on the GPU and in the FP64
+    oracle: the update within 1e-4 of its largest component, except node
+    components whose support holds a sample within 1e-4 px of a pixel line
+    (FP32 and FP64 may take different floor cells there; counted)."""
+    c = cfg4_refined
+    P, Af, Bf = c["P"], c["Af"], c["Bf"]
+    for i in (0, 3):
+        U0 = c["U0"][i:i + 1].copy()
+        Ug = dev(U0.copy())
+        hist = torch.empty((1, 2), device="cuda")
+        P.ssd_refine(Af[i:i + 1], Bf[i:i + 1], Ug, steps=1, hist=hist)
+        Ug = Ug.cpu().numpy()[0]
+        A, B = Af[i].cpu().numpy().astype(np.float64), Bf[i].cpu().numpy().astype(np.float64)
+        Uo, ho = oracle.ssd_refine(A, B, U0[0].astype(np.float64), 16, 8, steps=1)
+        step = np.abs(Uo - U0[0]).max()
+        kink = cell_edge_nodes(U0[0].astype(np.float64), 512, 512)
+        err = np.abs(Ug - Uo)
+        tol = TOL_REL * step + 2e-6   # + the FP32 rounding of U itself (|U| <= ~8 px)
+        bad = (err > tol) & ~kink
+        say(f"  pair {i}: max update {step:.3f} px, max |gpu - oracle| off kinks {err[~kink].max():.2e} px, "
+            f"kink components {int(kink.sum())}; loss {hist[0, 0].item():.4f} vs {ho[0]:.4f}")
+        record(f"refine one step, pair {i}", "near-kink", int((err > tol).sum()))
+        assert not bad.any(), (int(bad.sum()), err[bad].max())
+        assert abs(hist[0, 0].item() - ho[0]) <= TOL_REL * ho[0]
+        assert abs(hist[0, 1].item() - ho[1]) <= TOL_REL * ho[0]
+
+
+def test_refine_ten_steps_parity(cfg4_refined):
+    """Ten steps (the bench's launch configuration, 64 pairs) on two of the
+    distinct pairs.  Per step, from identical inputs (the oracle's field
+    after k steps, rounded to FP32): the GPU's step within 1e-4 of the
+    step's largest component, except components whose support holds a
+    sample within 1e-4 px of a pixel line (counted).  Over the ten steps:
+    the total loss within 1e-4 at every step, and the field within 0.01 px
+    of the oracle's except at components within one node of a component
+    some step exempted (the iteration carries such a difference on)."""
+    c = cfg4_refined
+    P = c["P"]
+    for i in (1, 6):
+        A = c["Af"][i].cpu().numpy().astype(np.float64)
+        B = c["Bf"][i].cpu().numpy().astype(np.float64)
+        U = c["U0"][i].astype(np.float64)
+        ex = np.zeros(U.shape[1:], bool)
+        ho = []
+        nex = 0
+        for k in range(10):
+            Uin = U.astype(np.float32)
+            Ug = dev(Uin[None].copy())
+            P.ssd_refine(c["Af"][i:i + 1], c["Bf"][i:i + 1], Ug, steps=1)
+            U, h = oracle.ssd_refine(A, B, Uin.astype(np.float64), 16, 8, steps=1)
+            ho.append(h[0])
+            err = np.abs(Ug.cpu().numpy()[0] - U)
+            tol = TOL_REL * np.abs(U - Uin).max() + 2e-6
+            bad = err > tol
+            kink = cell_edge_nodes(Uin.astype(np.float64), 512, 512)
+            assert not (bad & ~kink).any(), (k, int((bad & ~kink).sum()), err[bad & ~kink].max())
+            ex |= bad[0] | bad[1]
+            nex += int(bad.sum())
+        ho.append(h[1])
+        hg = c["hist"][i]
+        assert np.abs(hg - np.array(ho)).max() <= TOL_REL * ho[0], (hg, ho)
+        err = np.abs(c["U10"][i] - U).max(axis=0)
+        far = err > 0.01
+        near = dilate(ex)
+        say(f"  pair {i}: per-step exemptions {nex} (near a pixel line); after 10 steps max |gpu - oracle| "
+            f"{err.max():.2e} px, {int(far.sum())} nodes beyond 0.01 px, all within one node of an exemption: "
+            f"{bool(not (far & ~near).any())}")
+        record(f"refine step-by-step, pair {i}", "near-kink", nex)
+        record(f"refine ten steps, pair {i}", "propagated", int(far.sum()))
+        assert not (far & ~near).any()
+
+
+def test_refinement_beats_gaussian_fit(cfg4_refined):
+    """Config 4: the refined field is closer to the truth than the plain
+    method's Gaussian-fit field it starts from (interior nodes, every pair),
+    and the total SSD falls at every step."""
+    c = cfg4_refined
     inner = (slice(None), slice(None), slice(2, -2), slice(2, -2))
-    e0 = np.sqrt(((U0.cpu().numpy() - T)[inner] ** 2).mean())
-    e1 = np.sqrt(((U10.cpu().numpy() - T)[inner] ** 2).mean())
-    say(f"  total SSD {hist[0]:.2f} -> {hist[-1]:.2f}; rms vs truth: gaussian fit {e0:.4f} px, refined {e1:.4f} px")
-    assert hist[-1] < hist[0]
-    assert e1 < 1.5 * e0
+    e0 = np.sqrt(((c["U0"] - c["T"])[inner] ** 2).mean())
+    e1 = np.sqrt(((c["U10"] - c["T"])[inner] ** 2).mean())
+    h = c["hist"]
+    say(f"  total SSD {h[:, 0].sum():.1f} -> {h[:, -1].sum():.1f}; rms vs truth: gaussian fit {e0:.4f} px, "
+        f"refined {e1:.4f} px")
+    assert (np.diff(h, axis=1) < 0).all()
+    assert e1 < e0
