@@ -195,6 +195,25 @@ piv_status piv_run(piv_plan_t plan, const void* A, const void* B, int64_t pitch_
                    float* pred, float* disp, float* peak, uint8_t* flags, float* omega,
                    hipStream_t stream);
 
+/* Size of the device array piv_run_noalloc works in, per GPU. */
+#define PIV_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/* piv_run for callers that cannot allocate (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same steps and
+ * results as piv_run, with the workspace taken from a fixed device array of
+ * the library (PIV_NOALLOC_SCRATCH_BYTES on every GPU it runs on, held from
+ * library load to process end) instead of the plan's bound workspace, which
+ * may be absent.  The call allocates nothing; the caller passes inputs and
+ * outputs as for piv_run.  Each call first zeroes the array's pyramid
+ * margins for its n pairs (the array keeps whatever the previous call on
+ * that GPU left).  All calls on one GPU share its array: calls that overlap
+ * on one GPU (other streams, other threads) race.  Errors as piv_run, and
+ * PIV_ENOWORKSPACE, before any device work, when n pairs need more than
+ * PIV_NOALLOC_SCRATCH_BYTES (piv_plan_workspace_bytes(plan, n)). */
+piv_status piv_run_noalloc(piv_plan_t plan, const void* A, const void* B, int64_t pitch_bytes, int32_t n,
+                           float* pred, float* disp, float* peak, uint8_t* flags, float* omega,
+                           hipStream_t stream);
+
 /* Exponential smoothing in time (Sec. 2; alpha1 = alpha2 = 0.5 in both
  * experiments of Sec. 3), in place on field [n][2][ny][nx] with per-stream
  * state [nstate][2][ny][nx] (device, caller-owned).  Pairs are taken in

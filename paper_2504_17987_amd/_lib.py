@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(HERE, "libpiv.so")
 PIV_OK, PIV_EINVAL, PIV_EUNSUPPORTED, PIV_ENOWORKSPACE, PIV_EDEVICE = 0, 1, 2, 3, 4
 PIV_U8, PIV_U16, PIV_F32 = 1, 2, 3
 PIV_WARP_B, PIV_WARP_CENTRAL = 0, 1
+NOALLOC_SCRATCH_BYTES = 64 << 20   # PIV_NOALLOC_SCRATCH_BYTES
 PIV_PEAK_ARGMAX, PIV_PEAK_FIXED_CENTER = 0, 1
 F_FLAT, F_BORDER, F_NOCURV, F_OUTLIER, F_REPLACED, F_UNRESOLVED = 1, 2, 4, 8, 16, 32
 
@@ -22,7 +23,8 @@ F_FLAT, F_BORDER, F_NOCURV, F_OUTLIER, F_REPLACED, F_UNRESOLVED = 1, 2, 4, 8, 16
 EXPORTS = [
     "piv_params_default", "piv_plan", "piv_plan_grid", "piv_plan_workspace_bytes",
     "piv_plan_bind_workspace", "piv_plan_bind_slot_mask", "piv_plan_destroy", "piv_predict",
-    "piv_correct", "piv_validate", "piv_vorticity", "piv_run", "piv_smooth", "piv_run_temporal",
+    "piv_correct", "piv_validate", "piv_vorticity", "piv_run", "piv_run_noalloc", "piv_smooth",
+    "piv_run_temporal",
     "piv_ssd_forward", "piv_ssd_backward", "piv_ssd_refine", "piv_status_string", "piv_last_error",
     "piv_debug_correct_impl", "piv_debug_level",
 ]
@@ -71,6 +73,7 @@ def lib() -> C.CDLL:
         L.piv_validate.argtypes = [vp, vp, vp, i32, vp]
         L.piv_vorticity.argtypes = [vp, vp, vp, i32, vp]
         L.piv_run.argtypes = [vp, vp, vp, i64, i32, vp, vp, vp, vp, vp, vp]
+        L.piv_run_noalloc.argtypes = [vp, vp, vp, i64, i32, vp, vp, vp, vp, vp, vp]
         L.piv_ssd_forward.argtypes = [vp, vp, vp, vp, i32, vp, vp]
         L.piv_ssd_backward.argtypes = [vp, vp, vp, vp, vp, i32, vp, vp, vp]
         f32 = C.c_float
@@ -79,7 +82,7 @@ def lib() -> C.CDLL:
         L.piv_ssd_refine.argtypes = [vp, vp, vp, vp, i32, i32, f32, f32, vp, vp]
         for name in ["piv_plan", "piv_plan_grid", "piv_plan_bind_workspace", "piv_plan_bind_slot_mask",
                      "piv_predict", "piv_correct", "piv_validate", "piv_vorticity", "piv_run",
-                     "piv_smooth", "piv_run_temporal", "piv_ssd_forward", "piv_ssd_backward",
+                     "piv_run_noalloc", "piv_smooth", "piv_run_temporal", "piv_ssd_forward", "piv_ssd_backward",
                      "piv_ssd_refine"]:
             getattr(L, name).restype = st
         L.piv_status_string.argtypes = [st]

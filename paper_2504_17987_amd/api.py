@@ -244,6 +244,20 @@ class Plan:
                                 _ptr(out["omega"]), _stream(self.device)))
         return out
 
+    def run_noalloc(self, A, B, out: Dict[str, torch.Tensor]) -> Dict[str, torch.Tensor]:
+        """piv_run on the library's fixed device scratch array instead of the
+        plan's workspace (which may be absent): allocates nothing, so every
+        output must be passed in `out` (pred, disp, flags, omega; peak
+        optional).  Calls that overlap on one GPU share the array and race."""
+        n, pitch = self._images(A, B)
+        self._outputs(n, out)
+        self._devices(A=A, B=B)
+        self._out_devices(out)
+        L.check(L.lib().piv_run_noalloc(self.handle, _ptr(A), _ptr(B), pitch, n, _ptr(out["pred"]),
+                                        _ptr(out["disp"]), _ptr(out.get("peak")), _ptr(out["flags"]),
+                                        _ptr(out["omega"]), _stream(self.device)))
+        return out
+
     def _new_outputs(self, n):
         return dict(pred=self._field(n), disp=self._field(n), peak=self._vec(n),
                     flags=self._vec(n, torch.uint8), omega=self._vec(n))

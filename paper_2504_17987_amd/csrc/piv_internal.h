@@ -94,5 +94,15 @@ bool sad_supported(int block_words);
 // Which correlation kernel a plan uses (exposed for tests and the bench).
 int correct_impl(const Plan& P);
 
+// piv_run's host checks for a workspace of ws_bytes (no device work), and
+// piv_run's checks and steps on the workspace `ws` of ws_bytes (instead of
+// the plan's bound one), whose margins are zeroed first (plan.cpp).
+piv_status check_on_workspace(const Plan& P, size_t ws_bytes, const void* A, const void* B, int64_t pitch,
+                              int32_t n, float* pred, float* disp, uint8_t* flags, float* omega);
+piv_status run_on_workspace(const Plan& P, uint8_t* ws, size_t ws_bytes, const void* A, const void* B,
+                            int64_t pitch, int32_t n, float* pred, float* disp, float* peak, uint8_t* flags,
+                            float* omega, hipStream_t stream);
+// records msg as the calling thread's last error and returns s
+piv_status set_error(piv_status s, const char* msg);
 
 }  // namespace piv

@@ -311,6 +311,39 @@ piv_status check_alpha(float a, const char* name) {
 
 }  // namespace
 
+extern "C++" {
+namespace piv {
+
+piv_status check_on_workspace(const Plan& P, size_t ws_bytes, const void* A, const void* B, int64_t pitch,
+                              int32_t n, float* pred, float* disp, uint8_t* flags, float* omega) {
+  if (piv_status s = check_images(P, A, B, pitch, n)) return s;
+  if (!pred || !disp || !flags || !omega) return fail(PIV_EINVAL, "pred, disp, flags, omega must not be NULL");
+  if (P.p.dtype == PIV_F32) return fail(PIV_EUNSUPPORTED, "the predictor takes U8/U16 frames");
+  if ((size_t)n * P.per_pair > ws_bytes)
+    return fail(PIV_ENOWORKSPACE, "%d pairs need %zu bytes of workspace, the scratch holds %zu", n,
+                (size_t)n * P.per_pair, ws_bytes);
+  return PIV_OK;
+}
+
+piv_status run_on_workspace(const Plan& P, uint8_t* ws, size_t ws_bytes, const void* A, const void* B,
+                            int64_t pitch, int32_t n, float* pred, float* disp, float* peak, uint8_t* flags,
+                            float* omega, hipStream_t stream) {
+  if (piv_status s = check_on_workspace(P, ws_bytes, A, B, pitch, n, pred, disp, flags, omega)) return s;
+  if (n == 0) return PIV_OK;
+  Plan Q = P;   // host copy: the same geometry on the given workspace
+  Q.ws = ws;
+  Q.ws_bytes = ws_bytes;
+  Q.ws_pairs = n;
+  // the memory holds whatever the previous call left: zero the margins first
+  if (piv_status s = dev(launch_clear_margins(Q, ws, n, stream), "clear_margins")) return s;
+  return run_path(Q, A, B, pitch, n, pred, disp, peak, flags, omega, nullptr, stream);
+}
+
+piv_status set_error(piv_status s, const char* msg) { return fail(s, "%s", msg); }
+
+}  // namespace piv
+}  // extern "C++"
+
 piv_status piv_run(piv_plan_t plan, const void* A, const void* B, int64_t pitch, int32_t n,
                    float* pred, float* disp, float* peak, uint8_t* flags, float* omega,
                    hipStream_t stream) {

@@ -317,3 +317,23 @@ def test_level0_in_place_reads_stay_in_written_bytes(L, kw):
                 for cx in (cs if b in (0, 1, v["nx"] - 2, v["nx"] - 1) else (-cand, 0, cand)):
                     xs = b * step + off + cx - R
                     check(y0, blk + 2 * R, xs & ~3, 4 * (RW + 1))
+
+
+def test_noalloc_rejects_before_any_device_call(L):
+    """piv_run_noalloc checks its arguments and the size of its fixed scratch
+    array on the host: work beyond the array, bad arguments and n = 0 return
+    without touching a device (this runs without one)."""
+    lib = L.lib()
+    s, h = plan(L, width=2048, height=2048, max_batch=16)
+    assert s == 0
+    per = lib.piv_plan_workspace_bytes(h, 1)
+    n = L.NOALLOC_SCRATCH_BYTES // per + 1
+    assert n <= 16
+    fake = C.c_void_p(1 << 20)
+    assert lib.piv_run_noalloc(h, fake, fake, 2048, n, fake, fake, None, fake, fake, None) == L.PIV_ENOWORKSPACE
+    assert b"scratch" in lib.piv_last_error()
+    assert lib.piv_run_noalloc(h, fake, fake, 2048, 0, fake, fake, None, fake, fake, None) == 0
+    assert lib.piv_run_noalloc(h, fake, fake, 2046, 1, fake, fake, None, fake, fake, None) == L.PIV_EINVAL
+    assert lib.piv_run_noalloc(h, fake, fake, 2048, 1, None, fake, None, fake, fake, None) == L.PIV_EINVAL
+    assert lib.piv_run_noalloc(None, fake, fake, 2048, 1, fake, fake, None, fake, fake, None) == L.PIV_EINVAL
+    lib.piv_plan_destroy(h)
