@@ -66,6 +66,10 @@ def lib():
         L.o_ssd_grad.argtypes = [_D, _D, _D, _D, _i, _i, _i, _i, _D, _Dn]
         L.o_ssd_refine.argtypes = [_D, _D, _D, _i, _i, _i, _i, _i, _d, _d, _Dn]
         L.o_smooth.argtypes = [_D, _D, _i, _d, _i]
+        L.o_highpass.argtypes = [_I, _i, _i, _i, _I]
+        L.o_clahe_clip.argtypes = [C.c_int64, _i, _d]
+        L.o_clahe_clip.restype = C.c_int64
+        L.o_clahe.argtypes = [_I, _i, _i, _i, _i, _i, _d, _I]
         _lib = L
     return _lib
 
@@ -234,6 +238,30 @@ def smooth_batch(fields, states, slots, alpha):
             continue
         out[i], st[k] = smooth(out[i], st[k], alpha, first)
     return out, st
+
+
+def highpass(img, radius):
+    """Background removal: max(0, I - floor(box mean over the image part of
+    the (2 radius + 1)^2 box))."""
+    I = _img_i(img)
+    H, W = I.shape
+    out = np.zeros_like(I)
+    lib().o_highpass(I, W, H, int(radius), out)
+    return out
+
+
+def clahe_clip(npix, nbins, clip_factor):
+    return int(lib().o_clahe_clip(int(npix), int(nbins), float(clip_factor)))
+
+
+def clahe(img, bits, tiles_x, tiles_y, clip_factor):
+    """Contrast-limited adaptive histogram equalisation on a tiles_x x
+    tiles_y grid (see oracle.c for the exact reading)."""
+    I = _img_i(img)
+    H, W = I.shape
+    out = np.zeros_like(I)
+    lib().o_clahe(I, W, H, int(bits), int(tiles_x), int(tiles_y), float(clip_factor), out)
+    return out
 
 
 def run(A, B, *, win, step, r, levels, block=0, Rc, Rf, median=True, warp_mode=0, peak_mode=0,

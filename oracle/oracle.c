@@ -658,3 +658,128 @@ void o_smooth(double* field, double* state, int np2, double alpha, int first) {
     field[j] = s;
   }
 }
+
+/* ------------------------------------------------------------------------
+ * Pre-processing (Sec. 2: a high-pass filter removes the static background,
+ * then contrast-limited adaptive histogram equalisation brightens the
+ * image; Sec. 3.1 uses both to match intensities across stitched images).
+ * The paper does not specify either filter; these are the readings, in
+ * integer arithmetic throughout.
+ * ---------------------------------------------------------------------- */
+
+/* High-pass: out = max(0, I - floor(mean of I over the (2r+1)^2 box around
+ * the pixel, restricted to the image)).  I, out [H][W]. */
+void o_highpass(const int32_t* I, int W, int H, int r, int32_t* out) {
+#pragma omp parallel for schedule(static)
+  for (int y = 0; y < H; ++y)
+    for (int x = 0; x < W; ++x) {
+      int64_t s = 0, c = 0;
+      for (int v = y - r; v <= y + r; ++v)
+        for (int u = x - r; u <= x + r; ++u)
+          if (u >= 0 && v >= 0 && u < W && v < H) {
+            s += I[(size_t)v * W + u];
+            ++c;
+          }
+      int64_t m = s / c; /* s, c > 0: floor */
+      int64_t d = I[(size_t)y * W + x] - m;
+      out[(size_t)y * W + x] = (int32_t)(d > 0 ? d : 0);
+    }
+}
+
+/* Tile boundary j of n tiles over a length L: floor(j L / n). */
+static int tile_edge(int j, int L, int n) { return (int)(((int64_t)j * L) / n); }
+
+/* One tile's mapping (contrast-limited equalisation):
+ * histogram over nbins (bin = value >> shift); clip every bin at `clip`;
+ * the clipped excess is spread evenly: excess / nbins to every bin, then one
+ * more to each of the first `rest` bins taken at a stride of
+ * max(nbins / rest, 1) from bin 0; lut[b] = round-half-up of
+ * cdf(b) * maxval / npix. */
+static void clahe_tile_lut(const int32_t* I, int W, int x0, int x1, int y0, int y1, int nbins, int shift,
+                           int64_t clip, int maxval, int32_t* lut) {
+  int64_t* h = (int64_t*)calloc((size_t)nbins, sizeof(int64_t));
+  int64_t npix = (int64_t)(x1 - x0) * (y1 - y0);
+  for (int y = y0; y < y1; ++y)
+    for (int x = x0; x < x1; ++x) h[I[(size_t)y * W + x] >> shift]++;
+  int64_t excess = 0;
+  for (int b = 0; b < nbins; ++b)
+    if (h[b] > clip) {
+      excess += h[b] - clip;
+      h[b] = clip;
+    }
+  int64_t each = excess / nbins, rest = excess - each * nbins;
+  for (int b = 0; b < nbins; ++b) h[b] += each;
+  if (rest > 0) {
+    int64_t stride = nbins / rest;
+    if (stride < 1) stride = 1;
+    for (int64_t b = 0; b < nbins && rest > 0; b += stride, --rest) h[b]++;
+  }
+  int64_t cdf = 0;
+  for (int b = 0; b < nbins; ++b) {
+    cdf += h[b];
+    lut[b] = npix > 0 ? (int32_t)((cdf * maxval + npix / 2) / npix) : 0;
+  }
+  free(h);
+}
+
+/* The clip limit of a tile of npix pixels: max(1, floor(clip_factor *
+ * npix / nbins)). */
+int64_t o_clahe_clip(int64_t npix, int nbins, double clip_factor) {
+  double c = floor(clip_factor * (double)npix / (double)nbins);
+  return c < 1.0 ? 1 : (int64_t)c;
+}
+
+/* CLAHE on a tx x ty grid of tiles (tile j spans [floor(j W/tx),
+ * floor((j+1) W/tx)) and likewise in y).  Every tile's mapping is evaluated
+ * at the tile centre; a pixel takes the bilinear blend of the mappings of
+ * the (up to) four tiles whose centres surround it, clamped at the outer
+ * centres; weights are computed in doubled coordinates (centres may be
+ * half-integers) and the blend rounds half up, all in integers.
+ * bits: meaningful bits of the values (8 for u8); nbins = 2^min(bits, 12). */
+void o_clahe(const int32_t* I, int W, int H, int bits, int tx, int ty, double clip_factor, int32_t* out) {
+  int lb = bits < 12 ? bits : 12, nbins = 1 << lb, shift = bits - lb, maxval = (1 << bits) - 1;
+  int32_t* luts = (int32_t*)malloc(sizeof(int32_t) * (size_t)nbins * tx * ty);
+  for (int j = 0; j < ty; ++j)
+    for (int i = 0; i < tx; ++i) {
+      int x0 = tile_edge(i, W, tx), x1 = tile_edge(i + 1, W, tx);
+      int y0 = tile_edge(j, H, ty), y1 = tile_edge(j + 1, H, ty);
+      int64_t clip = o_clahe_clip((int64_t)(x1 - x0) * (y1 - y0), nbins, clip_factor);
+      clahe_tile_lut(I, W, x0, x1, y0, y1, nbins, shift, clip, maxval, luts + ((size_t)j * tx + i) * nbins);
+    }
+  for (int y = 0; y < H; ++y)
+    for (int x = 0; x < W; ++x) {
+      /* doubled coordinates: pixel 2x, tile centre x0 + x1 - 1 */
+      int ia = 0, ib = 0, ja = 0, jb = 0;
+      int64_t wx = 0, dx = 1, wy = 0, dy = 1;
+      int X = 2 * x, Y = 2 * y;
+      for (int i = 0; i < tx; ++i)
+        if (tile_edge(i, W, tx) + tile_edge(i + 1, W, tx) - 1 <= X) ia = i;
+      if (tile_edge(0, W, tx) + tile_edge(1, W, tx) - 1 > X) ia = 0, ib = 0;
+      else if (ia == tx - 1) ib = ia;
+      else {
+        ib = ia + 1;
+        int ca = tile_edge(ia, W, tx) + tile_edge(ia + 1, W, tx) - 1;
+        int cb = tile_edge(ib, W, tx) + tile_edge(ib + 1, W, tx) - 1;
+        wx = X - ca;
+        dx = cb - ca;
+      }
+      for (int j = 0; j < ty; ++j)
+        if (tile_edge(j, H, ty) + tile_edge(j + 1, H, ty) - 1 <= Y) ja = j;
+      if (tile_edge(0, H, ty) + tile_edge(1, H, ty) - 1 > Y) ja = 0, jb = 0;
+      else if (ja == ty - 1) jb = ja;
+      else {
+        jb = ja + 1;
+        int ca = tile_edge(ja, H, ty) + tile_edge(ja + 1, H, ty) - 1;
+        int cb = tile_edge(jb, H, ty) + tile_edge(jb + 1, H, ty) - 1;
+        wy = Y - ca;
+        dy = cb - ca;
+      }
+      int b = I[(size_t)y * W + x] >> shift;
+      int64_t l00 = luts[((size_t)ja * tx + ia) * nbins + b], l01 = luts[((size_t)ja * tx + ib) * nbins + b];
+      int64_t l10 = luts[((size_t)jb * tx + ia) * nbins + b], l11 = luts[((size_t)jb * tx + ib) * nbins + b];
+      int64_t num = (dy - wy) * ((dx - wx) * l00 + wx * l01) + wy * ((dx - wx) * l10 + wx * l11);
+      int64_t den = dx * dy;
+      out[(size_t)y * W + x] = (int32_t)((num + den / 2) / den);
+    }
+  free(luts);
+}
