@@ -240,6 +240,42 @@ piv_status piv_run_temporal(piv_plan_t plan, const void* A, const void* B, int64
                             float* state_disp, float alpha1, float alpha2, float* pred, float* disp,
                             float* peak, uint8_t* flags, float* omega, hipStream_t stream);
 
+/* Pre-processing (Sec. 2: every frame is high-pass filtered to remove the
+ * static background, then contrast-enhanced by CLAHE, before the predictor
+ * and the correlation; Sec. 3.1 uses both to match the intensities of
+ * stitched images).  The paper does not specify the filters; these are
+ * exact integer readings.  Frames as for piv_run (the plan's size, dtype
+ * U8 or U16 and bit_depth); out has the same layout and pitch as in.
+ *
+ * piv_highpass: out = max(0, in - floor(mean of in over the image part of
+ * the (2 radius + 1)^2 box around each pixel)), radius in [1, 16].  out
+ * must not alias in.  Errors: PIV_EINVAL (arguments), PIV_EUNSUPPORTED
+ * (F32 plan). */
+piv_status piv_highpass(piv_plan_t plan, const void* in, void* out, int64_t pitch_bytes, int32_t n,
+                        int32_t radius, hipStream_t stream);
+
+/* Device bytes of the CLAHE mappings for n pairs on a tiles_x x tiles_y
+ * grid: n * tiles_x * tiles_y * nbins uint16, nbins = 2^min(bits, 12)
+ * (256 for U8, 4096 for U16).  0 for bad arguments. */
+size_t piv_clahe_lut_bytes(piv_plan_t plan, int32_t n, int32_t tiles_x, int32_t tiles_y);
+
+/* Contrast-limited adaptive histogram equalisation.  Tile j of a row spans
+ * [floor(j W / tiles_x), floor((j+1) W / tiles_x)) (likewise in y).  Per
+ * tile: histogram of value >> (bits - log2 nbins); every bin clipped at
+ * max(1, floor(clip_factor * npix / nbins)) (double arithmetic), the
+ * clipped excess spread evenly (excess / nbins to every bin, then one more
+ * to the first excess % nbins bins taken at a stride of
+ * max(nbins / (excess % nbins), 1) from bin 0); mapping
+ * lut[b] = (cdf(b) * maxval + npix / 2) / npix, maxval = 2^bits - 1.
+ * Every pixel blends the mappings of the up to four tiles whose centres
+ * surround it (bilinear weights in doubled coordinates, clamped at the
+ * outer centres, rounded half up in integers).  lut: caller-owned device
+ * scratch of at least piv_clahe_lut_bytes (4-byte aligned), left holding
+ * the mappings.  out may equal in.  tiles in [1, min(64, size)]. */
+piv_status piv_clahe(piv_plan_t plan, const void* in, void* out, int64_t pitch_bytes, int32_t n,
+                     int32_t tiles_x, int32_t tiles_y, double clip_factor, void* lut, size_t lut_bytes,
+                     hipStream_t stream);
+
 /* Windowed SSD of the deformation (an addition, not in the paper): for
  * float32 frames A, B [n][height][width] (pitch = width) and a node field
  * U [n][2][ny][nx], loss[n][ny][nx] = sum over each window of

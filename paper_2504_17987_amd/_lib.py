@@ -24,7 +24,7 @@ EXPORTS = [
     "piv_params_default", "piv_plan", "piv_plan_grid", "piv_plan_workspace_bytes",
     "piv_plan_bind_workspace", "piv_plan_bind_slot_mask", "piv_plan_destroy", "piv_predict",
     "piv_correct", "piv_validate", "piv_vorticity", "piv_run", "piv_run_noalloc", "piv_smooth",
-    "piv_run_temporal",
+    "piv_run_temporal", "piv_highpass", "piv_clahe_lut_bytes", "piv_clahe",
     "piv_ssd_forward", "piv_ssd_backward", "piv_ssd_refine", "piv_status_string", "piv_last_error",
     "piv_debug_correct_impl", "piv_debug_level",
 ]
@@ -80,10 +80,14 @@ def lib() -> C.CDLL:
         L.piv_smooth.argtypes = [vp, vp, vp, vp, i32, f32, i32, vp]
         L.piv_run_temporal.argtypes = [vp, vp, vp, i64, i32, vp, i32, vp, vp, f32, f32, vp, vp, vp, vp, vp, vp]
         L.piv_ssd_refine.argtypes = [vp, vp, vp, vp, i32, i32, f32, f32, vp, vp]
+        L.piv_highpass.argtypes = [vp, vp, vp, i64, i32, i32, vp]
+        L.piv_clahe_lut_bytes.argtypes = [vp, i32, i32, i32]
+        L.piv_clahe_lut_bytes.restype = C.c_size_t
+        L.piv_clahe.argtypes = [vp, vp, vp, i64, i32, i32, i32, C.c_double, vp, C.c_size_t, vp]
         for name in ["piv_plan", "piv_plan_grid", "piv_plan_bind_workspace", "piv_plan_bind_slot_mask",
                      "piv_predict", "piv_correct", "piv_validate", "piv_vorticity", "piv_run",
                      "piv_run_noalloc", "piv_smooth", "piv_run_temporal", "piv_ssd_forward", "piv_ssd_backward",
-                     "piv_ssd_refine"]:
+                     "piv_ssd_refine", "piv_highpass", "piv_clahe"]:
             getattr(L, name).restype = st
         L.piv_status_string.argtypes = [st]
         L.piv_status_string.restype = C.c_char_p

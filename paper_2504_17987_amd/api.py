@@ -262,6 +262,42 @@ class Plan:
         return dict(pred=self._field(n), disp=self._field(n), peak=self._vec(n),
                     flags=self._vec(n, torch.uint8), omega=self._vec(n))
 
+    # -- pre-processing -------------------------------------------------------
+    def _frames(self, inp, out):
+        """inp [n][H][W] frames of the plan's dtype; out the same shape (new
+        when None)."""
+        if out is None:
+            out = torch.empty_like(inp)
+        n, pitch = self._images(inp, out)
+        self._devices(inp=inp, out=out)
+        return n, pitch, out
+
+    def highpass(self, inp, out=None, radius: int = 7):
+        """Background removal: max(0, I - floor(box mean)) over the image
+        part of the (2 radius + 1)^2 box; out must not alias inp."""
+        n, pitch, out = self._frames(inp, out)
+        L.check(L.lib().piv_highpass(self.handle, _ptr(inp), _ptr(out), pitch, n, int(radius),
+                                     _stream(self.device)))
+        return out
+
+    def clahe_lut_bytes(self, n: int, tiles_x: int, tiles_y: int) -> int:
+        return int(L.lib().piv_clahe_lut_bytes(self.handle, n, tiles_x, tiles_y))
+
+    def clahe(self, inp, out=None, tiles=(8, 8), clip_factor: float = 2.0, lut=None):
+        """Contrast-limited adaptive histogram equalisation on a tiles[0] x
+        tiles[1] grid (out may be inp); lut: optional uint8 device scratch of
+        clahe_lut_bytes(n, *tiles) bytes, left holding the tile mappings."""
+        n, pitch, out = self._frames(inp, out)
+        need = self.clahe_lut_bytes(n, tiles[0], tiles[1])
+        if lut is None:
+            lut = torch.empty(max(need, 4), dtype=torch.uint8, device=self.device)
+        if lut.dtype != torch.uint8 or not lut.is_contiguous() or lut.numel() < need:
+            raise ValueError(f"lut must be a contiguous uint8 tensor of at least {need} bytes")
+        self._devices(lut=lut)
+        L.check(L.lib().piv_clahe(self.handle, _ptr(inp), _ptr(out), pitch, n, int(tiles[0]), int(tiles[1]),
+                                  float(clip_factor), _ptr(lut), lut.numel(), _stream(self.device)))
+        return out
+
     # -- temporal smoothing ----------------------------------------------------
     def new_state(self, nstate: int) -> torch.Tensor:
         """Zeroed smoothing state for `nstate` streams, [nstate][2][ny][nx]."""

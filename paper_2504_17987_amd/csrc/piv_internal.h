@@ -88,6 +88,13 @@ hipError_t launch_ssd_update(const Plan& P, float* U, int n, float tau, float la
 hipError_t launch_smooth(const Plan& P, float* field, float* state, const int32_t* slot, int nstate,
                          float alpha, int n, hipStream_t s);
 
+// pre-processing: high-pass background removal and CLAHE (preproc.hip);
+// lut holds n * ty * tx * clahe_bins(P) uint16 entries
+hipError_t launch_highpass(const Plan& P, const void* in, void* out, int64_t pitch, int n, int r, hipStream_t s);
+hipError_t launch_clahe(const Plan& P, const void* in, void* out, int64_t pitch, int n, int tx, int ty,
+                        double clip_factor, uint16_t* lut, hipStream_t s);
+int clahe_bins(const Plan& P);
+
 // Block widths (in 4-byte words) the SAD kernel is built for.
 bool sad_supported(int block_words);
 

@@ -384,6 +384,46 @@ piv_status piv_run_temporal(piv_plan_t plan, const void* A, const void* B, int64
   return run_path(P, A, B, pitch, n, pred, disp, peak, flags, omega, &tm, stream);
 }
 
+piv_status piv_highpass(piv_plan_t plan, const void* in, void* out, int64_t pitch, int32_t n, int32_t radius,
+                        hipStream_t stream) {
+  if (!plan) return fail(PIV_EINVAL, "plan is NULL");
+  const Plan& P = *cplan(plan);
+  if (P.p.dtype == PIV_F32) return fail(PIV_EUNSUPPORTED, "pre-processing takes U8/U16 frames");
+  if (piv_status s = check_images(P, in, out, pitch, n)) return s;
+  if (in == out) return fail(PIV_EINVAL, "the high-pass cannot run in place (in == out)");
+  if (radius < 1 || radius > 16) return fail(PIV_EINVAL, "radius %d outside [1, 16]", radius);
+  if (n == 0) return PIV_OK;
+  return dev(piv::launch_highpass(P, in, out, pitch, n, radius, stream), "highpass");
+}
+
+size_t piv_clahe_lut_bytes(piv_plan_t plan, int32_t n, int32_t tiles_x, int32_t tiles_y) {
+  if (!plan || n < 0 || tiles_x <= 0 || tiles_y <= 0) return 0;
+  const Plan& P = *cplan(plan);
+  if (P.p.dtype == PIV_F32) return 0;
+  return sizeof(uint16_t) * (size_t)n * tiles_x * tiles_y * piv::clahe_bins(P);
+}
+
+piv_status piv_clahe(piv_plan_t plan, const void* in, void* out, int64_t pitch, int32_t n, int32_t tiles_x,
+                     int32_t tiles_y, double clip_factor, void* lut, size_t lut_bytes, hipStream_t stream) {
+  if (!plan) return fail(PIV_EINVAL, "plan is NULL");
+  const Plan& P = *cplan(plan);
+  if (P.p.dtype == PIV_F32) return fail(PIV_EUNSUPPORTED, "pre-processing takes U8/U16 frames");
+  if (piv_status s = check_images(P, in, out, pitch, n)) return s;
+  if (tiles_x < 1 || tiles_y < 1 || tiles_x > 64 || tiles_y > 64 || tiles_x > P.p.width || tiles_y > P.p.height)
+    return fail(PIV_EINVAL, "tiles %d x %d outside [1, min(64, size)]", tiles_x, tiles_y);
+  if (!(clip_factor > 0.0) || !(clip_factor < 1e300)) return fail(PIV_EINVAL, "clip_factor must be positive and finite");
+  if (!lut) return fail(PIV_EINVAL, "lut must not be NULL");
+  if ((uintptr_t)lut & 3) return fail(PIV_EINVAL, "lut must be 4-byte aligned");
+  if (lut_bytes < piv_clahe_lut_bytes(plan, n, tiles_x, tiles_y))
+    return fail(PIV_EINVAL, "lut holds %zu bytes, needs %zu", lut_bytes, piv_clahe_lut_bytes(plan, n, tiles_x, tiles_y));
+  if ((int64_t)(P.p.width / tiles_x + 1) * (P.p.height / tiles_y + 1) >= (int64_t(1) << 31))
+    return fail(PIV_EINVAL, "tiles too large");
+  if (n == 0) return PIV_OK;
+  return dev(piv::launch_clahe(P, in, out, pitch, n, tiles_x, tiles_y, clip_factor, static_cast<uint16_t*>(lut),
+                               stream),
+             "clahe");
+}
+
 piv_status piv_ssd_forward(piv_plan_t plan, const float* A, const float* B, const float* U, int32_t n,
                            float* loss, hipStream_t stream) {
   if (!plan) return fail(PIV_EINVAL, "plan is NULL");

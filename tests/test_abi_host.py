@@ -337,3 +337,32 @@ def test_noalloc_rejects_before_any_device_call(L):
     assert lib.piv_run_noalloc(h, fake, fake, 2048, 1, None, fake, None, fake, fake, None) == L.PIV_EINVAL
     assert lib.piv_run_noalloc(None, fake, fake, 2048, 1, fake, fake, None, fake, fake, None) == L.PIV_EINVAL
     lib.piv_plan_destroy(h)
+
+
+def test_preprocess_argument_errors(L):
+    """Pre-processing rejects bad arguments on the host, before any launch."""
+    lib = L.lib()
+    s, h = plan(L, max_batch=2)
+    assert s == 0
+    fake, fake2 = C.c_void_p(1 << 20), C.c_void_p(1 << 21)
+    assert lib.piv_highpass(h, fake, fake, 1024, 1, 7, None) == L.PIV_EINVAL          # in place
+    assert lib.piv_highpass(h, fake, fake2, 1024, 1, 0, None) == L.PIV_EINVAL         # radius
+    assert lib.piv_highpass(h, fake, fake2, 1024, 1, 17, None) == L.PIV_EINVAL
+    assert lib.piv_highpass(h, fake, fake2, 1023, 1, 7, None) == L.PIV_EINVAL         # pitch
+    assert lib.piv_highpass(h, fake, fake2, 1024, 3, 7, None) == L.PIV_EINVAL         # n > max_batch
+    assert lib.piv_highpass(h, fake, fake2, 1024, 0, 7, None) == 0
+    need = lib.piv_clahe_lut_bytes(h, 2, 8, 8)
+    assert need == 2 * 64 * 256 * 2
+    assert lib.piv_clahe(h, fake, fake, 1024, 2, 8, 8, 2.0, fake2, need - 1, None) == L.PIV_EINVAL
+    assert lib.piv_clahe(h, fake, fake, 1024, 2, 0, 8, 2.0, fake2, need, None) == L.PIV_EINVAL
+    assert lib.piv_clahe(h, fake, fake, 1024, 2, 65, 8, 2.0, fake2, 1 << 30, None) == L.PIV_EINVAL
+    assert lib.piv_clahe(h, fake, fake, 1024, 2, 8, 8, 0.0, fake2, need, None) == L.PIV_EINVAL
+    assert lib.piv_clahe(h, fake, fake, 1024, 2, 8, 8, 2.0, None, need, None) == L.PIV_EINVAL
+    assert lib.piv_clahe(h, fake, fake, 1024, 0, 8, 8, 2.0, fake2, need, None) == 0
+    lib.piv_plan_destroy(h)
+    s, u = plan(L, dtype=2, bit_depth=12, win=24, step=12, width=3840, height=2160)
+    assert s == 0 and lib.piv_clahe_lut_bytes(u, 1, 8, 8) == 64 * 4096 * 2
+    lib.piv_plan_destroy(u)
+    s, f = plan(L, dtype=3, levels=1, width=64, height=64)
+    assert lib.piv_highpass(f, fake, fake2, 256, 1, 7, None) == L.PIV_EUNSUPPORTED
+    lib.piv_plan_destroy(f)
