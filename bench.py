@@ -11,14 +11,18 @@ the memory-bound stages of one batch then run beside the ALU-bound
 correlation of the other.  The one-stream rate is reported beside it.
 
 Prints ONE JSON line with pairs/s (value), Mvectors/s, p50/p99 latency of
-the batched step and of a single pair, the HBM-roofline fraction of the
-whole step, the roofline of the dominant kernel (the correlation stage)
-measured with HIP events on its stream, the FP64 CPU oracle timed on a
-bounded sample of the same workload, and the other forms of the path:
-HIP-graph batches of 8, continuous batching of a served mix of sizes
-against the plain per-pair FIFO form on the same arrival trace, a stream
-of 4K u16 pairs in graph batches of 8, the differentiable SSD, and the
-largest image the paper runs (8192 x 4096).
+the batched step and of a single pair, the step's accuracy against the
+analytic truth, the HBM-roofline fraction of the whole step, the roofline
+of the dominant kernel (the correlation stage) measured with HIP events on
+its stream, the FP64 CPU oracle timed on a bounded sample of the same
+workload (all cores and one thread, with its agreement with the GPU on
+that pair), and the other forms of the path: the 256^2 config (plain
+correction and L = 1 path), HIP-graph batches of 8, pre-processing
+(high-pass, CLAHE), the 500-pair 4K u16 stream in graph batches of 8, the
+differentiable SSD and its refinement, the largest image the paper runs
+(8192 x 4096), the low-seeding study (fixed-centre stencil against the
+argmax search), and continuous batching of a served mix of sizes against
+the plain per-pair FIFO form over a sweep of offered loads.
 """
 from __future__ import annotations
 
@@ -51,7 +55,11 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-latency", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the graph/serving/stream/SSD forms")
-    ap.add_argument("--serve-seconds", type=float, default=3.0)
+    ap.add_argument("--serve-seconds", type=float, default=2.0, help="seconds of arrivals per load point")
+    ap.add_argument("--serve-first-scale", type=float, default=1.0,
+                    help="the first (3,000 pairs/s) load point runs this many times longer")
+    ap.add_argument("--serve-rates", type=float, nargs="+", default=[3000.0, 6000.0, 12000.0, 24000.0],
+                    help="offered loads (pairs/s, all 12 streams together)")
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="first run three plain device-to-device copies of MIB MiB (a known-size "
@@ -77,36 +85,109 @@ def algorithmic(W, H, nx, ny, r):
     return dict(corr_flop=corr_flop, path_bytes=path_bytes)
 
 
-def cpu_baseline(A, B, log_fn):
-    """The FP64 oracle (as it stands) on a bounded sample of one pair: the
-    full predictor, then the correction on a 512-row strip (8192 of the
-    16384 windows), validation and vorticity on the full grid; seconds per
-    pair are scaled from the strip."""
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(A, B, log_fn, strip_rows=16):
+    """The FP64 oracle (as it stands) on a bounded sample of one 1 MP pair of
+    the workload, on the host's cores.
+
+    All cores (OpenMP, the thread count the runtime takes): the whole path on
+    the full pair (predictor, its validation, correction, validation,
+    vorticity).  One thread: the full predictor, then the correction on a
+    strip of `strip_rows` window rows scaled to the 128 rows of the pair,
+    validation and vorticity on the full grid.  Runs before the GPU is
+    touched.  Returns the baseline and the all-core run's outputs (checked
+    against the GPU's results for the same pair afterwards)."""
+    import ctypes
+
     import oracle
-    W = A.shape[1]
+    gomp = ctypes.CDLL("libgomp.so.1")
+    nproc = os.cpu_count() or 1
+    threads = int(gomp.omp_get_max_threads())
     t0 = time.perf_counter()
-    pred = oracle.predict(A, B, 8, 16, 3, 6, 2).astype(np.float64)
-    pred, _ = oracle.validate(pred, None)
-    t_pred = time.perf_counter() - t0
-    rows = 64
-    strip = slice(256, 768)
-    As, Bs = A[strip], B[strip]
-    ps = np.ascontiguousarray(pred[:, 32:32 + rows])
+    ref = oracle.run(A, B, win=16, step=8, r=4, levels=3, Rc=6, Rf=2)
+    t_all = time.perf_counter() - t0
+    gomp.omp_set_num_threads(1)
+    try:
+        t0 = time.perf_counter()
+        pred = oracle.predict(A, B, 8, 16, 3, 6, 2).astype(np.float64)
+        pred, _ = oracle.validate(pred, None)
+        t_pred = time.perf_counter() - t0
+        ys = slice(512 - 8 * strip_rows // 2 - 4, 512 + 8 * strip_rows // 2 + 4)
+        ps = np.ascontiguousarray(pred[:, 64 - strip_rows // 2:64 + strip_rows // 2 + 1])
+        t0 = time.perf_counter()
+        oracle.correct(A[ys], B[ys], 16, 8, 4, ps)
+        t_corr = (time.perf_counter() - t0) * 128.0 / (strip_rows + 1)
+        t0 = time.perf_counter()
+        f = ref["disp_raw"].copy()
+        oracle.validate(f, ref["flags_raw"].copy())
+        oracle.vorticity(f, 8)
+        t_post = time.perf_counter() - t0
+    finally:
+        gomp.omp_set_num_threads(threads)
+    t_one = t_pred + t_corr + t_post
+    log_fn(f"cpu oracle ({_cpu_model()}, nproc {nproc}): all {threads} threads {t_all:.2f} s per pair; "
+           f"one thread {t_one:.2f} s per pair (predict {t_pred:.2f} s, correct scaled {t_corr:.2f} s)")
+    base = {"value": round(1.0 / t_all, 5), "unit": "pairs/s", "cores": threads, "kind": "oracle",
+            "sample": "one 1024x1024 pair of the workload, the whole path, all cores",
+            "single_thread": {"value": round(1.0 / t_one, 5), "unit": "pairs/s", "cores": 1,
+                              "sample": f"full predictor + validation + vorticity; correction on {strip_rows + 1} "
+                                        "of 128 window rows, scaled"},
+            "nproc": nproc, "cpu_model": _cpu_model(),
+            "vectors_per_s": round(128 * 128 / t_all, 1)}
+    return base, ref
+
+
+def _render(job):
+    """One rendered input (runs in a worker process before the GPU is
+    touched): ("cfg2", seed) | ("cfg3", k) | ("cfg5", stream, k) | ("cfg1", seed)
+    | ("cfg4", k) | ("wake", seed, ppp)."""
+    from paper_2504_17987_amd import synth
+    kind = job[0]
+    if kind == "cfg2":
+        A, B, _ = synth.cfg2_pair(job[1])
+        return A, B
+    if kind == "cfg3":
+        A, B, _ = synth.cfg3_pair(job[1])
+        return A, B
+    if kind == "cfg5":
+        A, B, _ = synth.cfg5_pair(job[1], job[2])
+        return A, B
+    if kind == "cfg1":
+        A, B, _ = synth.cfg1_pair(job[1])
+        return A, B
+    if kind == "cfg4":
+        A, B, _ = synth.cfg4_pair(job[1])
+        return A, B
+    if kind == "wake":
+        flow = synth.cylinder_wake(1024, 512)
+        A, B = synth.make_pair(1024, 512, flow, job[2], noise=2.0, seed=job[1])
+        return A, B
+    raise KeyError(kind)
+
+
+def render_all(jobs, log_fn):
+    """Render every input in a pool of worker processes (forked before the
+    GPU is initialised; the workers only run numpy)."""
+    import multiprocessing as mp
     t0 = time.perf_counter()
-    oracle.correct(As, Bs, 16, 8, 4, ps)
-    t_corr = (time.perf_counter() - t0) * (A.shape[0] // 8) / rows
-    t0 = time.perf_counter()
-    full = np.zeros((2, A.shape[0] // 8, W // 8))
-    fl = np.zeros(full.shape[1:], np.uint8)
-    oracle.validate(full, fl)
-    oracle.vorticity(full, 8)
-    t_post = time.perf_counter() - t0
-    sec = t_pred + t_corr + t_post
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    log_fn(f"cpu oracle: predict {t_pred:.2f}s, correct (scaled) {t_corr:.2f}s, post {t_post:.3f}s")
-    return {"value": round(1.0 / sec, 5), "unit": "pairs/s", "cores": cores, "kind": "oracle",
-            "sample": "one 1024x1024 pair: full predictor + validation + vorticity; correction on a "
-                      "512-row strip (8192 of 16384 windows) scaled x2"}
+    n = min(16, os.cpu_count() or 1, len(jobs))
+    if n <= 1:
+        out = [_render(j) for j in jobs]
+    else:
+        with mp.get_context("fork").Pool(n) as pool:
+            out = pool.map(_render, jobs, chunksize=1)
+    log_fn(f"rendered {len(jobs)} inputs in {time.perf_counter() - t0:.1f} s")
+    return dict(zip(jobs, out))
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_correct_bands_cfg2_b64_traffic.txt")
@@ -189,103 +270,174 @@ def graph_batched(torch, api, A, B, kw, args):
             "includes": "device-to-device copy of the 8 input pairs into the graph's slots"}
 
 
-def served(torch, api, synth, kw, args, log_fn):
+def _fifo_outputs(torch, p):
+    return dict(pred=torch.empty((1, 2, p.ny, p.nx), device="cuda"),
+                disp=torch.empty((1, 2, p.ny, p.nx), device="cuda"),
+                peak=torch.empty((1, p.ny, p.nx), device="cuda"),
+                flags=torch.empty((1, p.ny, p.nx), dtype=torch.uint8, device="cuda"),
+                omega=torch.empty((1, p.ny, p.nx), device="cuda"))
+
+
+SERVE_SIZES = {"s": (512, 512, 16), "m": (1024, 1024, 8), "l": (2048, 2048, 4)}
+SERVE_PER_STREAM = 16
+
+
+def served(torch, api, synth, kw, args, log_fn, inputs):
     """The serving mix: 12 streams (4 x 512^2, 4 x 1024^2, 4 x 2048^2 u8;
-    solid-body or shear flows, 0.03 ppp), Poisson arrivals at 250/s each
-    (3,000 pairs/s offered), device-resident pairs; continuous batching with
-    per-class graphs on their own streams, against the plain per-pair form
-    (one eager run at a time in arrival order) on the same trace."""
+    solid-body or shear flows, 0.03 ppp), each with 16 device-resident
+    pairs, Poisson arrivals.  Continuous batching (per-class graphs on their
+    own streams, HBM-budget admission) against the plain per-pair form (one
+    eager run at a time in arrival order) on the same traces, over a sweep
+    of the offered load from 3,000 pairs/s past the plain form's
+    saturation; at each point p50/p99 latency, completed pairs/s and the
+    batch sizes the server launched.  Then one run with a budget too small
+    for every class (admission refuses the 2048^2 streams)."""
     from paper_2504_17987_amd.serve import latency_stats, make_gpu_server, poisson_trace, run_fifo, serve_trace
-    per = 2
-    sizes = {"s": (512, 512, 16), "m": (1024, 1024, 8), "l": (2048, 2048, 4)}
+    per = SERVE_PER_STREAM
     cls_of = {512: "s", 1024: "m", 2048: "l"}
     stream_class, pairs = {}, {}
     for s in range(12):
         W = synth.CFG5_SIZES[s]
         stream_class[s] = cls_of[W]
-        a, b = zip(*[synth.cfg5_pair(s, k)[:2] for k in range(per)])
+        a, b = zip(*[inputs[("cfg5", s, k)] for k in range(per)])
         pairs[s] = (torch.from_numpy(np.stack(a)).cuda(), torch.from_numpy(np.stack(b)).cuda())
     free, _ = torch.cuda.mem_get_info()
-    sched, ex = make_gpu_server(sizes, pairs, stream_class, budget=int(0.5 * free), plan_kw=kw)
-    trace = poisson_trace(list(stream_class.items()), 250.0, args.serve_seconds, per, seed=5)
-    warm = poisson_trace(list(stream_class.items()), 250.0, 0.3, per, seed=6)
-    serve_trace(sched, warm, time.perf_counter, poll=0)
-    sched.finished.clear()
-    t0 = time.perf_counter()
-    serve_trace(sched, trace, time.perf_counter, poll=0, deadline=60.0 + 4 * args.serve_seconds)
-    torch.cuda.synchronize()
-    st = latency_stats(trace)
-    log_fn(f"served: {st['n']} pairs, p50 {st['p50_ms']:.3f} ms, p99 {st['p99_ms']:.3f} ms, "
-           f"{sched.batches} batches in {time.perf_counter() - t0:.2f} s")
-    # plain per-pair form on the same trace
-    plans = {c: api.Plan(W, H, max_batch=1, **kw) for c, (W, H, _) in sizes.items()}
-    for c, p in plans.items():
-        W, H, _ = sizes[c]
-        p._fifo_out = dict(pred=torch.empty((1, 2, p.ny, p.nx), device="cuda"),
-                           disp=torch.empty((1, 2, p.ny, p.nx), device="cuda"),
-                           peak=torch.empty((1, p.ny, p.nx), device="cuda"),
-                           flags=torch.empty((1, p.ny, p.nx), dtype=torch.uint8, device="cuda"),
-                           omega=torch.empty((1, p.ny, p.nx), device="cuda"))
-    fifo = [type(r)(r.rid, r.stream, r.cls, r.item, r.arrival) for r in trace]
-    run_fifo(lambda c: plans[c], pairs, fifo[: min(len(fifo), 50)], time.perf_counter)   # warm-up
-    fifo = [type(r)(r.rid, r.stream, r.cls, r.item, r.arrival) for r in trace]
-    run_fifo(lambda c: plans[c], pairs, fifo, time.perf_counter, deadline=120.0 + 10 * args.serve_seconds)
-    sf = latency_stats(fifo)
-    log_fn(f"plain FIFO: p50 {sf['p50_ms']:.3f} ms, p99 {sf['p99_ms']:.3f} ms")
+    sched, ex = make_gpu_server(SERVE_SIZES, pairs, stream_class, budget=int(0.5 * free), plan_kw=kw)
+    plans = {c: api.Plan(W, H, max_batch=1, **kw) for c, (W, H, _) in SERVE_SIZES.items()}
+    for p in plans.values():
+        p._fifo_out = _fifo_outputs(torch, p)
+    streams = list(stream_class.items())
+    serve_trace(sched, poisson_trace(streams, 250.0, 0.3, per, seed=6), time.perf_counter, poll=0)   # warm-up
+    run_fifo(lambda c: plans[c], pairs, poisson_trace(streams, 250.0, 0.1, per, seed=7), time.perf_counter)
     r4 = lambda d: {k: (round(v, 4) if isinstance(v, float) else v) for k, v in d.items()}
-    return {"offered_pairs_per_s": 3000, "seconds": args.serve_seconds, "mix": "4x512^2, 4x1024^2, 4x2048^2 u8",
-            "continuous_batching": r4(st), "plain_per_pair_fifo": r4(sf), "batches": sched.batches}
+    sweep = []
+    for rate_total in args.serve_rates:
+        secs = args.serve_seconds * (args.serve_first_scale if rate_total == args.serve_rates[0] else 1.0)
+        trace = poisson_trace(streams, rate_total / 12.0, secs, per, seed=int(rate_total))
+        sched.finished.clear()
+        b0 = len(ex.batch_sizes)
+        serve_trace(sched, trace, time.perf_counter, poll=0, deadline=60.0 + 20 * secs)
+        torch.cuda.synchronize()
+        st = latency_stats(trace)
+        hist = np.bincount(np.array(ex.batch_sizes[b0:], dtype=np.int64), minlength=17)
+        fifo = [type(r)(r.rid, r.stream, r.cls, r.item, r.arrival) for r in trace]
+        run_fifo(lambda c: plans[c], pairs, fifo, time.perf_counter, deadline=120.0 + 40 * secs)
+        sf = latency_stats(fifo)
+        log_fn(f"served at {rate_total:.0f}/s offered ({secs:.0f} s): {st['pairs_per_s']:.0f} pairs/s, p50 "
+               f"{st['p50_ms']:.3f} / p99 {st['p99_ms']:.3f} ms, {len(ex.batch_sizes) - b0} batches; plain FIFO "
+               f"{sf['pairs_per_s']:.0f} pairs/s, p50 {sf['p50_ms']:.3f} / p99 {sf['p99_ms']:.3f} ms")
+        sweep.append({"offered_pairs_per_s": rate_total, "seconds": secs,
+                      "continuous_batching": r4(st), "plain_per_pair_fifo": r4(sf),
+                      "batch_size_histogram": {str(k): int(v) for k, v in enumerate(hist) if v}})
+    # admission under a budget that holds classes s and m but not l
+    c = sched.classes
+    budget = sum(2 * c[k].slot_bytes + 4 * c[k].stream_bytes for k in ("s", "m"))
+    del sched, ex
+    torch.cuda.synchronize()
+    sched2, ex2 = make_gpu_server(SERVE_SIZES, pairs, stream_class, budget=budget, plan_kw=kw)
+    trace = poisson_trace(streams, 250.0, min(args.serve_seconds, 3.0), per, seed=99)
+    refused = serve_trace(sched2, trace, time.perf_counter, poll=0, deadline=120.0)
+    torch.cuda.synchronize()
+    sa = latency_stats(trace)
+    admission = {"budget_bytes": budget, "admitted_streams": len(sched2.admitted),
+                 "waiting_streams": len(sched2.waiting), "refused_requests": len(refused),
+                 "classes_built": sorted(ex2.runners), **r4(sa)}
+    log_fn(f"admission under {budget / 2**20:.0f} MiB: {len(sched2.admitted)} streams admitted, "
+           f"{len(refused)} requests refused, p99 {sa['p99_ms']:.3f} ms")
+    del sched2, ex2
+    return {"mix": "4x512^2, 4x1024^2, 4x2048^2 u8, 16 resident pairs per stream", "sweep": sweep,
+            "admission_budget": admission}
 
 
-def stream_cfg3(torch, api, synth, log_fn, npairs=128, distinct=4):
-    """3840x2160 u16 (12-bit) pairs, 24/12 windows, graph batches of 8; two
-    captured graphs (own plans and slots) replay alternately on their own
-    streams, so two batches are in flight.  The one-graph rate is reported
-    beside it."""
+def stream_cfg3(torch, api, synth, log_fn, inputs, npairs=500, distinct=16):
+    """The 3840x2160 u16 (12-bit) stream, 24/12 windows: 500 pairs in graph
+    replays of 8 (62 full and one of 4), each replay preceded by the copy of
+    its pairs into the graph's slots (device to device, on the graph's
+    stream).  The stream cycles `distinct` rendered pairs of the advected
+    flow (pair k at advection 0.5 k px), resident in HBM.  Two captured
+    graphs (own plans and slots) alternate on their own streams, so two
+    batches are in flight; the one-graph rate is reported beside it."""
     from paper_2504_17987_amd.serve import GraphRunner
     kw = dict(dtype="u16", win=24, step=12, radius=4, levels=3, radius_coarse=6, radius_fine=2)
-    prs = [synth.cfg3_pair(k) for k in range(distinct)]
+    prs = [inputs[("cfg3", k)] for k in range(distinct)]
     A = torch.stack([torch.from_numpy(p[0].view(np.int16)) for p in prs]).cuda().view(torch.uint16)
     B = torch.stack([torch.from_numpy(p[1].view(np.int16)) for p in prs]).cuda().view(torch.uint16)
     runs = []
     for _ in range(2):
         run = GraphRunner(api.Plan(3840, 2160, max_batch=8, **kw), 8)
         run.capture()
-        for i in range(8):
-            run.A[i].copy_(A[i % distinct])
-            run.B[i].copy_(B[i % distinct])
         run.replay(8)
         runs.append(run)
     torch.cuda.synchronize()
     main = torch.cuda.current_stream()
-    reps = npairs // 8
+    batches = [(lo, min(8, npairs - lo)) for lo in range(0, npairs, 8)]
 
     def timed(rs):
         e0, e1 = events(torch, 2)
-        beg, end = events(torch, reps), events(torch, reps)
+        beg, end = events(torch, len(batches)), events(torch, len(batches))
         e0.record(main)
         for r in rs:
             r.stream.wait_stream(main)
-        for k in range(reps):
+        for k, (lo, n) in enumerate(batches):
             r = rs[k % len(rs)]
             beg[k].record(r.stream)
-            r.replay(8)
+            with torch.cuda.stream(r.stream):
+                for i in range(n):
+                    r.A[i].copy_(A[(lo + i) % distinct], non_blocking=True)
+                    r.B[i].copy_(B[(lo + i) % distinct], non_blocking=True)
+            r.replay(n)
             end[k].record(r.stream)
         for r in rs:
             main.wait_stream(r.stream)
         e1.record(main)
         torch.cuda.synchronize()
-        return 8 * reps / (e0.elapsed_time(e1) / 1e3), np.array([beg[k].elapsed_time(end[k]) for k in range(reps)])
+        ms = np.array([beg[k].elapsed_time(end[k]) for k in range(len(batches))])
+        return npairs / (e0.elapsed_time(e1) / 1e3), ms
 
+    timed(runs)   # warm-up
     one, ms1 = timed(runs[:1])
     pps, ms = timed(runs)
-    log_fn(f"cfg3 stream: {pps:.0f} pairs/s with two graphs in flight (one graph {one:.0f} pairs/s, "
-           f"replay p50 {np.percentile(ms1, 50):.3f} ms)")
-    return {"pairs_per_s": round(pps, 1), "one_graph_pairs_per_s": round(one, 1),
+    log_fn(f"cfg3 stream: {npairs} pairs in {len(batches)} replays, {pps:.0f} pairs/s with two graphs in flight "
+           f"(one graph {one:.0f} pairs/s, replay p50 {np.percentile(ms1, 50):.3f} ms, with the slot copies)")
+    return {"pairs": npairs, "replays": len(batches), "distinct_rendered_pairs": distinct,
+            "pairs_per_s": round(pps, 1), "one_graph_pairs_per_s": round(one, 1),
             "replay_p50_ms": round(float(np.percentile(ms1, 50)), 4),
             "replay_p99_ms": round(float(np.percentile(ms1, 99)), 4),
             "replay_p50_ms_two_in_flight": round(float(np.percentile(ms, 50)), 4), "slots": 8,
-            "mvec_per_s": round(pps * 320 * 180 / 1e6, 2)}
+            "mvec_per_s": round(pps * 320 * 180 / 1e6, 2),
+            "includes": "device-to-device copy of each replay's pairs into the graph's slots"}
+
+
+def cfg1_forms(torch, api, log_fn, inputs, reps=1000):
+    """Config 1: one 256x256 u8 pair, 32x32 windows at step 16 (16x16
+    vectors), +-8 search.  The plain correction with no predictor
+    (piv_correct, pred = NULL) and the whole path with a one-level predictor
+    (radius 8), each timed with HIP events around every one of `reps`
+    calls."""
+    A, B = inputs[("cfg1", 1000)]
+    Ad, Bd = torch.from_numpy(A[None]).cuda(), torch.from_numpy(B[None]).cuda()
+    P = api.Plan(256, 256, max_batch=1, win=32, step=16, radius=8, levels=1, radius_coarse=8)
+    disp, peak, flags = P.correct(Ad, Bd, None)
+    out = P.run(Ad, Bd)
+    stream = torch.cuda.current_stream()
+    res = {}
+    for name, call in (("plain_correct", lambda: P.correct(Ad, Bd, None, disp, peak, flags)),
+                       ("path_L1", lambda: P.run(Ad, Bd, out))):
+        for _ in range(20):
+            call()
+        torch.cuda.synchronize()
+        beg, end = events(torch, reps), events(torch, reps)
+        for k in range(reps):
+            beg[k].record(stream)
+            call()
+            end[k].record(stream)
+        torch.cuda.synchronize()
+        ms = np.array([beg[k].elapsed_time(end[k]) for k in range(reps)])
+        res[name] = {"p50_ms": round(float(np.percentile(ms, 50)), 4), "p99_ms": round(float(np.percentile(ms, 99)), 4),
+                     "reps": reps}
+    log_fn(f"cfg1 256^2: plain correction p50 {res['plain_correct']['p50_ms']:.4f} ms, whole path (L=1) p50 "
+           f"{res['path_L1']['p50_ms']:.4f} ms")
+    return res
 
 
 def largest(torch, api, synth, kw, log_fn, n=4, reps=10):
@@ -328,19 +480,26 @@ def largest(torch, api, synth, kw, log_fn, n=4, reps=10):
             "pairs_per_s_two_in_flight": round(pps2, 1), "mvec_per_s": round(pps * 1024 * 512 / 1e6, 1)}
 
 
-def ssd_cfg4(torch, api, synth, log_fn, n=64, distinct=8):
-    """64 pairs of 512x512 f32, forward + backward of the windowed SSD."""
-    prs = [synth.cfg4_pair(k) for k in range(distinct)]
+def ssd_cfg4(torch, api, log_fn, inputs, n=64, distinct=8):
+    """64 pairs of 512x512 f32: forward and backward of the windowed SSD,
+    and 10 steps of the on-device refinement (piv_ssd_refine) with its
+    loss history."""
+    from paper_2504_17987_amd import synth
+    prs = [inputs[("cfg4", k)] for k in range(distinct)]
     A = torch.stack([torch.from_numpy(prs[i % distinct][0]) for i in range(n)]).cuda()
     B = torch.stack([torch.from_numpy(prs[i % distinct][1]) for i in range(n)]).cuda()
-    U = torch.stack([torch.from_numpy(synth.truth(prs[i % distinct][2], 512, 512, 8).astype(np.float32))
+    flows = [synth.smooth_random_flow(512, 512, 16.0, 6.0, seed=4000 + 10000 + k) for k in range(distinct)]
+    U = torch.stack([torch.from_numpy(synth.truth(flows[i % distinct], 512, 512, 8).astype(np.float32))
                      for i in range(n)]).cuda()
     P = api.Plan(512, 512, max_batch=n, dtype="f32", levels=1)
     g = torch.ones((n, 64, 64), device="cuda")
     loss = P.ssd_forward(A, B, U)
     gU, D = P.ssd_backward(A, B, U, g)
+    Ur = U.clone()
+    hist = torch.empty((n, 11), device="cuda")
+    P.ssd_refine(A, B, Ur, steps=10, hist=hist)
     torch.cuda.synchronize()
-    e = events(torch, 3)
+    e = events(torch, 4)
     reps = 20
     e[0].record()
     for _ in range(reps):
@@ -349,15 +508,98 @@ def ssd_cfg4(torch, api, synth, log_fn, n=64, distinct=8):
     for _ in range(reps):
         P.ssd_backward(A, B, U, g, gU, D)
     e[2].record()
+    for _ in range(3):
+        Ur.copy_(U)
+        P.ssd_refine(A, B, Ur, steps=10, hist=hist)
+    e[3].record()
     torch.cuda.synchronize()
     f_ms, b_ms = e[0].elapsed_time(e[1]) / reps, e[1].elapsed_time(e[2]) / reps
+    r_ms = e[2].elapsed_time(e[3]) / 3
     img = 512 * 512 * 4
     fwd_bytes = n * (2 * img + 2 * 64 * 64 * 4 + 64 * 64 * 4)
     bwd_bytes = n * (2 * img + 2 * 64 * 64 * 4 + 64 * 64 * 4 + 4 * 64 * 64 * 4)
     gbs = (fwd_bytes + bwd_bytes) / ((f_ms + b_ms) / 1e3) / 1e9
-    log_fn(f"ssd: forward {f_ms:.3f} ms, backward {b_ms:.3f} ms, {gbs:.0f} GB/s algorithmic")
+    log_fn(f"ssd: forward {f_ms:.3f} ms, backward {b_ms:.3f} ms, {gbs:.0f} GB/s algorithmic; "
+           f"10 refinement steps {r_ms:.3f} ms")
     return {"batch": n, "forward_ms": round(f_ms, 4), "backward_ms": round(b_ms, 4),
-            "achieved_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+            "forward_gbs": round(fwd_bytes / (f_ms / 1e3) / 1e9, 1),
+            "backward_gbs": round(bwd_bytes / (b_ms / 1e3) / 1e9, 1),
+            "achieved_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+            "refine_10_steps_ms": round(r_ms, 4),
+            "refine_loss_first_last": [round(float(hist[:, 0].sum()), 2), round(float(hist[:, -1].sum()), 2)]}
+
+
+def preprocess_cfg2(torch, api, A, log_fn, reps=20):
+    """Pre-processing of 64 frames of the headline workload (1024^2 u8):
+    high-pass background removal (radius 7) and CLAHE (8 x 8 tiles, clip 2),
+    each timed with HIP events; HBM roofline by algorithmic bytes (high-pass
+    reads and writes each frame once; CLAHE reads it twice and writes it
+    once)."""
+    n = A.shape[0]
+    P = api.Plan(1024, 1024, max_batch=n, workspace=False)
+    hp = torch.empty_like(A)
+    cl = torch.empty_like(A)
+    lut = torch.empty(P.clahe_lut_bytes(n, 8, 8), dtype=torch.uint8, device="cuda")
+    P.highpass(A, hp, radius=7)
+    P.clahe(hp, cl, tiles=(8, 8), clip_factor=2.0, lut=lut)
+    torch.cuda.synchronize()
+    e = events(torch, 3)
+    e[0].record()
+    for _ in range(reps):
+        P.highpass(A, hp, radius=7)
+    e[1].record()
+    for _ in range(reps):
+        P.clahe(hp, cl, tiles=(8, 8), clip_factor=2.0, lut=lut)
+    e[2].record()
+    torch.cuda.synchronize()
+    h_ms, c_ms = e[0].elapsed_time(e[1]) / reps, e[1].elapsed_time(e[2]) / reps
+    frame = 1024 * 1024
+    h_gbs = n * 2 * frame / (h_ms / 1e3) / 1e9
+    c_gbs = n * 3 * frame / (c_ms / 1e3) / 1e9
+    log_fn(f"pre-processing 64 x 1 MP: high-pass {h_ms:.3f} ms ({h_gbs:.0f} GB/s), CLAHE {c_ms:.3f} ms "
+           f"({c_gbs:.0f} GB/s)")
+    return {"frames": n, "highpass_ms": round(h_ms, 4), "highpass_gbs": round(h_gbs, 1),
+            "highpass_hbm_frac": round(h_gbs / HBM_PEAK_GBS, 4), "clahe_ms": round(c_ms, 4),
+            "clahe_gbs": round(c_gbs, 1), "clahe_hbm_frac": round(c_gbs / HBM_PEAK_GBS, 4),
+            "frames_per_s_both": round(n / ((h_ms + c_ms) / 1e3), 1)}
+
+
+def low_seeding_study(torch, api, log_fn, inputs, seeds):
+    """The paper's low-seeding case (Sec. 3.2, Sec. 4.3: a cylinder wake at
+    low particle concentration, 32 x 32 windows at 50% step-over), on a
+    synthetic cylinder-like wake at 0.002 ppp: the a-priori 5-point stencil
+    centred at zero shift against the +-4 argmax search, both after the
+    same predictor and validation.  Reports, over interior nodes, the RMS
+    error against the analytic truth and the share of vectors off by more
+    than 1 px, before validation (raw correction) and after it."""
+    from paper_2504_17987_amd import synth
+    flow = synth.cylinder_wake(1024, 512)
+    T = synth.truth(flow, 1024, 512, 16)
+    A = torch.from_numpy(np.stack([inputs[("wake", s, 0.002)][0] for s in seeds])).cuda()
+    B = torch.from_numpy(np.stack([inputs[("wake", s, 0.002)][1] for s in seeds])).cuda()
+    n = len(seeds)
+    res = {}
+    inner = (slice(None), slice(None), slice(2, -2), slice(2, -2))
+    for mode in ("fixed", "argmax"):
+        P = api.Plan(1024, 512, max_batch=n, win=32, step=16, radius=4, levels=2, radius_coarse=6,
+                     radius_fine=2, peak=mode)
+        out = P.run(A, B)
+        raw, _, _ = P.correct(A, B, out["pred"])
+        torch.cuda.synchronize()
+        r = {}
+        for name, f in (("raw", raw), ("validated", out["disp"])):
+            err = (f.cpu().numpy() - T[None])[inner]
+            mag = np.sqrt((err ** 2).sum(axis=1))
+            r[name] = {"rms_px": round(float(np.sqrt((err ** 2).mean())), 4),
+                       "beyond_1px": round(float((mag > 1.0).mean()), 4)}
+        r["outlier_share"] = round(float(((out["flags"].cpu().numpy() & 8) != 0).mean()), 4)
+        res[mode] = r
+    log_fn(f"low seeding (0.002 ppp, 32/16): fixed centre rms {res['fixed']['validated']['rms_px']:.3f} px, "
+           f"{res['fixed']['raw']['beyond_1px']:.1%} raw beyond 1 px; argmax rms "
+           f"{res['argmax']['validated']['rms_px']:.3f} px, {res['argmax']['raw']['beyond_1px']:.1%} raw beyond 1 px")
+    return {"ppp": 0.002, "image": "1024x512 u8", "windows": "32x32 step 16, +-4 (argmax)", "pairs": n,
+            "flow": "cylinder-like wake: 6 px free stream, 3 px deficit, alternating vortices of 2.5 px",
+            **res}
 
 
 def main():
@@ -367,16 +609,28 @@ def main():
               "pairs are independent, so N GPUs would each run this benchmark on their own stream of pairs.",
               file=sys.stderr)
         sys.exit(2)
+    lg = lambda *a: log(args, *a)
+    W = H = 1024
+    kw = dict(win=16, step=8, radius=4, levels=3, radius_coarse=6, radius_fine=2)
+    nb, nd = args.batch, min(args.distinct, args.batch)
+    # every input is rendered, and the CPU oracle timed, before the GPU is
+    # touched (the renderers run in forked worker processes)
+    jobs = [("cfg2", 2000 + i) for i in range(nd)]
+    if not args.no_extras:
+        jobs += [("cfg1", 1000)] + [("cfg3", k) for k in range(16)] + [("cfg4", k) for k in range(8)]
+        jobs += [("cfg5", s, k) for s in range(12) for k in range(SERVE_PER_STREAM)]
+        jobs += [("wake", 7000 + k, 0.002) for k in range(4)]
+    inputs = render_all(jobs, lg)
+    pairs = [inputs[("cfg2", 2000 + i)] for i in range(nd)]
+    cpu = ref0 = None
+    if not args.no_cpu_baseline:
+        cpu, ref0 = cpu_baseline(pairs[0][0], pairs[0][1], lg)
+
     import torch
     from paper_2504_17987_amd import api, synth
 
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
     dev = torch.device("cuda:0")
-    W = H = 1024
-    kw = dict(win=16, step=8, radius=4, levels=3, radius_coarse=6, radius_fine=2)
-    nb, nd = args.batch, min(args.distinct, args.batch)
-    log(args, f"rendering {nd} distinct 1 MP pairs ...")
-    pairs = [synth.cfg2_pair(2000 + i) for i in range(nd)]
     A = torch.empty((nb, H, W), dtype=torch.uint8, device=dev)
     B = torch.empty((nb, H, W), dtype=torch.uint8, device=dev)
     for i in range(nb):
@@ -400,6 +654,7 @@ def main():
     for _ in range(1, S):
         jobs.append((api.Plan(W, H, max_batch=nb, **kw), A.clone(), B.clone(), outputs(),
                      torch.cuda.Stream(dev)))
+    torch.cuda.synchronize()
     if args.copy_probe > 0:
         src = torch.zeros(args.copy_probe << 20, dtype=torch.uint8, device=dev)
         dst = torch.empty_like(src)
@@ -439,12 +694,33 @@ def main():
         one_ms, _, _ = timed(jobs[:1])
         single = {"pairs_per_s": round(nb * args.steps / (one_ms / 1e3), 1),
                   "ms_per_step": round(one_ms / args.steps, 4)}
-        log(args, f"one stream: step {one_ms / args.steps:.3f} ms, {single['pairs_per_s']:.0f} pairs/s")
+        lg(f"one stream: step {one_ms / args.steps:.3f} ms, {single['pairs_per_s']:.0f} pairs/s")
     total_ms, step_ms, wall = timed(jobs)
     ms_per_step = total_ms / args.steps
     pairs_s = nb * args.steps / (total_ms / 1e3)
-    log(args, f"{S} streams: step {ms_per_step:.3f} ms ({wall / args.steps * 1e3:.3f} ms wall), "
-              f"{pairs_s:.0f} pairs/s")
+    lg(f"{S} streams: step {ms_per_step:.3f} ms ({wall / args.steps * 1e3:.3f} ms wall), {pairs_s:.0f} pairs/s")
+
+    # accuracy of the step's field against the analytic truth (interior
+    # nodes of the distinct pairs) and, on the oracle's sample pair, its
+    # agreement with the FP64 oracle
+    T = synth.truth(synth.cfg2_flow(), W, H, 8)
+    got = out["disp"][:nd].cpu().numpy()
+    err = (got - T[None])[:, :, 2:-2, 2:-2]
+    accuracy = {"rms_px": round(float(np.sqrt((err ** 2).mean())), 4),
+                "p99_abs_px": round(float(np.percentile(np.abs(err), 99)), 4),
+                "nodes": int(err[:, 0].size), "pairs": nd,
+                "truth": "Lamb-Oseen displacement at the node centres, interior nodes (2 from each edge)"}
+    lg(f"accuracy vs truth: rms {accuracy['rms_px']:.3f} px")
+    if ref0 is not None:
+        g0 = {k: v[0].cpu().numpy() for k, v in out.items()}
+        d = np.abs(g0["disp"] - ref0["disp"]).max(axis=0)
+        cpu["parity_on_sample"] = {
+            "predictor_bit_exact": bool(np.array_equal(g0["pred"], ref0["pred"].astype(np.float32))),
+            "max_abs_disp_px": float(d.max()), "vectors_beyond_0.01px": int((d > 0.01).sum()),
+            "flags_equal": int((g0["flags"] == ref0["flags"]).sum()), "vectors": int(d.size),
+            "omega_max_rel": float(np.abs(g0["omega"] - ref0["omega"]).max() / np.abs(ref0["omega"]).max())}
+        lg(f"parity on the oracle's sample pair: max |d disp| {d.max():.2e} px, "
+           f"{int((d > 0.01).sum())} vectors beyond 0.01 px")
 
     # dominant kernel: the correlation stage, timed alone with events on its stream
     pred = out["pred"].clone()
@@ -461,7 +737,7 @@ def main():
     corr_ms = e0.elapsed_time(e1) / args.steps
     alg = algorithmic(W, H, nx, ny, kw["radius"])
     corr_tflops = alg["corr_flop"] * nb / (corr_ms / 1e3) / 1e12
-    log(args, f"correct kernel {corr_ms:.3f} ms/launch, {corr_tflops:.2f} TFLOP/s algorithmic")
+    lg(f"correct kernel {corr_ms:.3f} ms/launch, {corr_tflops:.2f} TFLOP/s algorithmic")
 
     lat = {}
     if not args.no_latency:
@@ -488,18 +764,16 @@ def main():
 
     forms = {}
     if not args.no_extras:
-        lg = lambda *a: log(args, *a)
+        forms["cfg1_256"] = cfg1_forms(torch, api, lg, inputs)
         forms["graph_batched_cfg2"] = graph_batched(torch, api, A, B, kw, args)
         lg(f"graph batches of 8: {forms['graph_batched_cfg2']['pairs_per_s']:.0f} pairs/s "
            f"(two graphs in flight {forms['graph_batched_cfg2']['pairs_per_s_two_in_flight']:.0f})")
-        forms["served_cfg5"] = served(torch, api, synth, kw, args, lg)
-        forms["stream_cfg3"] = stream_cfg3(torch, api, synth, lg)
-        forms["ssd_cfg4"] = ssd_cfg4(torch, api, synth, lg)
+        forms["preprocess_cfg2"] = preprocess_cfg2(torch, api, A, lg)
+        forms["stream_cfg3"] = stream_cfg3(torch, api, synth, lg, inputs)
+        forms["ssd_cfg4"] = ssd_cfg4(torch, api, lg, inputs)
         forms["largest_8192x4096"] = largest(torch, api, synth, kw, lg)
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        cpu = cpu_baseline(pairs[0][0], pairs[0][1], lambda *a: log(args, *a))
+        forms["low_seeding_wake"] = low_seeding_study(torch, api, lg, inputs, [7000 + k for k in range(4)])
+        forms["served_cfg5"] = served(torch, api, synth, kw, args, lg, inputs)
 
     path_gbs = alg["path_bytes"] * nb / (ms_per_step / 1e3) / 1e9
     line = {
@@ -526,6 +800,7 @@ def main():
         "single_stream": single,
         "mvec_per_s": round(pairs_s * nx * ny / 1e6, 2),
         "latency": lat,
+        "accuracy_vs_truth": accuracy,
         "hbm_roofline": {"achieved_gbs": round(path_gbs, 1), "peak_gbs": HBM_PEAK_GBS,
                          "frac": round(path_gbs / HBM_PEAK_GBS, 5),
                          "bytes_per_pair": alg["path_bytes"]},

@@ -448,6 +448,7 @@ class GpuExecutor(Executor):
         self.started: set = set()
         self.states: Dict[str, Dict[str, object]] = {}
         self.last_event: Dict[str, object] = {}
+        self.batch_sizes: List[int] = []   # size of every launched batch, in launch order
 
     def runner_bytes(self, cls: str) -> int:
         from .api import Plan
@@ -512,6 +513,7 @@ class GpuExecutor(Executor):
     def launch(self, cls, reqs, now):
         torch = self.torch
         run = self.free[cls].pop()
+        self.batch_sizes.append(len(reqs))
         if self.temporal is not None:
             run.set_slots(self._slot_values(reqs))
             prev = self.last_event.get(cls)

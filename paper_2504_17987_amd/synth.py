@@ -266,6 +266,42 @@ def cfg4_pair(k: int = 0, seed: int = 4000, W: int = 512, H: int = 512):
     return (A.astype(np.float32) / 255.0), (B.astype(np.float32) / 255.0), flow
 
 
+@dataclass
+class Deficit:
+    """Wake deficit behind a body: u = -D exp(-((y - yc)/w)^2) for x > x0
+    (growing in over `ramp` px), v = 0."""
+    D: float
+    x0: float
+    yc: float
+    w: float
+    ramp: float
+
+    def __call__(self, x, y):
+        x = np.asarray(x, dtype=np.float64)
+        y = np.asarray(y, dtype=np.float64)
+        on = 0.5 * (1.0 + np.tanh((x - self.x0) / self.ramp))
+        return -self.D * on * np.exp(-((y - self.yc) / self.w) ** 2), np.zeros_like(y)
+
+
+def cylinder_wake(W: int = 1024, H: int = 512, U: float = 6.0, D: float = 3.0, peak: float = 2.5):
+    """A cylinder-like wake (a stand-in for the paper's low-seeding cylinder
+    experiment, Sec. 3.2): free stream U px/frame in x, a velocity deficit
+    of D px behind a body of diameter H/8 at (W/6, H/2), and a staggered
+    street of alternating Lamb-Oseen vortices (peak `peak` px, core H/16)
+    shed downstream at a spacing of H/4."""
+    d = H / 8.0
+    xb, yc = W / 6.0, H / 2.0
+    parts: List[Callable] = [Uniform(U, 0.0), Deficit(D, xb, yc, 0.7 * d, d)]
+    k = 0
+    x = xb + 1.5 * d
+    while x < W + H / 4:
+        side = 1.0 if k % 2 == 0 else -1.0
+        parts.append(LambOseen.with_peak(x, yc + side * 0.6 * d, H / 16.0, peak, sign=-side))
+        x += H / 4.0
+        k += 1
+    return Sum(parts)
+
+
 def cfg5_flow(stream: int, W: int, H: int):
     """Even streams: solid-body rotation with |u| = 8 px at the corners;
     odd streams: shear 8 tanh((y - H/2)/(H/16))."""
