@@ -271,7 +271,8 @@ size_t piv_clahe_lut_bytes(piv_plan_t plan, int32_t n, int32_t tiles_x, int32_t 
  * surround it (bilinear weights in doubled coordinates, clamped at the
  * outer centres, rounded half up in integers).  lut: caller-owned device
  * scratch of at least piv_clahe_lut_bytes (4-byte aligned), left holding
- * the mappings.  out may equal in.  tiles in [1, min(64, size)]. */
+ * the mappings.  out may equal in.  tiles in [1, min(64, size)]; frames
+ * up to 32767 x 32767 (PIV_EUNSUPPORTED beyond). */
 piv_status piv_clahe(piv_plan_t plan, const void* in, void* out, int64_t pitch_bytes, int32_t n,
                      int32_t tiles_x, int32_t tiles_y, double clip_factor, void* lut, size_t lut_bytes,
                      hipStream_t stream);

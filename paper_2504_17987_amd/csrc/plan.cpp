@@ -416,8 +416,8 @@ piv_status piv_clahe(piv_plan_t plan, const void* in, void* out, int64_t pitch, 
   if ((uintptr_t)lut & 3) return fail(PIV_EINVAL, "lut must be 4-byte aligned");
   if (lut_bytes < piv_clahe_lut_bytes(plan, n, tiles_x, tiles_y))
     return fail(PIV_EINVAL, "lut holds %zu bytes, needs %zu", lut_bytes, piv_clahe_lut_bytes(plan, n, tiles_x, tiles_y));
-  if ((int64_t)(P.p.width / tiles_x + 1) * (P.p.height / tiles_y + 1) >= (int64_t(1) << 31))
-    return fail(PIV_EINVAL, "tiles too large");
+  if (P.p.width > 32767 || P.p.height > 32767)
+    return fail(PIV_EUNSUPPORTED, "CLAHE takes frames of at most 32767 x 32767 pixels");
   if (n == 0) return PIV_OK;
   return dev(piv::launch_clahe(P, in, out, pitch, n, tiles_x, tiles_y, clip_factor, static_cast<uint16_t*>(lut),
                                stream),

@@ -4,6 +4,8 @@
 // stitched images).  Integer arithmetic throughout, so the results are
 // exact.  Both passes stream the frames once (reads and writes coalesced by
 // rows); the tile halos of the high-pass come from L2.
+#include <algorithm>
+
 #include "dev_common.h"
 #include "piv_internal.h"
 
@@ -12,89 +14,153 @@ namespace {
 
 // ---------------------------------------------------------------------------
 // High-pass: out = max(0, I - floor(sum / count)) over the image part of the
-// (2r+1)^2 box around each pixel.  A workgroup owns HT rows x HW columns of
-// output: it stages the tile with an r-pixel halo in LDS, forms the
-// horizontal box sums of every staged row (a running sum per 16-column
-// segment), then the vertical sums down each output column (a running sum
-// per 8-row segment).  The pixel count of the clipped box is a product of
-// two clipped spans.
+// (2r+1)^2 box around each pixel.  A workgroup owns HR rows x HQ columns of
+// output: it stages the tile with an r-pixel halo in LDS (aligned word
+// loads), forms the horizontal box sums of every staged row (a running sum
+// per 16-column segment), then the vertical sums for four columns at a time
+// (one 16-byte LDS read per row) and writes four pixels per store.  The
+// pixel count of the clipped box is a product of two clipped spans; the
+// quotient comes from a float reciprocal, corrected to the exact floor.
 // ---------------------------------------------------------------------------
-constexpr int HW = 64, HT = 32, kMaxR = 16;
-constexpr int RWmax = HW + 2 * kMaxR, RHmax = HT + 2 * kMaxR;
+constexpr int HQ = 128, HR = 32, kMaxR = 16;
+constexpr int HRW = HQ + 2 * kMaxR + 4, HRH = HR + 2 * kMaxR;
+static_assert(HQ / 16 == 8, "row-sum thread layout");
+
+// floor(s / c) for s < 2^27, 1 <= c < 2^11: the float estimate is within
+// two of the quotient, then integer corrections make it exact
+__device__ __forceinline__ uint32_t udiv_small(uint32_t s, uint32_t c) {
+  int q = (int)((float)s * __builtin_amdgcn_rcpf((float)c));
+  int r = (int)s - q * (int)c;
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    q += r < 0 ? -1 : (r >= (int)c ? 1 : 0);
+    r = (int)s - q * (int)c;
+  }
+  return (uint32_t)q;
+}
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_highpass(const uint8_t* __restrict__ in, uint8_t* __restrict__ out,
                                                   int64_t pitch, int64_t stride, int W, int H, int r,
                                                   const uint8_t* mask) {
-  __shared__ uint32_t reg[RHmax][RWmax];   // staged pixels (0 outside the image)
-  __shared__ uint32_t hs[RHmax][HW];       // horizontal box sums of the output columns
+  constexpr int ES = (int)sizeof(T), PW = 4 / ES;   // pixels per word
+  __shared__ uint16_t reg[HRH][HRW];                 // staged pixels (0 outside the image)
+  __shared__ __align__(16) uint32_t hs[HRH][HQ];    // horizontal box sums of the output columns
   const int pair = blockIdx.z;
   if (slot_off(mask, pair)) return;
   const int t = threadIdx.x;
-  const int x0 = blockIdx.x * HW, y0 = blockIdx.y * HT;
-  const int RW = HW + 2 * r, RH = HT + 2 * r;
+  const int x0 = blockIdx.x * HQ, y0 = blockIdx.y * HR;
+  const int RW = HQ + 2 * r, RH = HR + 2 * r;
   const uint8_t* src = in + (int64_t)pair * stride;
-  for (int i = t; i < RW * RH; i += 256) {
-    const int ry = i / RW, rx = i - (i / RW) * RW;
-    const int y = y0 - r + ry, x = x0 - r + rx;
-    uint32_t v = 0u;
-    if ((unsigned)y < (unsigned)H && (unsigned)x < (unsigned)W)
-      v = reinterpret_cast<const T*>(src + (int64_t)y * pitch)[x];
-    reg[ry][rx] = v;
-  }
-  __syncthreads();
-  // horizontal sums: (row, 16-column segment) per thread
-  for (int i = t; i < RH * (HW / 16); i += 256) {
-    const int ry = i / (HW / 16), c0 = (i - ry * (HW / 16)) * 16;
-    uint32_t s = 0u;
-    for (int u = 0; u <= 2 * r; ++u) s += reg[ry][c0 + u];
-    hs[ry][c0] = s;
+  const int rowbytes = W * ES;
+  // aligned words covering region columns [x0 - r, x0 + HQ + r)
+  const int xl = x0 - r;
+  const int w0 = (xl * ES) >> 2;                     // (arithmetic shift: floor)
+  const int nw = (((x0 + HQ + r) * ES + 3) >> 2) - w0;
+  // thread = (word column k of 64, row group of 4); u16 rows take up to
+  // two words per thread column
+  for (int k = t & 63; k < nw; k += 64) {
+    {
+      const int xa = 4 * (w0 + k);
+      for (int ry = t >> 6; ry < RH; ry += 4) {
+        const int y = y0 - r + ry;
+        const uint32_t ok = (unsigned)y < (unsigned)H ? 0xffffffffu : 0u;
+        const uint32_t wd = masked_word(src + (int64_t)min(max(y, 0), H - 1) * pitch, rowbytes, xa) & ok;
 #pragma unroll
-    for (int c = 1; c < 16; ++c) {
-      s += reg[ry][c0 + c + 2 * r] - reg[ry][c0 + c - 1];
-      hs[ry][c0 + c] = s;
+        for (int e = 0; e < PW; ++e) {
+          const int c = xa / ES + e - xl;   // region column
+          if (c >= 0 && c < RW)
+            reg[ry][c] = (uint16_t)(ES == 1 ? (wd >> (8 * e)) & 0xffu : (wd >> (16 * e)) & 0xffffu);
+        }
+      }
     }
   }
   __syncthreads();
-  // vertical sums: (column, 8-row segment) per thread; consecutive threads
-  // take consecutive columns, so the writes of a row coalesce
-  const int col = t & (HW - 1), seg = t >> 6;   // 4 segments of 8 rows
-  const int x = x0 + col;
-  if (x >= W) return;
-  const int cx = min(x + r, W - 1) - max(x - r, 0) + 1;
-  uint8_t* dst = out + (int64_t)pair * stride;
-  const int r0 = seg * 8;
-  uint32_t s = 0u;
-  for (int v = 0; v <= 2 * r; ++v) s += hs[r0 + v][col];
+  for (int i = t; i < RH * (HQ / 16); i += 256) {
+    const int ry = i >> 3, c0 = (i & 7) * 16;
+    uint32_t sm = 0u;
+    for (int u = 0; u <= 2 * r; ++u) sm += reg[ry][c0 + u];
+    hs[ry][c0] = sm;
 #pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    if (k) s += hs[r0 + k + 2 * r][col] - hs[r0 + k - 1][col];
+    for (int c = 1; c < 16; ++c) {
+      sm += (uint32_t)reg[ry][c0 + c + 2 * r] - (uint32_t)reg[ry][c0 + c - 1];
+      hs[ry][c0 + c] = sm;
+    }
+  }
+  __syncthreads();
+  // vertical sums: thread = (quad of columns, segment of 4 rows)
+  const int q = t & (HQ / 4 - 1), seg = t / (HQ / 4);
+  const int xq = x0 + 4 * q;
+  if (xq >= W) return;
+  uint32_t cx[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) cx[e] = (uint32_t)(min(xq + e + r, W - 1) - max(xq + e - r, 0) + 1);
+  constexpr int RSEG = HR / (256 / (HQ / 4));       // rows per thread
+  const int r0 = seg * RSEG;
+  uint32_t sm[4] = {0u, 0u, 0u, 0u};
+  for (int v = 0; v <= 2 * r; ++v) {
+    const uint4 h = *reinterpret_cast<const uint4*>(&hs[r0 + v][4 * q]);
+    sm[0] += h.x; sm[1] += h.y; sm[2] += h.z; sm[3] += h.w;
+  }
+  uint8_t* dst = out + (int64_t)pair * stride;
+  const bool full = xq + 4 <= W;
+#pragma unroll
+  for (int k = 0; k < RSEG; ++k) {
+    if (k) {
+      const uint4 hi = *reinterpret_cast<const uint4*>(&hs[r0 + k + 2 * r][4 * q]);
+      const uint4 lo = *reinterpret_cast<const uint4*>(&hs[r0 + k - 1][4 * q]);
+      sm[0] += hi.x - lo.x; sm[1] += hi.y - lo.y; sm[2] += hi.z - lo.z; sm[3] += hi.w - lo.w;
+    }
     const int y = y0 + r0 + k;
     if (y >= H) break;
-    const int cy = min(y + r, H - 1) - max(y - r, 0) + 1;
-    const uint32_t m = s / (uint32_t)(cx * cy);
-    const uint32_t I = reg[r0 + k + r][col + r];
-    reinterpret_cast<T*>(dst + (int64_t)y * pitch)[x] = (T)(I > m ? I - m : 0u);
+    const uint32_t cy = (uint32_t)(min(y + r, H - 1) - max(y - r, 0) + 1);
+    uint32_t o[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const uint32_t m = udiv_small(sm[e], cx[e] * cy);
+      const uint32_t I = reg[r0 + k + r][4 * q + e + r];
+      o[e] = I > m ? I - m : 0u;
+    }
+    T* orow = reinterpret_cast<T*>(dst + (int64_t)y * pitch);
+    if (full) {
+      if constexpr (ES == 1) {
+        *reinterpret_cast<uint32_t*>(orow + xq) = o[0] | (o[1] << 8) | (o[2] << 16) | (o[3] << 24);
+      } else {
+        *reinterpret_cast<uint32_t*>(orow + xq) = o[0] | (o[1] << 16);
+        *reinterpret_cast<uint32_t*>(orow + xq + 2) = o[2] | (o[3] << 16);
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if (xq + e < W) orow[xq + e] = (T)o[e];
+    }
   }
 }
 
 // ---------------------------------------------------------------------------
-// CLAHE, pass 1: one workgroup per tile.  Histogram in LDS (integer atomics,
-// so the order of the adds does not matter), clip at
-// max(1, floor(clip * npix / nbins)) (the same double arithmetic as the
-// host), the clipped excess spread evenly (excess / nbins to every bin, one
-// more to the first `rest` bins at a stride of max(nbins / rest, 1)), then a
-// prefix sum and lut[b] = (cdf * maxval + npix / 2) / npix.
+// CLAHE, pass 1: one workgroup per tile.  Histogram in LDS with integer
+// atomics (the order of the adds does not matter): 8 copies for u8 (2 for
+// u16) spread the atomics of a wave over different addresses, and zeros (the
+// bulk of a particle image's background) are counted in registers and added
+// once.  Then the clip at max(1, floor(clip * npix / nbins)) (the same
+// double arithmetic as the host), the clipped excess spread evenly
+// (excess / nbins to every bin, one more to the first `rest` bins at a
+// stride of max(nbins / rest, 1)), a prefix sum and
+// lut[b] = (cdf * maxval + npix / 2) / npix.
 // ---------------------------------------------------------------------------
 constexpr int kLutT = 256;
 
-__device__ __forceinline__ int tile_edge(int j, int L, int n) { return (int)(((int64_t)j * L) / n); }
+// (j L < 2^31: frames are at most 32767 px and grids 64 tiles)
+__device__ __forceinline__ int tile_edge(int j, int L, int n) { return (j * L) / n; }
 
 template <typename T>
 __global__ __launch_bounds__(kLutT) void k_clahe_lut(const uint8_t* __restrict__ in, int64_t pitch, int64_t stride,
                                                      int W, int H, int tx, int ty, int nbins, int shift, int maxval,
                                                      double clip_factor, uint16_t* lut, const uint8_t* mask) {
-  __shared__ uint32_t hist[4096];
+  constexpr int ES = (int)sizeof(T), PW = 4 / ES;
+  constexpr int NH = ES == 1 ? 8 : 2;               // histogram copies
+  constexpr int HB = ES == 1 ? 256 : 4096;
+  __shared__ uint32_t hist[NH * HB];
   __shared__ uint32_t part[kLutT];
   const int pair = blockIdx.z;
   if (slot_off(mask, pair)) return;
@@ -104,13 +170,40 @@ __global__ __launch_bounds__(kLutT) void k_clahe_lut(const uint8_t* __restrict__
   const int ya = tile_edge(j, H, ty), yb = tile_edge(j + 1, H, ty);
   const int tw = xb - xa, th = yb - ya;
   const int64_t npix = (int64_t)tw * th;
-  for (int b = t; b < nbins; b += kLutT) hist[b] = 0u;
+  for (int b = t; b < NH * nbins; b += kLutT) hist[b] = 0u;
   __syncthreads();
+  uint32_t* hc = hist + (t / (kLutT / NH)) * nbins;   // this thread's copy
   const uint8_t* src = in + (int64_t)pair * stride;
-  for (int p = t; p < tw * th; p += kLutT) {
-    const int y = ya + p / tw, x = xa + (p - (p / tw) * tw);
-    const uint32_t v = reinterpret_cast<const T*>(src + (int64_t)y * pitch)[x];
-    atomicAdd(&hist[v >> shift], 1u);
+  const int rowbytes = W * ES;
+  const int w0 = (xa * ES) >> 2, nw = ((xb * ES + 3) >> 2) - w0;
+  uint32_t zeros = 0u;
+  for (int p = t; p < th * nw; p += kLutT) {
+    const int ry = p / nw, k = p - (p / nw) * nw;
+    const uint32_t wd = masked_word(src + (int64_t)(ya + ry) * pitch, rowbytes, 4 * (w0 + k));
+#pragma unroll
+    for (int e = 0; e < PW; ++e) {
+      const int x = (4 * (w0 + k)) / ES + e;
+      if (x >= xa && x < xb) {
+        const uint32_t v = ES == 1 ? (wd >> (8 * e)) & 0xffu : (wd >> (16 * e)) & 0xffffu;
+        if (v == 0u) ++zeros;
+        else atomicAdd(&hc[v >> shift], 1u);
+      }
+    }
+  }
+  part[t] = zeros;
+  __syncthreads();
+  for (int o = kLutT / 2; o > 0; o >>= 1) {
+    if (t < o) part[t] += part[t + o];
+    __syncthreads();
+  }
+  const uint32_t nzero = part[0];
+  __syncthreads();
+  // merge the copies into copy 0 (bin 0 takes the zeros)
+  for (int b = t; b < nbins; b += kLutT) {
+    uint32_t h = b == 0 ? nzero : 0u;
+#pragma unroll
+    for (int c = 0; c < NH; ++c) h += hist[c * nbins + b];
+    hist[b] = h;
   }
   __syncthreads();
   // (a limit at or above npix clips nothing)
@@ -165,14 +258,14 @@ __global__ __launch_bounds__(kLutT) void k_clahe_lut(const uint8_t* __restrict__
 // whose centres surround it.  In doubled coordinates (centres may be
 // half-integers) the tile holding x is k = ceil((x+1) tx / W) - 1 and the
 // centre at or left of 2x is k or k - 1; before the first centre or after
-// the last a single tile is used.  Four pixels of a row per thread.
+// the last a single tile is used.
 struct Axis {
   int a, b;
-  int64_t w, d;
+  int w, d;
 };
 __device__ __forceinline__ Axis clahe_axis(int x, int L, int n) {
   const int X = 2 * x;
-  const int k = (int)((((int64_t)x + 1) * n + L - 1) / L) - 1;
+  const int k = ((x + 1) * n + L - 1) / L - 1;
   const int ck = tile_edge(k, L, n) + tile_edge(k + 1, L, n) - 1;
   const int a = ck <= X ? k : k - 1;
   Axis r;
@@ -191,35 +284,131 @@ __device__ __forceinline__ Axis clahe_axis(int x, int L, int n) {
   return r;
 }
 
-template <typename T>
+// A workgroup covers MQ columns (four per thread) and MR rows.  The column
+// blend data (tile pair and weights) is tabulated once per workgroup in LDS;
+// when the mappings the block touches fit (u8), they are staged in LDS too,
+// otherwise they are read from memory (L1/L2).  Every thread reads its four
+// pixels, then writes them, so the pass may run in place.
+constexpr int MQ = 1024, MR = 16;
+
+// floor((num + den / 2) / den) for 0 <= num < 2^52, 1 <= den < 2^32: the
+// double quotient is within one of the result, then an integer correction
+// makes it exact (cheaper than a 64-bit integer division)
+__device__ __forceinline__ int64_t round_div(int64_t num, int64_t den) {
+  const int64_t n2 = num + den / 2;
+  int64_t q = (int64_t)((double)n2 / (double)den);
+  int64_t r = n2 - q * den;
+  q += r < 0 ? -1 : (r >= den ? 1 : 0);
+  return q;
+}
+constexpr int kStageWords = 6144;   // LDS words for staged mappings (24 KB)
+
+template <typename T, bool kStaged, bool kNarrow>
 __global__ __launch_bounds__(256) void k_clahe_map(const uint8_t* in, uint8_t* out, int64_t pitch, int64_t stride,
                                                    int W, int H, int tx, int ty, int nbins, int shift,
                                                    const uint16_t* __restrict__ lut, const uint8_t* mask) {
+  constexpr int ES = (int)sizeof(T);
+  __shared__ uint32_t s_ax[MQ];          // per column: a | b << 8 | w << 16 (w < 2^16, d in s_ad)
+  __shared__ uint16_t s_ad[MQ];
+  __shared__ Axis s_ay[MR];
+  __shared__ uint32_t s_lut[kStaged ? kStageWords : 1];
   const int pair = blockIdx.z;
   if (slot_off(mask, pair)) return;
-  const int y = blockIdx.y;
-  const int x0 = (blockIdx.x * 256 + threadIdx.x) * 4;
-  if (x0 >= W) return;
-  const Axis ay = clahe_axis(y, H, ty);
+  const int t = threadIdx.x;
+  const int x0 = blockIdx.x * MQ, y0 = blockIdx.y * MR;
+  const int nq = min(MQ, W - x0);
+  for (int c = t; c < nq; c += 256) {
+    const Axis a = clahe_axis(x0 + c, W, tx);
+    s_ax[c] = (uint32_t)a.a | ((uint32_t)a.b << 8) | ((uint32_t)a.w << 16);
+    s_ad[c] = (uint16_t)a.d;
+  }
+  if (t < MR && y0 + t < H) s_ay[t] = clahe_axis(y0 + t, H, ty);
   const uint16_t* Lp = lut + (int64_t)pair * ty * tx * nbins;
-  const T* row = reinterpret_cast<const T*>(in + (int64_t)pair * stride + (int64_t)y * pitch);
-  T* orow = reinterpret_cast<T*>(out + (int64_t)pair * stride + (int64_t)y * pitch);
-  T v[4];
+  // tiles the block can touch: columns of its first and last pixel, rows of
+  // its first and last row
+  const Axis axl = clahe_axis(x0, W, tx), axr = clahe_axis(x0 + nq - 1, W, tx);
+  const int yl = min(y0 + MR, H) - 1;
+  const Axis ayt = clahe_axis(y0, H, ty), ayb = clahe_axis(yl, H, ty);
+  const int i0 = axl.a, i1 = axr.b, j0 = ayt.a, j1 = ayb.b;
+  const int ni = i1 - i0 + 1;
+  if constexpr (kStaged) {
+    const int words = (j1 - j0 + 1) * ni * nbins / 2;
+    for (int k = t; k < words; k += 256) {
+      const int e = 2 * k;
+      const int tile = e / nbins, b = e - tile * nbins;
+      const int jj = j0 + tile / ni, ii = i0 + tile - (tile / ni) * ni;
+      s_lut[k] = *reinterpret_cast<const uint32_t*>(Lp + ((int64_t)jj * tx + ii) * nbins + b);
+    }
+  }
+  __syncthreads();
+  const uint16_t* sl = reinterpret_cast<const uint16_t*>(s_lut);
+  auto L = [&](int jj, int ii, int b) -> int {
+    if constexpr (kStaged) return sl[((jj - j0) * ni + (ii - i0)) * nbins + b];
+    else return Lp[((int64_t)jj * tx + ii) * nbins + b];
+  };
+  const int c0 = 4 * t;
+  if (c0 >= nq) return;
+  const int xq = x0 + c0;
+  const bool full = c0 + 4 <= nq;
+  for (int k = 0; k < MR; ++k) {
+    const int y = y0 + k;
+    if (y >= H) break;
+    const Axis ay = s_ay[k];
+    const T* row = reinterpret_cast<const T*>(in + (int64_t)pair * stride + (int64_t)y * pitch);
+    T* orow = reinterpret_cast<T*>(out + (int64_t)pair * stride + (int64_t)y * pitch);
+    uint32_t v[4];
+    if (full) {
+      if constexpr (ES == 1) {
+        const uint32_t wd = *reinterpret_cast<const uint32_t*>(row + xq);
 #pragma unroll
-  for (int e = 0; e < 4; ++e) v[e] = x0 + e < W ? row[x0 + e] : (T)0;
+        for (int e = 0; e < 4; ++e) v[e] = (wd >> (8 * e)) & 0xffu;
+      } else {
+        const uint32_t w0 = *reinterpret_cast<const uint32_t*>(row + xq);
+        const uint32_t w1 = *reinterpret_cast<const uint32_t*>(row + xq + 2);
+        v[0] = w0 & 0xffffu; v[1] = w0 >> 16; v[2] = w1 & 0xffffu; v[3] = w1 >> 16;
+      }
+    } else {
 #pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    const int x = x0 + e;
-    if (x >= W) break;
-    const Axis ax = clahe_axis(x, W, tx);
-    const int b = (int)v[e] >> shift;
-    const int64_t l00 = Lp[((int64_t)ay.a * tx + ax.a) * nbins + b];
-    const int64_t l01 = Lp[((int64_t)ay.a * tx + ax.b) * nbins + b];
-    const int64_t l10 = Lp[((int64_t)ay.b * tx + ax.a) * nbins + b];
-    const int64_t l11 = Lp[((int64_t)ay.b * tx + ax.b) * nbins + b];
-    const int64_t num = (ay.d - ay.w) * ((ax.d - ax.w) * l00 + ax.w * l01) + ay.w * ((ax.d - ax.w) * l10 + ax.w * l11);
-    const int64_t den = ax.d * ay.d;
-    orow[x] = (T)((num + den / 2) / den);
+      for (int e = 0; e < 4; ++e) v[e] = c0 + e < nq ? (uint32_t)row[xq + e] : 0u;
+    }
+    uint32_t o[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int c = min(c0 + e, nq - 1);
+      const uint32_t ax = s_ax[c];
+      const int ia = ax & 0xff, ib = (ax >> 8) & 0xff, wx = (int)(ax >> 16), dx = s_ad[c];
+      const int b = (int)(v[e] >> shift);
+      if constexpr (kNarrow) {
+        // every numerator and denominator below 2^24 (checked on the host):
+        // float estimate of the rounded quotient, then an exact correction
+        const int l00 = L(ay.a, ia, b), l01 = L(ay.a, ib, b), l10 = L(ay.b, ia, b), l11 = L(ay.b, ib, b);
+        const int num = (ay.d - ay.w) * ((dx - wx) * l00 + wx * l01) + ay.w * ((dx - wx) * l10 + wx * l11);
+        const int den = dx * ay.d;
+        const int n2 = num + den / 2;
+        int q = (int)((float)n2 * __builtin_amdgcn_rcpf((float)den));
+        int rr = n2 - q * den;
+        q += rr < 0 ? -1 : (rr >= den ? 1 : 0);
+        o[e] = (uint32_t)q;
+      } else {
+        const int64_t l00 = L(ay.a, ia, b), l01 = L(ay.a, ib, b), l10 = L(ay.b, ia, b), l11 = L(ay.b, ib, b);
+        const int64_t num = (int64_t)(ay.d - ay.w) * ((dx - wx) * l00 + wx * l01) +
+                            (int64_t)ay.w * ((dx - wx) * l10 + wx * l11);
+        const int64_t den = (int64_t)dx * ay.d;
+        o[e] = (uint32_t)round_div(num, den);
+      }
+    }
+    if (full) {
+      if constexpr (ES == 1) {
+        *reinterpret_cast<uint32_t*>(orow + xq) = o[0] | (o[1] << 8) | (o[2] << 16) | (o[3] << 24);
+      } else {
+        *reinterpret_cast<uint32_t*>(orow + xq) = o[0] | (o[1] << 16);
+        *reinterpret_cast<uint32_t*>(orow + xq + 2) = o[2] | (o[3] << 16);
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if (c0 + e < nq) orow[xq + e] = (T)o[e];
+    }
   }
 }
 
@@ -231,7 +420,7 @@ int clahe_bins(const Plan& P) {
 }
 
 hipError_t launch_highpass(const Plan& P, const void* in, void* out, int64_t pitch, int n, int r, hipStream_t s) {
-  dim3 grid((P.p.width + HW - 1) / HW, (P.p.height + HT - 1) / HT, n);
+  dim3 grid((P.p.width + HQ - 1) / HQ, (P.p.height + HR - 1) / HR, n);
   const int64_t stride = pitch * P.p.height;
   if (P.es == 1)
     hipLaunchKernelGGL(k_highpass<uint8_t>, grid, dim3(256), 0, s, (const uint8_t*)in, (uint8_t*)out, pitch, stride,
@@ -242,26 +431,51 @@ hipError_t launch_highpass(const Plan& P, const void* in, void* out, int64_t pit
   return hipGetLastError();
 }
 
+// The staged map kernel holds the mappings of every tile a block can touch:
+// at most (columns of MQ pixels' tiles + 2) x (rows of MR rows' tiles + 2).
+static bool clahe_stage_fits(const Plan& P, int tx, int ty, int nbins) {
+  const int tw = P.p.width / tx, th = P.p.height / ty;   // smallest tile sizes
+  if (tw < 1 || th < 1) return false;
+  const int ncol = MQ / tw + 3, nrow = MR / th + 3;
+  return (int64_t)ncol * nrow * nbins / 2 <= kStageWords;
+}
+
 hipError_t launch_clahe(const Plan& P, const void* in, void* out, int64_t pitch, int n, int tx, int ty,
                         double clip_factor, uint16_t* lut, hipStream_t s) {
   const int bits = P.p.dtype == PIV_U8 ? 8 : P.p.bit_depth;
   const int nbins = clahe_bins(P), shift = bits - (bits < 12 ? bits : 12), maxval = (1 << bits) - 1;
   const int64_t stride = pitch * P.p.height;
   dim3 g1(tx, ty, n);
-  dim3 g2((P.p.width + 1023) / 1024, P.p.height, n);
+  dim3 g2((P.p.width + MQ - 1) / MQ, (P.p.height + MR - 1) / MR, n);
+  const bool staged = clahe_stage_fits(P, tx, ty, nbins);
+  // the blend denominator per axis is a centre distance in doubled
+  // coordinates, e(a+2) - e(a); the 32-bit path needs
+  // maxval dx dy + dx dy / 2 < 2^24 for the largest ones
+  auto dmax = [](int L, int n) {
+    int64_t m = 1;
+    for (int a = 0; a + 2 <= n; ++a) m = std::max<int64_t>(m, (int64_t)(a + 2) * L / n - (int64_t)a * L / n);
+    return m;
+  };
+  const int64_t dd = dmax(P.p.width, tx) * dmax(P.p.height, ty);
+  const bool narrow = (int64_t)maxval * dd + dd / 2 < (int64_t(1) << 24);
+#define PIV_MAP(T_, ST_, NA_)                                                                              \
+  hipLaunchKernelGGL((k_clahe_map<T_, ST_, NA_>), g2, dim3(256), 0, s, (const uint8_t*)in, (uint8_t*)out, pitch, \
+                     stride, P.p.width, P.p.height, tx, ty, nbins, shift, (const uint16_t*)lut, P.slot_mask)
+#define PIV_CLAHE(T_)                                                                                           \
+  hipLaunchKernelGGL(k_clahe_lut<T_>, g1, dim3(kLutT), 0, s, (const uint8_t*)in, pitch, stride, P.p.width,        \
+                     P.p.height, tx, ty, nbins, shift, maxval, clip_factor, lut, P.slot_mask);                  \
+  if (hipError_t e = hipGetLastError()) return e;                                                              \
+  if (staged && narrow) PIV_MAP(T_, true, true);                                                                \
+  else if (staged) PIV_MAP(T_, true, false);                                                                    \
+  else if (narrow) PIV_MAP(T_, false, true);                                                                    \
+  else PIV_MAP(T_, false, false)
   if (P.es == 1) {
-    hipLaunchKernelGGL(k_clahe_lut<uint8_t>, g1, dim3(kLutT), 0, s, (const uint8_t*)in, pitch, stride, P.p.width,
-                       P.p.height, tx, ty, nbins, shift, maxval, clip_factor, lut, P.slot_mask);
-    if (hipError_t e = hipGetLastError()) return e;
-    hipLaunchKernelGGL(k_clahe_map<uint8_t>, g2, dim3(256), 0, s, (const uint8_t*)in, (uint8_t*)out, pitch, stride,
-                       P.p.width, P.p.height, tx, ty, nbins, shift, (const uint16_t*)lut, P.slot_mask);
+    PIV_CLAHE(uint8_t);
   } else {
-    hipLaunchKernelGGL(k_clahe_lut<uint16_t>, g1, dim3(kLutT), 0, s, (const uint8_t*)in, pitch, stride, P.p.width,
-                       P.p.height, tx, ty, nbins, shift, maxval, clip_factor, lut, P.slot_mask);
-    if (hipError_t e = hipGetLastError()) return e;
-    hipLaunchKernelGGL(k_clahe_map<uint16_t>, g2, dim3(256), 0, s, (const uint8_t*)in, (uint8_t*)out, pitch, stride,
-                       P.p.width, P.p.height, tx, ty, nbins, shift, (const uint16_t*)lut, P.slot_mask);
+    PIV_CLAHE(uint16_t);
   }
+#undef PIV_CLAHE
+#undef PIV_MAP
   return hipGetLastError();
 }
 

@@ -134,6 +134,10 @@ CORR_CASES = {
     "tiled_u16_12_central": ("u16", dict(dtype="u16", win=24, step=12, radius=4, warp="central"), True),
     "tiled_u16_8_central": ("u16", dict(dtype="u16", win=16, step=8, radius=4, warp="central"), True),
     "generic_u8_fixed_pred": ("vortex", dict(win=24, step=8, radius=4, block=16, peak="fixed"), True),
+    # the low-seeding wake (0.002 ppp, 32 x 32 windows at 50% step-over):
+    # the a-priori stencil and the argmax search
+    "wake_fixed_32_16": ("wake", dict(win=32, step=16, radius=4, levels=2, radius_coarse=6, peak="fixed"), True),
+    "wake_argmax_32_16": ("wake", dict(win=32, step=16, radius=4, levels=2, radius_coarse=6), True),
 }
 
 
@@ -150,6 +154,8 @@ def _images(kind):
         return synth.cfg1_pair(1001)[:2]
     if kind == "u16":
         return synth.cfg3_pair(1, W=384, H=216)[:2]
+    if kind == "wake":
+        return synth.make_pair(512, 256, synth.cylinder_wake(512, 256), 0.002, noise=2.0, seed=7100)
     raise KeyError(kind)
 
 
@@ -357,7 +363,7 @@ def test_vorticity_parity():
     assert np.abs(om - 0.02).max() < 1e-4 * 0.02 + 1e-6
 
 
-def _run_both(A, B, kw, where):
+def _run_both(A, B, kw, where, peak_mode=0):
     """The whole path on the GPU (piv_run) and in the oracle, compared stage
     by stage on identical inputs, every difference explained:
     the predictor bit-exact; the raw correction (piv_correct on the run's
@@ -375,11 +381,11 @@ def _run_both(A, B, kw, where):
     g = {k: v.cpu().numpy()[0] for k, v in out.items()}
     raw, peak, flags = raw.cpu().numpy()[0], peak.cpu().numpy()[0], flags.cpu().numpy()[0]
     o = oracle.run(A, B, win=kw["win"], step=kw["step"], r=kw["radius"], levels=kw["levels"],
-                   Rc=kw["radius_coarse"], Rf=kw["radius_fine"])
+                   Rc=kw["radius_coarse"], Rf=kw["radius_fine"], peak_mode=peak_mode)
     assert np.array_equal(g["pred"], o["pred"].astype(np.float32)), f"{where}: predictor"
     raw_ex = compare_correct(None, None, A.astype(float), B.astype(float), kw["win"], kw["step"], kw["radius"],
                              o["pred"], raw, peak, flags, o["disp_raw"], o["peak"], o["flags_raw"],
-                             where=f"{where} raw")
+                             fixed=peak_mode == 1, where=f"{where} raw")
     vo, flo = oracle.validate(raw.astype(np.float64), flags.copy())
     uod_ex = compare_validate(raw.astype(np.float64), flags, g["disp"], g["flags"], vo, flo,
                               where=f"{where} validate")
@@ -417,6 +423,20 @@ def test_run_end_to_end_strong_vortex():
     err = np.abs(g["disp"] - T)[:, 2:-2, 2:-2]
     say(f"  vs truth: rms {np.sqrt((err ** 2).mean()):.3f} px (oracle "
         f"{np.sqrt(((o['disp'] - T)[:, 2:-2, 2:-2] ** 2).mean()):.3f} px)")
+
+
+@pytest.mark.parametrize("peak", ["fixed", "argmax"])
+def test_run_end_to_end_low_seeding_wake(peak):
+    """The low-seeding case (0.002 ppp cylinder-like wake, 32 x 32 windows
+    at step 16, two-level predictor): the whole path stage by stage against
+    the oracle, with the a-priori stencil and with the argmax search."""
+    say(f"[run] low-seeding wake, {peak}")
+    A, B = synth.make_pair(512, 256, synth.cylinder_wake(512, 256), 0.002, noise=2.0, seed=7101)
+    kw = dict(win=32, step=16, radius=4, levels=2, radius_coarse=6, radius_fine=2, peak=peak)
+    g, o = _run_both(A, B, kw, f"run[wake {peak}]", peak_mode=1 if peak == "fixed" else 0)
+    T = synth.truth(synth.cylinder_wake(512, 256), 512, 256, 16)
+    err = np.abs(g["disp"] - T)[:, 2:-2, 2:-2]
+    say(f"  vs truth: rms {np.sqrt((err ** 2).mean()):.3f} px")
 
 
 def test_run_end_to_end_cfg1():
