@@ -1024,7 +1024,9 @@ struct BandCfg {
   static constexpr int BW4 = (BW + 3) / 4 * 4;            // B' columns written (whole groups)
   static constexpr int TAB_WORDS = 2 * (BH + BW4);
   static constexpr int RES_WORDS = NWIN * NS + 2 * NG * NWIN;
-  static constexpr int RAW_WORDS = 3888;
+  // raw source box of B (words): at step 8 a 3888-word box; at step 12 room
+  // for a predictor range of 16 px across the tile (u16 rows)
+  static constexpr int RAW_WORDS = STEP == 8 ? 3888 : ((BW + 19) * 2 / 4 + 2) * (BH + 19);
   static constexpr int UNION = RAW_WORDS + TAB_WORDS > RES_WORDS ? RAW_WORDS + TAB_WORDS : RES_WORDS;
   static_assert(NC <= 64, "a cell per lane");
   static_assert(NSY % SYG == 0, "shift rows must split evenly");
@@ -1032,7 +1034,7 @@ struct BandCfg {
 };
 
 template <typename T, int STEP, int R, int SYG, int TW, int TH>
-__global__ __launch_bounds__(64 * ((2 * R + 1) / SYG)) __attribute__((amdgpu_waves_per_eu(3)))
+__global__ __launch_bounds__(64 * ((2 * R + 1) / SYG)) __attribute__((amdgpu_waves_per_eu(STEP == 8 ? 3 : 2)))
 void k_correct_bands(CorrArgs g) {
   using C = BandCfg<STEP, R, SYG, TW, TH>;
   constexpr int NT = 64 * C::NG;
@@ -1322,15 +1324,21 @@ void k_correct_bands(CorrArgs g) {
     sa = (float)((int)s1 - STEP * STEP * Ki);
     saa = (float)((int)s2 - 2 * Ki * (int)s1 + STEP * STEP * Ki * Ki);
   }
+  // (with large cells the S/Q column sums take a second pass over the band's
+  // rows, after the products, so that their registers and the A cell's are
+  // never live together)
+  constexpr bool kSplitSQ = STEP > 8;
+  const float* bbase = sB + (ci * STEP + band * SYG) * C::BP + cj * STEP;
+  float cs[BRW], cq[BRW];
   {
 #pragma unroll
     for (int k = 0; k < SYG; ++k)
 #pragma unroll
       for (int j = 0; j < C::NSY; ++j) Pacc[k][j] = 0.0f;
-    float cs[BRW], cq[BRW];
+    if constexpr (!kSplitSQ) {
 #pragma unroll
-    for (int x = 0; x < BRW; ++x) cs[x] = cq[x] = 0.0f;
-    const float* bbase = sB + (ci * STEP + band * SYG) * C::BP + cj * STEP;
+      for (int x = 0; x < BRW; ++x) cs[x] = cq[x] = 0.0f;
+    }
     // stream the B' rows of the band once each; B' row rb meets A row
     // rb - k for shift row k, so the last SYG A rows are kept (converted)
     float ar[SYG][STEP];
@@ -1351,10 +1359,12 @@ void k_correct_bands(CorrArgs g) {
             saa += an[x] * an[x];
           }
         }
+        if constexpr (!kSplitSQ) {
 #pragma unroll
-        for (int x = 0; x < BRW; ++x) {
-          cs[x] += brow[x];
-          cq[x] += brow[x] * brow[x];
+          for (int x = 0; x < BRW; ++x) {
+            cs[x] += brow[x];
+            cq[x] += brow[x] * brow[x];
+          }
         }
       }
 #pragma unroll
@@ -1372,6 +1382,22 @@ void k_correct_bands(CorrArgs g) {
         }
       }
     }
+  }
+  if constexpr (kSplitSQ) {
+    // column sums of the band's first STEP rows
+#pragma unroll
+    for (int x = 0; x < BRW; ++x) cs[x] = cq[x] = 0.0f;
+#pragma unroll
+    for (int rb = 0; rb < STEP; ++rb) {
+#pragma unroll
+      for (int x = 0; x < BRW; ++x) {
+        const float b = bbase[rb * C::BP + x];
+        cs[x] += b;
+        cq[x] += b * b;
+      }
+    }
+  }
+  {
     // column sums of the band's first row, slid down for the other rows;
     // box sums over STEP columns for every shift column
 #pragma unroll
@@ -1525,6 +1551,9 @@ template <typename T>
 hipError_t launch_tiled_t(const CorrArgs& g, int n, hipStream_t s) {
   if (!g.central && g.step == 8 && g.R == 4) return launch_bands<T, 8, 4, 3, 8, 6>(g, n, s);
   if (!g.central && g.step == 8 && g.R == 1) return launch_bands<T, 8, 1, 1, 8, 6>(g, n, s);
+  if constexpr (sizeof(T) == 2) {   // (u8 cells of 12 px are not whole words at half a cell)
+    if (!g.central && g.step == 12 && g.R == 4) return launch_bands<T, 12, 4, 3, 8, 6>(g, n, s);
+  }
   if (g.step == 8 && g.R == 4) return launch_tiled<T, 8, 4, 3, 8, 8, 256>(g, n, s);
   if (g.step == 8 && g.R == 1) return launch_tiled<T, 8, 1, 1, 8, 8, 256>(g, n, s);
   if (g.step == 12 && g.R == 4) return launch_tiled<T, 12, 4, 3, 5, 5, 128>(g, n, s);
