@@ -67,6 +67,10 @@ def lib():
         L.o_ssd_refine.argtypes = [_D, _D, _D, _i, _i, _i, _i, _i, _d, _d, _Dn]
         L.o_smooth.argtypes = [_D, _D, _i, _d, _i]
         L.o_highpass.argtypes = [_I, _i, _i, _i, _I]
+        _L = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
+        L.o_sgm_aggregate.argtypes = [_L, _i, _i, _i, C.c_int64, C.c_int64, _L]
+        L.o_sgm_level.argtypes = [_I, _I, _i, _i, _i, _i, _i, _i, _i, _i, _i, _I]
+        L.o_predict_sgm.argtypes = [_I, _I, _i, _i, _i, _i, _i, _i, _i, _i, _i, _i, _i, _I]
         L.o_clahe_clip.argtypes = [C.c_int64, _i, _d]
         L.o_clahe_clip.restype = C.c_int64
         L.o_clahe.argtypes = [_I, _i, _i, _i, _i, _i, _d, _I]
@@ -109,12 +113,35 @@ def median3_int(d):
     return out
 
 
-def predict(A, B, step, block, levels, Rc, Rf, median=True):
+def predict(A, B, step, block, levels, Rc, Rf, median=True, sgm=None):
+    """The predictor; sgm = (p1, p2) searches the coarsest level by
+    semi-global matching with those penalties per block pixel."""
     A, B = _img_i(A), _img_i(B)
     H, W = A.shape
     pred = np.zeros((2, H // step, W // step), np.int32)
-    lib().o_predict(A, B, W, H, step, block, levels, Rc, Rf, int(bool(median)), pred)
+    if sgm is None:
+        lib().o_predict(A, B, W, H, step, block, levels, Rc, Rf, int(bool(median)), pred)
+    else:
+        lib().o_predict_sgm(A, B, W, H, step, block, levels, Rc, Rf, int(bool(median)), 1, int(sgm[0]),
+                            int(sgm[1]), pred)
     return pred
+
+
+def sgm_aggregate(C, R, P1, P2):
+    """C [ny][nx][(2R+1)^2] int64 -> S, the sum of the four path costs."""
+    C = np.ascontiguousarray(C, dtype=np.int64)
+    ny, nx, nd = C.shape
+    S = np.zeros_like(C)
+    lib().o_sgm_aggregate(C, nx, ny, int(R), int(P1), int(P2), S)
+    return S
+
+
+def sgm_level(A, B, nx, ny, step, block, R, p1, p2):
+    A, B = _img_i(A), _img_i(B)
+    H, W = A.shape
+    d = np.zeros((2, ny, nx), np.int32)
+    lib().o_sgm_level(A, B, W, H, nx, ny, step, block, R, int(p1), int(p2), d)
+    return d
 
 
 def interp(U, step, x, y):
@@ -265,11 +292,11 @@ def clahe(img, bits, tiles_x, tiles_y, clip_factor):
 
 
 def run(A, B, *, win, step, r, levels, block=0, Rc, Rf, median=True, warp_mode=0, peak_mode=0,
-        thr=2.0, eps=0.1):
+        thr=2.0, eps=0.1, sgm=None):
     """The whole plain path: predict, validate the predictor, correct,
     validate, vorticity.  Returns dict of numpy arrays."""
     blk = block or win
-    pred = predict(A, B, step, blk, levels, Rc, Rf, median).astype(np.float64)
+    pred = predict(A, B, step, blk, levels, Rc, Rf, median, sgm).astype(np.float64)
     pred, _ = validate(pred, None, thr, eps)
     disp, peak, flags = correct(A, B, win, step, r, pred, warp_mode, peak_mode)
     disp_v, flags_v = validate(disp, flags, thr, eps)

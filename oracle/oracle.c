@@ -126,8 +126,21 @@ void o_median3_int(const int32_t* d, int nx, int ny, int32_t* out) {
  * node's result, a 3x3 median after every level when `median` is set.
  * Level grids: nx_0 = W/step, nx_l = ceil(nx_{l-1}/2); level-l node (a,b)
  * has parent (a/2, b/2).  pred is [2][ny][nx] integers in level-0 pixels. */
+void o_sgm_level(const int32_t* A, const int32_t* B, int W, int H, int nx, int ny, int step, int block, int R,
+                 int p1, int p2, int32_t* d);
+
+/* The predictor with the coarsest level searched by semi-global matching
+ * (sgm != 0, penalties p1, p2 per block pixel) instead of block matching. */
+void o_predict_sgm(const int32_t* A, const int32_t* B, int W, int H, int step, int block, int levels,
+                   int Rc, int Rf, int median, int sgm, int p1, int p2, int32_t* pred);
+
 void o_predict(const int32_t* A, const int32_t* B, int W, int H, int step, int block, int levels,
                int Rc, int Rf, int median, int32_t* pred) {
+  o_predict_sgm(A, B, W, H, step, block, levels, Rc, Rf, median, 0, 0, 0, pred);
+}
+
+void o_predict_sgm(const int32_t* A, const int32_t* B, int W, int H, int step, int block, int levels,
+                   int Rc, int Rf, int median, int sgm, int p1, int p2, int32_t* pred) {
   int Wl[16], Hl[16], nxl[16], nyl[16];
   const int32_t* PA[16];
   const int32_t* PB[16];
@@ -160,7 +173,10 @@ void o_predict(const int32_t* A, const int32_t* B, int W, int H, int step, int b
         }
     }
     int32_t* d = (int32_t*)malloc(sizeof(int32_t) * 2 * np);
-    o_sad_level(PA[l], PB[l], Wl[l], Hl[l], nx, ny, step, block, l == levels - 1 ? Rc : Rf, cand, d);
+    if (sgm && l == levels - 1)
+      o_sgm_level(PA[l], PB[l], Wl[l], Hl[l], nx, ny, step, block, Rc, p1, p2, d);
+    else
+      o_sad_level(PA[l], PB[l], Wl[l], Hl[l], nx, ny, step, block, l == levels - 1 ? Rc : Rf, cand, d);
     if (median) {
       int32_t* m = (int32_t*)malloc(sizeof(int32_t) * 2 * np);
       o_median3_int(d, nx, ny, m);
@@ -782,4 +798,107 @@ void o_clahe(const int32_t* I, int W, int H, int bits, int tx, int ty, double cl
       out[(size_t)y * W + x] = (int32_t)((num + den / 2) / den);
     }
   free(luts);
+}
+
+/* ------------------------------------------------------------------------
+ * Semi-global matching on the node grid (the family of methods the paper's
+ * optical-flow engine implements, Sec. 2): the block-SAD cost of every
+ * candidate displacement at every node is aggregated along four paths
+ * (left to right, right to left, top to bottom, bottom to top) with a small
+ * penalty P1 for a change of one pixel in either component between path
+ * neighbours and a large penalty P2 for any larger change; the winner
+ * minimises (sum over paths, |dx|+|dy|, dy, dx).  Integer throughout.
+ * ---------------------------------------------------------------------- */
+
+/* Aggregate a cost volume C[node][k] (nodes row-major on an nx x ny grid, k
+ * = (dy+R)(2R+1) + (dx+R) over the (2R+1)^2 candidates) along the four
+ * paths; S[node][k] = sum of the four path costs.  Path cost at the first
+ * node of a path = C; then
+ *   L(p,d) = C(p,d) + min(L(q,d), min_{d' 8-adjacent to d} L(q,d') + P1,
+ *                         min_d' L(q,d') + P2) - min_d' L(q,d')
+ * with q the previous node on the path. */
+void o_sgm_aggregate(const int64_t* C, int nx, int ny, int R, int64_t P1, int64_t P2, int64_t* S) {
+  int n1 = 2 * R + 1, nd = n1 * n1;
+  size_t np = (size_t)nx * ny;
+  memset(S, 0, sizeof(int64_t) * np * nd);
+  int64_t* prev = (int64_t*)malloc(sizeof(int64_t) * nd);
+  int64_t* cur = (int64_t*)malloc(sizeof(int64_t) * nd);
+  /* dir: 0 left->right, 1 right->left, 2 top->bottom, 3 bottom->top */
+  for (int dir = 0; dir < 4; ++dir) {
+    int nlines = dir < 2 ? ny : nx, len = dir < 2 ? nx : ny;
+    for (int line = 0; line < nlines; ++line)
+      for (int s = 0; s < len; ++s) {
+        int pos = (dir == 1 || dir == 3) ? len - 1 - s : s;
+        int a = dir < 2 ? line : pos, b = dir < 2 ? pos : line;
+        const int64_t* c = C + ((size_t)a * nx + b) * nd;
+        if (s == 0) {
+          for (int k = 0; k < nd; ++k) cur[k] = c[k];
+        } else {
+          int64_t m = prev[0];
+          for (int k = 1; k < nd; ++k) if (prev[k] < m) m = prev[k];
+          for (int k = 0; k < nd; ++k) {
+            int ky = k / n1, kx = k % n1;
+            int64_t best = prev[k];
+            for (int oy = -1; oy <= 1; ++oy)
+              for (int ox = -1; ox <= 1; ++ox) {
+                if (!oy && !ox) continue;
+                int y2 = ky + oy, x2 = kx + ox;
+                if (y2 < 0 || x2 < 0 || y2 >= n1 || x2 >= n1) continue;
+                int64_t v = prev[y2 * n1 + x2] + P1;
+                if (v < best) best = v;
+              }
+            if (m + P2 < best) best = m + P2;
+            cur[k] = c[k] + best - m;
+          }
+        }
+        int64_t* sp = S + ((size_t)a * nx + b) * nd;
+        for (int k = 0; k < nd; ++k) sp[k] += cur[k];
+        int64_t* t = prev; prev = cur; cur = t;
+      }
+  }
+  free(prev);
+  free(cur);
+}
+
+/* One level searched by semi-global matching (no candidate: the search is
+ * centred at zero): C from the block SAD of o_sad_level's definition, then
+ * o_sgm_aggregate with P1 = p1 block^2 and P2 = p2 block^2, then the winner
+ * per node.  d is [2][ny][nx]. */
+void o_sgm_level(const int32_t* A, const int32_t* B, int W, int H, int nx, int ny, int step, int block, int R,
+                 int p1, int p2, int32_t* d) {
+  int off = (step - block) / 2, n1 = 2 * R + 1, nd = n1 * n1;
+  size_t np = (size_t)nx * ny;
+  int64_t* C = (int64_t*)malloc(sizeof(int64_t) * np * nd);
+  int64_t* S = (int64_t*)malloc(sizeof(int64_t) * np * nd);
+#pragma omp parallel for schedule(dynamic)
+  for (int a = 0; a < ny; ++a)
+    for (int b = 0; b < nx; ++b) {
+      int oy = a * step + off, ox = b * step + off;
+      for (int dy = -R; dy <= R; ++dy)
+        for (int dx = -R; dx <= R; ++dx) {
+          int64_t s = 0;
+          for (int i = 0; i < block; ++i)
+            for (int j = 0; j < block; ++j)
+              s += llabs((long long)ipx(A, W, H, oy + i, ox + j) - (long long)ipx(B, W, H, oy + i + dy, ox + j + dx));
+          C[((size_t)a * nx + b) * nd + (dy + R) * n1 + (dx + R)] = s;
+        }
+    }
+  int64_t bb = (int64_t)block * block;
+  o_sgm_aggregate(C, nx, ny, R, (int64_t)p1 * bb, (int64_t)p2 * bb, S);
+  for (size_t p = 0; p < np; ++p) {
+    int64_t bs = -1;
+    int bl = 0, bdy = 0, bdx = 0;
+    for (int dy = -R; dy <= R; ++dy)
+      for (int dx = -R; dx <= R; ++dx) {
+        int64_t s = S[p * nd + (dy + R) * n1 + (dx + R)];
+        int l = abs(dx) + abs(dy);
+        if (bs < 0 || key_less(s, l, dy, dx, bs, bl, bdy, bdx)) {
+          bs = s; bl = l; bdy = dy; bdx = dx;
+        }
+      }
+    d[p] = bdx;
+    d[np + p] = bdy;
+  }
+  free(C);
+  free(S);
 }
