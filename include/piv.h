@@ -86,6 +86,9 @@ typedef struct {
   piv_peak peak;
   float uod_threshold;     /* normalised-median threshold (Sec. 3: 2)                */
   float uod_epsilon;       /* normalised-median regulariser in px (Sec. 3: 0.1)      */
+  int32_t sgm;             /* 1: the coarsest level by semi-global matching (0: off) */
+  int32_t sgm_p1;          /* its penalty for a 1 px change between path neighbours, */
+  int32_t sgm_p2;          /*   and for a larger one, per block pixel (0..255)       */
 } piv_params;
 
 /* Per-vector flag bits. */
@@ -150,7 +153,16 @@ void piv_plan_destroy(piv_plan_t plan);
  * cand + [-R, R]^2 (R = radius_coarse on the coarsest level around 0,
  * radius_fine below, around twice the parent node's result); the d with the
  * least (SAD, |dx|+|dy|, dy, dx) wins.  Pyramid levels are 2x2 box means
- * floor((sum+2)/4).  pred: [n][2][ny][nx] float32 holding integers.
+ * floor((sum+2)/4).  With params.sgm the coarsest level is searched by
+ * semi-global matching instead (the family of methods of the paper's
+ * optical-flow engine): the block SAD of every candidate d in
+ * [-radius_coarse, radius_coarse]^2 at every node, aggregated along four
+ * paths over the node grid (left to right, right to left, top to bottom,
+ * bottom to top), L(p,d) = C(p,d) + min(L(q,d), min over the 8 candidates
+ * adjacent to d of L(q,d') + P1, min L(q,.) + P2) - min L(q,.) with q the
+ * previous node on the path (L = C at a path's first node), P1 = sgm_p1 *
+ * block^2, P2 = sgm_p2 * block^2; the least (sum of the four, |dx|+|dy|,
+ * dy, dx) wins.  pred: [n][2][ny][nx] float32 holding integers.
  * Needs a bound workspace. */
 piv_status piv_predict(piv_plan_t plan, const void* A, const void* B, int64_t pitch_bytes,
                        int32_t n, float* pred, hipStream_t stream);

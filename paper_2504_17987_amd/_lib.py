@@ -39,6 +39,7 @@ class Params(C.Structure):
         ("radius_fine", C.c_int32), ("median", C.c_int32),
         ("warp", C.c_int), ("peak", C.c_int),
         ("uod_threshold", C.c_float), ("uod_epsilon", C.c_float),
+        ("sgm", C.c_int32), ("sgm_p1", C.c_int32), ("sgm_p2", C.c_int32),
     ]
 
 

@@ -41,8 +41,8 @@ class Plan:
                  bit_depth: Optional[int] = None, win: int = 16, step: int = 8, radius: int = 4,
                  levels: int = 3, block: int = 0, radius_coarse: int = 6, radius_fine: int = 2,
                  median: bool = True, warp: str = "b", peak: str = "argmax",
-                 uod_threshold: float = 2.0, uod_epsilon: float = 0.1, device="cuda",
-                 workspace: bool = True):
+                 uod_threshold: float = 2.0, uod_epsilon: float = 0.1, sgm: bool = False,
+                 sgm_p1: int = 2, sgm_p2: int = 16, device="cuda", workspace: bool = True):
         code, tdt, es = _DT[dtype]
         self.dtype, self.tdtype, self.es = dtype, tdt, es
         p = L.Params()
@@ -56,6 +56,7 @@ class Plan:
         p.warp = {"b": L.PIV_WARP_B, "central": L.PIV_WARP_CENTRAL}[warp]
         p.peak = {"argmax": L.PIV_PEAK_ARGMAX, "fixed": L.PIV_PEAK_FIXED_CENTER}[peak]
         p.uod_threshold, p.uod_epsilon = uod_threshold, uod_epsilon
+        p.sgm, p.sgm_p1, p.sgm_p2 = int(bool(sgm)), sgm_p1, sgm_p2
         self.params = p
         h = C.c_void_p()
         L.check(L.lib().piv_plan(C.byref(p), C.byref(h)))

@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpiv.so")
 OBJ = os.path.join(HERE, "_build")
-SOURCES = ["plan.cpp", "predictor.hip", "correct.hip", "postproc.hip", "ssd.hip", "noalloc.hip", "preproc.hip"]
+SOURCES = ["plan.cpp", "predictor.hip", "correct.hip", "postproc.hip", "ssd.hip", "noalloc.hip", "preproc.hip", "sgm.hip"]
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("PIV_OFFLOAD_ARCH", "gfx950")
 

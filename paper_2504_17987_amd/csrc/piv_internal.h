@@ -40,6 +40,9 @@ struct Plan {
   // F32 plans only: per-pair offsets of the refinement's gradient and
   // Gauss-Newton diagonal ([2][ny][nx] each) and window losses ([ny][nx])
   size_t off_gu = 0, off_dd = 0, off_loss = 0;
+  // with semi-global matching: per-pair offsets of the coarsest level's cost
+  // volume and aggregated cost (uint32 [node][candidate] each)
+  size_t off_sgm_c = 0, off_sgm_s = 0;
   size_t per_pair;    // workspace bytes per pair
   uint8_t* ws = nullptr;
   size_t ws_bytes = 0;
@@ -63,6 +66,8 @@ hipError_t launch_pyramid(const Plan& P, const void* A, const void* B, int64_t p
 hipError_t launch_sad_level(const Plan& P, int l, const void* A, const void* B, int64_t pitch,
                             int n, hipStream_t s);
 hipError_t launch_pred_out(const Plan& P, int n, float* pred, hipStream_t s);
+// the coarsest level by semi-global matching into its level field (sgm.hip)
+hipError_t launch_sgm_level(const Plan& P, int n, hipStream_t s);
 // disp_stride: floats per pair of disp (0: 2 nx ny)
 hipError_t launch_correct(const Plan& P, const void* A, const void* B, int64_t pitch, int n,
                           const float* pred, float* disp, float* peak, uint8_t* flags,

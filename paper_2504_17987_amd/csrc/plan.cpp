@@ -72,6 +72,9 @@ void piv_params_default(piv_params* p) {
   p->peak = PIV_PEAK_ARGMAX;
   p->uod_threshold = 2.0f;
   p->uod_epsilon = 0.1f;
+  p->sgm = 0;
+  p->sgm_p1 = 2;
+  p->sgm_p2 = 16;
 }
 
 piv_status piv_plan(const piv_params* pp, piv_plan_t* out) {
@@ -104,6 +107,11 @@ piv_status piv_plan(const piv_params* pp, piv_plan_t* out) {
   // largest predictor displacement: Rc 2^(L-1) + Rf (2^(L-1) - 1); keys hold |d| <= 127
   long reach = (long)p.radius_coarse * (1L << (p.levels - 1)) + (long)p.radius_fine * ((1L << (p.levels - 1)) - 1);
   if (reach > 127) return fail(PIV_EINVAL, "predictor reach %ld px exceeds 127", reach);
+  if (p.sgm != 0 && p.sgm != 1) return fail(PIV_EINVAL, "sgm must be 0 or 1");
+  if (p.sgm && (p.sgm_p1 < 0 || p.sgm_p1 > 255 || p.sgm_p2 < 0 || p.sgm_p2 > 255))
+    return fail(PIV_EINVAL, "sgm penalties outside [0, 255]");
+  if (p.sgm && p.radius_coarse < 1) return fail(PIV_EINVAL, "semi-global matching needs radius_coarse >= 1");
+  if (p.sgm && p.dtype == PIV_F32) return fail(PIV_EUNSUPPORTED, "the predictor takes U8/U16 frames");
   if (p.dtype == PIV_F32 && p.levels > 1)
     return fail(PIV_EUNSUPPORTED, "the integer predictor takes U8/U16 frames (F32 is for the SSD path)");
   if ((block * es) % 4) return fail(PIV_EUNSUPPORTED, "block*bytes_per_pixel must be a multiple of 4");
@@ -156,6 +164,14 @@ piv_status piv_plan(const piv_params* pp, piv_plan_t* out) {
   }
   P->off_raw = off;
   off = align256(off + sizeof(float) * 2 * (size_t)P->nx * P->ny);
+  if (p.sgm) {
+    const piv::Level& c = P->lv[P->L - 1];
+    const size_t cells = (size_t)c.nx * c.ny * (size_t)(2 * c.R + 1) * (2 * c.R + 1);
+    P->off_sgm_c = off;
+    off = align256(off + sizeof(uint32_t) * cells);
+    P->off_sgm_s = off;
+    off = align256(off + sizeof(uint32_t) * cells);
+  }
   if (p.dtype == PIV_F32) {
     const size_t np = (size_t)P->nx * P->ny;
     P->off_gu = off;

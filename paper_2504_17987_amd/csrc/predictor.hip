@@ -1422,6 +1422,7 @@ bool sad_supported(int block_words) {
 // by the streamed or cell-shared u16 kernel (radius 1-2, 12-24 px blocks).
 static bool level0_in_place(const Plan& P, int64_t pitch) {
   const Level& v = P.lv[0];
+  if (P.p.sgm && P.L == 1) return false;   // the semi-global cost reads the padded copy
   const int NW = P.block * P.es / 4;
   if (P.es == 2)   // the streamed u16 kernel (64-bit row addresses)
     return v.R >= 1 && v.R <= 2 && (NW == 6 || NW == 8 || NW == 12);
@@ -1505,6 +1506,7 @@ hipError_t launch_pyramid(const Plan& P, const void* A, const void* B, int64_t p
 
 hipError_t launch_sad_level(const Plan& P, int l, const void* A, const void* B, int64_t pitch, int n,
                             hipStream_t s) {
+  if (P.p.sgm && l == P.L - 1) return launch_sgm_level(P, n, s);
   const Level& v = P.lv[l];
   SadArgs g;
   g.direct = l == 0 && level0_in_place(P, pitch) ? 1 : 0;

@@ -54,6 +54,7 @@ def test_defaults_are_the_papers(L):
     (dict(radius_coarse=30, levels=4), 1), (dict(max_batch=0), 1),
     (dict(dtype=2, bit_depth=10), 1), (dict(dtype=3, levels=3), 2), (dict(block=36), 2),
     (dict(), 0), (dict(dtype=2, bit_depth=12, win=24, step=12, width=3840, height=2160), 0),
+    (dict(sgm=2), 1), (dict(sgm=1, sgm_p2=256), 1), (dict(sgm=1, radius_coarse=0), 1), (dict(sgm=1), 0),
 ])
 def test_plan_validation(L, kw, status):
     s, h = plan(L, **kw)

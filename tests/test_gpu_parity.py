@@ -53,6 +53,16 @@ PRED_CASES = {
     # one-node-per-lane fine level with unaligned block columns
     "block12_step8": (lambda: small_vortex_pair(seed=15)[:2],
                       dict(win=12, step=8, levels=2, radius_coarse=4, radius_fine=2)),
+    # the coarsest level by semi-global matching (three levels, and one level
+    # with a wide search), then block matching below
+    "sgm_vortex_L3": (lambda: small_vortex_pair(seed=16)[:2],
+                      dict(win=16, step=8, levels=3, radius_coarse=6, radius_fine=2, sgm=True)),
+    "sgm_cfg1_L1": (lambda: synth.cfg1_pair(1002)[:2],
+                    dict(win=32, step=16, levels=1, radius_coarse=8, radius_fine=2, radius=8, sgm=True,
+                         sgm_p1=1, sgm_p2=8)),
+    "sgm_ragged_L2": (lambda: small_vortex_pair(200, 136, seed=17)[:2],
+                      dict(win=16, step=8, levels=2, radius_coarse=5, radius_fine=2, sgm=True, sgm_p1=4,
+                           sgm_p2=40)),
 }
 
 
@@ -66,9 +76,10 @@ def test_predict_bitexact(case):
     Ad, Bd = dev(np.stack([A, B])), dev(np.stack([B, A]))   # two pairs: (A,B) and (B,A)
     pred = P.predict(Ad, Bd).cpu().numpy()
     blk = kw.get("block", 0) or kw["win"]
+    sgm = (kw.get("sgm_p1", 2), kw.get("sgm_p2", 16)) if kw.get("sgm") else None
     for i, (a, b) in enumerate([(A, B), (B, A)]):
         ref = oracle.predict(a, b, kw["step"], blk, kw["levels"], kw["radius_coarse"],
-                             kw["radius_fine"], kw.get("median", True))
+                             kw["radius_fine"], kw.get("median", True), sgm)
         assert np.array_equal(pred[i], ref.astype(np.float32)), f"pair {i}"
 
 
@@ -80,6 +91,32 @@ def test_predict_u16_bitexact():
                      dev(B[None].view(np.int16)).view(torch.uint16)).cpu().numpy()[0]
     ref = oracle.predict(A, B, 12, 24, 3, 6, 2)
     assert np.array_equal(pred, ref.astype(np.float32))
+
+
+def test_predict_u16_sgm_bitexact():
+    say("[predict] u16 step 12, semi-global coarsest level")
+    A, B, _ = synth.cfg3_pair(2, W=384, H=216)
+    P = api().Plan(384, 216, dtype="u16", win=24, step=12, levels=3, radius_coarse=6, radius_fine=2, sgm=True)
+    pred = P.predict(dev(A[None].view(np.int16)).view(torch.uint16),
+                     dev(B[None].view(np.int16)).view(torch.uint16)).cpu().numpy()[0]
+    ref = oracle.predict(A, B, 12, 24, 3, 6, 2, sgm=(2, 16))
+    assert np.array_equal(pred, ref.astype(np.float32))
+
+
+def test_run_end_to_end_sgm_predictor():
+    """The whole path with the semi-global coarsest level (strong vortex),
+    stage by stage against the oracle; accuracy against the truth reported
+    beside the block-matching predictor's."""
+    say("[run] semi-global predictor, strong vortex")
+    flow = synth.LambOseen.with_peak(127.5, 95.5, 40.0, 8.0)
+    A, B = synth.make_pair(256, 192, flow, 0.04, noise=2.0, dropout=0.1, seed=7)
+    kw = dict(win=16, step=8, radius=4, levels=3, radius_coarse=6, radius_fine=2)
+    g, o = _run_both(A, B, dict(kw, sgm=True), "run[sgm]", sgm=(2, 16))
+    T = synth.truth(flow, 256, 192, 8)
+    e = lambda d: np.sqrt(((d - T)[:, 2:-2, 2:-2] ** 2).mean())
+    ob = oracle.run(A, B, win=16, step=8, r=4, levels=3, Rc=6, Rf=2)
+    say(f"  vs truth: rms {e(g['disp']):.3f} px with the semi-global level, {e(ob['disp']):.3f} px with block "
+        f"matching")
 
 
 @pytest.mark.parametrize("W,H,step,win", [(200, 136, 8, 16), (204, 204, 12, 24)])
@@ -363,7 +400,7 @@ def test_vorticity_parity():
     assert np.abs(om - 0.02).max() < 1e-4 * 0.02 + 1e-6
 
 
-def _run_both(A, B, kw, where, peak_mode=0):
+def _run_both(A, B, kw, where, peak_mode=0, sgm=None):
     """The whole path on the GPU (piv_run) and in the oracle, compared stage
     by stage on identical inputs, every difference explained:
     the predictor bit-exact; the raw correction (piv_correct on the run's
@@ -381,7 +418,7 @@ def _run_both(A, B, kw, where, peak_mode=0):
     g = {k: v.cpu().numpy()[0] for k, v in out.items()}
     raw, peak, flags = raw.cpu().numpy()[0], peak.cpu().numpy()[0], flags.cpu().numpy()[0]
     o = oracle.run(A, B, win=kw["win"], step=kw["step"], r=kw["radius"], levels=kw["levels"],
-                   Rc=kw["radius_coarse"], Rf=kw["radius_fine"], peak_mode=peak_mode)
+                   Rc=kw["radius_coarse"], Rf=kw["radius_fine"], peak_mode=peak_mode, sgm=sgm)
     assert np.array_equal(g["pred"], o["pred"].astype(np.float32)), f"{where}: predictor"
     raw_ex = compare_correct(None, None, A.astype(float), B.astype(float), kw["win"], kw["step"], kw["radius"],
                              o["pred"], raw, peak, flags, o["disp_raw"], o["peak"], o["flags_raw"],
