@@ -299,6 +299,23 @@ __device__ __forceinline__ void ssd_residual(const SsdArgs& a, const float* A, c
   gy = (1.0f - ex) * (p10 - p00) + ex * (p11 - p01);
 }
 
+// residual and floor-cell gradient at region pixel (i, j) for a given
+// displacement (u, v) of that pixel
+__device__ __forceinline__ void ssd_residual_uv(const SsdArgs& a, const float* A, const float* B, int ylo, int xlo,
+                                                int i, int j, float u, float v, float& r, float& gx, float& gy) {
+  const int x = xlo + j, y = ylo + i;
+  const float qx = (float)x + u, qy = (float)y + v;
+  const float x0 = floorf(qx), y0 = floorf(qy);
+  const float ex = qx - x0, ey = qy - y0;
+  const int ix = (int)x0, iy = (int)y0;
+  const float p00 = ldA(B, a.W, a.H, iy, ix), p01 = ldA(B, a.W, a.H, iy, ix + 1);
+  const float p10 = ldA(B, a.W, a.H, iy + 1, ix), p11 = ldA(B, a.W, a.H, iy + 1, ix + 1);
+  const float bs = (1.0f - ey) * ((1.0f - ex) * p00 + ex * p01) + ey * ((1.0f - ex) * p10 + ex * p11);
+  r = bs - ldA(A, a.W, a.H, y, x);
+  gx = (1.0f - ey) * (p01 - p00) + ey * (p11 - p10);
+  gy = (1.0f - ex) * (p10 - p00) + ex * (p11 - p01);
+}
+
 // Forward, TN x TN windows per workgroup: squared residuals of the tile's
 // pixel region in LDS, then 4 threads per window sum its block.
 template <int STEP, int TN>
@@ -364,6 +381,7 @@ __global__ __launch_bounds__(256) void k_ssd_backward_t(SsdArgs a) {
   __shared__ float s_part[C::RW][NCH][8];              // [row][chunk][term*2 + side]
   __shared__ float s_g[C::NG][C::NG];                  // upstream window gradients
   __shared__ int s_chb[NCH];                           // base node column of a chunk
+  __shared__ int s_rfirst[C::NNC], s_rlast[C::NNC];    // region rows based on each cached node row
   const WgIdx wg = xcd_order();
   const int pair = wg.z;
   if (slot_off(a.mask, pair)) return;
@@ -392,8 +410,15 @@ __global__ __launch_bounds__(256) void k_ssd_backward_t(SsdArgs a) {
     s_g[r][q] = (gi < a.ny && gj < a.nx) ? (G ? G[gi * a.nx + gj] : 1.0f) : 0.0f;
   }
   int nly, nlx;
-  ssd_prepare<STEP, TN>(a, U, ylo, xlo, RH, RWc, sh, nly, nlx);
+  if (t < C::NNC) s_rfirst[t] = s_rlast[t] = -1;
+  ssd_prepare<STEP, TN>(a, U, ylo, xlo, RH, RWc, sh, nly, nlx);   // (ends with a barrier)
   if (t < NCH) s_chb[t] = t * STEP < RWc ? sh.cb[t * STEP] : -100;
+  for (int i = t; i < RH; i += 256) {
+    const int rb = sh.rb[i];
+    if (i == 0 || sh.rb[i - 1] != rb) s_rfirst[rb] = i;
+    if (i == RH - 1 || sh.rb[i + 1] != rb) s_rlast[rb] = i;
+  }
+  __syncthreads();
   const int nchunks = (RWc + STEP - 1) / STEP;
   for (int item = t; item < RH * nchunks; item += 256) {
     const int i = item / nchunks, c = item - (item / nchunks) * nchunks;
@@ -409,12 +434,22 @@ __global__ __launch_bounds__(256) void k_ssd_backward_t(SsdArgs a) {
 #pragma unroll
     for (int k = 0; k < 8; ++k) acc[k] = 0.0f;
     if (m != 0.0f) {
+      // the chunk's pixels share their node row and node columns (it starts
+      // on a cell boundary), so the node field is interpolated down the
+      // two node columns once and across per pixel
+      const int rb = sh.rb[i], cbase = s_chb[c];
+      const float fy = sh.rf[i];
+      const float uL = sh.node[0][rb][cbase] + fy * (sh.node[0][rb + 1][cbase] - sh.node[0][rb][cbase]);
+      const float uR = sh.node[0][rb][cbase + 1] + fy * (sh.node[0][rb + 1][cbase + 1] - sh.node[0][rb][cbase + 1]);
+      const float vL = sh.node[1][rb][cbase] + fy * (sh.node[1][rb + 1][cbase] - sh.node[1][rb][cbase]);
+      const float vR = sh.node[1][rb][cbase + 1] + fy * (sh.node[1][rb + 1][cbase + 1] - sh.node[1][rb][cbase + 1]);
 #pragma unroll
       for (int e = 0; e < STEP; ++e) {
         const int j = c * STEP + e;
         if (j < RWc) {
           float r, gx, gy;
-          ssd_residual<STEP, TN>(a, A, B, sh, ylo, xlo, i, j, r, gx, gy);
+          const float fxp = sh.cf[j];
+          ssd_residual_uv(a, A, B, ylo, xlo, i, j, uL + fxp * (uR - uL), vL + fxp * (vR - vL), r, gx, gy);
           const float f = sh.cf[j], wl = a.nx > 1 ? 1.0f - f : 1.0f, wr = a.nx > 1 ? f : 0.0f;
           const float t0 = 2.0f * m * r * gx, t1 = 2.0f * m * r * gy;
           const float t2 = 2.0f * m * gx * gx, t3 = 2.0f * m * gy * gy;
@@ -439,11 +474,13 @@ __global__ __launch_bounds__(256) void k_ssd_backward_t(SsdArgs a) {
     const int rbn = na - nly;
     const bool sq = term >= 2;
     // base rows and chunk bases do not decrease along the region: the rows
-    // and chunks that touch the node are contiguous runs
+    // and chunks that touch the node are contiguous runs (rows: those based
+    // on the node's row and, with more than one node row, on the row before)
     int rf = RH, rl = -1, cf0 = nchunks, cl = -1;
-    for (int i = 0; i < RH; ++i) {
-      const int rb = sh.rb[i];
-      if (rb == rbn || (a.ny > 1 && rb + 1 == rbn)) { rf = min(rf, i); rl = i; }
+    if (rbn >= 0 && rbn < C::NNC && s_rfirst[rbn] >= 0) { rf = s_rfirst[rbn]; rl = s_rlast[rbn]; }
+    if (a.ny > 1 && rbn >= 1 && rbn - 1 < C::NNC && s_rfirst[rbn - 1] >= 0) {
+      rf = min(rf, s_rfirst[rbn - 1]);
+      rl = max(rl, s_rlast[rbn - 1]);
     }
     for (int c = 0; c < nchunks; ++c) {
       const int base = s_chb[c];
