@@ -55,6 +55,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-latency", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the graph/serving/stream/SSD forms")
+    ap.add_argument("--forms", default="all",
+                    help="comma-separated forms to run beside the headline (default all): cfg1_256, "
+                         "graph_batched_cfg2, preprocess_cfg2, sgm_predictor_cfg2, stream_cfg3, ssd_cfg4, "
+                         "largest_8192x4096, low_seeding_wake, served_cfg5")
     ap.add_argument("--serve-seconds", type=float, default=2.0, help="seconds of arrivals per load point")
     ap.add_argument("--serve-first-scale", type=float, default=1.0,
                     help="the first (3,000 pairs/s) load point runs this many times longer")
@@ -564,6 +568,38 @@ def preprocess_cfg2(torch, api, A, log_fn, reps=20):
             "frames_per_s_both": round(n / ((h_ms + c_ms) / 1e3), 1)}
 
 
+def sgm_predictor(torch, api, A, B, kw, T, nd, args, log_fn):
+    """The headline workload with the predictor's coarsest level searched by
+    semi-global matching (penalties 2 and 16 per block pixel) instead of
+    block matching: the whole path per batch of 64 and the predictor alone,
+    with the accuracy against the truth beside the block-matching path's."""
+    nb = A.shape[0]
+    res = {}
+    for name, extra in (("block_matching", {}), ("semi_global", dict(sgm=True, sgm_p1=2, sgm_p2=16))):
+        P = api.Plan(1024, 1024, max_batch=nb, **kw, **extra)
+        out = P.run(A, B)
+        pred = P.predict(A, B)
+        torch.cuda.synchronize()
+        e = events(torch, 3)
+        reps = max(5, args.steps // 2)
+        e[0].record()
+        for _ in range(reps):
+            P.run(A, B, out)
+        e[1].record()
+        for _ in range(reps):
+            P.predict(A, B, pred)
+        e[2].record()
+        torch.cuda.synchronize()
+        run_ms, pred_ms = e[0].elapsed_time(e[1]) / reps, e[1].elapsed_time(e[2]) / reps
+        err = (out["disp"][:nd].cpu().numpy() - T[None])[:, :, 2:-2, 2:-2]
+        res[name] = {"path_ms": round(run_ms, 4), "pairs_per_s": round(nb / (run_ms / 1e3), 1),
+                     "predictor_ms": round(pred_ms, 4), "rms_vs_truth_px": round(float(np.sqrt((err ** 2).mean())), 4)}
+    log_fn(f"semi-global predictor: path {res['semi_global']['path_ms']:.3f} ms per 64 pairs (block matching "
+           f"{res['block_matching']['path_ms']:.3f}), rms {res['semi_global']['rms_vs_truth_px']:.3f} px "
+           f"(block matching {res['block_matching']['rms_vs_truth_px']:.3f})")
+    return {"batch": nb, "penalties_per_block_pixel": [2, 16], **res}
+
+
 def low_seeding_study(torch, api, log_fn, inputs, seeds):
     """The paper's low-seeding case (Sec. 3.2, Sec. 4.3: a cylinder wake at
     low particle concentration, 32 x 32 windows at 50% step-over), on a
@@ -764,16 +800,28 @@ def main():
 
     forms = {}
     if not args.no_extras:
-        forms["cfg1_256"] = cfg1_forms(torch, api, lg, inputs)
-        forms["graph_batched_cfg2"] = graph_batched(torch, api, A, B, kw, args)
-        lg(f"graph batches of 8: {forms['graph_batched_cfg2']['pairs_per_s']:.0f} pairs/s "
-           f"(two graphs in flight {forms['graph_batched_cfg2']['pairs_per_s_two_in_flight']:.0f})")
-        forms["preprocess_cfg2"] = preprocess_cfg2(torch, api, A, lg)
-        forms["stream_cfg3"] = stream_cfg3(torch, api, synth, lg, inputs)
-        forms["ssd_cfg4"] = ssd_cfg4(torch, api, lg, inputs)
-        forms["largest_8192x4096"] = largest(torch, api, synth, kw, lg)
-        forms["low_seeding_wake"] = low_seeding_study(torch, api, lg, inputs, [7000 + k for k in range(4)])
-        forms["served_cfg5"] = served(torch, api, synth, kw, args, lg, inputs)
+        want = None if args.forms == "all" else set(args.forms.split(","))
+        run = lambda name: want is None or name in want
+        if run("cfg1_256"):
+            forms["cfg1_256"] = cfg1_forms(torch, api, lg, inputs)
+        if run("graph_batched_cfg2"):
+            forms["graph_batched_cfg2"] = graph_batched(torch, api, A, B, kw, args)
+            lg(f"graph batches of 8: {forms['graph_batched_cfg2']['pairs_per_s']:.0f} pairs/s "
+               f"(two graphs in flight {forms['graph_batched_cfg2']['pairs_per_s_two_in_flight']:.0f})")
+        if run("preprocess_cfg2"):
+            forms["preprocess_cfg2"] = preprocess_cfg2(torch, api, A, lg)
+        if run("sgm_predictor_cfg2"):
+            forms["sgm_predictor_cfg2"] = sgm_predictor(torch, api, A, B, kw, T, nd, args, lg)
+        if run("stream_cfg3"):
+            forms["stream_cfg3"] = stream_cfg3(torch, api, synth, lg, inputs)
+        if run("ssd_cfg4"):
+            forms["ssd_cfg4"] = ssd_cfg4(torch, api, lg, inputs)
+        if run("largest_8192x4096"):
+            forms["largest_8192x4096"] = largest(torch, api, synth, kw, lg)
+        if run("low_seeding_wake"):
+            forms["low_seeding_wake"] = low_seeding_study(torch, api, lg, inputs, [7000 + k for k in range(4)])
+        if run("served_cfg5"):
+            forms["served_cfg5"] = served(torch, api, synth, kw, args, lg, inputs)
 
     path_gbs = alg["path_bytes"] * nb / (ms_per_step / 1e3) / 1e9
     line = {
