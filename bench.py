@@ -64,6 +64,9 @@ def parse():
                     help="the first (3,000 pairs/s) load point runs this many times longer")
     ap.add_argument("--serve-rates", type=float, nargs="+", default=[3000.0, 6000.0, 12000.0, 24000.0],
                     help="offered loads (pairs/s, all 12 streams together)")
+    ap.add_argument("--form-reps", type=int, default=None, metavar="K",
+                    help="timed repetitions in the pre-processing, semi-global and SSD forms (default: "
+                         "each form's own; a small K keeps counter-collection runs short)")
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="first run three plain device-to-device copies of MIB MiB (a known-size "
@@ -484,7 +487,7 @@ def largest(torch, api, synth, kw, log_fn, n=4, reps=10):
             "pairs_per_s_two_in_flight": round(pps2, 1), "mvec_per_s": round(pps * 1024 * 512 / 1e6, 1)}
 
 
-def ssd_cfg4(torch, api, log_fn, inputs, n=64, distinct=8):
+def ssd_cfg4(torch, api, log_fn, inputs, n=64, distinct=8, reps=20):
     """64 pairs of 512x512 f32: forward and backward of the windowed SSD,
     and 10 steps of the on-device refinement (piv_ssd_refine) with its
     loss history."""
@@ -504,7 +507,7 @@ def ssd_cfg4(torch, api, log_fn, inputs, n=64, distinct=8):
     P.ssd_refine(A, B, Ur, steps=10, hist=hist)
     torch.cuda.synchronize()
     e = events(torch, 4)
-    reps = 20
+    nref = min(3, reps)
     e[0].record()
     for _ in range(reps):
         P.ssd_forward(A, B, U, loss)
@@ -512,13 +515,13 @@ def ssd_cfg4(torch, api, log_fn, inputs, n=64, distinct=8):
     for _ in range(reps):
         P.ssd_backward(A, B, U, g, gU, D)
     e[2].record()
-    for _ in range(3):
+    for _ in range(nref):
         Ur.copy_(U)
         P.ssd_refine(A, B, Ur, steps=10, hist=hist)
     e[3].record()
     torch.cuda.synchronize()
     f_ms, b_ms = e[0].elapsed_time(e[1]) / reps, e[1].elapsed_time(e[2]) / reps
-    r_ms = e[2].elapsed_time(e[3]) / 3
+    r_ms = e[2].elapsed_time(e[3]) / nref
     img = 512 * 512 * 4
     fwd_bytes = n * (2 * img + 2 * 64 * 64 * 4 + 64 * 64 * 4)
     bwd_bytes = n * (2 * img + 2 * 64 * 64 * 4 + 64 * 64 * 4 + 4 * 64 * 64 * 4)
@@ -581,7 +584,7 @@ def sgm_predictor(torch, api, A, B, kw, T, nd, args, log_fn):
         pred = P.predict(A, B)
         torch.cuda.synchronize()
         e = events(torch, 3)
-        reps = max(5, args.steps // 2)
+        reps = args.form_reps or max(5, args.steps // 2)
         e[0].record()
         for _ in range(reps):
             P.run(A, B, out)
@@ -809,13 +812,13 @@ def main():
             lg(f"graph batches of 8: {forms['graph_batched_cfg2']['pairs_per_s']:.0f} pairs/s "
                f"(two graphs in flight {forms['graph_batched_cfg2']['pairs_per_s_two_in_flight']:.0f})")
         if run("preprocess_cfg2"):
-            forms["preprocess_cfg2"] = preprocess_cfg2(torch, api, A, lg)
+            forms["preprocess_cfg2"] = preprocess_cfg2(torch, api, A, lg, reps=args.form_reps or 20)
         if run("sgm_predictor_cfg2"):
             forms["sgm_predictor_cfg2"] = sgm_predictor(torch, api, A, B, kw, T, nd, args, lg)
         if run("stream_cfg3"):
             forms["stream_cfg3"] = stream_cfg3(torch, api, synth, lg, inputs)
         if run("ssd_cfg4"):
-            forms["ssd_cfg4"] = ssd_cfg4(torch, api, lg, inputs)
+            forms["ssd_cfg4"] = ssd_cfg4(torch, api, lg, inputs, reps=args.form_reps or 20)
         if run("largest_8192x4096"):
             forms["largest_8192x4096"] = largest(torch, api, synth, kw, lg)
         if run("low_seeding_wake"):
