@@ -67,6 +67,10 @@ def parse():
     ap.add_argument("--form-reps", type=int, default=None, metavar="K",
                     help="timed repetitions in the pre-processing, semi-global and SSD forms (default: "
                          "each form's own; a small K keeps counter-collection runs short)")
+    ap.add_argument("--cfg3-pairs", type=int, default=500, metavar="N",
+                    help="pairs through the 4K u16 stream form (default 500; a few keep counter runs short)")
+    ap.add_argument("--render-workers", type=int, default=16,
+                    help="processes that render the synthetic inputs (1: in this process, e.g. under a profiler)")
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="first run three plain device-to-device copies of MIB MiB (a known-size "
@@ -182,12 +186,13 @@ def _render(job):
     raise KeyError(kind)
 
 
-def render_all(jobs, log_fn):
+def render_all(jobs, log_fn, workers=16):
     """Render every input in a pool of worker processes (forked before the
-    GPU is initialised; the workers only run numpy)."""
+    GPU is initialised; the workers only run numpy); workers <= 1 renders in
+    this process."""
     import multiprocessing as mp
     t0 = time.perf_counter()
-    n = min(16, os.cpu_count() or 1, len(jobs))
+    n = min(workers, os.cpu_count() or 1, len(jobs))
     if n <= 1:
         out = [_render(j) for j in jobs]
     else:
@@ -656,10 +661,19 @@ def main():
     # touched (the renderers run in forked worker processes)
     jobs = [("cfg2", 2000 + i) for i in range(nd)]
     if not args.no_extras:
-        jobs += [("cfg1", 1000)] + [("cfg3", k) for k in range(16)] + [("cfg4", k) for k in range(8)]
-        jobs += [("cfg5", s, k) for s in range(12) for k in range(SERVE_PER_STREAM)]
-        jobs += [("wake", 7000 + k, 0.002) for k in range(4)]
-    inputs = render_all(jobs, lg)
+        want = None if args.forms == "all" else set(args.forms.split(","))
+        need = lambda name: want is None or name in want
+        if need("cfg1_256"):
+            jobs += [("cfg1", 1000)]
+        if need("stream_cfg3"):
+            jobs += [("cfg3", k) for k in range(16)]
+        if need("ssd_cfg4"):
+            jobs += [("cfg4", k) for k in range(8)]
+        if need("served_cfg5"):
+            jobs += [("cfg5", s, k) for s in range(12) for k in range(SERVE_PER_STREAM)]
+        if need("low_seeding_wake"):
+            jobs += [("wake", 7000 + k, 0.002) for k in range(4)]
+    inputs = render_all(jobs, lg, args.render_workers)
     pairs = [inputs[("cfg2", 2000 + i)] for i in range(nd)]
     cpu = ref0 = None
     if not args.no_cpu_baseline:
@@ -816,7 +830,7 @@ def main():
         if run("sgm_predictor_cfg2"):
             forms["sgm_predictor_cfg2"] = sgm_predictor(torch, api, A, B, kw, T, nd, args, lg)
         if run("stream_cfg3"):
-            forms["stream_cfg3"] = stream_cfg3(torch, api, synth, lg, inputs)
+            forms["stream_cfg3"] = stream_cfg3(torch, api, synth, lg, inputs, npairs=args.cfg3_pairs)
         if run("ssd_cfg4"):
             forms["ssd_cfg4"] = ssd_cfg4(torch, api, lg, inputs, reps=args.form_reps or 20)
         if run("largest_8192x4096"):

@@ -1044,6 +1044,7 @@ void k_correct_bands(CorrArgs g) {
   __shared__ __align__(16) float sB[C::BH * C::BP];
   __shared__ __align__(16) float s_un[C::UNION];
   __shared__ float s_node[2][C::NNY][C::NNX];
+  __shared__ float s_asum[2][ES == 1 ? 1 : C::NG][64];   // u16 cell sums, per wave
 
   const WgIdx wg = xcd_order();
   const int pair = wg.z;
@@ -1213,10 +1214,28 @@ void k_correct_bands(CorrArgs g) {
 #pragma unroll
     for (int k = 0; k < NWR; ++k) {
       if constexpr (ES == 1) isum = (int)__builtin_amdgcn_sad_u8(aw[py][k], 0u, (uint32_t)isum);
-      else isum += (int)(aw[py][k] & 0xffffu) + (int)(aw[py][k] >> 16);
+      else isum = (int)__builtin_amdgcn_sad_u16(aw[py][k], 0u, (uint32_t)isum);
     }
   isum = wave_sum(isum);
   const float K = (float)((isum + C::AH * C::AW / 2) / (C::AH * C::AW));   // (isum >= 0)
+  // u16: the cell's sums of (A-K) and (A-K)^2 in FP32, rows dealt to the
+  // waves (row py to wave py mod NG); the partial sums meet in LDS
+  if constexpr (ES != 1) {
+    float s1 = 0.0f, s2 = 0.0f;
+#pragma unroll
+    for (int py = 0; py < STEP; ++py) {
+      if (py % C::NG != band) continue;
+#pragma unroll
+      for (int x = 0; x < STEP; ++x) {
+        const uint32_t wd = aw[py][(x * ES) >> 2];
+        const float d = (float)((wd >> (16 * (x & 1))) & 0xffffu) - K;
+        s1 += d;
+        s2 += d * d;
+      }
+    }
+    s_asum[0][band][lane] = s1;
+    s_asum[1][band][lane] = s2;
+  }
   __syncthreads();
 
   // deformed B' tile, in groups of four pixels of one row
@@ -1232,7 +1251,9 @@ void k_correct_bands(CorrArgs g) {
     const int ixhi = ix1 - 1 - ix0, iyhi = iy1 - 1 - iy0;
     const int xadd = ix0 * ES - xoff;   // byte offset of box column 0 in a staged row
     const uint8_t* rawx = rawb + xadd;  // (folded into the base: one multiply-add per pixel)
-    for (int idx = t; idx < C::BH * BQ; idx += NT) {
+    // one group of four pixels; two groups per pass, so that one group's
+    // LDS round trips overlap the other's arithmetic
+    auto group = [&](int idx) __attribute__((always_inline)) {
       const int r = idx / BQ, q = 4 * (idx - (idx / BQ) * BQ);
       float uu[4] = {0.0f, 0.0f, 0.0f, 0.0f}, vv[4] = {0.0f, 0.0f, 0.0f, 0.0f};
       if (Pn) {
@@ -1283,7 +1304,14 @@ void k_correct_bands(CorrArgs g) {
         out[e] = (top + fy * (bot - top)) - K;
       }
       *reinterpret_cast<float4*>(sB + r * C::BP + q) = make_float4(out[0], out[1], out[2], out[3]);
+    };
+    constexpr int NGR = C::BH * BQ;
+    int idx = t;
+    for (; idx + NT < NGR; idx += 2 * NT) {
+      group(idx);
+      group(idx + NT);
     }
+    if (idx < NGR) group(idx);
   } else {
     for (int idx = t; idx < C::BH * C::BW; idx += NT) {
       const int r = idx / C::BW, q = idx - (idx / C::BW) * C::BW;
@@ -1305,8 +1333,9 @@ void k_correct_bands(CorrArgs g) {
   }
   __syncthreads();
 
-  // ---- this lane's cell against the wave's shift band: P = sum (A-K)(B'-K),
+  // ---- this lane's cell against the wave's shift band: P = sum A (B'-K),
   // S = sum (B'-K), Q = sum (B'-K)^2, and the cell's own sum (A-K), (A-K)^2
+  // (the covariance sum (A-K)(B'-K) - mean(A-K) S equals P - mean(A) S)
   constexpr int BRW = STEP + 2 * R;   // B' columns one cell row needs
   float Pacc[SYG][C::NSY], Sacc[SYG][C::NSY], Qacc[SYG][C::NSY];
   float sa = 0.0f, saa = 0.0f;
@@ -1323,6 +1352,12 @@ void k_correct_bands(CorrArgs g) {
     const int Ki = (int)K;
     sa = (float)((int)s1 - STEP * STEP * Ki);
     saa = (float)((int)s2 - 2 * Ki * (int)s1 + STEP * STEP * Ki * Ki);
+  } else {
+#pragma unroll
+    for (int q = 0; q < C::NG; ++q) {
+      sa += s_asum[0][q][lane];
+      saa += s_asum[1][q][lane];
+    }
   }
   // (with large cells the S/Q column sums take a second pass over the band's
   // rows, after the products, so that their registers and the A cell's are
@@ -1353,11 +1388,7 @@ void k_correct_bands(CorrArgs g) {
         for (int x = 0; x < STEP; ++x) {
           const uint32_t wd = aw[rb][(x * ES) >> 2];
           const uint32_t px = ES == 1 ? (wd >> (8 * (x & 3))) & 0xffu : (wd >> (16 * (x & 1))) & 0xffffu;
-          an[x] = (float)px - K;
-          if constexpr (ES != 1) {
-            sa += an[x];
-            saa += an[x] * an[x];
-          }
+          an[x] = (float)px;   // raw A: the offset K enters through the mean below
         }
         if constexpr (!kSplitSQ) {
 #pragma unroll
@@ -1453,9 +1484,10 @@ void k_correct_bands(CorrArgs g) {
   float* const s_best = s_un + C::NWIN * C::NS;  // [band][window]
   int* const s_pk = reinterpret_cast<int*>(s_best + C::NG * C::NWIN);
   {
-    const float n = (float)(4 * STEP * STEP);
-    const float mA = sa / n;
+    constexpr float kInvN = 1.0f / (float)(4 * STEP * STEP);
+    const float mA = sa * kInvN;
     const float varA = saa - sa * mA;
+    const float meanA = K + mA;
     const bool flatA = !(varA > kFlatRel * saa);
     // coefficients first (no control flow), then the band's peak
     float rv[SYG][C::NSY];
@@ -1465,8 +1497,8 @@ void k_correct_bands(CorrArgs g) {
 #pragma unroll
       for (int j = 0; j < C::NSY; ++j) {
         const int sy = band * SYG + k - R, sx = j - R;
-        const float num = Pacc[k][j] - mA * Sacc[k][j];
-        const float varB = Qacc[k][j] - Sacc[k][j] * Sacc[k][j] / n;
+        const float num = Pacc[k][j] - meanA * Sacc[k][j];
+        const float varB = Qacc[k][j] - Sacc[k][j] * Sacc[k][j] * kInvN;
         const bool flat = flatA || !(varB > kFlatRel * Qacc[k][j]);
         // (varA varB > 0 unless flat; the flat value replaces the quotient)
         const float r = num * __builtin_amdgcn_rsqf(varA * varB);
