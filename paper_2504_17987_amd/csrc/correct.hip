@@ -1167,7 +1167,9 @@ void k_correct_bands(CorrArgs g) {
     const int rowbytes = g.W * ES;
     const int rstep = NT / nwords;
     const int r0 = t / nwords, w = t - r0 * nwords;
-    constexpr int U = 8;
+    // reads in flight per thread: enough for the whole box in one round
+    // (about 9 rows per thread at step 8 u8, 33 at step 12 u16)
+    constexpr int U = STEP == 8 ? 12 : 36;
     const bool inside = off32 && iy0 >= 0 && iy0 + nrows <= g.H && xw0 >= 0 && 4 * (xw0 + nwords) <= rowbytes;
     if (r0 < rstep) {
       // slots past the box take its last row again (the same word is
@@ -1533,8 +1535,12 @@ void k_correct_bands(CorrArgs g) {
   }
   __syncthreads();
   // ---- peak over the bands, fit, composition with the predictor's window mean
-  if (t < C::NWIN) {
-    const int wi = t / TW, wj = t - (t / TW) * TW;
+  // (the windows are dealt to the waves, so that the fits of one tile run
+  // side by side instead of in one wave while the others have finished)
+  constexpr int WPW = (C::NWIN + C::NG - 1) / C::NG;   // windows per wave
+  const int wt = band * WPW + lane;
+  if (lane < WPW && wt < C::NWIN) {
+    const int wi = wt / TW, wj = wt - (wt / TW) * TW;
     const int a = a0 + wi, b = b0 + wj;
     if (a < g.ny && b < g.nx) {
       float best = -2.0f;
@@ -1542,8 +1548,8 @@ void k_correct_bands(CorrArgs g) {
       bool allflat = true;
 #pragma unroll
       for (int q = 0; q < C::NG; ++q) {
-        const float bq = s_best[q * C::NWIN + t];
-        const int pk = s_pk[q * C::NWIN + t];
+        const float bq = s_best[q * C::NWIN + wt];
+        const int pk = s_pk[q * C::NWIN + wt];
         allflat = allflat && (pk & 1);
         if (better(bq, pk >> 1, best, bkey)) {
           best = bq;
@@ -1555,7 +1561,7 @@ void k_correct_bands(CorrArgs g) {
         sx = (bkey & 63) - 32;
         sy = ((bkey >> 6) & 63) - 32;
       }
-      const float* rr = rhoW + t * C::NS;
+      const float* rr = rhoW + wt * C::NS;
       auto rhof = [&](int y, int x) { return rr[(y + R) * C::NSY + x + R]; };
       auto node = [&](int c, int y, int x) { return s_node[c][y - nlo_y][x - nlo_x]; };
       float pu = 0.0f, pv = 0.0f;

@@ -68,6 +68,7 @@ hipError_t launch_sad_level(const Plan& P, int l, const void* A, const void* B, 
 hipError_t launch_pred_out(const Plan& P, int n, float* pred, hipStream_t s);
 // the coarsest level by semi-global matching into its level field (sgm.hip)
 hipError_t launch_sgm_level(const Plan& P, int n, hipStream_t s);
+hipError_t launch_sad_cost_cells(const Plan& P, uint32_t* C, int64_t cstride, int n, hipStream_t s);
 // disp_stride: floats per pair of disp (0: 2 nx ny)
 hipError_t launch_correct(const Plan& P, const void* A, const void* B, int64_t pitch, int n,
                           const float* pred, float* disp, float* peak, uint8_t* flags,

@@ -222,6 +222,10 @@ struct SadArgs {
   const uint8_t* srcB;
   int64_t spitch, sstride;
   int W, H;               // level size (px)
+  // cost-volume mode of k_sad_cells (semi-global matching): every node's SAD
+  // for every shift, [pair][node][(dy+R)(2R+1) + dx+R], pair stride cstride
+  uint32_t* cost;
+  int64_t cstride;
   int direct;
 };
 
@@ -454,7 +458,7 @@ __global__ __launch_bounds__(256) void k_sad_q(SadArgs g) {
 // below (lane + 9); four cells stay below 2^16, so the packed fields add
 // without carries.  Winner: the least (SAD, |dx|+|dy|, dy, dx).
 // ---------------------------------------------------------------------------
-template <int R, int DYG>
+template <int R, int DYG, bool kCost = false>
 __global__ __launch_bounds__(256) void k_sad_cells(SadArgs g) {
   constexpr int G = 2 * R + 1, NGRP = (G + 3) / 4, REM = G - 4 * (NGRP - 1);
   constexpr bool TAIL = REM <= 2;           // last group by full-rate v_sad_u8
@@ -491,6 +495,9 @@ __global__ __launch_bounds__(256) void k_sad_cells(SadArgs g) {
   const int node_a = ty * (CH - 1) + lr, node_b = tx * (CW - 1) + lc;
   const bool node = lr < CH - 1 && lc < CW - 1 && node_a < g.ny && node_b < g.nx;
   uint32_t best = ~0u;
+  // (cost mode: this node's row of the cost volume)
+  uint32_t* const crow = kCost && node ? g.cost + (int64_t)pair * g.cstride + (int64_t)(node_a * g.nx + node_b) * (G * G)
+                                       : nullptr;
 #pragma unroll
   for (int ps = 0; ps < NPASS; ++ps) {
     const int k0 = ps * DYG;                 // first shift row of the pass
@@ -552,7 +559,11 @@ __global__ __launch_bounds__(256) void k_sad_cells(SadArgs g) {
           if (c >= G) continue;
           const uint32_t sad = ((f < 2 ? lo : hi) >> (16 * (f & 1))) & 0xffffu;
           const int dx = c - R;
-          best = min(best, (sad << 12) | (kdy + ((uint32_t)abs(dx) << 8)) | (uint32_t)(dx + R));
+          if constexpr (kCost) {
+            if (node) crow[(dy + R) * G + c] = sad;
+          } else {
+            best = min(best, (sad << 12) | (kdy + ((uint32_t)abs(dx) << 8)) | (uint32_t)(dx + R));
+          }
         }
       }
       if constexpr (TAIL) {
@@ -560,7 +571,11 @@ __global__ __launch_bounds__(256) void k_sad_cells(SadArgs g) {
         for (int f = 0; f < REM; ++f) {
           const int c = 4 * NQ + f, dx = c - R;
           const uint32_t sad = quad(tacc[k][f]);
-          best = min(best, (sad << 12) | (kdy + ((uint32_t)abs(dx) << 8)) | (uint32_t)(dx + R));
+          if constexpr (kCost) {
+            if (node) crow[(dy + R) * G + c] = sad;
+          } else {
+            best = min(best, (sad << 12) | (kdy + ((uint32_t)abs(dx) << 8)) | (uint32_t)(dx + R));
+          }
         }
       }
       __builtin_amdgcn_sched_barrier(0);   // one shift row's permutes in flight at a time
@@ -569,7 +584,7 @@ __global__ __launch_bounds__(256) void k_sad_cells(SadArgs g) {
     // pass of accumulators is live at a time
     asm volatile("" : "+v"(best)::"memory");
   }
-  if (node) {
+  if (!kCost && node) {
     int32_t* out = g.out + (int64_t)pair * g.ostride;
     out[node_a * g.nx + node_b] = (int)(best & 15u) - R;
     out[g.nx * g.ny + node_a * g.nx + node_b] = (int)((best >> 4) & 15u) - R;
@@ -1649,6 +1664,47 @@ hipError_t launch_sad_level(const Plan& P, int l, const void* A, const void* B, 
 #undef PIV_SAD_R
   }
   return P.es == 1 ? sad_dispatch<1>(NW, G, grid, lds, s, g) : sad_dispatch<2>(NW, G, grid, lds, s, g);
+}
+
+// The coarsest level's SAD of every node and shift into a cost volume
+// (semi-global matching) by the cell-shared kernel, where its geometry
+// applies (u8, 16x16 blocks at step 8, R 3..7); hipErrorNotSupported
+// otherwise.
+hipError_t launch_sad_cost_cells(const Plan& P, uint32_t* C, int64_t cstride, int n, hipStream_t s) {
+  const int l = P.L - 1;
+  const Level& v = P.lv[l];
+  if (!(P.es == 1 && P.p.step == 8 && P.block == 16 && v.R >= 3 && v.R <= 7 &&
+        (size_t)v.rows * v.pitch < (1u << 31) && v.pitch < (1 << 24)))
+    return hipErrorNotSupported;
+  SadArgs g = {};
+  const size_t origin = (size_t)v.margin * v.pitch + (size_t)v.margin * P.es;
+  g.A = P.ws + v.off_a + origin;
+  g.B = P.ws + v.off_b + origin;
+  g.pitch = v.pitch;
+  g.stride = (int64_t)P.per_pair;
+  g.nx = v.nx;
+  g.ny = v.ny;
+  g.step = P.p.step;
+  g.block = P.block;
+  g.R = v.R;
+  g.parent = nullptr;
+  g.out = nullptr;
+  g.mask = P.slot_mask;
+  g.margin = v.margin;
+  g.W = v.W;
+  g.H = v.H;
+  g.cost = C;
+  g.cstride = cstride;
+  const int tiles = ((v.nx + 7) / 8) * ((v.ny + 5) / 6);
+  dim3 grid((tiles + 3) / 4, 1, n);
+  switch (g.R) {
+    case 3: hipLaunchKernelGGL((k_sad_cells<3, 7, true>), grid, dim3(256), 0, s, g); break;
+    case 4: hipLaunchKernelGGL((k_sad_cells<4, 5, true>), grid, dim3(256), 0, s, g); break;
+    case 5: hipLaunchKernelGGL((k_sad_cells<5, 6, true>), grid, dim3(256), 0, s, g); break;
+    case 6: hipLaunchKernelGGL((k_sad_cells<6, 7, true>), grid, dim3(256), 0, s, g); break;
+    default: hipLaunchKernelGGL((k_sad_cells<7, 5, true>), grid, dim3(256), 0, s, g); break;
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_pred_out(const Plan& P, int n, float* pred, hipStream_t s) {

@@ -211,11 +211,17 @@ hipError_t launch_sgm_level(const Plan& P, int n, hipStream_t s) {
   g.out = reinterpret_cast<int32_t*>(P.ws + v.off_d);
   g.ostride = (int64_t)(P.per_pair / sizeof(int32_t));
   g.mask = P.slot_mask;
-  const int64_t total = (int64_t)v.nx * v.ny * g.nd;
-  dim3 gc((unsigned)((total + 255) / 256), 1, n);
-  if (P.es == 1) hipLaunchKernelGGL(k_sgm_cost<1>, gc, dim3(256), 0, s, g);
-  else hipLaunchKernelGGL(k_sgm_cost<2>, gc, dim3(256), 0, s, g);
-  if (hipError_t e = hipGetLastError()) return e;
+  // cost volume: by the cell-shared coarse SAD kernel where its geometry
+  // applies, otherwise one thread per node and candidate
+  hipError_t ec = launch_sad_cost_cells(P, g.C, g.cstride, n, s);
+  if (ec == hipErrorNotSupported) {
+    const int64_t total = (int64_t)v.nx * v.ny * g.nd;
+    dim3 gc((unsigned)((total + 255) / 256), 1, n);
+    if (P.es == 1) hipLaunchKernelGGL(k_sgm_cost<1>, gc, dim3(256), 0, s, g);
+    else hipLaunchKernelGGL(k_sgm_cost<2>, gc, dim3(256), 0, s, g);
+    ec = hipGetLastError();
+  }
+  if (ec != hipSuccess) return ec;
   const int per = (g.nd + kAggT - 1) / kAggT;
   for (int dir = 0; dir < 2; ++dir) {
     dim3 ga(dir == 0 ? v.ny : v.nx, n);
