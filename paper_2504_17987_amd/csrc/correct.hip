@@ -1535,9 +1535,11 @@ void k_correct_bands(CorrArgs g) {
   }
   __syncthreads();
   // ---- peak over the bands, fit, composition with the predictor's window mean
-  // (the windows are dealt to the waves, so that the fits of one tile run
-  // side by side instead of in one wave while the others have finished)
-  constexpr int WPW = (C::NWIN + C::NG - 1) / C::NG;   // windows per wave
+  // (with large cells, whose kernel has two workgroups per CU and is bound
+  // by latency, the windows are dealt to the waves so that the fits of a
+  // tile run side by side; with small cells, where VALU issue bounds the
+  // kernel, one wave fits them all and the others end)
+  constexpr int WPW = STEP > 8 ? (C::NWIN + C::NG - 1) / C::NG : C::NWIN;   // windows per wave
   const int wt = band * WPW + lane;
   if (lane < WPW && wt < C::NWIN) {
     const int wi = wt / TW, wj = wt - (wt / TW) * TW;
