@@ -65,125 +65,153 @@ __global__ __launch_bounds__(256) void k_sgm_cost(SgmArgs g) {
   g.C[(int64_t)pair * g.cstride + i] = s;
 }
 
-constexpr int kAggT = 256;
-
-// Minimum over the workgroup (every thread gets it)
-__device__ __forceinline__ uint32_t block_min(uint32_t v, uint32_t* red) {
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = min(v, (uint32_t)__shfl_xor((int)v, o));
-  if (lane == 0) red[w] = v;
-  __syncthreads();
-  uint32_t m = red[0];
-#pragma unroll
-  for (int q = 1; q < kAggT / 64; ++q) m = min(m, red[q]);
-  __syncthreads();
-  return m;
+// Minimum over the wave by DPP (every lane gets it; min is idempotent, so
+// lanes of masked rows keeping their own value is harmless)
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
+  int x = (int)v;
+  x = (int)min((uint32_t)x, (uint32_t)PIV_DPP_I(x, 0xB1, 0xF, x));
+  x = (int)min((uint32_t)x, (uint32_t)PIV_DPP_I(x, 0x4E, 0xF, x));
+  x = (int)min((uint32_t)x, (uint32_t)PIV_DPP_I(x, 0x141, 0xF, x));
+  x = (int)min((uint32_t)x, (uint32_t)PIV_DPP_I(x, 0x140, 0xF, x));
+  x = (int)min((uint32_t)x, (uint32_t)PIV_DPP_I(x, 0x142, 0xA, x));
+  x = (int)min((uint32_t)x, (uint32_t)PIV_DPP_I(x, 0x143, 0xC, x));
+  return (uint32_t)__builtin_amdgcn_readlane(x, 63);
 }
 
-// One path direction over one line of nodes.  Candidates are spread over
-// the workgroup's threads (kPer per thread); the previous node's path costs
-// live in LDS.  With `write` the path's costs are stored into S (the first
-// of the four passes), otherwise added to it.
+// The previous node's path costs live in LDS on a (2R+3)^2 grid whose
+// one-cell border holds 0xffffffff, so every candidate reads its eight
+// neighbours without bounds tests (a border never wins the minimum, and
+// every candidate has at least one real neighbour since R >= 1).
+constexpr int kMaxR = 16, kPad = 2 * kMaxR + 3, kPrevWords = kPad * kPad + 1;
+
+// Per-lane candidate constants of a wave (kPer candidates per lane).
 template <int kPer>
-__device__ void sgm_path(const SgmArgs& g, const uint32_t* C, uint32_t* S, int len, int64_t nstride, bool reverse,
-                         bool write, uint32_t* prev, uint32_t* red) {
+struct Cand {
+  int rd[kPer];        // LDS cell read as the candidate's own (a real cell even for padding lanes)
+  int wr[kPer];        // LDS cell written (a spare word for padding lanes)
+  bool ok[kPer];       // a real candidate (k < nd)
+  uint32_t code[kPer]; // tie code (|dx|+|dy|, dy, dx) of the winner search
+};
+
+// One path direction over one line of nodes by one wave.  The next node's
+// cost and (when adding) its running sum are requested before this node is
+// worked, so the global reads overlap a whole node's work.  With `write`
+// the path's costs are stored into S (the first of the four passes),
+// otherwise added; with `wta` (the last pass) the node's total is final and
+// its winner, the least (S, |dx|+|dy|, dy, dx), is written.
+template <int kPer>
+__device__ void sgm_path(const SgmArgs& g, const Cand<kPer>& cd, const uint32_t* C, uint32_t* S, int len,
+                         int64_t nstride, bool reverse, bool write, bool wta, uint32_t* prev, int32_t* out,
+                         int node0, int nodestep) {
   const int t = threadIdx.x;
-  const int n1 = 2 * g.R + 1;
-  uint32_t cur[kPer];
-  for (int s = 0; s < len; ++s) {
+  const int P = 2 * g.R + 3;
+  const int np = g.nx * g.ny;
+  uint32_t cn[kPer], sn[kPer];
+  auto request = [&](int s) {
     const int pos = reverse ? len - 1 - s : s;
     const uint32_t* c = C + pos * nstride;
+    const uint32_t* sp = S + pos * nstride;
+#pragma unroll
+    for (int e = 0; e < kPer; ++e) {
+      const int k = t + e * 64;
+      cn[e] = cd.ok[e] ? c[k] : 0u;
+      sn[e] = (!write && cd.ok[e]) ? sp[k] : 0u;
+    }
+  };
+  request(0);
+  for (int s = 0; s < len; ++s) {
+    const int pos = reverse ? len - 1 - s : s;
     uint32_t* sp = S + pos * nstride;
+    uint32_t cv[kPer], sv[kPer], cur[kPer];
+#pragma unroll
+    for (int e = 0; e < kPer; ++e) {
+      cv[e] = cn[e];
+      sv[e] = sn[e];
+    }
+    if (s + 1 < len) request(s + 1);
     if (s == 0) {
 #pragma unroll
-      for (int e = 0; e < kPer; ++e) {
-        const int k = t + e * kAggT;
-        cur[e] = k < g.nd ? c[k] : 0xffffffffu;
-      }
+      for (int e = 0; e < kPer; ++e) cur[e] = cv[e];
     } else {
+      uint32_t own[kPer], nb[kPer];
       uint32_t lmin = 0xffffffffu;
 #pragma unroll
       for (int e = 0; e < kPer; ++e) {
-        const int k = t + e * kAggT;
-        if (k < g.nd) lmin = min(lmin, prev[k]);
+        const uint32_t* q = prev + cd.rd[e];
+        own[e] = q[0];
+        nb[e] = min(min(min(q[-P - 1], q[-P]), min(q[-P + 1], q[-1])), min(min(q[1], q[P - 1]), min(q[P], q[P + 1])));
+        lmin = min(lmin, cd.ok[e] ? own[e] : 0xffffffffu);
       }
-      const uint32_t m = block_min(lmin, red);
+      const uint32_t m = wave_min_u32(lmin);
 #pragma unroll
-      for (int e = 0; e < kPer; ++e) {
-        const int k = t + e * kAggT;
-        if (k < g.nd) {
-          const int ky = k / n1, kx = k - (k / n1) * n1;
-          uint32_t nb = 0xffffffffu;
-#pragma unroll
-          for (int oy = -1; oy <= 1; ++oy)
-#pragma unroll
-            for (int ox = -1; ox <= 1; ++ox) {
-              if (!oy && !ox) continue;
-              const int y2 = ky + oy, x2 = kx + ox;
-              if (y2 >= 0 && x2 >= 0 && y2 < n1 && x2 < n1) nb = min(nb, prev[y2 * n1 + x2]);
-            }
-          const uint32_t best = min(min(prev[k], nb == 0xffffffffu ? nb : nb + g.P1), m + g.P2);
-          cur[e] = c[k] + best - m;
-        }
-      }
+      for (int e = 0; e < kPer; ++e) cur[e] = cv[e] + min(min(own[e], nb[e] + g.P1), m + g.P2) - m;
     }
-    __syncthreads();   // every thread has read prev
+    __syncthreads();   // (one wave) every lane has read prev
+    uint32_t best = 0xffffffffu, code = 0xffffffffu;
 #pragma unroll
     for (int e = 0; e < kPer; ++e) {
-      const int k = t + e * kAggT;
-      if (k < g.nd) {
-        prev[k] = cur[e];
-        sp[k] = write ? cur[e] : sp[k] + cur[e];
+      prev[cd.wr[e]] = cur[e];
+      const uint32_t tot = write ? cur[e] : sv[e] + cur[e];
+      if (wta) {
+        const uint32_t tv = cd.ok[e] ? tot : 0xffffffffu;
+        code = tv < best ? cd.code[e] : (tv == best ? min(code, cd.code[e]) : code);
+        best = min(best, tv);
+      } else if (cd.ok[e]) {
+        sp[t + e * 64] = tot;
+      }
+    }
+    if (wta) {
+      // (the least total, then among the lanes holding it the least code)
+      const uint32_t mt = wave_min_u32(best);
+      const uint32_t c = wave_min_u32(best == mt ? code : 0xffffffffu);
+      if (t == 0) {
+        const int node = node0 + pos * nodestep;
+        out[node] = (int)(c & 63) - g.R;
+        out[np + node] = (int)((c >> 6) & 63) - g.R;
       }
     }
     __syncthreads();
   }
 }
 
-// dir 0: one workgroup per node row, left to right then right to left;
-// dir 1: one workgroup per node column, top to bottom then bottom to top.
+// One wave per line.  dir 0: a node row, left to right then right to left;
+// dir 1: a node column, top to bottom then bottom to top, the last pass
+// taking each node's winner.
 template <int kPer>
-__global__ __launch_bounds__(kAggT) void k_sgm_aggregate(SgmArgs g, int dir) {
-  __shared__ uint32_t prev[kPer * kAggT];
-  __shared__ uint32_t red[kAggT / 64];
+__global__ __launch_bounds__(64) void k_sgm_aggregate(SgmArgs g, int dir) {
+  __shared__ uint32_t prev[kPrevWords];
   const int pair = blockIdx.y;
   if (slot_off(g.mask, pair)) return;
   const int line = blockIdx.x;
+  const int t = threadIdx.x;
+  const int n1 = 2 * g.R + 1, P = n1 + 2;
+  for (int i = t; i < P * P; i += 64) prev[i] = 0xffffffffu;
+  Cand<kPer> cd;
+#pragma unroll
+  for (int e = 0; e < kPer; ++e) {
+    const int k = t + e * 64;
+    const bool ok = k < g.nd;
+    const int ky = ok ? k / n1 : 0, kx = ok ? k - ky * n1 : 0;
+    const int cell = (ky + 1) * P + kx + 1;
+    cd.ok[e] = ok;
+    cd.rd[e] = cell;
+    cd.wr[e] = ok ? cell : P * P;
+    cd.code[e] = ((uint32_t)(abs(ky - g.R) + abs(kx - g.R)) << 12) | ((uint32_t)ky << 6) | (uint32_t)kx;
+  }
+  __syncthreads();
   const uint32_t* C = g.C + (int64_t)pair * g.cstride;
   uint32_t* S = g.S + (int64_t)pair * g.cstride;
+  int32_t* out = g.out + (int64_t)pair * g.ostride;
   if (dir == 0) {
     const int64_t base = (int64_t)line * g.nx * g.nd;
-    sgm_path<kPer>(g, C + base, S + base, g.nx, g.nd, false, true, prev, red);
-    sgm_path<kPer>(g, C + base, S + base, g.nx, g.nd, true, false, prev, red);
+    sgm_path<kPer>(g, cd, C + base, S + base, g.nx, g.nd, false, true, false, prev, out, 0, 0);
+    sgm_path<kPer>(g, cd, C + base, S + base, g.nx, g.nd, true, false, false, prev, out, 0, 0);
   } else {
     const int64_t base = (int64_t)line * g.nd;
     const int64_t ns = (int64_t)g.nx * g.nd;
-    sgm_path<kPer>(g, C + base, S + base, g.ny, ns, false, false, prev, red);
-    sgm_path<kPer>(g, C + base, S + base, g.ny, ns, true, false, prev, red);
+    sgm_path<kPer>(g, cd, C + base, S + base, g.ny, ns, false, false, false, prev, out, 0, 0);
+    sgm_path<kPer>(g, cd, C + base, S + base, g.ny, ns, true, false, true, prev, out, line, g.nx);
   }
-}
-
-// Winner per node: least (S, |dx|+|dy|, dy, dx), as one 64-bit key.
-__global__ __launch_bounds__(256) void k_sgm_wta(SgmArgs g) {
-  const int pair = blockIdx.y;
-  if (slot_off(g.mask, pair)) return;
-  const int node = blockIdx.x * 256 + threadIdx.x;
-  const int np = g.nx * g.ny;
-  if (node >= np) return;
-  const uint32_t* S = g.S + (int64_t)pair * g.cstride + (int64_t)node * g.nd;
-  const int n1 = 2 * g.R + 1;
-  uint64_t best = ~uint64_t(0);
-  for (int k = 0; k < g.nd; ++k) {
-    const int ky = k / n1, kx = k - (k / n1) * n1;
-    const int l = abs(ky - g.R) + abs(kx - g.R);
-    const uint64_t key = ((uint64_t)S[k] << 18) | ((uint64_t)l << 12) | ((uint64_t)ky << 6) | (uint64_t)kx;
-    best = key < best ? key : best;
-  }
-  const int ky = (int)((best >> 6) & 63), kx = (int)(best & 63);
-  int32_t* o = g.out + (int64_t)pair * g.ostride;
-  o[node] = kx - g.R;
-  o[np + node] = ky - g.R;
 }
 
 }  // namespace
@@ -222,17 +250,15 @@ hipError_t launch_sgm_level(const Plan& P, int n, hipStream_t s) {
     ec = hipGetLastError();
   }
   if (ec != hipSuccess) return ec;
-  const int per = (g.nd + kAggT - 1) / kAggT;
+  const int per = (g.nd + 63) / 64;
   for (int dir = 0; dir < 2; ++dir) {
     dim3 ga(dir == 0 ? v.ny : v.nx, n);
 #define PIV_SGM_AGG(K_) \
-  if (per <= K_) { hipLaunchKernelGGL(k_sgm_aggregate<K_>, ga, dim3(kAggT), 0, s, g, dir); }
-    PIV_SGM_AGG(1) else PIV_SGM_AGG(2) else PIV_SGM_AGG(3) else PIV_SGM_AGG(5)
+  if (per <= K_) { hipLaunchKernelGGL(k_sgm_aggregate<K_>, ga, dim3(64), 0, s, g, dir); }
+    PIV_SGM_AGG(1) else PIV_SGM_AGG(3) else PIV_SGM_AGG(4) else PIV_SGM_AGG(8) else PIV_SGM_AGG(12) else PIV_SGM_AGG(18)
 #undef PIV_SGM_AGG
     if (hipError_t e = hipGetLastError()) return e;
   }
-  dim3 gw((v.nx * v.ny + 255) / 256, n);
-  hipLaunchKernelGGL(k_sgm_wta, gw, dim3(256), 0, s, g);
   return hipGetLastError();
 }
 
