@@ -39,7 +39,7 @@ struct Plan {
                       // input of validation
   // F32 plans only: per-pair offsets of the refinement's gradient and
   // Gauss-Newton diagonal ([2][ny][nx] each) and window losses ([ny][nx])
-  size_t off_gu = 0, off_dd = 0, off_loss = 0;
+  size_t off_gu = 0, off_dd = 0, off_loss = 0, off_part = 0;
   // with semi-global matching: per-pair offsets of the coarsest level's cost
   // volume and aggregated cost (uint32 [node][candidate] each)
   size_t off_sgm_c = 0, off_sgm_s = 0;
@@ -88,6 +88,11 @@ hipError_t launch_ssd_backward(const Plan& P, const float* A, const float* B, co
 // one refinement update per pair from the workspace's gradient, diagonal and
 // losses: hist[pair * hstride + k] = total loss (if hist), and, when update
 // is set, U -= tau gU / (D + lam_rel mean(D))
+// refinement step for the tiled geometry (win = 2 step = 16): the adjoint
+// with per-tile sums of the GN diagonal and the loss, then the update
+bool ssd_tiled(const Plan& P);
+hipError_t launch_ssd_refine_step(const Plan& P, const float* A, const float* B, float* U, int n, float tau,
+                                  float lam_rel, float* hist, int hstride, int k, hipStream_t s);
 hipError_t launch_ssd_update(const Plan& P, float* U, int n, float tau, float lam_rel, float* hist,
                              int hstride, int k, int update, hipStream_t s);
 // exponential smoothing in time: see piv_smooth in include/piv.h

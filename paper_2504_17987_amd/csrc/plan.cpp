@@ -180,6 +180,8 @@ piv_status piv_plan(const piv_params* pp, piv_plan_t* out) {
     off = align256(off + sizeof(float) * 2 * np);
     P->off_loss = off;
     off = align256(off + sizeof(float) * np);
+    P->off_part = off;   // per node tile of 8 x 8: two floats
+    off = align256(off + sizeof(float) * 2 * (size_t)((P->nx + 7) / 8) * ((P->ny + 7) / 8));
   }
   P->per_pair = off;
   *out = reinterpret_cast<piv_plan_t>(P);
@@ -474,6 +476,22 @@ piv_status piv_ssd_refine(piv_plan_t plan, const float* A, const float* B, float
   if (!(lam_rel >= 0.0f) || !(lam_rel <= 1e6f)) return fail(PIV_EINVAL, "lam_rel=%g outside [0, 1e6]", (double)lam_rel);
   if (piv_status s = need_ws(P, n)) return s;
   if (n == 0) return PIV_OK;
+  if (piv::ssd_tiled(P)) {
+    // per step: the adjoint (gradient, GN diagonal and, per tile, the sums of
+    // the diagonal and of the loss before the step), then the update; the
+    // loss after the last step by the forward
+    for (int k = 0; k < steps; ++k)
+      if (piv_status s = dev(piv::launch_ssd_refine_step(P, A, B, U, n, tau, lam_rel, hist, steps + 1, k, stream),
+                             "ssd_refine_step"))
+        return s;
+    if (hist) {
+      if (piv_status s = dev(piv::launch_ssd_forward(P, A, B, U, n, nullptr, stream), "ssd_forward")) return s;
+      if (piv_status s = dev(piv::launch_ssd_update(P, U, n, tau, lam_rel, hist, steps + 1, steps, 0, stream),
+                             "ssd_update"))
+        return s;
+    }
+    return PIV_OK;
+  }
   // per step: window losses (for the history), gradient and Gauss-Newton
   // diagonal of the total loss into the workspace, then the update
   for (int k = 0; k <= steps; ++k) {

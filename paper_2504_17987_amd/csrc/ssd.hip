@@ -26,6 +26,11 @@ struct SsdArgs {
   int64_t lstride;      // floats per pair of loss
   int64_t gstride;      // floats per pair of gU and D
   const uint8_t* mask;
+  // (tiled adjoint, nullable) per node tile: [tile][2] = the tile's sum of
+  // the GN diagonal (both components) and of the window losses (each pixel
+  // counted by the tile owning its base node), pair stride pstride floats
+  float* part;
+  int64_t pstride;
 };
 
 __device__ __forceinline__ float ldA(const float* I, int W, int H, int y, int x) {
@@ -363,6 +368,20 @@ __global__ __launch_bounds__(256) void k_ssd_forward_t(SsdArgs a) {
   }
 }
 
+// Sum over a 256-thread workgroup in a fixed order (every thread gets it).
+__device__ __forceinline__ float tile_sum(float x, float* red) {
+  const int t = threadIdx.x;
+  __syncthreads();
+  red[t] = x;
+  __syncthreads();
+#pragma unroll
+  for (int o = 128; o > 0; o >>= 1) {
+    if (t < o) red[t] += red[t + o];
+    __syncthreads();
+  }
+  return red[0];
+}
+
 // Backward, TN x TN nodes per workgroup.  Every pixel of the nodes' support
 // region contributes to the two node columns and two node rows of its
 // bilinear cell (weights 1-f and f, squared for the diagonal), so the
@@ -373,7 +392,7 @@ __global__ __launch_bounds__(256) void k_ssd_forward_t(SsdArgs a) {
 // base node column (the region starts on a cell boundary), and m (the sum
 // of the upstream gradients of the windows holding the pixel) is constant
 // along a chunk.
-template <int STEP, int TN>
+template <int STEP, int TN, bool kPart>
 __global__ __launch_bounds__(256) void k_ssd_backward_t(SsdArgs a) {
   using C = SsdTile<STEP, TN>;
   constexpr int NCH = C::RW / STEP;                    // chunks per region row
@@ -382,6 +401,8 @@ __global__ __launch_bounds__(256) void k_ssd_backward_t(SsdArgs a) {
   __shared__ float s_g[C::NG][C::NG];                  // upstream window gradients
   __shared__ int s_chb[NCH];                           // base node column of a chunk
   __shared__ int s_rfirst[C::NNC], s_rlast[C::NNC];    // region rows based on each cached node row
+  __shared__ float s_red[256];                         // fixed-order tile sums
+  __shared__ uint8_t s_ownr[C::RW], s_ownc[C::RW];     // region rows / columns whose nearest node is the tile's
   const WgIdx wg = xcd_order();
   const int pair = wg.z;
   if (slot_off(a.mask, pair)) return;
@@ -418,8 +439,20 @@ __global__ __launch_bounds__(256) void k_ssd_backward_t(SsdArgs a) {
     if (i == 0 || sh.rb[i - 1] != rb) s_rfirst[rb] = i;
     if (i == RH - 1 || sh.rb[i + 1] != rb) s_rlast[rb] = i;
   }
+  // (the loss: a pixel counts at the tile holding its nearest node, whose
+  // support region holds it)
+  for (int i = t; kPart && i < RH + RWc; i += 256) {
+    const bool row = i < RH;
+    const int p = row ? ylo + i : xlo + (i - RH);
+    const int n = row ? a.ny : a.nx, lo = row ? ta : tb;
+    const int nn = min(max(fdiv(2 * p + 1, 2 * STEP), 0), n - 1);
+    const uint8_t o = nn >= lo && nn < lo + TN;
+    if (row) s_ownr[i] = o;
+    else s_ownc[i - RH] = o;
+  }
   __syncthreads();
   const int nchunks = (RWc + STEP - 1) / STEP;
+  float lsum = 0.0f;   // this thread's share of the tile's loss (owned items)
   for (int item = t; item < RH * nchunks; item += 256) {
     const int i = item / nchunks, c = item - (item / nchunks) * nchunks;
     const int y = ylo + i;
@@ -433,6 +466,8 @@ __global__ __launch_bounds__(256) void k_ssd_backward_t(SsdArgs a) {
     float acc[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) acc[k] = 0.0f;
+    const bool own = kPart && s_ownr[i];
+    float lacc = 0.0f;   // the loss terms r^2 of the chunk's pixels this tile counts
     if (m != 0.0f) {
       // the chunk's pixels share their node row and node columns (it starts
       // on a cell boundary), so the node field is interpolated down the
@@ -457,9 +492,11 @@ __global__ __launch_bounds__(256) void k_ssd_backward_t(SsdArgs a) {
           acc[2] += wl * t1; acc[3] += wr * t1;
           acc[4] += wl * wl * t2; acc[5] += wr * wr * t2;
           acc[6] += wl * wl * t3; acc[7] += wr * wr * t3;
+          if constexpr (kPart) lacc += s_ownc[j] ? r * r : 0.0f;
         }
       }
     }
+    if (kPart && own) lsum += m * lacc;
 #pragma unroll
     for (int k = 0; k < 8; ++k) s_part[i][c][k] = acc[k];
   }
@@ -469,6 +506,7 @@ __global__ __launch_bounds__(256) void k_ssd_backward_t(SsdArgs a) {
   // on the column before, weighted by its row weight
   const int nd = t >> 2, term = t & 3;
   const int na = ta + nd / TN, nb = tb + nd % TN;
+  float dsum = 0.0f;   // this thread's GN diagonal value (terms 2, 3)
   if (nd < TN * TN && na < a.ny && nb < a.nx) {
     const int cbn = nb - nlx;                          // node column in cache indices
     const int rbn = na - nly;
@@ -504,8 +542,19 @@ __global__ __launch_bounds__(256) void k_ssd_backward_t(SsdArgs a) {
     const int idx = na * a.nx + nb;
     if (term < 2) {
       a.gU[(int64_t)pair * a.gstride + term * np + idx] = s;
-    } else if (a.D) {
-      a.D[(int64_t)pair * a.gstride + (term - 2) * np + idx] = s;
+    } else {
+      if (a.D) a.D[(int64_t)pair * a.gstride + (term - 2) * np + idx] = s;
+      dsum = s;
+    }
+  }
+  if constexpr (kPart) {
+    // fixed-order sums over the workgroup (bitwise reproducible)
+    const float ls = tile_sum(lsum, s_red);
+    const float ds = tile_sum(dsum, s_red);
+    if (t == 0) {
+      float* o = a.part + (int64_t)pair * a.pstride + 2 * (wg.y * ((a.nx + TN - 1) / TN) + wg.x);
+      o[0] = ds;
+      o[1] = ls;
     }
   }
 }
@@ -528,6 +577,8 @@ SsdArgs make_args(const Plan& P, const float* A, const float* B, const float* U)
   a.lstride = (int64_t)P.nx * P.ny;
   a.gstride = 2 * (int64_t)P.nx * P.ny;
   a.mask = P.slot_mask;
+  a.part = nullptr;
+  a.pstride = 0;
   return a;
 }
 
@@ -581,6 +632,37 @@ __global__ __launch_bounds__(kUpdT) void k_ssd_update(float* U, const float* gU,
   }
 }
 
+// Refinement update from the adjoint's tile sums: every workgroup adds the
+// pair's tile sums in the same fixed order (so all agree on lambda and the
+// loss), the first writes the loss into the history, and each updates its
+// share of U.
+__global__ __launch_bounds__(kUpdT) void k_ssd_update_tiles(float* U, const float* gU, const float* D,
+                                                            const float* part, int64_t wstride, int np, int ntiles,
+                                                            float tau, float lam_rel, float* hist, int hstride,
+                                                            int k, const uint8_t* mask) {
+  __shared__ float red[kUpdT];
+  const int pair = blockIdx.y;
+  if (slot_off(mask, pair)) return;
+  const int t = threadIdx.x;
+  const float* pp = part + (int64_t)pair * wstride;
+  float ds = 0.0f, ls = 0.0f;
+  for (int i = t; i < ntiles; i += kUpdT) {
+    ds += pp[2 * i];
+    ls += pp[2 * i + 1];
+  }
+  ds = block_sum(ds, red);
+  ls = block_sum(ls, red);
+  if (hist && blockIdx.x == 0 && t == 0) hist[(int64_t)pair * hstride + k] = ls;
+  const float lam = lam_rel * (ds / (float)(2 * np));
+  const float* G = gU + (int64_t)pair * wstride;
+  const float* Dp = D + (int64_t)pair * wstride;
+  float* Up = U + (int64_t)pair * 2 * np;
+  for (int i = blockIdx.x * kUpdT + t; i < 2 * np; i += gridDim.x * kUpdT) {
+    const float den = Dp[i] + lam;
+    if (den > 0.0f) Up[i] -= tau * G[i] / den;
+  }
+}
+
 }  // namespace
 
 hipError_t launch_ssd_forward(const Plan& P, const float* A, const float* B, const float* U, int n,
@@ -618,7 +700,7 @@ hipError_t launch_ssd_backward(const Plan& P, const float* A, const float* B, co
   }
   if (a.step == 8 && a.win == 16) {
     dim3 grid((a.nx + 7) / 8, (a.ny + 7) / 8, n);
-    hipLaunchKernelGGL((k_ssd_backward_t<8, 8>), grid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_ssd_backward_t<8, 8, false>), grid, dim3(256), 0, s, a);
     return hipGetLastError();
   }
   // 16 threads per node -> 16 nodes per workgroup; support region of a
@@ -630,6 +712,27 @@ hipError_t launch_ssd_backward(const Plan& P, const float* A, const float* B, co
   if (lds > 65536) return hipErrorInvalidValue;
   dim3 grid((a.nx + TN - 1) / TN, (a.ny + TN - 1) / TN, n);
   hipLaunchKernelGGL(k_ssd_backward, grid, dim3(256), lds, s, a, TN);
+  return hipGetLastError();
+}
+
+bool ssd_tiled(const Plan& P) { return P.p.step == 8 && P.p.win == 16; }
+
+hipError_t launch_ssd_refine_step(const Plan& P, const float* A, const float* B, float* U, int n, float tau,
+                                  float lam_rel, float* hist, int hstride, int k, hipStream_t s) {
+  SsdArgs a = make_args(P, A, B, U);
+  a.gU = reinterpret_cast<float*>(P.ws + P.off_gu);
+  a.D = reinterpret_cast<float*>(P.ws + P.off_dd);
+  a.gstride = (int64_t)(P.per_pair / sizeof(float));
+  a.part = reinterpret_cast<float*>(P.ws + P.off_part);
+  a.pstride = a.gstride;
+  dim3 grid((a.nx + 7) / 8, (a.ny + 7) / 8, n);
+  hipLaunchKernelGGL((k_ssd_backward_t<8, 8, true>), grid, dim3(256), 0, s, a);
+  if (hipError_t e = hipGetLastError()) return e;
+  const int np = P.nx * P.ny;
+  const int ntiles = (int)(grid.x * grid.y);
+  dim3 gu((unsigned)max(1, min(64, (2 * np + 4 * kUpdT - 1) / (4 * kUpdT))), n);
+  hipLaunchKernelGGL(k_ssd_update_tiles, gu, dim3(kUpdT), 0, s, U, a.gU, a.D, a.part, a.gstride, np, ntiles, tau,
+                     lam_rel, hist, hstride, k, P.slot_mask);
   return hipGetLastError();
 }
 
