@@ -1298,8 +1298,17 @@ void k_correct_bands(CorrArgs g) {
       for (int e = 0; e < 4; ++e) {
         const float qx = (xq + (float)e) + uu[e], qy = yr + vv[e];
         const float fx = __builtin_amdgcn_fractf(qx), fy = __builtin_amdgcn_fractf(qy);
-        // (as unsigned, a negative index would clamp to the top as well)
-        const unsigned ix = min((unsigned)(int)qx, (unsigned)ixhi), iy = min((unsigned)(int)qy, (unsigned)iyhi);
+        // Without padding columns the box bounds every coordinate: qx lies in
+        // [q + e + 1 - floor(lo) + lo, q + e + 1 - floor(lo) + hi] up to the
+        // interpolation's rounding, so floor(qx) is in [0, ixhi] (and its
+        // right-hand neighbour in the box), likewise in y; with padding
+        // columns the clamps keep their reads inside the box.  (As unsigned,
+        // a negative index would clamp to the top as well.)
+        unsigned ix = (unsigned)(int)qx, iy = (unsigned)(int)qy;
+        if constexpr (C::BW4 != C::BW) {
+          ix = min(ix, (unsigned)ixhi);
+          iy = min(iy, (unsigned)iyhi);
+        }
         const uint8_t* p0 = rawx + (__umul24(iy, (unsigned)rowb) + ix * ES);
         const float p00 = rawv(p0), p01 = rawv(p0 + ES), p10 = rawv(p0 + rowb), p11 = rawv(p0 + rowb + ES);
         const float top = p00 + fx * (p01 - p00), bot = p10 + fx * (p11 - p10);
