@@ -59,8 +59,8 @@ def parse():
                     help="comma-separated forms to run beside the headline (default all): cfg1_256, "
                          "graph_batched_cfg2, preprocess_cfg2, sgm_predictor_cfg2, stream_cfg3, ssd_cfg4, "
                          "largest_8192x4096, low_seeding_wake, served_cfg5")
-    ap.add_argument("--serve-seconds", type=float, default=2.0, help="seconds of arrivals per load point")
-    ap.add_argument("--serve-first-scale", type=float, default=1.0,
+    ap.add_argument("--serve-seconds", type=float, default=10.0, help="seconds of arrivals per load point")
+    ap.add_argument("--serve-first-scale", type=float, default=3.0,
                     help="the first (3,000 pairs/s) load point runs this many times longer")
     ap.add_argument("--serve-rates", type=float, nargs="+", default=[3000.0, 6000.0, 12000.0, 24000.0],
                     help="offered loads (pairs/s, all 12 streams together)")
