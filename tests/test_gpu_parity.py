@@ -63,6 +63,19 @@ PRED_CASES = {
     "sgm_ragged_L2": (lambda: small_vortex_pair(200, 136, seed=17)[:2],
                       dict(win=16, step=8, levels=2, radius_coarse=5, radius_fine=2, sgm=True, sgm_p1=4,
                            sgm_p2=40)),
+    # every candidate count per lane of the path aggregation (1, 4, 8, 12, 18
+    # candidates per lane), by the cell kernel's cost volume (R 3 and 7) and
+    # by the per-candidate cost kernel (12 px blocks, R above 7)
+    "sgm_R3_L2": (lambda: small_vortex_pair(seed=18)[:2],
+                  dict(win=16, step=8, levels=2, radius_coarse=3, radius_fine=2, sgm=True)),
+    "sgm_R7_L1": (lambda: small_vortex_pair(seed=19)[:2],
+                  dict(win=16, step=8, levels=1, radius_coarse=7, radius_fine=2, sgm=True, sgm_p1=3, sgm_p2=24)),
+    "sgm_R10_L1_block12": (lambda: small_vortex_pair(seed=20)[:2],
+                           dict(win=12, step=8, levels=1, radius_coarse=10, radius_fine=2, sgm=True)),
+    "sgm_R13_L2": (lambda: small_vortex_pair(seed=21)[:2],
+                   dict(win=16, step=8, levels=2, radius_coarse=13, radius_fine=2, sgm=True)),
+    "sgm_R16_L1": (lambda: small_vortex_pair(160, 96, seed=22)[:2],
+                   dict(win=16, step=8, levels=1, radius_coarse=16, radius_fine=2, sgm=True, sgm_p1=1, sgm_p2=4)),
 }
 
 
