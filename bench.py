@@ -771,6 +771,10 @@ def main():
             "predictor_bit_exact": bool(np.array_equal(g0["pred"], ref0["pred"].astype(np.float32))),
             "max_abs_disp_px": float(d.max()), "vectors_beyond_0.01px": int((d > 0.01).sum()),
             "flags_equal": int((g0["flags"] == ref0["flags"]).sum()), "vectors": int(d.size),
+            # vectors that would need one of the parity tests' explained
+            # exemptions (near-tie, near-flat, near-threshold): those beyond
+            # the tolerance or with another flag
+            "exemptions_needed": int(((d > 0.01) | (g0["flags"] != ref0["flags"])).sum()),
             "omega_max_rel": float(np.abs(g0["omega"] - ref0["omega"]).max() / np.abs(ref0["omega"]).max())}
         lg(f"parity on the oracle's sample pair: max |d disp| {d.max():.2e} px, "
            f"{int((d > 0.01).sum())} vectors beyond 0.01 px")
