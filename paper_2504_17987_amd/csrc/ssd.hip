@@ -8,6 +8,8 @@
 // lets every node sum its partials over its rows.  The general forms gather
 // per node with per-pixel weights.  No atomics anywhere, so the results are
 // bitwise reproducible.
+#include <type_traits>
+
 #include "dev_common.h"
 #include "piv_internal.h"
 
@@ -251,8 +253,14 @@ struct SsdShared {
 
 // Loads the node cache and the interpolation tables of the region rows and
 // columns (base node as a cache index, fraction towards base + 1).
+// Returns (the same in every thread) whether the tile is interior: every
+// pixel of the region lies in the frames and so does every bilinear sample
+// with its right and lower neighbours, with a pixel to spare.  The samples
+// of region pixel x lie at x + u with u between the cached nodes' extremes
+// (the interpolation stays within them), so the nodes decide; a NaN node
+// makes the tile not interior.
 template <int STEP, int TN>
-__device__ __forceinline__ void ssd_prepare(const SsdArgs& a, const float* U, int ylo, int xlo, int RH, int RWc,
+__device__ __forceinline__ bool ssd_prepare(const SsdArgs& a, const float* U, int ylo, int xlo, int RH, int RWc,
                                             SsdShared<STEP, TN>& sh, int& nly, int& nlx) {
   using C = SsdTile<STEP, TN>;
   const int t = threadIdx.x;
@@ -260,11 +268,16 @@ __device__ __forceinline__ void ssd_prepare(const SsdArgs& a, const float* U, in
   nly = max(0, (int)floorf(((float)ylo - cen) / STEP));
   nlx = max(0, (int)floorf(((float)xlo - cen) / STEP));
   const int np = a.nx * a.ny;
+  const int xhi = xlo + RWc - 1, yhi = ylo + RH - 1;
+  bool inside = xlo >= 0 && ylo >= 0 && xhi <= a.W - 1 && yhi <= a.H - 1;
   for (int i = t; i < C::NNC * C::NNC; i += 256) {
     const int r = i / C::NNC, q = i - (i / C::NNC) * C::NNC;
     const int ny_ = min(nly + r, a.ny - 1), nx_ = min(nlx + q, a.nx - 1);
-    sh.node[0][r][q] = U[ny_ * a.nx + nx_];
-    sh.node[1][r][q] = U[np + ny_ * a.nx + nx_];
+    const float u = U[ny_ * a.nx + nx_], v = U[np + ny_ * a.nx + nx_];
+    sh.node[0][r][q] = u;
+    sh.node[1][r][q] = v;
+    inside = inside && (float)xlo + u >= 1.0f && (float)xhi + u <= (float)(a.W - 3) && (float)ylo + v >= 1.0f &&
+             (float)yhi + v <= (float)(a.H - 3);
   }
   for (int i = t; i < RH + RWc; i += 256) {
     const bool row = i < RH;
@@ -276,12 +289,48 @@ __device__ __forceinline__ void ssd_prepare(const SsdArgs& a, const float* U, in
     if (row) { sh.rb[i] = bb - nly; sh.rf[i] = ff; }
     else { sh.cb[i - RH] = bb - nlx; sh.cf[i - RH] = ff; }
   }
-  __syncthreads();
+  return __syncthreads_and(inside ? 1 : 0) != 0;
 }
 
 // residual r = B'(p) - A(p) at region pixel (i, j) = (y - ylo, x - xlo), and
 // the floor-cell gradient of the sample
-template <int STEP, int TN>
+
+// residual and floor-cell gradient at region pixel (i, j) for a given
+// displacement (u, v) of that pixel; kInside: the tile is interior (every
+// read in the frames), so the reads need no bounds tests and take 32-bit
+// offsets from the frame base
+template <bool kInside>
+__device__ __forceinline__ void ssd_residual_uv(const SsdArgs& a, const float* A, const float* B, int ylo, int xlo,
+                                                int i, int j, float u, float v, float& r, float& gx, float& gy) {
+  const int x = xlo + j, y = ylo + i;
+  const float qx = (float)x + u, qy = (float)y + v;
+  const float x0 = floorf(qx), y0 = floorf(qy);
+  const float ex = qx - x0, ey = qy - y0;
+  const int ix = (int)x0, iy = (int)y0;
+  float p00, p01, p10, p11, av;
+  if constexpr (kInside) {
+    const float* b0 = B + (unsigned)(iy * a.W + ix);
+    p00 = b0[0];
+    p01 = b0[1];
+    p10 = b0[a.W];
+    p11 = b0[a.W + 1];
+    av = A[(unsigned)(y * a.W + x)];
+  } else {
+    p00 = ldA(B, a.W, a.H, iy, ix);
+    p01 = ldA(B, a.W, a.H, iy, ix + 1);
+    p10 = ldA(B, a.W, a.H, iy + 1, ix);
+    p11 = ldA(B, a.W, a.H, iy + 1, ix + 1);
+    av = ldA(A, a.W, a.H, y, x);
+  }
+  const float bs = (1.0f - ey) * ((1.0f - ex) * p00 + ex * p01) + ey * ((1.0f - ex) * p10 + ex * p11);
+  r = bs - av;
+  gx = (1.0f - ey) * (p01 - p00) + ey * (p11 - p10);
+  gy = (1.0f - ex) * (p10 - p00) + ex * (p11 - p01);
+}
+
+// the same at region pixel (i, j), its displacement interpolated from the
+// cached nodes
+template <bool kInside, int STEP, int TN>
 __device__ __forceinline__ void ssd_residual(const SsdArgs& a, const float* A, const float* B,
                                              const SsdShared<STEP, TN>& sh, int ylo, int xlo, int i, int j,
                                              float& r, float& gx, float& gy) {
@@ -291,34 +340,7 @@ __device__ __forceinline__ void ssd_residual(const SsdArgs& a, const float* A, c
                   fy * ((1.0f - fx) * sh.node[0][rb + 1][cb] + fx * sh.node[0][rb + 1][cb + 1]);
   const float v = (1.0f - fy) * ((1.0f - fx) * sh.node[1][rb][cb] + fx * sh.node[1][rb][cb + 1]) +
                   fy * ((1.0f - fx) * sh.node[1][rb + 1][cb] + fx * sh.node[1][rb + 1][cb + 1]);
-  const int x = xlo + j, y = ylo + i;
-  const float qx = (float)x + u, qy = (float)y + v;
-  const float x0 = floorf(qx), y0 = floorf(qy);
-  const float ex = qx - x0, ey = qy - y0;
-  const int ix = (int)x0, iy = (int)y0;
-  const float p00 = ldA(B, a.W, a.H, iy, ix), p01 = ldA(B, a.W, a.H, iy, ix + 1);
-  const float p10 = ldA(B, a.W, a.H, iy + 1, ix), p11 = ldA(B, a.W, a.H, iy + 1, ix + 1);
-  const float bs = (1.0f - ey) * ((1.0f - ex) * p00 + ex * p01) + ey * ((1.0f - ex) * p10 + ex * p11);
-  r = bs - ldA(A, a.W, a.H, y, x);
-  gx = (1.0f - ey) * (p01 - p00) + ey * (p11 - p10);
-  gy = (1.0f - ex) * (p10 - p00) + ex * (p11 - p01);
-}
-
-// residual and floor-cell gradient at region pixel (i, j) for a given
-// displacement (u, v) of that pixel
-__device__ __forceinline__ void ssd_residual_uv(const SsdArgs& a, const float* A, const float* B, int ylo, int xlo,
-                                                int i, int j, float u, float v, float& r, float& gx, float& gy) {
-  const int x = xlo + j, y = ylo + i;
-  const float qx = (float)x + u, qy = (float)y + v;
-  const float x0 = floorf(qx), y0 = floorf(qy);
-  const float ex = qx - x0, ey = qy - y0;
-  const int ix = (int)x0, iy = (int)y0;
-  const float p00 = ldA(B, a.W, a.H, iy, ix), p01 = ldA(B, a.W, a.H, iy, ix + 1);
-  const float p10 = ldA(B, a.W, a.H, iy + 1, ix), p11 = ldA(B, a.W, a.H, iy + 1, ix + 1);
-  const float bs = (1.0f - ey) * ((1.0f - ex) * p00 + ex * p01) + ey * ((1.0f - ex) * p10 + ex * p11);
-  r = bs - ldA(A, a.W, a.H, y, x);
-  gx = (1.0f - ey) * (p01 - p00) + ey * (p11 - p10);
-  gy = (1.0f - ex) * (p10 - p00) + ex * (p11 - p01);
+  ssd_residual_uv<kInside>(a, A, B, ylo, xlo, i, j, u, v, r, gx, gy);
 }
 
 // Forward, TN x TN windows per workgroup: squared residuals of the tile's
@@ -342,13 +364,18 @@ __global__ __launch_bounds__(256) void k_ssd_forward_t(SsdArgs a) {
   const int ta = wg.y * TN, tb = wg.x * TN;
   const int ylo = ta * STEP - C::H2, xlo = tb * STEP - C::H2;
   int nly, nlx;
-  ssd_prepare<STEP, TN>(a, U, ylo, xlo, RWF, RWF, sh, nly, nlx);
-  for (int idx = t; idx < RWF * RWF; idx += 256) {
-    const int i = idx / RWF, j = idx - (idx / RWF) * RWF;
-    float r, gx, gy;
-    ssd_residual<STEP, TN>(a, A, B, sh, ylo, xlo, i, j, r, gx, gy);
-    s_r2[idx] = r * r;
-  }
+  const bool interior = ssd_prepare<STEP, TN>(a, U, ylo, xlo, RWF, RWF, sh, nly, nlx);
+  auto squares = [&](auto inside) {
+    constexpr bool kIn = decltype(inside)::value;
+    for (int idx = t; idx < RWF * RWF; idx += 256) {
+      const int i = idx / RWF, j = idx - (idx / RWF) * RWF;
+      float r, gx, gy;
+      ssd_residual<kIn, STEP, TN>(a, A, B, sh, ylo, xlo, i, j, r, gx, gy);
+      s_r2[idx] = r * r;
+    }
+  };
+  if (interior) squares(std::true_type{});
+  else squares(std::false_type{});
   __syncthreads();
   const int w = t >> 2, p = t & 3;
   const int wi = w / TN, wj = w - (w / TN) * TN;
@@ -432,7 +459,7 @@ __global__ __launch_bounds__(256) void k_ssd_backward_t(SsdArgs a) {
   }
   int nly, nlx;
   if (t < C::NNC) s_rfirst[t] = s_rlast[t] = -1;
-  ssd_prepare<STEP, TN>(a, U, ylo, xlo, RH, RWc, sh, nly, nlx);   // (ends with a barrier)
+  const bool interior = ssd_prepare<STEP, TN>(a, U, ylo, xlo, RH, RWc, sh, nly, nlx);   // (ends with a barrier)
   if (t < NCH) s_chb[t] = t * STEP < RWc ? sh.cb[t * STEP] : -100;
   for (int i = t; i < RH; i += 256) {
     const int rb = sh.rb[i];
@@ -478,27 +505,35 @@ __global__ __launch_bounds__(256) void k_ssd_backward_t(SsdArgs a) {
       const float uR = sh.node[0][rb][cbase + 1] + fy * (sh.node[0][rb + 1][cbase + 1] - sh.node[0][rb][cbase + 1]);
       const float vL = sh.node[1][rb][cbase] + fy * (sh.node[1][rb + 1][cbase] - sh.node[1][rb][cbase]);
       const float vR = sh.node[1][rb][cbase + 1] + fy * (sh.node[1][rb + 1][cbase + 1] - sh.node[1][rb][cbase + 1]);
+      // the pixels' terms without the chunk's common factor 2 m, which
+      // scales the sums once below
+      auto pixels = [&](auto inside) {
+        constexpr bool kIn = decltype(inside)::value;
 #pragma unroll
-      for (int e = 0; e < STEP; ++e) {
-        const int j = c * STEP + e;
-        if (j < RWc) {
-          float r, gx, gy;
-          const float fxp = sh.cf[j];
-          ssd_residual_uv(a, A, B, ylo, xlo, i, j, uL + fxp * (uR - uL), vL + fxp * (vR - vL), r, gx, gy);
-          const float f = sh.cf[j], wl = a.nx > 1 ? 1.0f - f : 1.0f, wr = a.nx > 1 ? f : 0.0f;
-          const float t0 = 2.0f * m * r * gx, t1 = 2.0f * m * r * gy;
-          const float t2 = 2.0f * m * gx * gx, t3 = 2.0f * m * gy * gy;
-          acc[0] += wl * t0; acc[1] += wr * t0;
-          acc[2] += wl * t1; acc[3] += wr * t1;
-          acc[4] += wl * wl * t2; acc[5] += wr * wr * t2;
-          acc[6] += wl * wl * t3; acc[7] += wr * wr * t3;
-          if constexpr (kPart) lacc += s_ownc[j] ? r * r : 0.0f;
+        for (int e = 0; e < STEP; ++e) {
+          const int j = c * STEP + e;
+          if (j < RWc) {
+            float r, gx, gy;
+            const float f = sh.cf[j];
+            ssd_residual_uv<kIn>(a, A, B, ylo, xlo, i, j, uL + f * (uR - uL), vL + f * (vR - vL), r, gx, gy);
+            const float wl = a.nx > 1 ? 1.0f - f : 1.0f, wr = a.nx > 1 ? f : 0.0f;
+            const float t0 = r * gx, t1 = r * gy, t2 = gx * gx, t3 = gy * gy;
+            const float wl2 = wl * wl, wr2 = wr * wr;
+            acc[0] += wl * t0; acc[1] += wr * t0;
+            acc[2] += wl * t1; acc[3] += wr * t1;
+            acc[4] += wl2 * t2; acc[5] += wr2 * t2;
+            acc[6] += wl2 * t3; acc[7] += wr2 * t3;
+            if constexpr (kPart) lacc += s_ownc[j] ? r * r : 0.0f;
+          }
         }
-      }
+      };
+      if (interior) pixels(std::true_type{});
+      else pixels(std::false_type{});
     }
     if (kPart && own) lsum += m * lacc;
+    const float m2 = 2.0f * m;
 #pragma unroll
-    for (int k = 0; k < 8; ++k) s_part[i][c][k] = acc[k];
+    for (int k = 0; k < 8; ++k) s_part[i][c][k] = m2 * acc[k];
   }
   __syncthreads();
   // pass 2: thread = (node, term); a node collects the left partials of the
@@ -520,10 +555,21 @@ __global__ __launch_bounds__(256) void k_ssd_backward_t(SsdArgs a) {
       rf = min(rf, s_rfirst[rbn - 1]);
       rl = max(rl, s_rlast[rbn - 1]);
     }
+    // the chunks based on the node's column (their left partials) and on
+    // the column before (their right partials), found once: one or two each
+    // (two where the region's edge chunks are clamped to the end cells;
+    // three when the grid is two nodes wide and every chunk has base 0); a
+    // missing one reads chunk 0 with weight 0
+    int lc[3] = {0, 0, 0}, rc[3] = {0, 0, 0};
+    float lw[3] = {0.0f, 0.0f, 0.0f}, rw[3] = {0.0f, 0.0f, 0.0f};
+    int nl = 0, nr = 0;
     for (int c = 0; c < nchunks; ++c) {
       const int base = s_chb[c];
-      if (base == cbn || (a.nx > 1 && base + 1 == cbn)) { cf0 = min(cf0, c); cl = c; }
+      if (base == cbn && nl < 3) { lc[nl] = c; lw[nl] = 1.0f; ++nl; }
+      if (a.nx > 1 && base + 1 == cbn && nr < 3) { rc[nr] = c; rw[nr] = 1.0f; ++nr; }
     }
+    (void)cf0;
+    (void)cl;
     float s = 0.0f;
     for (int i = rf; i <= rl; ++i) {
       const int rb = sh.rb[i];
@@ -532,11 +578,9 @@ __global__ __launch_bounds__(256) void k_ssd_backward_t(SsdArgs a) {
       if (rb == rbn) wy += a.ny > 1 ? 1.0f - f : 1.0f;
       if (a.ny > 1 && rb + 1 == rbn) wy += f;
       float rowsum = 0.0f;
-      for (int c = cf0; c <= cl; ++c) {
-        const int base = s_chb[c];
-        if (base == cbn) rowsum += s_part[i][c][2 * term];
-        if (base + 1 == cbn) rowsum += s_part[i][c][2 * term + 1];
-      }
+#pragma unroll
+      for (int q = 0; q < 3; ++q)
+        rowsum += lw[q] * s_part[i][lc[q]][2 * term] + rw[q] * s_part[i][rc[q]][2 * term + 1];
       s += (sq ? wy * wy : wy) * rowsum;
     }
     const int idx = na * a.nx + nb;

@@ -47,7 +47,9 @@ def cell_edge_nodes(U, W, H, step=8, win=16, eps=1e-4):
     return mark
 
 
-@pytest.mark.parametrize("W,H,n", [(128, 96, 3), (512, 512, 2)])
+# (the small grids: two and three nodes wide, where every or two edge chunks
+# of the adjoint's region share a base node, and a last tile one node wide)
+@pytest.mark.parametrize("W,H,n", [(128, 96, 3), (512, 512, 2), (16, 24, 2), (24, 16, 2), (72, 40, 2)])
 def test_ssd_forward_backward_parity(W, H, n):
     from paper_2504_17987_amd import api
     say(f"[ssd] {W}x{H} n={n}")
@@ -67,7 +69,7 @@ def test_ssd_forward_backward_parity(W, H, n):
         kink = cell_edge_nodes(Ui, W, H)
         ok = ~kink
         say(f"  pair {i}: {int(kink.sum())} of {kink.size} node components next to a cell edge excluded")
-        assert ok.mean() > 0.9
+        assert ok.mean() > (0.9 if W * H >= 128 * 96 else 0.5)
         eg = float(np.abs(gU[i] - go)[ok].max() / np.abs(go).max())
         eD = float(np.abs(D[i] - Do)[ok].max() / np.abs(Do).max())
         say(f"  pair {i}: rel err grad {eg:.2e}, GN diag {eD:.2e}")
