@@ -14,20 +14,22 @@ namespace {
 
 // ---------------------------------------------------------------------------
 // High-pass: out = max(0, I - floor(sum / count)) over the image part of the
-// (2r+1)^2 box around each pixel.  A workgroup owns HR rows x HQ columns of
-// output: it stages the tile with an r-pixel halo in LDS (aligned word
-// loads), forms the horizontal box sums of every staged row (a running sum
-// per 16-column segment), then the vertical sums for four columns at a time
-// (one 16-byte LDS read per row) and writes four pixels per store.  The
-// pixel count of the clipped box is a product of two clipped spans; the
-// quotient comes from a float reciprocal, corrected to the exact floor.
+// (2r+1)^2 box around each pixel.  One wave owns a strip of columns and a
+// band of rows and walks down it: lane L holds the vertical box sums of the
+// PX pixels of one aligned word (PX = 4 for u8, 2 for u16), updated per row
+// by the row entering and the row leaving the box (each a coalesced word
+// read; the leaving row comes from cache); the wave's sums go through LDS,
+// where each lane adds the 2r+1 columns around its pixels.  The strip's
+// first and last h = ceil(r / PX) lanes only supply sums, so strips overlap
+// by 2h words.  The pixel count of the clipped box is a product of two
+// clipped spans; the quotient comes from a float reciprocal, corrected to
+// the exact floor.
 // ---------------------------------------------------------------------------
-constexpr int HQ = 128, HR = 32, kMaxR = 16;
-constexpr int HRW = HQ + 2 * kMaxR + 4, HRH = HR + 2 * kMaxR;
-static_assert(HQ / 16 == 8, "row-sum thread layout");
+constexpr int HBAND = 64;
 
-// floor(s / c) for s < 2^27, 1 <= c < 2^11: the float estimate is within
-// two of the quotient, then integer corrections make it exact
+// floor(s / c) for quotients below 2^16 (s < 2^27, 1 <= c < 2^11): the
+// float estimate is then within one of the quotient, and integer
+// corrections make it exact
 __device__ __forceinline__ uint32_t udiv_small(uint32_t s, uint32_t c) {
   int q = (int)((float)s * __builtin_amdgcn_rcpf((float)c));
   int r = (int)s - q * (int)c;
@@ -39,100 +41,139 @@ __device__ __forceinline__ uint32_t udiv_small(uint32_t s, uint32_t c) {
   return (uint32_t)q;
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_highpass(const uint8_t* __restrict__ in, uint8_t* __restrict__ out,
-                                                  int64_t pitch, int64_t stride, int W, int H, int r,
-                                                  const uint8_t* mask) {
-  constexpr int ES = (int)sizeof(T), PW = 4 / ES;   // pixels per word
-  __shared__ uint16_t reg[HRH][HRW];                 // staged pixels (0 outside the image)
-  __shared__ __align__(16) uint32_t hs[HRH][HQ];    // horizontal box sums of the output columns
+// floor(s / d) for the whole box, d = (2R+1)^2, s < 2^27: the product with
+// M = ceil(2^(32+k) / d), k = ceil(log2 d) - 1 (so that M < 2^32), keeps
+// its error s (M d - 2^(32+k)) / d below 2^(32+k) / d > 2^31 > s, hence exact
+template <int D>
+struct BoxDiv {
+  static constexpr int K = []() { int k = 0; while ((1 << (k + 1)) < D) ++k; return k; }();
+  static constexpr uint32_t M = (uint32_t)((((uint64_t)1 << (32 + K)) + D - 1) / D);
+  static_assert((1ull << K) < (unsigned long long)D && (((uint64_t)1 << (32 + K)) / D) > (1u << 27), "magic range");
+};
+
+template <typename T, int R>
+__global__ __launch_bounds__(64) void k_highpass(const uint8_t* __restrict__ in, uint8_t* __restrict__ out,
+                                                 int64_t pitch, int64_t stride, int W, int H,
+                                                 const uint8_t* mask) {
+  constexpr int ES = (int)sizeof(T), PX = 4 / ES;   // pixels per word
+  constexpr int r = R;
+  using Div = BoxDiv<(2 * R + 1) * (2 * R + 1)>;
+  __shared__ uint32_t vbuf[2][64 * PX + 1];          // the wave's vertical sums of a row (two rows alternate)
   const int pair = blockIdx.z;
   if (slot_off(mask, pair)) return;
-  const int t = threadIdx.x;
-  const int x0 = blockIdx.x * HQ, y0 = blockIdx.y * HR;
-  const int RW = HQ + 2 * r, RH = HR + 2 * r;
-  const uint8_t* src = in + (int64_t)pair * stride;
+  const int L = threadIdx.x;
+  constexpr int h = (r + PX - 1) / PX, nout = 64 - 2 * h;
+  const int word = blockIdx.x * nout + L - h;        // this lane's word column (may lie off the image)
+  const int xa = 4 * word;                           // its byte offset in a row
   const int rowbytes = W * ES;
-  // aligned words covering region columns [x0 - r, x0 + HQ + r)
-  const int xl = x0 - r;
-  const int w0 = (xl * ES) >> 2;                     // (arithmetic shift: floor)
-  const int nw = (((x0 + HQ + r) * ES + 3) >> 2) - w0;
-  // thread = (word column k of 64, row group of 4); u16 rows take up to
-  // two words per thread column
-  for (int k = t & 63; k < nw; k += 64) {
-    {
-      const int xa = 4 * (w0 + k);
-      for (int ry = t >> 6; ry < RH; ry += 4) {
-        const int y = y0 - r + ry;
-        const uint32_t ok = (unsigned)y < (unsigned)H ? 0xffffffffu : 0u;
-        const uint32_t wd = masked_word(src + (int64_t)min(max(y, 0), H - 1) * pitch, rowbytes, xa) & ok;
+  const uint8_t* src = in + (int64_t)pair * stride;
+  // the lane's word in a row, zero where it leaves the image (the column
+  // clamp and byte mask are the lane's own, the row's test is uniform)
+  const int xc = min(max(xa, 0), (rowbytes - 1) & ~3);
+  const int valid = rowbytes - xa;
+  const uint32_t keep = (xa < 0 || valid <= 0) ? 0u : (valid >= 4 ? 0xffffffffu : (1u << (8 * (valid & 3))) - 1u);
+  auto row_word = [&](int y) -> uint32_t {
+    const uint32_t ok = (unsigned)y < (unsigned)H ? keep : 0u;
+    return *reinterpret_cast<const uint32_t*>(src + (int64_t)min(max(y, 0), H - 1) * pitch + xc) & ok;
+  };
+  auto px = [&](uint32_t w, int e) -> uint32_t { return ES == 1 ? (w >> (8 * e)) & 0xffu : (w >> (16 * e)) & 0xffffu; };
+  const bool outl = L >= h && L < 64 - h;            // lanes whose pixels are written
+  const int x0 = word * PX;                          // first pixel column of the lane
+  uint32_t cx[PX];
+  bool fx = true;
 #pragma unroll
-        for (int e = 0; e < PW; ++e) {
-          const int c = xa / ES + e - xl;   // region column
-          if (c >= 0 && c < RW)
-            reg[ry][c] = (uint16_t)(ES == 1 ? (wd >> (8 * e)) & 0xffu : (wd >> (16 * e)) & 0xffffu);
+  for (int e = 0; e < PX; ++e) {
+    cx[e] = (uint32_t)(min(x0 + e + r, W - 1) - max(x0 + e - r, 0) + 1);
+    fx = fx && cx[e] == 2 * r + 1;
+  }
+  // (every written pixel of the strip has its box's full width)
+  const bool full_x = __all(fx || !(L >= h && L < 64 - h));
+  const int ys = blockIdx.y * HBAND, ye = min(ys + HBAND, H);
+  uint32_t V[PX];
+#pragma unroll
+  for (int e = 0; e < PX; ++e) V[e] = 0u;
+  for (int dy = -r; dy <= r; ++dy) {
+    const uint32_t w = row_word(ys + dy);
+#pragma unroll
+    for (int e = 0; e < PX; ++e) V[e] += px(w, e);
+  }
+  uint8_t* dst = out + (int64_t)pair * stride;
+  // rows in groups of G: the words of the next group (entering, leaving and
+  // centre rows) are requested while this group is worked
+  constexpr int G = 4;
+  uint32_t ci[G], co[G], cc[G], ni[G], no[G], nc[G];
+  auto fetch = [&](int yg, uint32_t* wi, uint32_t* wo, uint32_t* wc) {
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      wi[g] = row_word(yg + g + r);
+      wo[g] = row_word(yg + g - r - 1);
+      wc[g] = row_word(yg + g);
+    }
+  };
+  fetch(ys, ci, co, cc);
+  for (int yg = ys; yg < ye; yg += G) {
+    if (yg + G < ye) fetch(yg + G, ni, no, nc);
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const int y = yg + g;
+      if (y >= ye) break;
+      if (y > ys) {
+#pragma unroll
+        for (int e = 0; e < PX; ++e) V[e] += px(ci[g], e) - px(co[g], e);
+      }
+      const uint32_t wc = cc[g];
+      // (rows alternate between two buffers: a row's buffer is written again
+      // two rows later, after the next row's barrier, when every lane has
+      // finished reading it)
+      uint32_t* vb = vbuf[(y - ys) & 1];
+#pragma unroll
+      for (int e = 0; e < PX; ++e) vb[L * PX + e] = V[e];
+      __syncthreads();
+      if (outl) {
+        // box sums of the lane's pixels: the first by 2r+1 columns, then slid
+        const int c0 = L * PX;
+        uint32_t hsum = 0u;
+#pragma unroll
+        for (int i = -r; i <= r; ++i) hsum += vb[c0 + i];
+        const uint32_t cy = (uint32_t)(min(y + r, H - 1) - max(y - r, 0) + 1);
+        uint32_t hs[PX];
+#pragma unroll
+        for (int e = 0; e < PX; ++e) {
+          if (e) hsum += vb[c0 + e + r] - vb[c0 + e - 1 - r];
+          hs[e] = hsum;
+        }
+        uint32_t m[PX];
+        if (cy == 2 * r + 1 && full_x) {
+          // the whole box inside the image (the usual case, taken by the
+          // whole wave): the constant divisor's product
+#pragma unroll
+          for (int e = 0; e < PX; ++e) m[e] = __umulhi(hs[e], Div::M) >> Div::K;
+        } else {
+#pragma unroll
+          for (int e = 0; e < PX; ++e) m[e] = udiv_small(hs[e], cx[e] * cy);
+        }
+        uint32_t o[PX];
+#pragma unroll
+        for (int e = 0; e < PX; ++e) {
+          const uint32_t I = px(wc, e);
+          o[e] = I > m[e] ? I - m[e] : 0u;
+        }
+        T* orow = reinterpret_cast<T*>(dst + (int64_t)y * pitch);
+        if (x0 >= 0 && x0 + PX <= W) {
+          if constexpr (ES == 1) *reinterpret_cast<uint32_t*>(orow + x0) = o[0] | (o[1] << 8) | (o[2] << 16) | (o[3] << 24);
+          else *reinterpret_cast<uint32_t*>(orow + x0) = o[0] | (o[1] << 16);
+        } else {
+#pragma unroll
+          for (int e = 0; e < PX; ++e)
+            if (x0 + e >= 0 && x0 + e < W) orow[x0 + e] = (T)o[e];
         }
       }
     }
-  }
-  __syncthreads();
-  for (int i = t; i < RH * (HQ / 16); i += 256) {
-    const int ry = i >> 3, c0 = (i & 7) * 16;
-    uint32_t sm = 0u;
-    for (int u = 0; u <= 2 * r; ++u) sm += reg[ry][c0 + u];
-    hs[ry][c0] = sm;
 #pragma unroll
-    for (int c = 1; c < 16; ++c) {
-      sm += (uint32_t)reg[ry][c0 + c + 2 * r] - (uint32_t)reg[ry][c0 + c - 1];
-      hs[ry][c0 + c] = sm;
-    }
-  }
-  __syncthreads();
-  // vertical sums: thread = (quad of columns, segment of 4 rows)
-  const int q = t & (HQ / 4 - 1), seg = t / (HQ / 4);
-  const int xq = x0 + 4 * q;
-  if (xq >= W) return;
-  uint32_t cx[4];
-#pragma unroll
-  for (int e = 0; e < 4; ++e) cx[e] = (uint32_t)(min(xq + e + r, W - 1) - max(xq + e - r, 0) + 1);
-  constexpr int RSEG = HR / (256 / (HQ / 4));       // rows per thread
-  const int r0 = seg * RSEG;
-  uint32_t sm[4] = {0u, 0u, 0u, 0u};
-  for (int v = 0; v <= 2 * r; ++v) {
-    const uint4 h = *reinterpret_cast<const uint4*>(&hs[r0 + v][4 * q]);
-    sm[0] += h.x; sm[1] += h.y; sm[2] += h.z; sm[3] += h.w;
-  }
-  uint8_t* dst = out + (int64_t)pair * stride;
-  const bool full = xq + 4 <= W;
-#pragma unroll
-  for (int k = 0; k < RSEG; ++k) {
-    if (k) {
-      const uint4 hi = *reinterpret_cast<const uint4*>(&hs[r0 + k + 2 * r][4 * q]);
-      const uint4 lo = *reinterpret_cast<const uint4*>(&hs[r0 + k - 1][4 * q]);
-      sm[0] += hi.x - lo.x; sm[1] += hi.y - lo.y; sm[2] += hi.z - lo.z; sm[3] += hi.w - lo.w;
-    }
-    const int y = y0 + r0 + k;
-    if (y >= H) break;
-    const uint32_t cy = (uint32_t)(min(y + r, H - 1) - max(y - r, 0) + 1);
-    uint32_t o[4];
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const uint32_t m = udiv_small(sm[e], cx[e] * cy);
-      const uint32_t I = reg[r0 + k + r][4 * q + e + r];
-      o[e] = I > m ? I - m : 0u;
-    }
-    T* orow = reinterpret_cast<T*>(dst + (int64_t)y * pitch);
-    if (full) {
-      if constexpr (ES == 1) {
-        *reinterpret_cast<uint32_t*>(orow + xq) = o[0] | (o[1] << 8) | (o[2] << 16) | (o[3] << 24);
-      } else {
-        *reinterpret_cast<uint32_t*>(orow + xq) = o[0] | (o[1] << 16);
-        *reinterpret_cast<uint32_t*>(orow + xq + 2) = o[2] | (o[3] << 16);
-      }
-    } else {
-#pragma unroll
-      for (int e = 0; e < 4; ++e)
-        if (xq + e < W) orow[xq + e] = (T)o[e];
+    for (int g = 0; g < G; ++g) {
+      ci[g] = ni[g];
+      co[g] = no[g];
+      cc[g] = nc[g];
     }
   }
 }
@@ -420,14 +461,28 @@ int clahe_bins(const Plan& P) {
 }
 
 hipError_t launch_highpass(const Plan& P, const void* in, void* out, int64_t pitch, int n, int r, hipStream_t s) {
-  dim3 grid((P.p.width + HQ - 1) / HQ, (P.p.height + HR - 1) / HR, n);
+  const int px = P.es == 1 ? 4 : 2;
+  const int nout = 64 - 2 * ((r + px - 1) / px);       // words written per strip
+  const int words = (P.p.width + px - 1) / px;
+  dim3 grid((words + nout - 1) / nout, (P.p.height + HBAND - 1) / HBAND, n);
   const int64_t stride = pitch * P.p.height;
-  if (P.es == 1)
-    hipLaunchKernelGGL(k_highpass<uint8_t>, grid, dim3(256), 0, s, (const uint8_t*)in, (uint8_t*)out, pitch, stride,
-                       P.p.width, P.p.height, r, P.slot_mask);
-  else
-    hipLaunchKernelGGL(k_highpass<uint16_t>, grid, dim3(256), 0, s, (const uint8_t*)in, (uint8_t*)out, pitch,
-                       stride, P.p.width, P.p.height, r, P.slot_mask);
+  const uint8_t* i8 = (const uint8_t*)in;
+  uint8_t* o8 = (uint8_t*)out;
+  switch (r) {
+#define PIV_HP(R_)                                                                                               \
+  case R_:                                                                                                     \
+    if (P.es == 1)                                                                                             \
+      hipLaunchKernelGGL((k_highpass<uint8_t, R_>), grid, dim3(64), 0, s, i8, o8, pitch, stride, P.p.width,   \
+                         P.p.height, P.slot_mask);                                                              \
+    else                                                                                                       \
+      hipLaunchKernelGGL((k_highpass<uint16_t, R_>), grid, dim3(64), 0, s, i8, o8, pitch, stride, P.p.width,  \
+                         P.p.height, P.slot_mask);                                                              \
+    break;
+    PIV_HP(1) PIV_HP(2) PIV_HP(3) PIV_HP(4) PIV_HP(5) PIV_HP(6) PIV_HP(7) PIV_HP(8)
+    PIV_HP(9) PIV_HP(10) PIV_HP(11) PIV_HP(12) PIV_HP(13) PIV_HP(14) PIV_HP(15) PIV_HP(16)
+#undef PIV_HP
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
