@@ -383,18 +383,38 @@ __global__ __launch_bounds__(256) void k_clahe_map(const uint8_t* in, uint8_t* o
   }
   __syncthreads();
   const uint16_t* sl = reinterpret_cast<const uint16_t*>(s_lut);
-  auto L = [&](int jj, int ii, int b) -> int {
-    if constexpr (kStaged) return sl[((jj - j0) * ni + (ii - i0)) * nbins + b];
-    else return Lp[((int64_t)jj * tx + ii) * nbins + b];
+  // a mapping entry at (row part, column part, bin): the staged copy or the
+  // global one, with the parts of the offset formed once per row and column
+  auto L = [&](int rpart, int cpart, int b) -> int {
+    if constexpr (kStaged) return sl[rpart + cpart + b];
+    else return Lp[(int64_t)rpart + cpart + b];
   };
+  auto rpart_of = [&](int jj) { return kStaged ? (jj - j0) * ni * nbins : jj * tx * nbins; };
+  auto cpart_of = [&](int ii) { return kStaged ? (ii - i0) * nbins : ii * nbins; };
   const int c0 = 4 * t;
   if (c0 >= nq) return;
   const int xq = x0 + c0;
   const bool full = c0 + 4 <= nq;
+  // this thread's four columns: tiles, weights and mapping offsets (the
+  // same on every row)
+  int ca[4], cb[4], cwx[4], cdx[4];
+  float rdx[4];   // 1 / dx (the quotient's estimate is corrected exactly below)
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int c = min(c0 + e, nq - 1);
+    const uint32_t ax = s_ax[c];
+    ca[e] = cpart_of((int)(ax & 0xff));
+    cb[e] = cpart_of((int)((ax >> 8) & 0xff));
+    cwx[e] = (int)(ax >> 16);
+    cdx[e] = s_ad[c];
+    rdx[e] = __builtin_amdgcn_rcpf((float)cdx[e]);
+  }
   for (int k = 0; k < MR; ++k) {
     const int y = y0 + k;
     if (y >= H) break;
     const Axis ay = s_ay[k];
+    const int ra = rpart_of(ay.a), rb = rpart_of(ay.b);
+    const float rdy = __builtin_amdgcn_rcpf((float)ay.d);
     const T* row = reinterpret_cast<const T*>(in + (int64_t)pair * stride + (int64_t)y * pitch);
     T* orow = reinterpret_cast<T*>(out + (int64_t)pair * stride + (int64_t)y * pitch);
     uint32_t v[4];
@@ -415,23 +435,23 @@ __global__ __launch_bounds__(256) void k_clahe_map(const uint8_t* in, uint8_t* o
     uint32_t o[4];
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      const int c = min(c0 + e, nq - 1);
-      const uint32_t ax = s_ax[c];
-      const int ia = ax & 0xff, ib = (ax >> 8) & 0xff, wx = (int)(ax >> 16), dx = s_ad[c];
+      const int wx = cwx[e], dx = cdx[e];
       const int b = (int)(v[e] >> shift);
       if constexpr (kNarrow) {
         // every numerator and denominator below 2^24 (checked on the host):
         // float estimate of the rounded quotient, then an exact correction
-        const int l00 = L(ay.a, ia, b), l01 = L(ay.a, ib, b), l10 = L(ay.b, ia, b), l11 = L(ay.b, ib, b);
+        const int l00 = L(ra, ca[e], b), l01 = L(ra, cb[e], b), l10 = L(rb, ca[e], b), l11 = L(rb, cb[e], b);
         const int num = (ay.d - ay.w) * ((dx - wx) * l00 + wx * l01) + ay.w * ((dx - wx) * l10 + wx * l11);
         const int den = dx * ay.d;
         const int n2 = num + den / 2;
-        int q = (int)((float)n2 * __builtin_amdgcn_rcpf((float)den));
+        // (the rounded quotient is below 2^16, so the estimate from the two
+        // reciprocals is within one of it)
+        int q = (int)((float)n2 * rdx[e] * rdy);
         int rr = n2 - q * den;
         q += rr < 0 ? -1 : (rr >= den ? 1 : 0);
         o[e] = (uint32_t)q;
       } else {
-        const int64_t l00 = L(ay.a, ia, b), l01 = L(ay.a, ib, b), l10 = L(ay.b, ia, b), l11 = L(ay.b, ib, b);
+        const int64_t l00 = L(ra, ca[e], b), l01 = L(ra, cb[e], b), l10 = L(rb, ca[e], b), l11 = L(rb, cb[e], b);
         const int64_t num = (int64_t)(ay.d - ay.w) * ((dx - wx) * l00 + wx * l01) +
                             (int64_t)ay.w * ((dx - wx) * l10 + wx * l11);
         const int64_t den = (int64_t)dx * ay.d;
