@@ -292,40 +292,59 @@ __device__ __forceinline__ bool ssd_prepare(const SsdArgs& a, const float* U, in
   return __syncthreads_and(inside ? 1 : 0) != 0;
 }
 
-// residual r = B'(p) - A(p) at region pixel (i, j) = (y - ylo, x - xlo), and
-// the floor-cell gradient of the sample
-
-// residual and floor-cell gradient at region pixel (i, j) for a given
-// displacement (u, v) of that pixel; kInside: the tile is interior (every
-// read in the frames), so the reads need no bounds tests and take 32-bit
-// offsets from the frame base
+// bilinear sample bs = B(x + u, y + v) at the pixel (x, y), given as floats
+// xf, yf, and its floor-cell gradient: with top/bottom the row
+// interpolations of the cell, bs = top + ey (bottom - top), dbs/dy =
+// bottom - top and dbs/dx the row differences interpolated in y.  kInside:
+// the tile is interior (every read in the frames), so the reads need no
+// bounds tests and take 32-bit byte offsets from the frame base (a frame
+// holds fewer than 2^30 pixels).
 template <bool kInside>
-__device__ __forceinline__ void ssd_residual_uv(const SsdArgs& a, const float* A, const float* B, int ylo, int xlo,
-                                                int i, int j, float u, float v, float& r, float& gx, float& gy) {
-  const int x = xlo + j, y = ylo + i;
-  const float qx = (float)x + u, qy = (float)y + v;
+__device__ __forceinline__ void ssd_sample(const SsdArgs& a, const float* B, float xf, float yf, float u, float v,
+                                           float& bs, float& gx, float& gy) {
+  const float qx = xf + u, qy = yf + v;
   const float x0 = floorf(qx), y0 = floorf(qy);
   const float ex = qx - x0, ey = qy - y0;
   const int ix = (int)x0, iy = (int)y0;
-  float p00, p01, p10, p11, av;
+  float p00, p01, p10, p11;
   if constexpr (kInside) {
-    const float* b0 = B + (unsigned)(iy * a.W + ix);
-    p00 = b0[0];
-    p01 = b0[1];
-    p10 = b0[a.W];
-    p11 = b0[a.W + 1];
-    av = A[(unsigned)(y * a.W + x)];
+    const char* Bb = reinterpret_cast<const char*>(B);
+    const uint32_t o = 4u * (uint32_t)(iy * a.W + ix), ow = 4u * (uint32_t)a.W;
+    p00 = *reinterpret_cast<const float*>(Bb + o);
+    p01 = *reinterpret_cast<const float*>(Bb + o + 4u);
+    p10 = *reinterpret_cast<const float*>(Bb + (o + ow));
+    p11 = *reinterpret_cast<const float*>(Bb + (o + ow) + 4u);
   } else {
     p00 = ldA(B, a.W, a.H, iy, ix);
     p01 = ldA(B, a.W, a.H, iy, ix + 1);
     p10 = ldA(B, a.W, a.H, iy + 1, ix);
     p11 = ldA(B, a.W, a.H, iy + 1, ix + 1);
-    av = ldA(A, a.W, a.H, y, x);
   }
-  const float bs = (1.0f - ey) * ((1.0f - ex) * p00 + ex * p01) + ey * ((1.0f - ex) * p10 + ex * p11);
-  r = bs - av;
-  gx = (1.0f - ey) * (p01 - p00) + ey * (p11 - p10);
-  gy = (1.0f - ex) * (p10 - p00) + ex * (p11 - p01);
+  const float d0 = p01 - p00, d1 = p11 - p10;
+  const float top = p00 + ex * d0, bot = p10 + ex * d1;
+  gy = bot - top;
+  bs = top + ey * gy;
+  gx = d0 + ey * (d1 - d0);
+}
+
+// A at the pixel (x, y) (zero outside the frame)
+template <bool kInside>
+__device__ __forceinline__ float ssd_a(const SsdArgs& a, const float* A, int x, int y) {
+  if constexpr (kInside)
+    return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(A) + 4u * (uint32_t)(y * a.W + x));
+  else
+    return ldA(A, a.W, a.H, y, x);
+}
+
+// residual r = B'(p) - A(p) and the sample's gradient at the pixel (x, y)
+// for a given displacement (u, v) of that pixel
+template <bool kInside>
+__device__ __forceinline__ void ssd_residual_uv(const SsdArgs& a, const float* A, const float* B, int x, int y,
+                                                float xf, float yf, float u, float v, float& r, float& gx,
+                                                float& gy) {
+  float bs;
+  ssd_sample<kInside>(a, B, xf, yf, u, v, bs, gx, gy);
+  r = bs - ssd_a<kInside>(a, A, x, y);
 }
 
 // the same at region pixel (i, j), its displacement interpolated from the
@@ -340,7 +359,7 @@ __device__ __forceinline__ void ssd_residual(const SsdArgs& a, const float* A, c
                   fy * ((1.0f - fx) * sh.node[0][rb + 1][cb] + fx * sh.node[0][rb + 1][cb + 1]);
   const float v = (1.0f - fy) * ((1.0f - fx) * sh.node[1][rb][cb] + fx * sh.node[1][rb][cb + 1]) +
                   fy * ((1.0f - fx) * sh.node[1][rb + 1][cb] + fx * sh.node[1][rb + 1][cb + 1]);
-  ssd_residual_uv<kInside>(a, A, B, ylo, xlo, i, j, u, v, r, gx, gy);
+  ssd_residual_uv<kInside>(a, A, B, xlo + j, ylo + i, (float)(xlo + j), (float)(ylo + i), u, v, r, gx, gy);
 }
 
 // Forward, TN x TN windows per workgroup: squared residuals of the tile's
@@ -423,6 +442,7 @@ template <int STEP, int TN, bool kPart>
 __global__ __launch_bounds__(256) void k_ssd_backward_t(SsdArgs a) {
   using C = SsdTile<STEP, TN>;
   constexpr int NCH = C::RW / STEP;                    // chunks per region row
+  static_assert(STEP % 4 == 0, "chunks of whole groups of four pixels");
   __shared__ SsdShared<STEP, TN> sh;
   __shared__ float s_part[C::RW][NCH][8];              // [row][chunk][term*2 + side]
   __shared__ float s_g[C::NG][C::NG];                  // upstream window gradients
@@ -430,6 +450,7 @@ __global__ __launch_bounds__(256) void k_ssd_backward_t(SsdArgs a) {
   __shared__ int s_rfirst[C::NNC], s_rlast[C::NNC];    // region rows based on each cached node row
   __shared__ float s_red[256];                         // fixed-order tile sums
   __shared__ uint8_t s_ownr[C::RW], s_ownc[C::RW];     // region rows / columns whose nearest node is the tile's
+  __shared__ float4 s_cw[C::RW];                       // per region column: wr (the fraction), wl, wr^2, wl^2
   const WgIdx wg = xcd_order();
   const int pair = wg.z;
   if (slot_off(a.mask, pair)) return;
@@ -466,6 +487,13 @@ __global__ __launch_bounds__(256) void k_ssd_backward_t(SsdArgs a) {
     if (i == 0 || sh.rb[i - 1] != rb) s_rfirst[rb] = i;
     if (i == RH - 1 || sh.rb[i + 1] != rb) s_rlast[rb] = i;
   }
+  // column weights towards the left and right node columns (one node
+  // column: all on the left)
+  for (int j = t; j < RWc; j += 256) {
+    const float f = sh.cf[j];
+    const float wr = a.nx > 1 ? f : 0.0f, wl = a.nx > 1 ? 1.0f - f : 1.0f;
+    s_cw[j] = make_float4(wr, wl, wr * wr, wl * wl);
+  }
   // (the loss: a pixel counts at the tile holding its nearest node, whose
   // support region holds it)
   for (int i = t; kPart && i < RH + RWc; i += 256) {
@@ -479,6 +507,9 @@ __global__ __launch_bounds__(256) void k_ssd_backward_t(SsdArgs a) {
   }
   __syncthreads();
   const int nchunks = (RWc + STEP - 1) / STEP;
+  // chunks start 16-byte aligned in A (frame base, row length and the
+  // region's first column multiples of four floats)
+  const bool a16 = (reinterpret_cast<uintptr_t>(A) & 15) == 0 && (a.W & 3) == 0 && (xlo & 3) == 0;
   float lsum = 0.0f;   // this thread's share of the tile's loss (owned items)
   for (int item = t; item < RH * nchunks; item += 256) {
     const int i = item / nchunks, c = item - (item / nchunks) * nchunks;
@@ -506,25 +537,45 @@ __global__ __launch_bounds__(256) void k_ssd_backward_t(SsdArgs a) {
       const float vL = sh.node[1][rb][cbase] + fy * (sh.node[1][rb + 1][cbase] - sh.node[1][rb][cbase]);
       const float vR = sh.node[1][rb][cbase + 1] + fy * (sh.node[1][rb + 1][cbase + 1] - sh.node[1][rb][cbase + 1]);
       // the pixels' terms without the chunk's common factor 2 m, which
-      // scales the sums once below
+      // scales the sums once below; a whole chunk (every one when the
+      // region width is a multiple of STEP) runs without per-pixel tests,
+      // so its pixels' reads can be in flight together
+      const float xf0 = (float)x0c, yf = (float)y;
       auto pixels = [&](auto inside) {
         constexpr bool kIn = decltype(inside)::value;
-#pragma unroll
-        for (int e = 0; e < STEP; ++e) {
+        auto px = [&](int e, float av) __attribute__((always_inline)) {
           const int j = c * STEP + e;
-          if (j < RWc) {
-            float r, gx, gy;
-            const float f = sh.cf[j];
-            ssd_residual_uv<kIn>(a, A, B, ylo, xlo, i, j, uL + f * (uR - uL), vL + f * (vR - vL), r, gx, gy);
-            const float wl = a.nx > 1 ? 1.0f - f : 1.0f, wr = a.nx > 1 ? f : 0.0f;
-            const float t0 = r * gx, t1 = r * gy, t2 = gx * gx, t3 = gy * gy;
-            const float wl2 = wl * wl, wr2 = wr * wr;
-            acc[0] += wl * t0; acc[1] += wr * t0;
-            acc[2] += wl * t1; acc[3] += wr * t1;
-            acc[4] += wl2 * t2; acc[5] += wr2 * t2;
-            acc[6] += wl2 * t3; acc[7] += wr2 * t3;
-            if constexpr (kPart) lacc += s_ownc[j] ? r * r : 0.0f;
+          const float4 w = s_cw[j];
+          float bs, gx, gy;
+          ssd_sample<kIn>(a, B, xf0 + (float)e, yf, uL + w.x * (uR - uL), vL + w.x * (vR - vL), bs, gx, gy);
+          const float r = bs - av;
+          const float t0 = r * gx, t1 = r * gy, t2 = gx * gx, t3 = gy * gy;
+          acc[0] += w.y * t0; acc[1] += w.x * t0;
+          acc[2] += w.y * t1; acc[3] += w.x * t1;
+          acc[4] += w.w * t2; acc[5] += w.z * t2;
+          acc[6] += w.w * t3; acc[7] += w.z * t3;
+          if constexpr (kPart) lacc += s_ownc[j] ? r * r : 0.0f;
+        };
+        if (kIn && a16 && (c + 1) * STEP <= RWc) {
+          // A's pixels of the chunk four at a time (16-byte aligned)
+          const float4* a4 = reinterpret_cast<const float4*>(reinterpret_cast<const char*>(A) +
+                                                             4u * (uint32_t)(y * a.W + x0c));
+#pragma unroll 1
+          for (int e4 = 0; e4 < STEP; e4 += 4) {
+            const float4 av = a4[e4 / 4];
+            px(e4, av.x);
+            px(e4 + 1, av.y);
+            px(e4 + 2, av.z);
+            px(e4 + 3, av.w);
           }
+        } else if ((c + 1) * STEP <= RWc) {
+#pragma unroll 1
+          for (int e4 = 0; e4 < STEP; e4 += 4) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) px(e4 + e, ssd_a<kIn>(a, A, x0c + e4 + e, y));
+          }
+        } else {
+          for (int e = 0; e < STEP && c * STEP + e < RWc; ++e) px(e, ssd_a<kIn>(a, A, x0c + e, y));
         }
       };
       if (interior) pixels(std::true_type{});
