@@ -93,85 +93,98 @@ struct Cand {
   uint32_t code[kPer]; // tie code (|dx|+|dy|, dy, dx) of the winner search
 };
 
-// One path direction over one line of nodes by one wave.  The next node's
-// cost and (when adding) its running sum are requested before this node is
-// worked, so the global reads overlap a whole node's work.  With `write`
-// the path's costs are stored into S (the first of the four passes),
-// otherwise added; with `wta` (the last pass) the node's total is final and
-// its winner, the least (S, |dx|+|dy|, dy, dx), is written.
-template <int kPer>
+// One path direction over one line of nodes by one wave.  The costs (and
+// the running sums) of the node two ahead are requested before a node is
+// worked, into two register sets used in turn, so the global reads overlap
+// more than one node's work.  The workgroup is the one wave: its LDS reads
+// and writes complete in program order, so the exchange of the previous
+// node's costs needs no barrier (and none that would wait for the requests
+// in flight).  kWrite: the path's costs are stored into S (the first of the
+// four passes), otherwise added; kWta (the last pass): the node's total is
+// final and its winner, the least (S, |dx|+|dy|, dy, dx), is written.
+template <int kPer, bool kWrite, bool kWta>
 __device__ void sgm_path(const SgmArgs& g, const Cand<kPer>& cd, const uint32_t* C, uint32_t* S, int len,
-                         int64_t nstride, bool reverse, bool write, bool wta, uint32_t* prev, int32_t* out,
-                         int node0, int nodestep) {
+                         int64_t nstride, bool reverse, uint32_t* prev, int32_t* out, int node0, int nodestep) {
   const int t = threadIdx.x;
   const int P = 2 * g.R + 3;
   const int np = g.nx * g.ny;
-  uint32_t cn[kPer], sn[kPer];
-  auto request = [&](int s) {
-    const int pos = reverse ? len - 1 - s : s;
+  // (unconditional reads, padding lanes from the node's first candidate and
+  // nodes past the end from the last node, so that the requests in flight
+  // need no branches; the values are masked where they are used)
+  auto request = [&](int s, uint32_t (&c_)[kPer], uint32_t (&s_)[kPer]) __attribute__((always_inline)) {
+    const int sc = min(s, len - 1);
+    const int pos = reverse ? len - 1 - sc : sc;
     const uint32_t* c = C + pos * nstride;
     const uint32_t* sp = S + pos * nstride;
 #pragma unroll
     for (int e = 0; e < kPer; ++e) {
-      const int k = t + e * 64;
-      cn[e] = cd.ok[e] ? c[k] : 0u;
-      sn[e] = (!write && cd.ok[e]) ? sp[k] : 0u;
+      const int k = cd.ok[e] ? t + e * 64 : 0;
+      c_[e] = c[k];
+      if constexpr (!kWrite) s_[e] = sp[k];
     }
   };
-  request(0);
-  for (int s = 0; s < len; ++s) {
+  auto node = [&](int s, uint32_t (&cq)[kPer], uint32_t (&sq)[kPer]) __attribute__((always_inline)) {
     const int pos = reverse ? len - 1 - s : s;
     uint32_t* sp = S + pos * nstride;
     uint32_t cv[kPer], sv[kPer], cur[kPer];
 #pragma unroll
     for (int e = 0; e < kPer; ++e) {
-      cv[e] = cn[e];
-      sv[e] = sn[e];
+      cv[e] = cd.ok[e] ? cq[e] : 0u;
+      sv[e] = kWrite ? 0u : sq[e];
     }
-    if (s + 1 < len) request(s + 1);
-    if (s == 0) {
+    request(s + 2, cq, sq);
+    // (the first node takes its own costs; its reads of prev are unused)
+    uint32_t own[kPer], nb[kPer];
+    uint32_t lmin = 0xffffffffu;
 #pragma unroll
-      for (int e = 0; e < kPer; ++e) cur[e] = cv[e];
-    } else {
-      uint32_t own[kPer], nb[kPer];
-      uint32_t lmin = 0xffffffffu;
-#pragma unroll
-      for (int e = 0; e < kPer; ++e) {
-        const uint32_t* q = prev + cd.rd[e];
-        own[e] = q[0];
-        nb[e] = min(min(min(q[-P - 1], q[-P]), min(q[-P + 1], q[-1])), min(min(q[1], q[P - 1]), min(q[P], q[P + 1])));
-        lmin = min(lmin, cd.ok[e] ? own[e] : 0xffffffffu);
-      }
-      const uint32_t m = wave_min_u32(lmin);
-#pragma unroll
-      for (int e = 0; e < kPer; ++e) cur[e] = cv[e] + min(min(own[e], nb[e] + g.P1), m + g.P2) - m;
+    for (int e = 0; e < kPer; ++e) {
+      const uint32_t* q = prev + cd.rd[e];
+      own[e] = q[0];
+      nb[e] = min(min(min(q[-P - 1], q[-P]), min(q[-P + 1], q[-1])), min(min(q[1], q[P - 1]), min(q[P], q[P + 1])));
+      lmin = min(lmin, cd.ok[e] ? own[e] : 0xffffffffu);
     }
-    __syncthreads();   // (one wave) every lane has read prev
+    const uint32_t m = wave_min_u32(lmin);
+#pragma unroll
+    for (int e = 0; e < kPer; ++e) cur[e] = s == 0 ? cv[e] : cv[e] + min(min(own[e], nb[e] + g.P1), m + g.P2) - m;
+    // (every lane's reads of prev above are issued before these writes)
+    __builtin_amdgcn_wave_barrier();
     uint32_t best = 0xffffffffu, code = 0xffffffffu;
 #pragma unroll
     for (int e = 0; e < kPer; ++e) {
       prev[cd.wr[e]] = cur[e];
-      const uint32_t tot = write ? cur[e] : sv[e] + cur[e];
-      if (wta) {
+      const uint32_t tot = kWrite ? cur[e] : sv[e] + cur[e];
+      if constexpr (kWta) {
         const uint32_t tv = cd.ok[e] ? tot : 0xffffffffu;
         code = tv < best ? cd.code[e] : (tv == best ? min(code, cd.code[e]) : code);
         best = min(best, tv);
-      } else if (cd.ok[e]) {
-        sp[t + e * 64] = tot;
+      } else {
+        if (cd.ok[e]) sp[t + e * 64] = tot;
       }
     }
-    if (wta) {
+    if constexpr (kWta) {
       // (the least total, then among the lanes holding it the least code)
       const uint32_t mt = wave_min_u32(best);
       const uint32_t c = wave_min_u32(best == mt ? code : 0xffffffffu);
       if (t == 0) {
-        const int node = node0 + pos * nodestep;
-        out[node] = (int)(c & 63) - g.R;
-        out[np + node] = (int)((c >> 6) & 63) - g.R;
+        const int nd = node0 + pos * nodestep;
+        out[nd] = (int)(c & 63) - g.R;
+        out[np + nd] = (int)((c >> 6) & 63) - g.R;
       }
     }
-    __syncthreads();
+    // (these writes are issued before the next node's reads)
+    __builtin_amdgcn_wave_barrier();
+  };
+  uint32_t c0[kPer], s0[kPer], c1[kPer], s1[kPer];
+  request(0, c0, s0);
+  request(1, c1, s1);
+  int s = 0;
+  for (; s + 1 < len; s += 2) {
+    node(s, c0, s0);
+    node(s + 1, c1, s1);
   }
+  if (s < len) node(s, c0, s0);
+  // the pass's sums are complete (in memory and LDS) before the next pass
+  __syncthreads();
 }
 
 // One wave per line.  dir 0: a node row, left to right then right to left;
@@ -204,13 +217,13 @@ __global__ __launch_bounds__(64) void k_sgm_aggregate(SgmArgs g, int dir) {
   int32_t* out = g.out + (int64_t)pair * g.ostride;
   if (dir == 0) {
     const int64_t base = (int64_t)line * g.nx * g.nd;
-    sgm_path<kPer>(g, cd, C + base, S + base, g.nx, g.nd, false, true, false, prev, out, 0, 0);
-    sgm_path<kPer>(g, cd, C + base, S + base, g.nx, g.nd, true, false, false, prev, out, 0, 0);
+    sgm_path<kPer, true, false>(g, cd, C + base, S + base, g.nx, g.nd, false, prev, out, 0, 0);
+    sgm_path<kPer, false, false>(g, cd, C + base, S + base, g.nx, g.nd, true, prev, out, 0, 0);
   } else {
     const int64_t base = (int64_t)line * g.nd;
     const int64_t ns = (int64_t)g.nx * g.nd;
-    sgm_path<kPer>(g, cd, C + base, S + base, g.ny, ns, false, false, false, prev, out, 0, 0);
-    sgm_path<kPer>(g, cd, C + base, S + base, g.ny, ns, true, false, true, prev, out, line, g.nx);
+    sgm_path<kPer, false, false>(g, cd, C + base, S + base, g.ny, ns, false, prev, out, 0, 0);
+    sgm_path<kPer, false, true>(g, cd, C + base, S + base, g.ny, ns, true, prev, out, line, g.nx);
   }
 }
 
