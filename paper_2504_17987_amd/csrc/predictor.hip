@@ -444,6 +444,10 @@ __global__ __launch_bounds__(256) void k_sad_q(SadArgs g) {
   }
 }
 
+// passes of DYG shift rows over the 2R+1 of a coarse search
+template <int R, int DYG>
+constexpr int sad_passes() { return (2 * R + 1 + DYG - 1) / DYG; }
+
 // ---------------------------------------------------------------------------
 // Coarsest-level SAD search with cell-shared sums (u8, block = 2 step,
 // step 8).  Without a parent every node searches the same (2R+1)^2 shifts,
@@ -456,22 +460,26 @@ __global__ __launch_bounds__(256) void k_sad_q(SadArgs g) {
 // fields: a cell is at most 64 x 255).  Cell sums become block sums with a
 // DPP add of the right-hand cell (lane + 1) and a lane permute of the cell
 // below (lane + 9); four cells stay below 2^16, so the packed fields add
-// without carries.  Winner: the least (SAD, |dx|+|dy|, dy, dx).
+// without carries.  Winner: the least (SAD, |dx|+|dy|, dy, dx).  A
+// workgroup is one tile; its waves take the passes side by side (a coarse
+// level has few tiles) and the first wave merges their winners.
 // ---------------------------------------------------------------------------
 template <int R, int DYG, bool kCost = false>
-__global__ __launch_bounds__(256) void k_sad_cells(SadArgs g) {
+__global__ __launch_bounds__(64 * ((2 * R + DYG) / DYG)) void k_sad_cells(SadArgs g) {
   constexpr int G = 2 * R + 1, NGRP = (G + 3) / 4, REM = G - 4 * (NGRP - 1);
   constexpr bool TAIL = REM <= 2;           // last group by full-rate v_sad_u8
   constexpr int NQ = TAIL ? NGRP - 1 : NGRP;  // groups by quad SAD
   constexpr int CWD = 2, RW = CWD + NGRP;     // cell words, realigned B words
-  constexpr int CW = 9, CH = 7, NPASS = (G + DYG - 1) / DYG;
+  constexpr int CW = 9, CH = 7, NPASS = sad_passes<R, DYG>();
   static_assert(G <= 15, "4-bit shift indices in the key");
+  __shared__ uint32_t s_win[NPASS][64];
   const int lane = threadIdx.x & 63;
+  const int ps = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // this wave's pass
   const int pair = blockIdx.z;
   if (slot_off(g.mask, pair)) return;
   const int ntx = (g.nx + CW - 2) / (CW - 1), nty = (g.ny + CH - 2) / (CH - 1);
-  const int tile = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (tile >= ntx * nty) return;   // a whole wave (no barriers below)
+  const int tile = blockIdx.x;
+  if (tile >= ntx * nty) return;   // the whole workgroup
   const int ty = tile / ntx, tx = tile - ty * ntx;
   const int lr = lane / CW, lc = lane - lr * CW;
   // cells beyond the last node's read the last needed cell (results unused)
@@ -498,8 +506,7 @@ __global__ __launch_bounds__(256) void k_sad_cells(SadArgs g) {
   // (cost mode: this node's row of the cost volume)
   uint32_t* const crow = kCost && node ? g.cost + (int64_t)pair * g.cstride + (int64_t)(node_a * g.nx + node_b) * (G * G)
                                        : nullptr;
-#pragma unroll
-  for (int ps = 0; ps < NPASS; ++ps) {
+  {
     const int k0 = ps * DYG;                 // first shift row of the pass
     const int nk = min(DYG, G - k0);         // shift rows in the pass
     unsigned long long acc[DYG][NQ > 0 ? NQ : 1];
@@ -580,14 +587,18 @@ __global__ __launch_bounds__(256) void k_sad_cells(SadArgs g) {
       }
       __builtin_amdgcn_sched_barrier(0);   // one shift row's permutes in flight at a time
     }
-    // the next pass's row reads stay behind this pass's sums, so that one
-    // pass of accumulators is live at a time
-    asm volatile("" : "+v"(best)::"memory");
   }
-  if (!kCost && node) {
-    int32_t* out = g.out + (int64_t)pair * g.ostride;
-    out[node_a * g.nx + node_b] = (int)(best & 15u) - R;
-    out[g.nx * g.ny + node_a * g.nx + node_b] = (int)((best >> 4) & 15u) - R;
+  if constexpr (!kCost) {
+    // the passes' winners: the least key over them is the sequential search's
+    s_win[ps][lane] = best;
+    __syncthreads();
+    if (ps == 0 && node) {
+#pragma unroll
+      for (int q = 1; q < NPASS; ++q) best = min(best, s_win[q][lane]);
+      int32_t* out = g.out + (int64_t)pair * g.ostride;
+      out[node_a * g.nx + node_b] = (int)(best & 15u) - R;
+      out[g.nx * g.ny + node_a * g.nx + node_b] = (int)((best >> 4) & 15u) - R;
+    }
   }
 }
 
@@ -597,18 +608,22 @@ __global__ __launch_bounds__(256) void k_sad_cells(SadArgs g) {
 // block is four 12x12 cells it shares with its neighbours, block sums by DPP
 // and lane permute), with v_sad_u16 on realigned words (an odd shift column
 // is a 2-byte realignment).  The lane streams its cell's A rows through a
-// ring and the B rows once per pass of DYG shift rows.
+// ring and the B rows once per pass of DYG shift rows.  A workgroup is one
+// tile; its waves take the passes side by side (a coarse level has few
+// tiles) and the first wave merges their winners.
 // ---------------------------------------------------------------------------
 template <int R, int DYG>
-__global__ __launch_bounds__(256) void k_sad_cells16(SadArgs g) {
+__global__ __launch_bounds__(64 * ((2 * R + DYG) / DYG)) void k_sad_cells16(SadArgs g) {
   constexpr int G = 2 * R + 1, CWD = 6, RW = CWD + R;   // cell words, realigned B words
-  constexpr int CW = 9, CH = 7, NPASS = (G + DYG - 1) / DYG;
+  constexpr int CW = 9, CH = 7, NPASS = sad_passes<R, DYG>();
+  __shared__ unsigned long long s_win[NPASS][64];
   const int lane = threadIdx.x & 63;
+  const int ps = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // this wave's pass
   const int pair = blockIdx.z;
   if (slot_off(g.mask, pair)) return;
   const int ntx = (g.nx + CW - 2) / (CW - 1), nty = (g.ny + CH - 2) / (CH - 1);
-  const int tile = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (tile >= ntx * nty) return;   // a whole wave (no barriers below)
+  const int tile = blockIdx.x;
+  if (tile >= ntx * nty) return;   // the whole workgroup
   const int ty = tile / ntx, tx = tile - ty * ntx;
   const int lr = lane / CW, lc = lane - lr * CW;
   // cells beyond the last node's read the last needed cell (results unused)
@@ -624,8 +639,7 @@ __global__ __launch_bounds__(256) void k_sad_cells16(SadArgs g) {
     return h + (uint32_t)__builtin_amdgcn_ds_bpermute((lane + CW) << 2, (int)h);
   };
   unsigned long long best = ~0ull;
-#pragma unroll
-  for (int ps = 0; ps < NPASS; ++ps) {
+  {
     const int k0 = ps * DYG;             // first shift row of the pass
     const int nk = min(DYG, G - k0);     // shift rows in the pass
     uint32_t acc[DYG][G];
@@ -672,9 +686,13 @@ __global__ __launch_bounds__(256) void k_sad_cells16(SadArgs g) {
       }
       __builtin_amdgcn_sched_barrier(0);
     }
-    asm volatile("" : "+v"(best)::"memory");
   }
-  if (node) {
+  // the passes' winners: the least key over them is the sequential search's
+  s_win[ps][lane] = best;
+  __syncthreads();
+  if (ps == 0 && node) {
+#pragma unroll
+    for (int q = 1; q < NPASS; ++q) best = min(best, s_win[q][lane]);
     int32_t* out = g.out + (int64_t)pair * g.ostride;
     out[node_a * g.nx + node_b] = (int)(best & 0xff) - 128;
     out[g.nx * g.ny + node_a * g.nx + node_b] = (int)((best >> 8) & 0xff) - 128;
@@ -1603,28 +1621,33 @@ hipError_t launch_sad_level(const Plan& P, int l, const void* A, const void* B, 
   // coarsest level, u16, 24x24 blocks at step 12: cell-shared sums
   if (!g.parent && P.es == 2 && P.p.step == 12 && P.block == 24 && g.R >= 3 && g.R <= 7) {
     const int tiles = ((v.nx + 7) / 8) * ((v.ny + 5) / 6);
-    dim3 grid((tiles + 3) / 4, 1, n);
+    dim3 grid(tiles, 1, n);
+#define PIV_SAD16(R_, D_) \
+  hipLaunchKernelGGL((k_sad_cells16<R_, D_>), grid, dim3(64 * sad_passes<R_, D_>()), 0, s, g)
     switch (g.R) {
-      case 3: hipLaunchKernelGGL((k_sad_cells16<3, 4>), grid, dim3(256), 0, s, g); break;
-      case 4: hipLaunchKernelGGL((k_sad_cells16<4, 4>), grid, dim3(256), 0, s, g); break;
-      case 5: hipLaunchKernelGGL((k_sad_cells16<5, 3>), grid, dim3(256), 0, s, g); break;
-      case 6: hipLaunchKernelGGL((k_sad_cells16<6, 3>), grid, dim3(256), 0, s, g); break;
-      default: hipLaunchKernelGGL((k_sad_cells16<7, 3>), grid, dim3(256), 0, s, g); break;
+      case 3: PIV_SAD16(3, 4); break;
+      case 4: PIV_SAD16(4, 4); break;
+      case 5: PIV_SAD16(5, 3); break;
+      case 6: PIV_SAD16(6, 3); break;
+      default: PIV_SAD16(7, 3); break;
     }
+#undef PIV_SAD16
     return hipGetLastError();
   }
   // coarsest level, u8, 16x16 blocks at step 8: cell-shared sums
   if (!g.parent && P.es == 1 && P.p.step == 8 && P.block == 16 && g.R >= 3 && g.R <= 7 &&
       (size_t)v.rows * v.pitch < (1u << 31) && v.pitch < (1 << 24)) {
     const int tiles = ((v.nx + 7) / 8) * ((v.ny + 5) / 6);
-    dim3 grid((tiles + 3) / 4, 1, n);
+    dim3 grid(tiles, 1, n);
+#define PIV_SAD8(R_, D_) hipLaunchKernelGGL((k_sad_cells<R_, D_>), grid, dim3(64 * sad_passes<R_, D_>()), 0, s, g)
     switch (g.R) {
-      case 3: hipLaunchKernelGGL((k_sad_cells<3, 7>), grid, dim3(256), 0, s, g); break;
-      case 4: hipLaunchKernelGGL((k_sad_cells<4, 5>), grid, dim3(256), 0, s, g); break;
-      case 5: hipLaunchKernelGGL((k_sad_cells<5, 6>), grid, dim3(256), 0, s, g); break;
-      case 6: hipLaunchKernelGGL((k_sad_cells<6, 7>), grid, dim3(256), 0, s, g); break;
-      default: hipLaunchKernelGGL((k_sad_cells<7, 5>), grid, dim3(256), 0, s, g); break;
+      case 3: PIV_SAD8(3, 7); break;
+      case 4: PIV_SAD8(4, 5); break;
+      case 5: PIV_SAD8(5, 6); break;
+      case 6: PIV_SAD8(6, 7); break;
+      default: PIV_SAD8(7, 5); break;
     }
+#undef PIV_SAD8
     return hipGetLastError();
   }
   // nodes per workgroup: G lanes each, A blocks within 64 KiB of LDS
@@ -1696,14 +1719,17 @@ hipError_t launch_sad_cost_cells(const Plan& P, uint32_t* C, int64_t cstride, in
   g.cost = C;
   g.cstride = cstride;
   const int tiles = ((v.nx + 7) / 8) * ((v.ny + 5) / 6);
-  dim3 grid((tiles + 3) / 4, 1, n);
+  dim3 grid(tiles, 1, n);
+#define PIV_SADC(R_, D_) \
+  hipLaunchKernelGGL((k_sad_cells<R_, D_, true>), grid, dim3(64 * sad_passes<R_, D_>()), 0, s, g)
   switch (g.R) {
-    case 3: hipLaunchKernelGGL((k_sad_cells<3, 7, true>), grid, dim3(256), 0, s, g); break;
-    case 4: hipLaunchKernelGGL((k_sad_cells<4, 5, true>), grid, dim3(256), 0, s, g); break;
-    case 5: hipLaunchKernelGGL((k_sad_cells<5, 6, true>), grid, dim3(256), 0, s, g); break;
-    case 6: hipLaunchKernelGGL((k_sad_cells<6, 7, true>), grid, dim3(256), 0, s, g); break;
-    default: hipLaunchKernelGGL((k_sad_cells<7, 5, true>), grid, dim3(256), 0, s, g); break;
+    case 3: PIV_SADC(3, 7); break;
+    case 4: PIV_SADC(4, 5); break;
+    case 5: PIV_SADC(5, 6); break;
+    case 6: PIV_SADC(6, 7); break;
+    default: PIV_SADC(7, 5); break;
   }
+#undef PIV_SADC
   return hipGetLastError();
 }
 
