@@ -245,12 +245,26 @@ __global__ __launch_bounds__(256) void k_correct_generic(CorrArgs g) {
     sB[idx] = v - K;
   }
   __syncthreads();
-  // A statistics (every thread, from LDS; small)
+  // A statistics (every thread, from LDS; small).  The LDS reads go eight
+  // at a time so that they are in flight together; the sums keep their order.
   float sa = 0.0f, saa = 0.0f;
-  for (int i = 0; i < win * win; ++i) {
-    float v = sA[i];
-    sa += v;
-    saa += v * v;
+  {
+    int i = 0;
+    for (; i + 8 <= win * win; i += 8) {
+      float v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = sA[i + u];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        sa += v[u];
+        saa += v[u] * v[u];
+      }
+    }
+    for (; i < win * win; ++i) {
+      const float v = sA[i];
+      sa += v;
+      saa += v * v;
+    }
   }
   const float n = (float)(win * win);
   const float mA = sa / n;
@@ -268,8 +282,24 @@ __global__ __launch_bounds__(256) void k_correct_generic(CorrArgs g) {
       for (int i = 0; i < win; ++i) {
         const float* arow = sA + i * win;
         const float* brow = sB + (i + sy + R) * BWd + sx + R;
-        for (int j = 0; j < win; ++j) {
-          float bv = brow[j];
+        // eight pixels' reads in flight together; the sums keep their order
+        int j = 0;
+        for (; j + 8 <= win; j += 8) {
+          float av[8], bv[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            av[u] = arow[j + u];
+            bv[u] = brow[j + u];
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            P += av[u] * bv[u];
+            Sb += bv[u];
+            Q += bv[u] * bv[u];
+          }
+        }
+        for (; j < win; ++j) {
+          const float bv = brow[j];
           P += arow[j] * bv;
           Sb += bv;
           Q += bv * bv;
