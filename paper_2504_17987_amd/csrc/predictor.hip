@@ -213,6 +213,8 @@ struct SadArgs {
   int64_t ostride;        // int32 elements per pair
   const uint8_t* mask;
   int npw;                // nodes per workgroup (k_sad)
+  int qsplit;             // k_sad: groups of candidate rows per candidate column
+  int band;               // k_sad without a parent: staged B band row words (at most), 0 = none
   int margin;             // level margin (px): A - margin (pitch + bytes per px) is padded row 0
   // level 0 read in place (k_sad_lane, k_sad_cols, k_sad_stream, k_sad_cells16_fine): an A block or B span wholly inside
   // the image reads the caller's frames (pair 0 at srcA/srcB); one that
@@ -1163,26 +1165,30 @@ __global__ __launch_bounds__(256) void k_sad_r(SadArgs g) {
 }
 
 // ---------------------------------------------------------------------------
-// SAD block search, general form: a group of G = 2R+1 lanes per node, lane k
-// owning the candidate column dx = cand_x - R + k; npw nodes of one node row
-// per workgroup.  The node's A block is staged in LDS as packed words; every
-// lane streams the rows of B its column needs (realigned to its dx), and
-// accumulates, for each of its G candidates dy, v_sad_u8 / v_sad_u16.  The
-// winner minimises the packed key (SAD, |dx|+|dy|, dy, dx): a plain u64
-// min, independent of the reduction order.
+// SAD block search, general form: G = 2R+1 candidate columns per node, each
+// split into qsplit groups of at most KMAX candidate rows, one thread per
+// (column, group): the thread owns dx = cand_x - R + k and its rows dy, and
+// streams only the B rows they meet (realigned to its dx), accumulating
+// v_sad_u8 / v_sad_u16; npw nodes of one node row per workgroup.  The node's
+// A block is staged in LDS as packed words, and without a parent (every
+// node searching the same rows) so is the band of B rows the workgroup
+// reads.  The winner minimises the packed key (SAD, |dx|+|dy|, dy, dx): a
+// plain u64 min, independent of the reduction order.
 // ---------------------------------------------------------------------------
 template <int ES, int NW, int KMAX>
 __global__ __launch_bounds__(256) void k_sad(SadArgs g) {
-  extern __shared__ uint32_t s_ablk[];        // [npw][block][NW]
+  extern __shared__ uint32_t s_ablk[];        // [npw][block][NW], then the staged B band [rows][band]
   __shared__ unsigned long long s_key[256];
 
   const WgIdx wg = xcd_order();
   const int pair = wg.z;
   if (slot_off(g.mask, pair)) return;
   const int G = 2 * g.R + 1;
+  const int QS = g.qsplit, qn = (G + QS - 1) / QS, TPN = G * QS;   // (qn <= KMAX)
   const int npw = g.npw;
   const int t = threadIdx.x;
-  const int j = t / G, k = t - j * G;
+  const int j = t / TPN, rem = t - j * TPN;
+  const int qg = rem / G, k = rem - qg * G;   // candidate-row group, candidate column
   const int a = wg.y;
   const int b0 = wg.x * npw;
   const int b = b0 + j;
@@ -1194,10 +1200,22 @@ __global__ __launch_bounds__(256) void k_sad(SadArgs g) {
 
   const int nblk = min(npw, g.nx - b0);
   const int words = g.block * NW;
+  const int nrows = g.block + 2 * g.R;
   for (int idx = t; idx < nblk * words; idx += 256) {
     int jj = idx / words, r = (idx / NW) % g.block, w = idx % NW;
     const uint8_t* row = Ab + (int64_t)(oy + r) * g.pitch;
     s_ablk[idx] = word_at(row, ((b0 + jj) * g.step + off) * ES + 4 * w);
+  }
+  // the band: words xw0 .. the last one a node of the workgroup reads
+  uint32_t* const s_band = s_ablk + npw * words;
+  const int xw0 = ((b0 * g.step + off - g.R) * ES) >> 2;   // (a floor for negative offsets)
+  if (g.band) {
+    const int nbw = ((((b0 + nblk - 1) * g.step + off + g.R) * ES) >> 2) + NW - xw0 + 1;
+    const uint8_t* Bs = Bb + (int64_t)(oy - g.R) * g.pitch + 4 * (int64_t)xw0;
+    for (int idx = t; idx < nrows * nbw; idx += 256) {
+      const int r = idx / nbw, w = idx - r * nbw;
+      s_band[r * g.band + w] = *reinterpret_cast<const uint32_t*>(Bs + (int64_t)r * g.pitch + 4 * w);
+    }
   }
 
   int cx = 0, cy = 0;
@@ -1210,7 +1228,8 @@ __global__ __launch_bounds__(256) void k_sad(SadArgs g) {
   __syncthreads();
 
   unsigned long long best = ~0ull;
-  if (active) {
+  const int q0 = qg * qn, q1 = min(q0 + qn, G);   // this thread's candidate rows
+  if (active && q0 < q1) {
     const int dx = cx - g.R + k;
     const int xb = (b * g.step + off + dx) * ES;
     const int xa = xb & ~3, sh = xb & 3;
@@ -1219,38 +1238,51 @@ __global__ __launch_bounds__(256) void k_sad(SadArgs g) {
 #pragma unroll
     for (int q = 0; q < KMAX; ++q) acc[q] = 0u;
     const uint32_t* ablk = s_ablk + j * words;
-    const int nrows = g.block + 2 * g.R;
-    for (int rb = 0; rb < nrows; ++rb) {
-      const uint32_t* row = reinterpret_cast<const uint32_t*>(Bb + (int64_t)(by0 + rb) * g.pitch + xa);
+    const uint32_t* brow0 = s_band + ((xa >> 2) - xw0);
+    // B row rb meets A row rb - q for candidate row q
+    for (int rb = q0; rb < q1 - 1 + g.block; ++rb) {
       uint32_t w[NW + 1];
+      if (g.band) {
 #pragma unroll
-      for (int i = 0; i <= NW; ++i) w[i] = row[i];
+        for (int i = 0; i <= NW; ++i) w[i] = brow0[rb * g.band + i];
+      } else {
+        const uint32_t* row = reinterpret_cast<const uint32_t*>(Bb + (int64_t)(by0 + rb) * g.pitch + xa);
+#pragma unroll
+        for (int i = 0; i <= NW; ++i) w[i] = row[i];
+      }
       uint32_t bw[NW];
 #pragma unroll
       for (int i = 0; i < NW; ++i) bw[i] = __builtin_amdgcn_alignbyte(w[i + 1], w[i], sh);
 #pragma unroll
-      for (int q = 0; q < KMAX; ++q) {
-        const int ar = rb - q;
-        if (q < G && ar >= 0 && ar < g.block) {
+      for (int qi = 0; qi < KMAX; ++qi) {
+        const int ar = rb - (q0 + qi);
+        if (qi < qn && q0 + qi < q1 && ar >= 0 && ar < g.block) {
           const uint32_t* arow = ablk + ar * NW;
-          uint32_t s = acc[q];
+          uint32_t s = acc[qi];
 #pragma unroll
           for (int i = 0; i < NW; ++i) s = sad_word<ES>(arow[i], bw[i], s);
-          acc[q] = s;
+          acc[qi] = s;
         }
       }
     }
 #pragma unroll
-    for (int q = 0; q < KMAX; ++q) {
-      if (q < G) {
-        unsigned long long key = sad_key(acc[q], cy - g.R + q, dx);
+    for (int qi = 0; qi < KMAX; ++qi) {
+      if (qi < qn && q0 + qi < q1) {
+        unsigned long long key = sad_key(acc[qi], cy - g.R + q0 + qi, dx);
         best = key < best ? key : best;
       }
     }
   }
+  // a node's winner: over its row groups per column, then over the columns
   s_key[t] = best;
   __syncthreads();
-  if (active && k == 0) {
+  if (active && qg == 0) {
+    unsigned long long m = s_key[t];
+    for (int q = 1; q < QS; ++q) m = s_key[t + q * G] < m ? s_key[t + q * G] : m;
+    s_key[t] = m;
+  }
+  __syncthreads();
+  if (active && rem == 0) {
     unsigned long long m = s_key[t];
     for (int q = 1; q < G; ++q) m = s_key[t + q] < m ? s_key[t + q] : m;
     int32_t* out = g.out + (int64_t)pair * g.ostride;
@@ -1677,6 +1709,8 @@ hipError_t launch_sad_level(const Plan& P, int l, const void* A, const void* B, 
   g.npw = npw;
   dim3 grid((v.nx + npw - 1) / npw, v.ny, n);
   size_t lds = sizeof(uint32_t) * (size_t)npw * P.block * NW;
+  g.qsplit = 1;
+  g.band = 0;
   if (P.es == 2 && G <= 17) {
     // a lane per candidate row (u16 blocks of 8..32 px)
 #define PIV_SAD_R(NW_, K_) \
@@ -1686,7 +1720,26 @@ hipError_t launch_sad_level(const Plan& P, int l, const void* A, const void* B, 
 #undef PIV_SAD_R_NW
 #undef PIV_SAD_R
   }
-  return P.es == 1 ? sad_dispatch<1>(NW, G, grid, lds, s, g) : sad_dispatch<2>(NW, G, grid, lds, s, g);
+  // k_sad: the candidate rows of a column in groups of about two, each its
+  // own thread, so that few nodes still make many threads; and without a
+  // parent the workgroup's band of B rows staged in LDS
+  {
+    int qs = max(1, min((G + 1) / 2, 256 / G));
+    const int qn = (G + qs - 1) / qs;
+    qs = (G + qn - 1) / qn;   // (no empty group)
+    const int npq = max(1, min(256 / (G * qs), 65536 / (P.block * NW * 4)));
+    g.qsplit = qs;
+    g.npw = npq;
+    grid = dim3((v.nx + npq - 1) / npq, v.ny, n);
+    lds = sizeof(uint32_t) * (size_t)npq * P.block * NW;
+    const int bw = ((npq - 1) * P.p.step + 2 * g.R) * P.es / 4 + NW + 2;
+    const size_t bbytes = sizeof(uint32_t) * (size_t)bw * (size_t)(P.block + 2 * g.R);
+    if (!g.parent && lds + bbytes <= 60 * 1024) {
+      g.band = bw;
+      lds += bbytes;
+    }
+    return P.es == 1 ? sad_dispatch<1>(NW, qn, grid, lds, s, g) : sad_dispatch<2>(NW, qn, grid, lds, s, g);
+  }
 }
 
 // The coarsest level's SAD of every node and shift into a cost volume
