@@ -185,21 +185,29 @@ __device__ __forceinline__ void finish_vector(const CorrArgs& g, int pair, int a
 }
 
 // ---------------------------------------------------------------------------
-// Generic: one workgroup per window.
+// Generic: one workgroup per window.  The window and its B' box are staged
+// in LDS; a thread takes one shift and one of H parts of the window's rows
+// (H = as many parts as fit the workgroup, so that a window with many shifts
+// still gives every SIMD several waves), the parts' sums meet in LDS in a
+// fixed order, and a thread per shift forms the coefficient.
 // ---------------------------------------------------------------------------
+constexpr int kGenT = 1024;
+
 template <typename T>
-__global__ __launch_bounds__(256) void k_correct_generic(CorrArgs g) {
+__global__ __launch_bounds__(kGenT) void k_correct_generic(CorrArgs g) {
   extern __shared__ float s_mem[];
-  __shared__ float s_red[256];
-  __shared__ int s_key[256];
+  __shared__ float s_red[kGenT], s_red2[kGenT];
+  __shared__ int s_key[kGenT];
   __shared__ float s_K;
   const int pair = blockIdx.z;
   if (slot_off(g.mask, pair)) return;
   const int a = blockIdx.y, b = blockIdx.x, t = threadIdx.x;
-  const int win = g.win, R = g.R, S = 2 * R + 1, BWd = win + 2 * R;
+  const int win = g.win, R = g.R, S = 2 * R + 1, BWd = win + 2 * R, S2 = S * S;
+  const int H = max(1, min(win, kGenT / S2));   // row parts per shift
   float* sA = s_mem;                 // [win][win]
   float* sB = sA + win * win;        // [BWd][BWd]
   float* sRho = sB + BWd * BWd;      // [S][S]
+  float* sPart = sRho + S2;          // [3][H][S2]: P, S, Q of each shift's row parts
   const uint8_t* Ai = g.A + (int64_t)pair * g.stride;
   const uint8_t* Bi = g.B + (int64_t)pair * g.stride;
   const float* Pn = g.pred ? g.pred + (int64_t)pair * 2 * g.nx * g.ny : nullptr;
@@ -207,9 +215,25 @@ __global__ __launch_bounds__(256) void k_correct_generic(CorrArgs g) {
   auto node = [&](int c, int y, int x) { return Pn[c * np + y * g.nx + x]; };
   const int h = (win - g.step) / 2, oy = a * g.step - h, ox = b * g.step - h;
   const float sgnA = -0.5f, sgnB = g.central ? 0.5f : 1.0f;
+  // fixed-order tree over the workgroup (every thread returns the total)
+  auto tree2 = [&](float x, float y, float& sx_, float& sy_) {
+    s_red[t] = x;
+    s_red2[t] = y;
+    __syncthreads();
+    for (int o = kGenT / 2; o > 0; o >>= 1) {
+      if (t < o) {
+        s_red[t] += s_red[t + o];
+        s_red2[t] += s_red2[t + o];
+      }
+      __syncthreads();
+    }
+    sx_ = s_red[0];
+    sy_ = s_red2[0];
+    __syncthreads();
+  };
 
   float part = 0.0f;
-  for (int idx = t; idx < win * win; idx += 256) {
+  for (int idx = t; idx < win * win; idx += kGenT) {
     int y = oy + idx / win, x = ox + idx % win;
     float v;
     if (g.central && Pn) {
@@ -222,17 +246,15 @@ __global__ __launch_bounds__(256) void k_correct_generic(CorrArgs g) {
     sA[idx] = v;
     part += v;
   }
-  s_red[t] = part;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if (t < o) s_red[t] += s_red[t + o];
+  {
+    float tot, unused;
+    tree2(part, 0.0f, tot, unused);
+    if (t == 0) s_K = rintf(tot / (float)(win * win));
     __syncthreads();
   }
-  if (t == 0) s_K = rintf(s_red[0] / (float)(win * win));
-  __syncthreads();
   const float K = s_K;
-  for (int idx = t; idx < win * win; idx += 256) sA[idx] -= K;
-  for (int idx = t; idx < BWd * BWd; idx += 256) {
+  for (int idx = t; idx < win * win; idx += kGenT) sA[idx] -= K;
+  for (int idx = t; idx < BWd * BWd; idx += kGenT) {
     int y = oy - R + idx / BWd, x = ox - R + idx % BWd;
     float v;
     if (Pn) {
@@ -245,44 +267,33 @@ __global__ __launch_bounds__(256) void k_correct_generic(CorrArgs g) {
     sB[idx] = v - K;
   }
   __syncthreads();
-  // A statistics (every thread, from LDS; small).  The LDS reads go eight
-  // at a time so that they are in flight together; the sums keep their order.
-  float sa = 0.0f, saa = 0.0f;
+  // A statistics (of A - K)
+  float sa, saa;
   {
-    int i = 0;
-    for (; i + 8 <= win * win; i += 8) {
-      float v[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = sA[i + u];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        sa += v[u];
-        saa += v[u] * v[u];
-      }
+    float p1 = 0.0f, p2 = 0.0f;
+    for (int idx = t; idx < win * win; idx += kGenT) {
+      const float v = sA[idx];
+      p1 += v;
+      p2 += v * v;
     }
-    for (; i < win * win; ++i) {
-      const float v = sA[i];
-      sa += v;
-      saa += v * v;
-    }
+    tree2(p1, p2, sa, saa);
   }
   const float n = (float)(win * win);
   const float mA = sa / n;
   const float varA = saa - sa * mA;
   const bool flatA = !(varA > kFlatRel * saa);
 
-  float best = -2.0f;
-  int bkey = 1 << 30, nflat = 0;
-  for (int s = t; s < S * S; s += 256) {
-    int sy = s / S - R, sx = s % S - R;
-    float r = 0.0f;
-    bool used = !g.fixed || sx == 0 || sy == 0;
-    if (used) {
-      float P = 0.0f, Sb = 0.0f, Q = 0.0f;
-      for (int i = 0; i < win; ++i) {
+  // shift s, row part hp: rows [hp win / H, (hp + 1) win / H) of the window
+  for (int item = t; item < S2 * H; item += kGenT) {
+    const int hp = item / S2, sidx = item - hp * S2;
+    const int sy = sidx / S - R, sx = sidx % S - R;
+    float P = 0.0f, Sb = 0.0f, Q = 0.0f;
+    if (!g.fixed || sx == 0 || sy == 0) {
+      const int r0 = hp * win / H, r1 = (hp + 1) * win / H;
+      for (int i = r0; i < r1; ++i) {
         const float* arow = sA + i * win;
         const float* brow = sB + (i + sy + R) * BWd + sx + R;
-        // eight pixels' reads in flight together; the sums keep their order
+        // eight pixels' reads in flight together
         int j = 0;
         for (; j + 8 <= win; j += 8) {
           float av[8], bv[8];
@@ -305,6 +316,26 @@ __global__ __launch_bounds__(256) void k_correct_generic(CorrArgs g) {
           Q += bv * bv;
         }
       }
+    }
+    sPart[(0 * H + hp) * S2 + sidx] = P;
+    sPart[(1 * H + hp) * S2 + sidx] = Sb;
+    sPart[(2 * H + hp) * S2 + sidx] = Q;
+  }
+  __syncthreads();
+
+  float best = -2.0f;
+  int bkey = 1 << 30, nflat = 0;
+  for (int sidx = t; sidx < S2; sidx += kGenT) {
+    const int sy = sidx / S - R, sx = sidx % S - R;
+    float r = 0.0f;
+    const bool used = !g.fixed || sx == 0 || sy == 0;
+    if (used) {
+      float P = 0.0f, Sb = 0.0f, Q = 0.0f;
+      for (int hp = 0; hp < H; ++hp) {
+        P += sPart[(0 * H + hp) * S2 + sidx];
+        Sb += sPart[(1 * H + hp) * S2 + sidx];
+        Q += sPart[(2 * H + hp) * S2 + sidx];
+      }
       float num = P - mA * Sb;
       float varB = Q - Sb * Sb / n;
       bool flat = flatA || !(varB > kFlatRel * Q);
@@ -316,12 +347,12 @@ __global__ __launch_bounds__(256) void k_correct_generic(CorrArgs g) {
         bkey = key;
       }
     }
-    sRho[s] = r;
+    sRho[sidx] = r;
   }
   s_red[t] = best;
   s_key[t] = bkey;
   __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
+  for (int o = kGenT / 2; o > 0; o >>= 1) {
     if (t < o && better(s_red[t + o], s_key[t + o], s_red[t], s_key[t])) {
       s_red[t] = s_red[t + o];
       s_key[t] = s_key[t + o];
@@ -1676,13 +1707,14 @@ hipError_t launch_correct(const Plan& P, const void* A, const void* B, int64_t p
   if (correct_impl(P) == 1) {
     return P.p.dtype == PIV_U8 ? launch_tiled_t<uint8_t>(g, n, s) : launch_tiled_t<uint16_t>(g, n, s);
   }
-  const int BWd = g.win + 2 * g.R, S = 2 * g.R + 1;
-  size_t lds = sizeof(float) * ((size_t)g.win * g.win + (size_t)BWd * BWd + (size_t)S * S);
+  const int BWd = g.win + 2 * g.R, S = 2 * g.R + 1, S2 = S * S;
+  const int H = std::max(1, std::min(g.win, kGenT / S2));   // (as in the kernel)
+  size_t lds = sizeof(float) * ((size_t)g.win * g.win + (size_t)BWd * BWd + (size_t)S2 + 3 * (size_t)H * S2);
   dim3 grid(P.nx, P.ny, n);
   switch (P.p.dtype) {
-    case PIV_U8: hipLaunchKernelGGL(k_correct_generic<uint8_t>, grid, dim3(256), lds, s, g); break;
-    case PIV_U16: hipLaunchKernelGGL(k_correct_generic<uint16_t>, grid, dim3(256), lds, s, g); break;
-    default: hipLaunchKernelGGL(k_correct_generic<float>, grid, dim3(256), lds, s, g); break;
+    case PIV_U8: hipLaunchKernelGGL(k_correct_generic<uint8_t>, grid, dim3(kGenT), lds, s, g); break;
+    case PIV_U16: hipLaunchKernelGGL(k_correct_generic<uint16_t>, grid, dim3(kGenT), lds, s, g); break;
+    default: hipLaunchKernelGGL(k_correct_generic<float>, grid, dim3(kGenT), lds, s, g); break;
   }
   return hipGetLastError();
 }
