@@ -456,9 +456,9 @@ constexpr int sad_passes() { return (2 * R + 1 + DYG - 1) / DYG; }
 // and a node's 16x16 block is four 8x8 cells that it shares with its
 // neighbours, so the SAD of a block is the sum of four cell SADs for the same
 // shift: each pixel difference is taken once instead of four times.
-// Lane = cell of a 9x7 tile (8x6 nodes per wave, four independent waves per
-// workgroup); the lane keeps its A cell in registers and streams the B rows
-// once per pass of DYG shift rows, four shift columns per quad SAD (16-bit
+// Lane = cell of a 9x7 tile (8x6 nodes per tile); the lane keeps its A cell
+// in registers and streams the B rows once per pass of DYG shift rows, four
+// shift columns per quad SAD (16-bit
 // fields: a cell is at most 64 x 255).  Cell sums become block sums with a
 // DPP add of the right-hand cell (lane + 1) and a lane permute of the cell
 // below (lane + 9); four cells stay below 2^16, so the packed fields add
