@@ -397,7 +397,7 @@ __global__ __launch_bounds__(256) void k_clahe_map(const uint8_t* in, uint8_t* o
   const bool full = c0 + 4 <= nq;
   // this thread's four columns: tiles, weights and mapping offsets (the
   // same on every row)
-  int ca[4], cb[4], cwx[4], cdx[4];
+  int ca[4], cb[4], cwx[4], cdx[4], kdx[4];
   float rdx[4];   // 1 / dx (the quotient's estimate is corrected exactly below)
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
@@ -408,6 +408,7 @@ __global__ __launch_bounds__(256) void k_clahe_map(const uint8_t* in, uint8_t* o
     cwx[e] = (int)(ax >> 16);
     cdx[e] = s_ad[c];
     rdx[e] = __builtin_amdgcn_rcpf((float)cdx[e]);
+    kdx[e] = (cdx[e] & (cdx[e] - 1)) == 0 ? __builtin_ctz((unsigned)cdx[e]) : -1;   // log2 dx, or -1
   }
   for (int k = 0; k < MR; ++k) {
     const int y = y0 + k;
@@ -415,6 +416,7 @@ __global__ __launch_bounds__(256) void k_clahe_map(const uint8_t* in, uint8_t* o
     const Axis ay = s_ay[k];
     const int ra = rpart_of(ay.a), rb = rpart_of(ay.b);
     const float rdy = __builtin_amdgcn_rcpf((float)ay.d);
+    const int kdy = (ay.d & (ay.d - 1)) == 0 ? __builtin_ctz((unsigned)ay.d) : -1;
     const T* row = reinterpret_cast<const T*>(in + (int64_t)pair * stride + (int64_t)y * pitch);
     T* orow = reinterpret_cast<T*>(out + (int64_t)pair * stride + (int64_t)y * pitch);
     uint32_t v[4];
@@ -444,11 +446,17 @@ __global__ __launch_bounds__(256) void k_clahe_map(const uint8_t* in, uint8_t* o
         const int num = (ay.d - ay.w) * ((dx - wx) * l00 + wx * l01) + ay.w * ((dx - wx) * l10 + wx * l11);
         const int den = dx * ay.d;
         const int n2 = num + den / 2;
-        // (the rounded quotient is below 2^16, so the estimate from the two
-        // reciprocals is within one of it)
-        int q = (int)((float)n2 * rdx[e] * rdy);
-        int rr = n2 - q * den;
-        q += rr < 0 ? -1 : (rr >= den ? 1 : 0);
+        int q;
+        if (kdx[e] >= 0 && kdy >= 0) {
+          // a power-of-two denominator (tile spans of 2^k px): the floor by a shift
+          q = n2 >> (kdx[e] + kdy);
+        } else {
+          // (the rounded quotient is below 2^16, so the estimate from the two
+          // reciprocals is within one of it)
+          q = (int)((float)n2 * rdx[e] * rdy);
+          const int rr = n2 - q * den;
+          q += rr < 0 ? -1 : (rr >= den ? 1 : 0);
+        }
         o[e] = (uint32_t)q;
       } else {
         const int64_t l00 = L(ra, ca[e], b), l01 = L(ra, cb[e], b), l10 = L(rb, ca[e], b), l11 = L(rb, cb[e], b);
