@@ -188,6 +188,11 @@ CORR_CASES = {
     # the a-priori stencil and the argmax search
     "wake_fixed_32_16": ("wake", dict(win=32, step=16, radius=4, levels=2, radius_coarse=6, peak="fixed"), True),
     "wake_argmax_32_16": ("wake", dict(win=32, step=16, radius=4, levels=2, radius_coarse=6), True),
+    # the generic kernel at the largest geometries the plan accepts: a window
+    # of 64 px with 33 x 33 shifts (one row part per shift, 83 KB of LDS),
+    # and 48 px with 25 x 25 shifts (row parts of a 1,024-thread workgroup)
+    "generic_u8_win64_r16": ("cfg1", dict(win=64, step=32, radius=16, levels=1, radius_coarse=8), False),
+    "generic_u8_win48_r12": ("cfg1", dict(win=48, step=16, radius=12, levels=1, radius_coarse=8), False),
 }
 
 
