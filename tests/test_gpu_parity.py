@@ -37,6 +37,10 @@ PRED_CASES = {
                        dict(win=16, step=8, levels=3, radius_coarse=6, radius_fine=2)),
     "cfg1_L1_32_16_r8": (lambda: synth.cfg1_pair(1000)[:2],
                          dict(win=32, step=16, levels=1, radius_coarse=8, radius_fine=2, radius=8)),
+    # the generic SAD kernel at its widest: 64 px blocks, 33 x 33 candidates
+    # (candidate rows in groups of five per thread, one node per workgroup)
+    "cfg1_L1_64_32_r16": (lambda: synth.cfg1_pair(1001)[:2],
+                          dict(win=64, step=32, levels=1, radius_coarse=16, radius_fine=2, radius=8)),
     "ragged_200x136": (lambda: small_vortex_pair(200, 136, seed=3)[:2],
                        dict(win=16, step=8, levels=3, radius_coarse=5, radius_fine=2)),
     "median_off_L2": (lambda: small_vortex_pair(seed=11)[:2],
