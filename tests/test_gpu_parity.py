@@ -35,6 +35,12 @@ PRED_CASES = {
     # name: (image maker, plan kwargs)
     "vortex_L3_16_8": (lambda: small_vortex_pair()[:2],
                        dict(win=16, step=8, levels=3, radius_coarse=6, radius_fine=2)),
+    # the cell-shared u8 coarse search with three passes of shift rows (R 7)
+    # and one (R 3)
+    "coarse_r7_L3": (lambda: small_vortex_pair(seed=19)[:2],
+                     dict(win=16, step=8, levels=3, radius_coarse=7, radius_fine=2)),
+    "coarse_r3_L3": (lambda: small_vortex_pair(seed=20)[:2],
+                     dict(win=16, step=8, levels=3, radius_coarse=3, radius_fine=2)),
     "cfg1_L1_32_16_r8": (lambda: synth.cfg1_pair(1000)[:2],
                          dict(win=32, step=16, levels=1, radius_coarse=8, radius_fine=2, radius=8)),
     # the generic SAD kernel at its widest: 64 px blocks, 33 x 33 candidates
@@ -100,13 +106,16 @@ def test_predict_bitexact(case):
         assert np.array_equal(pred[i], ref.astype(np.float32)), f"pair {i}"
 
 
-def test_predict_u16_bitexact():
-    say("[predict] u16 step 12")
+# every coarse radius of the cell-shared u16 search (its waves take 2, 3, 4,
+# 5 and 5 passes of shift rows for R 3..7)
+@pytest.mark.parametrize("rc", [3, 4, 5, 6, 7])
+def test_predict_u16_bitexact(rc):
+    say(f"[predict] u16 step 12, coarse radius {rc}")
     A, B, _ = synth.cfg3_pair(0, W=384, H=216)
-    P = api().Plan(384, 216, dtype="u16", win=24, step=12, levels=3, radius_coarse=6, radius_fine=2)
+    P = api().Plan(384, 216, dtype="u16", win=24, step=12, levels=3, radius_coarse=rc, radius_fine=2)
     pred = P.predict(dev(A[None].view(np.int16)).view(torch.uint16),
                      dev(B[None].view(np.int16)).view(torch.uint16)).cpu().numpy()[0]
-    ref = oracle.predict(A, B, 12, 24, 3, 6, 2)
+    ref = oracle.predict(A, B, 12, 24, 3, rc, 2)
     assert np.array_equal(pred, ref.astype(np.float32))
 
 
