@@ -649,7 +649,7 @@ def low_seeding_study(torch, api, log_fn, inputs, seeds):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU: this build runs on a single MI355X (asked for {args.gpus}); "
+        print(f"bench.py measures one GPU: the path runs on a single MI355X (asked for {args.gpus}); "
               "pairs are independent, so N GPUs would each run this benchmark on their own stream of pairs.",
               file=sys.stderr)
         sys.exit(2)
