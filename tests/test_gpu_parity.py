@@ -145,6 +145,19 @@ def test_run_end_to_end_sgm_predictor():
         f"matching")
 
 
+# u16 coarse searches wider than the lane-per-row kernel takes (2R+1 > 17):
+# the general kernel with its candidate rows in groups, with the band staged
+@pytest.mark.parametrize("rc", [10, 16])
+def test_predict_u16_wide_coarse_bitexact(rc):
+    say(f"[predict] u16 16/8, coarse radius {rc}")
+    A, B, _ = synth.cfg3_pair(3, W=256, H=192)
+    P = api().Plan(256, 192, dtype="u16", win=16, step=8, levels=2, radius_coarse=rc, radius_fine=2)
+    pred = P.predict(dev(A[None].view(np.int16)).view(torch.uint16),
+                     dev(B[None].view(np.int16)).view(torch.uint16)).cpu().numpy()[0]
+    ref = oracle.predict(A, B, 8, 16, 2, rc, 2)
+    assert np.array_equal(pred, ref.astype(np.float32))
+
+
 @pytest.mark.parametrize("W,H,step,win", [(200, 136, 8, 16), (204, 204, 12, 24)])
 def test_predict_u16_ragged_bitexact(W, H, step, win):
     """u16 frames with ragged pyramid edges (204 px rows are not a whole
