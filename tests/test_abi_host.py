@@ -203,7 +203,9 @@ def test_padded_pyramid_holds_every_sad_read(L, kw):
             start = ((v["nx"] - 1) * step + off + cand - R) * es
             span = 4 * (NW + (2 * R + 4) // 4 + 1)
         else:
-            # G lanes per node: each from the floor word of its own shift, NW + 1 words
+            # the general kernel (a thread per candidate column and group of
+            # candidate rows; without a parent, the band those threads read,
+            # staged once): each from the floor word of its own shift, NW + 1 words
             start = ((v["nx"] - 1) * step + off + cand + R) * es
             span = 4 * (NW + 1)
         assert ((start + M * es) & ~3) + span <= v["pitch"], (l, v)
